@@ -1,0 +1,309 @@
+"""One iteration map of Alg. 1, the Picard self-consistency loop, and the
+LDOS post-process.
+
+Oracle (test infrastructure only).  Follows Alg. 1 (Sec. III.A), Eqs.
+gapeq_fixpoint and current_density (Sec. II), the Eilenberger free-energy
+form (Sec. II), App. D (A-solve), App. E (Picard on the concatenated x) and
+the LDOS definition of Sec. II with the burn-in of App. B.
+"""
+import math
+import numpy as np
+
+from . import tables, geometry, sweep, fields
+
+
+class Grain:
+    """A grain with its numerics.  components: list of (basis name or None,
+    critical temperature relative to Tc).  eta may be given directly as a
+    complex [ncomp][n_theta] table (then the names are ignored)."""
+
+    def __init__(self, nx, ny, h, shapes, n_theta, n_poles, t,
+                 components=(("s", 1.0),), crystal_rotation=0.0, kappa=0.0,
+                 flux_quanta=0.0, gauge="symmetric", charge_sign=-1,
+                 x0=None, y0=None, eta=None):
+        self.grid = geometry.Grid(nx, ny, h, x0, y0)
+        self.shapes = list(shapes)
+        self.mask = self.grid.mask(self.shapes)
+        self.area = h * h * float(self.mask.sum())
+        self.n_theta = int(n_theta)
+        self.n_poles = int(n_poles)
+        self.t = float(t)
+        self.tt = self.t / (2.0 * math.pi)
+        self.kappa = float(kappa)
+        self.flux = float(flux_quanta)
+        self.gauge = gauge
+        self.q = float(charge_sign)
+        self.phi = tables.fs_angles(self.n_theta)
+        self.wk = tables.fs_weights(self.n_theta)
+        self.zp, self.rp = tables.ozaki_poles(self.n_poles)
+        self.tc = np.array([c[1] for c in components], dtype=np.float64)
+        self.ncomp = len(components)
+        if eta is None:
+            eta = np.array([tables.basis(c[0], self.phi, crystal_rotation) for c in components])
+        self.eta = np.asarray(eta, dtype=np.complex128).reshape(self.ncomp, self.n_theta)
+        self.tables = [geometry.AngleTable(self.grid, self.shapes, p) for p in self.phi]
+        self._data = {}
+        self._rb = {}
+        self._taps = {}
+        self._maps = {}
+
+    # -- cached per-angle geometry ---------------------------------------
+    def maps(self, k):
+        if k not in self._maps:
+            self._maps[k] = self.tables[k].node_map()
+        return self._maps[k]
+
+    def data(self, k):
+        if k not in self._data:
+            self._data[k] = sweep.AngleSweepData(self.grid, self.mask, self.tables[k])
+        return self._data[k]
+
+    def rb_stencil(self, k):
+        """Rotate-back stencil of every grain cell for angle k."""
+        if k not in self._rb:
+            X, Y = self.grid.centres()
+            seg, pos = self.maps(k)
+            self._rb[k] = sweep.rotate_back_stencil(self.tables[k], seg, pos, X[self.mask], Y[self.mask])
+        return self._rb[k]
+
+    def taps(self, k, at_start):
+        key = (k, at_start)
+        if key not in self._taps:
+            self._taps[key] = [sweep.bc_taps(self.tables, k, s, at_start)
+                               for s in range(self.tables[k].nseg)]
+        return self._taps[key]
+
+    def gap_denominator(self):
+        """ln(t / t_c,G) + pi T sum_n 1/|e_n| = ln(t/t_c,G) + 2 pi sum_p R_p/z_p
+        (Eq. gapeq_fixpoint with the Ozaki poles)."""
+        return np.log(self.t / self.tc) + 2.0 * math.pi * np.sum(self.rp / self.zp)
+
+    def steps_per_sweep(self):
+        """Trajectory steps of one iteration: gamma and gamma~ each take
+        n+1 steps per segment and positive pole."""
+        nst = sum(int(np.sum(tb.nnodes + 1)) for tb in self.tables)
+        return 2 * self.n_poles * nst
+
+    # -- node values of one angle ----------------------------------------
+    def node_values(self, k, data, delta, A_ind):
+        """Delta(p_k, slot) and a(slot) on the value slots of angle k."""
+        ny, nx = self.grid.ny, self.grid.nx
+        dk = np.tensordot(self.eta[:, k], delta.reshape(self.ncomp, ny * nx), axes=(0, 0))
+        fx = data.px[data.valid]
+        fy = data.py[data.valid]
+        ex, ey = fields.external_A(self.gauge, self.flux, self.area, self.grid.cx, self.grid.cy, fx, fy)
+        return data.interpolate(dk, A_ind[0].ravel(), A_ind[1].ravel(), ex, ey)
+
+    def start_values(self, k, data, dnode, anode, eps, bc_prev):
+        """Start values of gamma at R_min and gamma~ at R_max: the bulk
+        roots at the segment ends in the first iteration (reading), then
+        the specular taps of the previous iteration's end values (Jacobi
+        update, Alg. 1), bulk where no tap exists."""
+        d0, d1 = data.end_values(dnode)
+        a0, a1 = data.end_values(anode)
+        z0 = eps[None, :] + self.q * a0[:, None]
+        z1 = eps[None, :] + self.q * a1[:, None]
+        g0 = sweep.bulk_gamma(z0, d0[:, None])
+        gt0 = sweep.bulk_gamma_tilde(z1, d1[:, None])
+        if bc_prev is None:
+            return g0, gt0
+        gend, gtend = bc_prev
+        for row, s in enumerate(data.seg_ids):
+            tp = self.taps(k, True)[s]
+            if tp:
+                g0[row] = sum(w * gend[kk][ss] for (kk, ss, w) in tp)
+            tp = self.taps(k, False)[s]
+            if tp:
+                gt0[row] = sum(w * gtend[kk][ss] for (kk, ss, w) in tp)
+        return g0, gt0
+
+    # -- the iteration map ------------------------------------------------
+    def iterate(self, delta, A_ind, bc_prev=None):
+        """One pass of the loop body of Alg. 1 with Delta and A_ind given:
+        for every angle and positive pole sweep gamma, gamma~, form the
+        Green's functions, sum over poles, rotate back and accumulate;
+        then the gap update, current and free-energy density.
+        Returns a dict with delta_new [ncomp,ny,nx], j [2,ny,nx],
+        omega_density [ny,nx], omega_total, bc (end values per angle)."""
+        ny, nx = self.grid.ny, self.grid.nx
+        delta = np.asarray(delta, dtype=np.complex128).reshape(self.ncomp, ny, nx)
+        A_ind = np.asarray(A_ind, dtype=np.float64).reshape(2, ny, nx)
+        m = self.mask
+        ncell = int(m.sum())
+        num = np.zeros((self.ncomp, ncell), dtype=np.complex128)
+        jx = np.zeros(ncell)
+        jy = np.zeros(ncell)
+        icell = np.zeros(ncell)
+        eps = 1j * self.zp * self.tt
+        gend, gtend = [], []
+        for k in range(self.n_theta):
+            data = self.data(k)
+            dnode, anode = self.node_values(k, data, delta, A_ind)
+            g0, gt0 = self.start_values(k, data, dnode, anode, eps, bc_prev)
+            gn, gtn, ge, gte = sweep.march(data, dnode, anode, eps, self.q, g0, gt0)
+            gend.append(ge)
+            gtend.append(gte)
+            sf, sg, si = sweep.node_sums(gn, gtn, dnode, self.rp, self.tt)
+            seg, pos, w = self.rb_stencil(k)
+            cf = np.sum(sf[seg, pos] * w, axis=1)
+            cg = np.sum(sg[seg, pos] * w, axis=1)
+            ci = np.sum(si[seg, pos] * w, axis=1)
+            wk = self.wk[k]
+            num += wk * np.conj(self.eta[:, k])[:, None] * cf[None, :]
+            jx += 4.0 * self.q * wk * math.cos(self.phi[k]) * cg
+            jy += 4.0 * self.q * wk * math.sin(self.phi[k]) * cg
+            icell += wk * ci
+        return self._finish(delta, A_ind, num, jx, jy, icell, (gend, gtend))
+
+    def _finish(self, delta, A_ind, num, jx, jy, icell, bc):
+        ny, nx = self.grid.ny, self.grid.nx
+        m = self.mask
+        den = self.gap_denominator()
+        dnew = np.zeros((self.ncomp, ny, nx), dtype=np.complex128)
+        for c in range(self.ncomp):
+            dnew[c][m] = num[c] / den[c]
+        j = np.zeros((2, ny, nx))
+        j[0][m] = jx
+        j[1][m] = jy
+        dcell = delta[:, m]
+        d2avg = np.zeros(dcell.shape[1])
+        for k in range(self.n_theta):
+            dk = np.tensordot(self.eta[:, k], dcell, axes=(0, 0))
+            d2avg += self.wk[k] * (dk * np.conj(dk)).real
+        om = np.zeros((ny, nx))
+        om[m] = (np.sum((dcell * np.conj(dcell)).real * np.log(self.t / self.tc)[:, None], axis=0)
+                 + 2.0 * math.pi * np.sum(self.rp / self.zp) * d2avg - icell)
+        h = self.grid.h
+        total = h * h * om.sum()
+        if self.kappa > 0.0:
+            b = fields.curl(A_ind[0], A_ind[1], h)
+            total += h * h * np.sum(0.5 * self.kappa ** 2 * b * b)
+        return {"delta_new": dnew, "j": j, "omega_density": om,
+                "omega_total": total, "bc": bc}
+
+    def iterate_cells(self, delta, A_ind, cells):
+        """The same map evaluated only at the given grain cells (flat
+        row-major indices), from bulk start values: only the segments that
+        feed those cells are swept.  Used to check full-size runs on
+        samples.  Returns (delta_new [ncomp,n], j [2,n])."""
+        ny, nx = self.grid.ny, self.grid.nx
+        delta = np.asarray(delta, dtype=np.complex128).reshape(self.ncomp, ny, nx)
+        A_ind = np.asarray(A_ind, dtype=np.float64).reshape(2, ny, nx)
+        cells = np.asarray(cells, dtype=np.int64)
+        X, Y = self.grid.centres()
+        cx = X.ravel()[cells]
+        cy = Y.ravel()[cells]
+        n = len(cells)
+        num = np.zeros((self.ncomp, n), dtype=np.complex128)
+        jx = np.zeros(n)
+        jy = np.zeros(n)
+        eps = 1j * self.zp * self.tt
+        for k in range(self.n_theta):
+            tab = self.tables[k]
+            segm, posm = self.maps(k)
+            seg, pos, w = sweep.rotate_back_stencil(tab, segm, posm, cx, cy)
+            need = np.unique(seg)
+            data = sweep.AngleSweepData(self.grid, self.mask, tab, need)
+            row = np.searchsorted(need, seg)
+            dnode, anode = self.node_values(k, data, delta, A_ind)
+            g0, gt0 = self.start_values(k, data, dnode, anode, eps, None)
+            gn, gtn, _, _ = sweep.march(data, dnode, anode, eps, self.q, g0, gt0)
+            sf, sg, si = sweep.node_sums(gn, gtn, dnode, self.rp, self.tt)
+            cf = np.sum(sf[row, pos] * w, axis=1)
+            cg = np.sum(sg[row, pos] * w, axis=1)
+            wk = self.wk[k]
+            num += wk * np.conj(self.eta[:, k])[:, None] * cf[None, :]
+            jx += 4.0 * self.q * wk * math.cos(self.phi[k]) * cg
+            jy += 4.0 * self.q * wk * math.sin(self.phi[k]) * cg
+        den = self.gap_denominator()
+        return num / den[:, None], np.stack([jx, jy])
+
+    # -- LDOS ---------------------------------------------------------------
+    def ldos(self, delta, A_ind, energies, broadening, bc_iters):
+        """Angle-averaged local density of states N(R, e)/N_F =
+        <-Im g^R / pi> (Sec. II) with z = e + i delta + q a, Delta and A
+        frozen.  bc_iters sweeps only update the boundary values (burn-in,
+        App. B); one more sweep gives the output.  Returns [E, ny, nx]."""
+        ny, nx = self.grid.ny, self.grid.nx
+        delta = np.asarray(delta, dtype=np.complex128).reshape(self.ncomp, ny, nx)
+        A_ind = np.asarray(A_ind, dtype=np.float64).reshape(2, ny, nx)
+        eps = np.asarray(energies, dtype=np.float64) + 1j * broadening
+        m = self.mask
+        ncell = int(m.sum())
+        bc = None
+        vals = [self.data(k) for k in range(self.n_theta)]
+        nodev = [self.node_values(k, vals[k], delta, A_ind) for k in range(self.n_theta)]
+        for it in range(bc_iters + 1):
+            gend, gtend = [], []
+            out = np.zeros((len(eps), ncell))
+            for k in range(self.n_theta):
+                data = vals[k]
+                dnode, anode = nodev[k]
+                g0, gt0 = self.start_values(k, data, dnode, anode, eps, bc)
+                gn, gtn, ge, gte = sweep.march(data, dnode, anode, eps, self.q, g0, gt0)
+                gend.append(ge)
+                gtend.append(gte)
+                if it == bc_iters:
+                    g, _, _ = sweep.green(gn, gtn)
+                    nval = -g.imag / math.pi                  # [S, W, E]
+                    seg, pos, w = self.rb_stencil(k)
+                    cell = np.sum(nval[seg, pos, :] * w[:, :, None], axis=1)  # [ncell, E]
+                    out += self.wk[k] * cell.T
+            bc = (gend, gtend)
+        res = np.zeros((len(eps), ny, nx))
+        res[:, m] = out
+        return res
+
+
+def rel_norm(new, old, p=2):
+    """Global error of Eq. global_error: ||new - old||_p / ||old||_p
+    (0 when both vanish, inf when only the old one does)."""
+    a = np.asarray(new - old).ravel()
+    b = np.asarray(old).ravel()
+    if p == np.inf or p == 0:
+        num, den = np.max(np.abs(a)) if a.size else 0.0, np.max(np.abs(b)) if b.size else 0.0
+    else:
+        num = np.sum(np.abs(a) ** p) ** (1.0 / p)
+        den = np.sum(np.abs(b) ** p) ** (1.0 / p)
+    if den == 0.0:
+        return 0.0 if num == 0.0 else math.inf
+    return num / den
+
+
+def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2):
+    """Picard self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on
+    grain cells, kappa^2 A_ind on all cells): x <- x + alpha (g(x) - x),
+    with A from the current of the same iteration (App. D).  During the
+    first `burnin` iterations Delta and A stay fixed and only the boundary
+    values update (App. B).  Returns the final fields and the per-iteration
+    history of (eps_Delta, eps_j, eps_A, eps_Omega, Omega)."""
+    ny, nx = grain.grid.ny, grain.grid.nx
+    delta = np.array(delta, dtype=np.complex128).reshape(grain.ncomp, ny, nx)
+    A = np.array(A_ind, dtype=np.float64).reshape(2, ny, nx)
+    m = grain.mask
+    bc = None
+    hist = []
+    j_old = None
+    om_old = None
+    for it in range(n_iter):
+        out = grain.iterate(delta, A, bc)
+        bc = out["bc"]
+        j = out["j"]
+        om = out["omega_total"]
+        if it < burnin:
+            hist.append((0.0, 0.0, 0.0, 0.0, om))
+            j_old, om_old = j, om
+            continue
+        ax, ay = fields.solve_A(j[0], j[1], m, grain.grid.h, grain.kappa)
+        A_new = np.stack([ax, ay])
+        d_new = delta + alpha * (out["delta_new"] - delta)
+        d_new[:, ~m] = 0.0
+        A_next = A + alpha * (A_new - A)
+        e_d = rel_norm(d_new[:, m], delta[:, m], norm_p)
+        e_a = rel_norm(A_next, A, norm_p)
+        e_j = rel_norm(j, j_old, norm_p) if j_old is not None else math.inf
+        e_o = abs(om - om_old) / abs(om_old) if (om_old is not None and om_old != 0.0) else math.inf
+        hist.append((e_d, e_j, e_a, e_o, om))
+        delta, A = d_new, A_next
+        j_old, om_old = j, om
+    return delta, A, hist, bc

@@ -1,0 +1,353 @@
+"""Pins of the oracle's sweep and iteration map against what the paper and
+mathematics fix (closed forms, invariants, brute force)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import geometry as geo, sweep, scf, bulk, fields, tables
+
+RNG = np.random.default_rng(1234)
+
+
+def crand(*shape, rng=RNG):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- App. C
+def test_midpoint_step_solves_the_implicit_equation():
+    g = 0.3 * crand(200)
+    d = crand(200)
+    z = 1j * np.abs(crand(200)) + 0.2 * RNG.standard_normal(200)
+    h = 0.05 + 0.3 * RNG.random(200)
+    gn = sweep.riccati_step(g, d, z, h)
+    m = 0.5 * (g + gn)
+    rhs = g + h * 1j * (np.conj(d) * m * m + 2 * z * m + d)
+    assert np.max(np.abs(gn - rhs)) < 1e-14
+
+
+def test_midpoint_march_is_second_order_against_rk45():
+    rng = np.random.default_rng(7)
+    L = 4.0
+    nodes_s = np.linspace(0, L, 9)
+    dn = 0.3 * crand(9, rng=rng)
+    zn = 1j * (0.2 + 0.1 * rng.random(9)) + 0.1 * rng.standard_normal(9)
+
+    def lin(v, s):
+        return np.interp(s, nodes_s, v.real) + 1j * np.interp(s, nodes_s, v.imag)
+
+    def rhs(s, y):
+        gm = y[0] + 1j * y[1]
+        d = lin(dn, s)
+        z = lin(zn, s)
+        f = 1j * (np.conj(d) * gm * gm + 2 * z * gm + d)
+        return [f.real, f.imag]
+
+    g0 = 0.1 + 0.2j
+    ref = solve_ivp(rhs, (0, L), [g0.real, g0.imag], rtol=1e-12, atol=1e-14, method="RK45",
+                    max_step=0.01)
+    gref = ref.y[0, -1] + 1j * ref.y[1, -1]
+    errs = []
+    for nstep in (64, 128, 256):
+        s = np.linspace(0, L, nstep + 1)
+        g = g0
+        for a in range(nstep):
+            dm = 0.5 * (lin(dn, s[a]) + lin(dn, s[a + 1]))
+            zm = 0.5 * (lin(zn, s[a]) + lin(zn, s[a + 1]))
+            g = sweep.riccati_step(g, dm, zm, s[a + 1] - s[a])
+        errs.append(abs(g - gref))
+    order = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.9 < o < 2.1 for o in order), (errs, order)
+
+
+# ------------------------------------------------------------ Sec. II.A
+def test_bulk_root_is_a_fixed_point_of_the_step():
+    d = crand(50)
+    z = 1j * np.abs(crand(50).real) + 0.1 * RNG.standard_normal(50)
+    gb = sweep.bulk_gamma(z, d)
+    assert np.max(np.abs(np.conj(d) * gb * gb + 2 * z * gb + d)) < 1e-13
+    assert np.max(np.abs(sweep.riccati_step(gb, d, z, 0.3) - gb)) < 1e-14
+    gt = sweep.bulk_gamma_tilde(z, d)
+    assert np.max(np.abs(-d * gt * gt + 2 * z * gt - np.conj(d))) < 1e-13
+
+
+def test_bulk_green_functions_closed_form():
+    # gamma = i D/(e+Om), f = pi D/Om, g = -i pi e/Om at Matsubara energies
+    d = crand(20)
+    e = 0.1 + RNG.random(20)
+    om = np.sqrt(e * e + np.abs(d) ** 2)
+    gb = sweep.bulk_gamma(1j * e, d)
+    gt = sweep.bulk_gamma_tilde(1j * e, d)
+    assert np.allclose(gb, 1j * d / (e + om), atol=1e-15)
+    assert np.allclose(gt, -1j * np.conj(d) / (e + om), atol=1e-15)
+    g, f, ft = sweep.green(gb, gt)
+    assert np.allclose(f, np.pi * d / om, atol=1e-14)
+    assert np.allclose(ft, np.pi * np.conj(d) / om, atol=1e-14)
+    assert np.allclose(g, -1j * np.pi * e / om, atol=1e-14)
+    # normalisation g^2 - f f~ = -pi^2 (g-hat^2 = -pi^2)
+    assert np.allclose(g * g - f * ft, -np.pi ** 2, atol=1e-12)
+
+
+def _cfg1_like(n_theta=32, n_poles=16, t=0.5):
+    return scf.Grain(32, 32, 0.625, [geo.Disc(0, 0, 10)], n_theta, n_poles, t)
+
+
+def test_uniform_state_nodes_are_bulk_roots():
+    gr = _cfg1_like()
+    d0 = 0.25 * np.exp(0.4j)
+    delta = np.where(gr.mask, d0, 0)[None]
+    k = 5
+    data = gr.data(k)
+    dn, an = gr.node_values(k, data, delta, np.zeros((2, 32, 32)))
+    eps = 1j * gr.zp * gr.tt
+    g0, gt0 = gr.start_values(k, data, dn, an, eps, None)
+    gn, gtn, ge, gte = sweep.march(data, dn, an, eps, gr.q, g0, gt0)
+    om = np.sqrt((gr.zp * gr.tt) ** 2 + abs(d0) ** 2)
+    exact = 1j * d0 / (gr.zp * gr.tt + om)
+    v = data.valid & (np.arange(data.W)[None, :] < data.n[:, None])
+    assert np.max(np.abs(gn[v] - exact[None, :])) < 1e-14
+    assert np.max(np.abs(gtn[v] + 1j * np.conj(d0) / (gr.zp * gr.tt + om)[None, :])) < 1e-14
+
+
+def test_tilde_march_is_conjugate_of_reversed_direction():
+    # gamma~(phi_k) = conj gamma(phi_k + pi) on the same line (Sec. II symmetry)
+    gr = scf.Grain(24, 24, 0.5, [geo.Disc(0, 0, 5.5), geo.Disc(1.0, 0.5, 1.5, add=False)], 16, 4, 0.4)
+    X, Y = gr.grid.centres()
+    delta = (0.2 + 0.05 * np.cos(X) + 0.07j * np.sin(0.6 * Y))[None] * gr.mask
+    A = np.stack([0.05 * np.sin(0.3 * Y), 0.04 * np.cos(0.2 * X)])
+    eps = 1j * gr.zp * gr.tt
+    M = gr.grid.lattice_size()
+    for k in (1, 3):
+        kk = k + 8
+        res = []
+        for kq in (k, kk):
+            data = gr.data(kq)
+            dn, an = gr.node_values(kq, data, delta, A)
+            g0, gt0 = gr.start_values(kq, data, dn, an, eps, None)
+            res.append((data, sweep.march(data, dn, an, eps, gr.q, g0, gt0)))
+        (da, (gna, gtna, _, _)), (db, (gnb, gtnb, _, _)) = res
+        ta, tb = gr.tables[k], gr.tables[kk]
+        sega, posa = ta.node_map()
+        segb, posb = tb.node_map()
+        I, J = np.nonzero(sega >= 0)
+        assert np.all(segb[M - 1 - I, M - 1 - J] >= 0)
+        a = gtna[sega[I, J], posa[I, J]]
+        b = gnb[segb[M - 1 - I, M - 1 - J], posb[M - 1 - I, M - 1 - J]]
+        assert np.max(np.abs(a - np.conj(b))) < 1e-13
+
+
+# ------------------------------------------------------ the iteration map
+def test_bcs_gap_is_the_fixed_point_of_an_s_wave_disc():
+    gr = _cfg1_like()
+    dbulk = bulk.bulk_gap(0.5, 16)
+    assert abs(dbulk / bulk.DELTA0 - 0.9568823) < 1e-7
+    delta = np.where(gr.mask, dbulk, 0)[None].astype(complex)
+    out = gr.iterate(delta, np.zeros((2, 32, 32)))
+    out = gr.iterate(delta, np.zeros((2, 32, 32)), out["bc"])
+    assert np.max(np.abs(out["delta_new"][0][gr.mask] - dbulk)) < 1e-13
+    assert abs(out["omega_total"] / gr.area - bulk.bulk_free_energy(dbulk, 0.5, 16)) < 1e-13
+    assert np.max(np.abs(out["j"])) < 1e-15
+
+
+def test_picard_converges_to_bcs_gap_from_noise():
+    gr = _cfg1_like()
+    rng = np.random.default_rng(1)
+    d0 = bulk.DELTA0 * (1.0 + rng.uniform(-0.05, 0.05, (32, 32)))
+    delta = np.where(gr.mask, d0, 0)[None].astype(complex)
+    dfin, A, hist, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 30)
+    dev = dfin[0][gr.mask] - bulk.bulk_gap(0.5, 16)
+    # Picard contracts (by ~0.885 per iteration here); the spatial noise is
+    # gone and only the slowly decaying uniform offset remains
+    eps = np.array([h_[0] for h_ in hist[2:]])
+    assert np.all(eps[1:] < eps[:-1])
+    assert np.max(np.abs(dev)) < 1.5e-3 * bulk.DELTA0
+    assert np.std(dev.real) < 0.05 * np.max(np.abs(dev))
+    assert np.max(np.abs(dev.imag)) < 1e-15
+
+
+def test_real_s_wave_carries_no_current():
+    gr = _cfg1_like()
+    rng = np.random.default_rng(1)
+    delta = np.where(gr.mask, bulk.DELTA0 * (1 + rng.uniform(-0.05, 0.05, (32, 32))), 0)[None].astype(complex)
+    out = gr.iterate(delta, np.zeros((2, 32, 32)))
+    out = gr.iterate(delta, np.zeros((2, 32, 32)), out["bc"])
+    assert np.max(np.abs(out["j"])) < 1e-15
+    assert np.max(np.abs(out["delta_new"].imag)) < 1e-15
+
+
+def test_d_wave_square_with_100_edges_keeps_uniform_bulk_state():
+    # d_{x2-y2} with [100] edges is not pair breaking: the discrete bulk root
+    # is an exact fixed point (reflected angles lie on the grid, N % 4 == 0)
+    nth, npol, t = 64, 64, 0.1
+    gr = scf.Grain(16, 16, 0.5, [geo.regular_polygon(0, 0, 4, 7.0)], nth, npol, t,
+                   components=(("dx2y2", 1.0),))
+    e2 = np.abs(gr.eta[0]) ** 2
+    db = bulk.bulk_gap(t, npol, e2, gr.wk)
+    assert abs(db / bulk.DELTA0 - 0.8577177) < 1e-7
+    delta = np.where(gr.mask, db, 0)[None].astype(complex)
+    out = gr.iterate(delta, np.zeros((2, 16, 16)))
+    out = gr.iterate(delta, np.zeros((2, 16, 16)), out["bc"])
+    assert np.max(np.abs(out["delta_new"][0][gr.mask] - db)) < 1e-12
+    assert abs(out["omega_total"] / gr.area - bulk.bulk_free_energy(db, t, npol, e2, gr.wk)) < 1e-12
+    assert abs(bulk.bulk_free_energy(db, t, npol, e2, gr.wk) + 0.028210534) < 1e-9
+
+
+def test_zero_energy_states_on_a_110_edge():
+    # d-wave with crystal axes at 45 deg: reflection changes the sign of
+    # Delta; at the wall g^R = -i pi s/z, so N(eps=0) = sqrt(|D|^2+delta^2)/delta
+    # (versus delta/sqrt(|D|^2+delta^2) in the bulk).  At eps ~ 0 the
+    # reflected start value sits near the unstable root, so the boundary
+    # values need several sweeps and long trajectories to settle.
+    t, npol, nth = 0.1, 8, 32
+    gr = scf.Grain(48, 48, 0.35, [geo.regular_polygon(0, 0, 4, 16.7)], nth, npol, t,
+                   components=(("dx2y2", 1.0),), crystal_rotation=0.125)
+    d0 = 0.25
+    delta = np.where(gr.mask, d0, 0)[None].astype(complex)
+    A = np.zeros((2, 48, 48))
+    dlt = 0.1
+    eps = np.array([0.0 + 1j * dlt])
+    bc = None
+    hist = []
+    for it in range(8):
+        ge_all, gte_all, st = [], [], []
+        for k in range(nth):
+            data = gr.data(k)
+            dn, an = gr.node_values(k, data, delta, A)
+            g0, gt0 = gr.start_values(k, data, dn, an, eps, bc)
+            gn, gtn, ge, gte = sweep.march(data, dn, an, eps, gr.q, g0, gt0)
+            ge_all.append(ge)
+            gte_all.append(gte)
+            st.append((g0, gte))
+        bc = (ge_all, gte_all)
+        hist.append(st)
+    checked = 0
+    for k in range(nth):
+        g0, gte = hist[-1][k]
+        g0p, _ = hist[-2][k]
+        tab = gr.tables[k]
+        eta = gr.eta[0, k]
+        if abs(eta) < 1.0:
+            continue
+        px, py = tab.start_point(np.arange(tab.nseg))
+        # away from the corners, long trajectories, converged start values
+        sel = (np.minimum(np.abs(px), np.abs(py)) < 3.0) & ((tab.smax - tab.smin) > 12.0)
+        sel &= np.abs(g0[:, 0] - g0p[:, 0]) < 1e-6
+        taps = gr.taps(k, True)
+        for s_ in np.nonzero(sel)[0]:
+            for (kk, ss, w) in taps[s_]:
+                t2 = gr.tables[kk]
+                if w > 0 and t2.smax[ss] - t2.smin[ss] < 12.0:
+                    sel[s_] = False
+        if not sel.any():
+            continue
+        g, _, _ = sweep.green(g0[sel, 0], gte[sel, 0])
+        nval = -g.imag / np.pi
+        dphi = abs(d0 * eta)
+        exact = math.sqrt(dphi ** 2 + dlt ** 2) / dlt
+        assert np.max(np.abs(nval / exact - 1)) < 3e-3
+        checked += int(sel.sum())
+    assert checked > 20
+
+
+def _annulus(n_wind, alpha, h=0.4, rout=12.0, rin=5.0):
+    nx = int(round(2 * rout / h)) + 2
+    gr = scf.Grain(nx, nx, h, [geo.Disc(0, 0, rout), geo.Disc(0, 0, rin, add=False)], 32, 16, 0.5,
+                   flux_quanta=alpha, gauge="solenoid")
+    X, Y = gr.grid.centres()
+    db = bulk.bulk_gap(0.5, 16)
+    delta = np.where(gr.mask, db * np.exp(1j * n_wind * np.arctan2(Y, X)), 0)[None]
+    return gr, delta, db
+
+
+def test_solenoid_annulus_linear_response_current():
+    # j_phi = q Y(t) (n + alpha) / (2 R)   (Sec. V.A, linear response)
+    n_wind, alpha = 0, 0.3
+    gr, delta, db = _annulus(n_wind, alpha)
+    out = gr.iterate(delta, np.zeros((2,) + delta.shape[1:]))
+    X, Y = gr.grid.centres()
+    r = np.hypot(X, Y)
+    jphi = (-Y * out["j"][0] + X * out["j"][1]) / np.where(r > 0, r, 1)
+    Y_t = bulk.yoshida(db, 0.5, 16)
+    assert abs(Y_t - 0.8340407) < 1e-6
+    ring = gr.mask & (r > 7.5) & (r < 9.5)
+    pred = gr.q * Y_t * (n_wind + alpha) / (2 * r)
+    rel = np.abs(jphi[ring] / pred[ring] - 1)
+    assert np.median(rel) < 0.03, np.median(rel)
+
+
+def test_fluxoid_periodicity():
+    # Omega(alpha, n) = Omega(alpha + 1, n - 1) with the same currents (Sec.
+    # V.A gauge argument).  The first sweep starts from bulk roots that see
+    # only the A-field Doppler shift, so compare after the boundary values
+    # have settled (frozen fields); the rest is O(h^2) (it falls 4x when h
+    # halves: phase winding interpolated bilinearly).
+    res = []
+    for (n, a) in ((0, 0.3), (-1, 1.3)):
+        gr, d, _ = _annulus(n, a)
+        z = np.zeros((2,) + d.shape[1:])
+        bc = None
+        for it in range(3):
+            o = gr.iterate(d, z, bc)
+            bc = o["bc"]
+        res.append(o)
+    o1, o2 = res
+    X, Y = gr.grid.centres()
+    r = np.hypot(X, Y)
+    inner = gr.mask & (r > 7) & (r < 10)
+    jn = np.max(np.abs(o1["j"]))
+    assert abs(o1["omega_total"] / o2["omega_total"] - 1) < 1.2e-2
+    assert np.max(np.abs(o1["j"] - o2["j"])[:, inner]) < 3e-3 * jn
+    # the state with n + alpha = 0.3 differs clearly from n + alpha = -0.7
+    g3, d3, _ = _annulus(0, -0.7)
+    o3 = g3.iterate(d3, np.zeros((2,) + d3.shape[1:]))
+    assert np.max(np.abs(o1["j"] - o3["j"])[:, inner]) > 0.5 * jn
+
+
+def test_c4_rotation_equivariance():
+    # a C4-symmetric grain with 90-degree-rotated input gives rotated output
+    gr = scf.Grain(24, 24, 0.5, [geo.Disc(0, 0, 5.6)], 16, 6, 0.5)
+    rng = np.random.default_rng(3)
+    d = np.where(gr.mask, 0.25 + 0.05 * (rng.random((24, 24)) + 1j * rng.random((24, 24))), 0)
+    dr = np.rot90(d)  # rows grow with y, so this is a -90 degree rotation
+    z = np.zeros((2, 24, 24))
+    a = gr.iterate(d[None], z)
+    b = gr.iterate(dr[None], z)
+    assert np.max(np.abs(np.rot90(a["delta_new"][0]) - b["delta_new"][0])) < 1e-13
+    # a vector field rotates too: (jx, jy) -> (jy, -jx)
+    assert np.max(np.abs(np.rot90(a["j"][1]) - b["j"][0])) < 1e-13
+    assert np.max(np.abs(np.rot90(-a["j"][0]) - b["j"][1])) < 1e-13
+    assert np.max(np.abs(a["j"])) > 1e-3
+    assert abs(a["omega_total"] - b["omega_total"]) < 1e-13
+
+
+# --------------------------------------------------------------- App. D
+def test_A_solve_fft_equals_direct_sum():
+    rng = np.random.default_rng(5)
+    m = np.ones((12, 14), dtype=bool)
+    m[:2, :3] = False
+    jx, jy = rng.standard_normal((2, 12, 14))
+    a1 = fields.solve_A(jx, jy, m, 0.3, 2.0, method="direct")
+    a2 = fields.solve_A(jx, jy, m, 0.3, 2.0, method="fft")
+    assert np.max(np.abs(a1[0] - a2[0])) < 1e-12 * np.max(np.abs(a1[0]))
+    assert np.max(np.abs(a1[1] - a2[1])) < 1e-12 * np.max(np.abs(a1[1]))
+
+
+def test_A_solve_azimuthal_current_gives_radial_field_integral():
+    # -lap A = j/kappa^2 with j_phi(r): B(r) = kappa^-2 int_r^inf j_phi dr
+    h, n, kappa = 0.1, 160, 3.0
+    grid = geo.Grid(n, n, h)
+    X, Y = grid.centres()
+    r = np.hypot(X, Y)
+    prof = lambda rr: rr * np.exp(-((rr - 3.0) / 1.0) ** 2)
+    jphi = prof(r)
+    jx, jy = -jphi * Y / r, jphi * X / r
+    m = np.ones((n, n), dtype=bool)
+    ax, ay = fields.solve_A(jx, jy, m, h, kappa)
+    B = fields.curl(ax, ay, h)
+    rr = np.linspace(0, 12, 20001)
+    tail = np.cumsum(prof(rr)[::-1])[::-1] * (rr[1] - rr[0])
+    for r0 in (0.5, 2.0, 3.0, 4.0):
+        sel = np.abs(r - r0) < 0.06
+        pred = np.interp(r0, rr, tail) / kappa ** 2
+        assert abs(np.mean(B[sel]) / pred - 1) < 1e-2
