@@ -1,0 +1,258 @@
+/*
+ * qcsweep: Riccati-sweep library for ballistic quasiclassical (Eilenberger)
+ * theory of 2D singlet superconducting grains, for AMD MI355X (gfx950).
+ *
+ * The method (arXiv:2205.15000): for every Fermi-surface angle phi_k and
+ * every Ozaki pole (or real energy), the coherence functions gamma and
+ * gamma~ are integrated with the implicit midpoint rule (App. C) along the
+ * lines of a square lattice rotated so that one axis is parallel to the
+ * Fermi velocity (Sec. III.A); Delta(R) and A(R) are interpolated onto the
+ * lattice bilinearly; the Green's functions of the Riccati parametrisation
+ * (Sec. II.A) are summed over energies, rotated back to the reference grid
+ * and averaged over angles into the gap update (Eq. gapeq_fixpoint), the
+ * current (Eq. current_density) and the Eilenberger free energy (Sec. II);
+ * between iterations the induced vector potential is re-solved with the
+ * cell-averaged Green's function of the 2D Laplacian (App. D).
+ *
+ * Units (App. F): lengths in xi0, energies in 2 pi k_B Tc, t = T/Tc,
+ * A in Phi0/(pi xi0), B in Phi0/(pi xi0^2), j in 2 pi k_B Tc |e| v_F N_F,
+ * free-energy density in (2 pi k_B Tc)^2 N_F per xi0^2.
+ *
+ * Layout: grid fields are row-major [..][ny][nx] with x fastest; cell (i,j)
+ * has its centre at (x0 + (i+1/2) h, y0 + (j+1/2) h).  Complex values are
+ * interleaved (re, im) doubles.
+ *
+ * Ownership: the caller owns every array argument.  Arguments of compute
+ * calls (qc_sweep, qc_solve_A, qc_scf_run, qc_ldos, qc_get_state,
+ * qc_set_state) that hold grid fields are DEVICE pointers on the grain's
+ * device (e.g. torch tensors' data_ptr); scalar outputs and small tables
+ * are host pointers, as stated per argument.  The library owns the
+ * handles and everything they hold; *_destroy frees it.
+ *
+ * Errors: no exception crosses this interface.  Status codes >= 0 are
+ * success (QC_NOT_CONVERGED is informational), < 0 are errors; the
+ * message of the last error on the calling thread is qc_last_error().
+ * Every argument is checked on the host before anything is launched.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ * return after enqueueing unless they return host scalars, in which case
+ * they synchronise the stream.  Calls on one grain must not overlap.
+ */
+#ifndef QCSWEEP_H
+#define QCSWEEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QC_OK = 0,
+  QC_NOT_CONVERGED = 1,   /* scf: max_iter reached above the tolerance */
+  QC_ERR_INVALID = -1,    /* bad argument; see qc_last_error() */
+  QC_ERR_NO_DEVICE = -2,  /* no usable gfx950 device */
+  QC_ERR_OOM = -3,        /* device or host allocation failed */
+  QC_ERR_HIP = -4,        /* a HIP runtime call failed */
+  QC_ERR_NAN = -5         /* a residual became NaN or Inf */
+} qc_status;
+
+typedef enum { QC_FP64 = 0, QC_MIXED = 1 } qc_precision;
+/* QC_MIXED: interpolated node values, the Riccati marches and the Green's
+ * functions in complex FP32; energy sums, angle sums, gap denominator, free
+ * energy, A-solve and residuals in FP64.  The interface is FP64 either way. */
+
+typedef enum {
+  QC_SHAPE_DISC = 0,             /* cx, cy, radius */
+  QC_SHAPE_REGULAR_POLYGON = 1,  /* cx, cy, n_edges, side, rotation (turns) */
+  QC_SHAPE_POLYGON = 2           /* convex, vertices vx/vy counter-clockwise */
+} qc_shape_kind;
+
+typedef enum {
+  QC_GAUGE_SYMMETRIC = 0,  /* A = B/2 (-(y-cy), x-cx), B = pi*flux/area */
+  QC_GAUGE_LANDAU = 1,     /* A = (-B (y-cy), 0) */
+  QC_GAUGE_SOLENOID = 2    /* A = flux/(2 r) along phi-hat */
+} qc_gauge;
+
+/* One geometry component (App. B).  Components are combined in order:
+ * add != 0 unites it with the grain, add == 0 removes it.  Points on a
+ * boundary count as inside.  A regular polygon with rotation 0 has a
+ * horizontal bottom edge.  vx/vy are host pointers read during the call. */
+typedef struct {
+  int kind;
+  int add;
+  double cx, cy;
+  double radius;
+  int n_edges;
+  double side;
+  double rotation;
+  const double* vx;
+  const double* vy;
+  int nv;
+} qc_shape;
+
+/* Grain description.  All pointers are host pointers read during the call.
+ *   nx, ny, h, x0, y0  reference grid (Sec. III.A)
+ *   n_theta            Fermi-surface angles phi_k = 2 pi k / n_theta with
+ *                      Boole / Simpson 3/8 / Simpson 1/3 / trapezoid
+ *                      weights when divisible by 4 / 3 / 2 / otherwise
+ *   n_poles            positive Ozaki poles of the energy sums (Sec. III.A)
+ *   t                  T/Tc, 0 < t
+ *   ncomp, tc_rel      order-parameter components and their T_c,G / Tc
+ *   eta                complex [ncomp][n_theta] basis values eta_G(phi_k)
+ *                      (App. F table, crystal rotation applied by caller)
+ *   kappa              penetration depth / xi0; <= 0 means infinite (A_ind=0)
+ *   flux_quanta, gauge external field (App. B, App. F)
+ *   charge_sign        +1 or -1 (sign of the carrier charge; -1 electrons)
+ *   precision          qc_precision
+ */
+typedef struct {
+  int nx, ny;
+  double h;
+  double x0, y0;
+  const qc_shape* shapes;
+  int n_shapes;
+  int n_theta;
+  int n_poles;
+  double t;
+  int ncomp;
+  const double* tc_rel;
+  const double* eta;
+  double kappa;
+  double flux_quanta;
+  int gauge;
+  int charge_sign;
+  int precision;
+} qc_grain_desc;
+
+typedef struct qc_plan qc_plan;    /* host-side trajectory tables */
+typedef struct qc_grain qc_grain;  /* a plan resident on one device */
+
+typedef struct {
+  int64_t n_segments;       /* trajectory segments over all angles */
+  int64_t n_slots;          /* interior lattice nodes + one midpoint slot per
+                               segment without interior node */
+  int64_t n_nodes;          /* interior lattice nodes over all angles */
+  int64_t n_grain_cells;    /* reference cells inside the grain */
+  int64_t steps_per_sweep;  /* 2 * n_poles * sum over segments of (n + 1) */
+  int lattice_m;            /* side of the rotated lattice */
+  double area;              /* h^2 * n_grain_cells, xi0^2 */
+} qc_plan_info;
+
+/* ---- library ---------------------------------------------------------- */
+/* Message of the last error on this thread ("" if none). */
+const char* qc_last_error(void);
+/* Interface version, 1 for this header. */
+int qc_version(void);
+/* Number of visible HIP devices (0 without a GPU; never an error). */
+qc_status qc_device_count(int* n_out);
+
+/* ---- host plan (no device needed) --------------------------------------
+ * Builds the trajectory tables of Sec. III.A on the host: grain mask,
+ * per-angle segments of the rotated lattice lines inside the grain with
+ * their exact end points (Fig. 2), interpolation stencils of Delta and
+ * A_ind at the lattice nodes, rotate-back stencils of the grain cells,
+ * specular boundary-condition taps (Sec. III.A: interpolation in angle and
+ * boundary coordinate), the Ozaki poles and the Fermi-surface weights. */
+qc_status qc_plan_create(const qc_grain_desc* desc, qc_plan** out);
+void qc_plan_destroy(qc_plan* plan);
+qc_status qc_plan_get_info(const qc_plan* plan, qc_plan_info* out);
+/* mask_out: host uint8 [ny][nx], 1 on grain cells. */
+qc_status qc_plan_get_mask(const qc_plan* plan, uint8_t* mask_out);
+/* out: host double [n_segments][8] = angle, line, s_min, s_max, first node
+ * index, interior node count, wall tangent angle at s_min, at s_max. */
+qc_status qc_plan_get_segments(const qc_plan* plan, double* out);
+/* Start-value taps of every segment: for gamma at s_min (at_start=1) or
+ * gamma~ at s_max (at_start=0).  seg_out: host int32 [n_segments][4]
+ * global segment indices, w_out: host double [n_segments][4] weights that
+ * sum to one; a row of zero weights means the bulk root is used. */
+qc_status qc_plan_get_taps(const qc_plan* plan, int at_start, int32_t* seg_out, double* w_out);
+/* z_out, r_out: host double [n_poles] Ozaki poles and residues. */
+qc_status qc_plan_get_poles(const qc_plan* plan, double* z_out, double* r_out);
+
+/* ---- device grain -------------------------------------------------------- */
+/* Builds the plan and uploads it to `device`.  The boundary-value store
+ * starts empty: the first sweep starts every trajectory at the bulk root of
+ * its end values. */
+qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out);
+void qc_grain_destroy(qc_grain* grain);
+qc_status qc_grain_get_info(const qc_grain* grain, qc_plan_info* out);
+/* Forget the boundary values: the next sweep starts from bulk roots. */
+qc_status qc_grain_reset_bc(qc_grain* grain);
+
+/* One iteration map (loop body of Alg. 1) with Delta and A_ind given:
+ * interpolate onto the rotated lattices, march gamma and gamma~ for every
+ * angle and positive pole, sum g, f, f~ over poles per node, rotate back,
+ * accumulate over angles; then Delta_new (Eq. gapeq_fixpoint), j
+ * (Eq. current_density) and the Eilenberger free-energy density.
+ *   delta       device complex [ncomp][ny][nx] (values off-grain ignored)
+ *   A_ind       device double [2][ny][nx] induced vector potential
+ *   delta_new   device complex [ncomp][ny][nx] (0 off-grain)
+ *   j           device double [2][ny][nx] (0 off-grain)
+ *   omega_density device double [ny][nx] condensation part (0 off-grain);
+ *               may be NULL
+ *   omega_total host double: h^2 sum omega + h^2 sum (kappa^2/2)|curl A_ind|^2;
+ *               may be NULL (then the call does not synchronise)
+ * Start values come from the boundary-value store (specular taps of the
+ * previous sweep's end values, Jacobi update as in Alg. 1); the store is
+ * then replaced by this sweep's end values. */
+qc_status qc_sweep(qc_grain* grain, const double* delta, const double* A_ind,
+                   double* delta_new, double* j, double* omega_density,
+                   double* omega_total, void* stream);
+
+/* Induced vector potential from a current (App. D): the grain mean of j is
+ * subtracted on grain cells, then A = -kappa^-2 sum G_{|dm|,|dn|} j' over the
+ * whole array (zero-padded FFT correlation), B = curl A with central
+ * differences (one-sided at the array edge).
+ *   j      device double [2][ny][nx]
+ *   A_out  device double [2][ny][nx]
+ *   B_out  device double [ny][nx], may be NULL
+ * With kappa <= 0 both outputs are zero. */
+qc_status qc_solve_A(qc_grain* grain, const double* j, double* A_out, double* B_out, void* stream);
+
+/* Picard self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on grain
+ * cells, kappa^2 A_ind): x <- x + alpha (g(x) - x), A from the current of
+ * the same iteration.  The first `burnin` iterations keep Delta and A fixed
+ * and only update boundary values (App. B).  Stops when every global error
+ * (Eq. global_error with norm_p in {1, 2, 0 = infinity}) of Delta, j, A and
+ * the free energy is below tol, after at least min_iter iterations, or at
+ * max_iter.
+ *   delta_io   device complex [ncomp][ny][nx], in: start, out: final
+ *   A_io       device double [2][ny][nx], in: start, out: final
+ *   iters_done host int
+ *   residuals_out host double [max_iter][5]: eps_Delta, eps_j, eps_A,
+ *              eps_Omega, Omega_total per iteration; may be NULL
+ * Returns QC_OK on convergence, QC_NOT_CONVERGED at max_iter. */
+qc_status qc_scf_run(qc_grain* grain, double* delta_io, double* A_io, int max_iter,
+                     int min_iter, int burnin, double tol, int norm_p, double alpha,
+                     int* iters_done, double* residuals_out, void* stream);
+
+/* Local density of states N(R, e)/N_F = < -Im g^R / pi > (Sec. II) at the
+ * real energies e + i*broadening, Delta and A frozen: bc_iters sweeps update
+ * only the boundary values (burn-in, App. B), then one sweep produces the
+ * output.  The boundary store used starts from bulk roots and is separate
+ * from the one of qc_sweep.
+ *   energies host double [n_e]
+ *   ldos_out device double [n_e][ny][nx] (0 off-grain) */
+qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,
+                  const double* energies, int n_e, double broadening, int bc_iters,
+                  double* ldos_out, void* stream);
+
+/* Boundary-value store of qc_sweep (resume without burn-in, App. B).
+ * bytes: in/out host size_t; with state == NULL only the size is returned.
+ * state: device buffer of that size. */
+qc_status qc_get_state(const qc_grain* grain, void* state, size_t* bytes, void* stream);
+qc_status qc_set_state(qc_grain* grain, const void* state, size_t bytes, void* stream);
+
+/* Kernel timing with HIP events on the launch stream (for roofline
+ * reports).  Enable, run, then read the summed milliseconds and launch
+ * count of the Riccati sweep kernel; reading resets the counters. */
+qc_status qc_profile_enable(qc_grain* grain, int enable);
+qc_status qc_profile_read(qc_grain* grain, double* sweep_ms, int64_t* sweep_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCSWEEP_H */

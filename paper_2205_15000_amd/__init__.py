@@ -1,0 +1,363 @@
+"""qcsweep: MI355X-native Riccati sweep for quasiclassical superconducting
+grains (arXiv:2205.15000), Python binding of the C-ABI library.
+
+This module only marshals arguments: every step of the method runs in the
+HIP library libqcsweep.so (built with paper_2205_15000_amd.build).  PyTorch
+supplies device memory and streams.  If the library has not been built the
+import fails with an error; there is no CPU fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+__all__ = ["Grain", "Plan", "QcError", "lib", "basis_table", "spec_desc", "PRECISIONS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqcsweep.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libqcsweep.so is not built: run `python -m paper_2205_15000_amd.build` "
+                      "(hipcc for gfx950) before importing paper_2205_15000_amd")
+lib = ctypes.CDLL(LIB_PATH)
+
+QC_OK, QC_NOT_CONVERGED = 0, 1
+PRECISIONS = {"fp64": 0, "mixed": 1}
+_SHAPES = {"disc": 0, "regular_polygon": 1, "polygon": 2}
+_GAUGES = {"symmetric": 0, "landau": 1, "solenoid": 2}
+
+
+class QcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("qcsweep error %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("add", ctypes.c_int), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("radius", ctypes.c_double), ("n_edges", ctypes.c_int),
+                ("side", ctypes.c_double), ("rotation", ctypes.c_double),
+                ("vx", ctypes.POINTER(ctypes.c_double)), ("vy", ctypes.POINTER(ctypes.c_double)),
+                ("nv", ctypes.c_int)]
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("h", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("shapes", ctypes.POINTER(_Shape)), ("n_shapes", ctypes.c_int),
+                ("n_theta", ctypes.c_int), ("n_poles", ctypes.c_int), ("t", ctypes.c_double),
+                ("ncomp", ctypes.c_int), ("tc_rel", ctypes.POINTER(ctypes.c_double)),
+                ("eta", ctypes.POINTER(ctypes.c_double)), ("kappa", ctypes.c_double),
+                ("flux_quanta", ctypes.c_double), ("gauge", ctypes.c_int),
+                ("charge_sign", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_segments", ctypes.c_int64), ("n_slots", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int64), ("n_grain_cells", ctypes.c_int64),
+                ("steps_per_sweep", ctypes.c_int64), ("lattice_m", ctypes.c_int),
+                ("area", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("qc_last_error", ctypes.c_char_p, [])
+_sig("qc_version", ctypes.c_int, [])
+_sig("qc_device_count", ctypes.c_int, [ctypes.POINTER(ctypes.c_int)])
+_sig("qc_plan_create", ctypes.c_int, [ctypes.POINTER(_Desc), ctypes.POINTER(_P)])
+_sig("qc_plan_destroy", None, [_P])
+_sig("qc_plan_get_info", ctypes.c_int, [_P, ctypes.POINTER(_Info)])
+_sig("qc_plan_get_mask", ctypes.c_int, [_P, _P])
+_sig("qc_plan_get_segments", ctypes.c_int, [_P, _P])
+_sig("qc_plan_get_taps", ctypes.c_int, [_P, ctypes.c_int, _P, _P])
+_sig("qc_plan_get_poles", ctypes.c_int, [_P, _P, _P])
+_sig("qc_grain_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_Desc), ctypes.POINTER(_P)])
+_sig("qc_grain_destroy", None, [_P])
+_sig("qc_grain_get_info", ctypes.c_int, [_P, ctypes.POINTER(_Info)])
+_sig("qc_grain_reset_bc", ctypes.c_int, [_P])
+_sig("qc_sweep", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P])
+_sig("qc_solve_A", ctypes.c_int, [_P, _P, _P, _P, _P])
+_sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int), _P, _P])
+_sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
+_sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
+_sig("qc_set_state", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P])
+_sig("qc_profile_enable", ctypes.c_int, [_P, ctypes.c_int])
+_sig("qc_profile_read", ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)])
+
+
+def _check(st):
+    if st < 0:
+        raise QcError(st, lib.qc_last_error().decode())
+    return st
+
+
+def device_count():
+    n = ctypes.c_int(0)
+    _check(lib.qc_device_count(ctypes.byref(n)))
+    return n.value
+
+
+def basis_table(components, n_theta, crystal_rotation=0.0):
+    """eta_G(phi_k) for the basis functions of App. F (circular Fermi
+    surface) at phi_k = 2 pi k / n_theta, rotated by the crystal-axes angle
+    (in full turns): s = 1, dx2y2 = sqrt2 cos 2phi, dxy = sqrt2 sin 2phi,
+    g = sqrt2 sin 4phi.  Returns complex [ncomp][n_theta]."""
+    phi = np.array([2.0 * math.pi * k / n_theta for k in range(n_theta)]) - 2.0 * math.pi * crystal_rotation
+    rows = []
+    for name, _tc in components:
+        if name == "s":
+            rows.append(np.ones(n_theta))
+        elif name == "dx2y2":
+            rows.append(math.sqrt(2.0) * np.cos(2.0 * phi))
+        elif name == "dxy":
+            rows.append(math.sqrt(2.0) * np.sin(2.0 * phi))
+        elif name == "g":
+            rows.append(math.sqrt(2.0) * np.sin(4.0 * phi))
+        else:
+            raise ValueError("unknown basis function %r" % (name,))
+    return np.array(rows, dtype=np.complex128)
+
+
+class _DescHolder:
+    """Keeps the ctypes descriptor and every array it points to alive."""
+
+    def __init__(self, spec, precision):
+        nx, ny, h = int(spec["nx"]), int(spec["ny"]), float(spec["h"])
+        x0 = spec.get("x0")
+        y0 = spec.get("y0")
+        x0 = -0.5 * nx * h if x0 is None else float(x0)
+        y0 = -0.5 * ny * h if y0 is None else float(y0)
+        comps = spec.get("components", [("s", 1.0)])
+        self.keep = []
+        shapes = (_Shape * len(spec["shapes"]))()
+        for i, sh in enumerate(spec["shapes"]):
+            s = shapes[i]
+            s.kind = _SHAPES[sh["kind"]]
+            s.add = 1 if sh.get("add", True) else 0
+            s.cx = float(sh.get("cx", 0.0))
+            s.cy = float(sh.get("cy", 0.0))
+            s.radius = float(sh.get("radius", 0.0))
+            s.n_edges = int(sh.get("n_edges", 0))
+            s.side = float(sh.get("side", 0.0))
+            s.rotation = float(sh.get("rotation", 0.0))
+            if sh["kind"] == "polygon":
+                vx = np.ascontiguousarray(sh["vx"], dtype=np.float64)
+                vy = np.ascontiguousarray(sh["vy"], dtype=np.float64)
+                self.keep += [vx, vy]
+                s.vx = vx.ctypes.data_as(_D)
+                s.vy = vy.ctypes.data_as(_D)
+                s.nv = len(vx)
+        self.keep.append(shapes)
+        n_theta = int(spec["n_theta"])
+        eta = spec.get("eta")
+        if eta is None:
+            eta = basis_table(comps, n_theta, spec.get("crystal_rotation", 0.0))
+        eta = np.ascontiguousarray(np.asarray(eta, dtype=np.complex128).reshape(len(comps), n_theta))
+        tc = np.ascontiguousarray([float(c[1]) for c in comps], dtype=np.float64)
+        self.keep += [eta, tc]
+        d = _Desc()
+        d.nx, d.ny, d.h, d.x0, d.y0 = nx, ny, h, x0, y0
+        d.shapes = shapes
+        d.n_shapes = len(spec["shapes"])
+        d.n_theta = n_theta
+        d.n_poles = int(spec["n_poles"])
+        d.t = float(spec["t"])
+        d.ncomp = len(comps)
+        d.tc_rel = tc.ctypes.data_as(_D)
+        d.eta = eta.ctypes.data_as(_D)
+        d.kappa = float(spec.get("kappa", 0.0))
+        d.flux_quanta = float(spec.get("flux_quanta", 0.0))
+        d.gauge = _GAUGES[spec.get("gauge", "symmetric")]
+        d.charge_sign = int(spec.get("charge_sign", -1))
+        d.precision = PRECISIONS[precision]
+        self.desc = d
+
+
+def spec_desc(spec, precision="fp64"):
+    return _DescHolder(spec, precision)
+
+
+def _info_dict(info):
+    return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+
+class Plan:
+    """Host-side trajectory tables (no device needed)."""
+
+    def __init__(self, spec, precision="fp64"):
+        self._h = _DescHolder(spec, precision)
+        p = _P()
+        _check(lib.qc_plan_create(ctypes.byref(self._h.desc), ctypes.byref(p)))
+        self._p = p
+        inf = _Info()
+        _check(lib.qc_plan_get_info(self._p, ctypes.byref(inf)))
+        self.info = _info_dict(inf)
+        self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            lib.qc_plan_destroy(self._p)
+            self._p = None
+
+    def mask(self):
+        m = np.zeros((self.ny, self.nx), dtype=np.uint8)
+        _check(lib.qc_plan_get_mask(self._p, m.ctypes.data))
+        return m.astype(bool)
+
+    def segments(self):
+        out = np.zeros((self.info["n_segments"], 8))
+        _check(lib.qc_plan_get_segments(self._p, out.ctypes.data))
+        return out
+
+    def taps(self, at_start):
+        n = self.info["n_segments"]
+        s = np.zeros((n, 4), dtype=np.int32)
+        w = np.zeros((n, 4))
+        _check(lib.qc_plan_get_taps(self._p, 1 if at_start else 0, s.ctypes.data, w.ctypes.data))
+        return s, w
+
+    def poles(self):
+        n = self._h.desc.n_poles
+        z = np.zeros(n)
+        r = np.zeros(n)
+        _check(lib.qc_plan_get_poles(self._p, z.ctypes.data, r.ctypes.data))
+        return z, r
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor of shape %s (got %s %s)"
+                         % (name, dtype, tuple(shape), t.dtype, tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Grain:
+    """A grain resident on one GPU.  spec: grain description dict (see
+    paper_2205_15000_amd.workloads); precision "fp64" or "mixed"."""
+
+    def __init__(self, spec, precision="fp64", device=0):
+        self._h = _DescHolder(spec, precision)
+        self.spec = spec
+        self.precision = precision
+        self.device = device
+        self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
+        self.ncomp = len(spec.get("components", [("s", 1.0)]))
+        p = _P()
+        _check(lib.qc_grain_create(int(device), ctypes.byref(self._h.desc), ctypes.byref(p)))
+        self._g = p
+        inf = _Info()
+        _check(lib.qc_grain_get_info(self._g, ctypes.byref(inf)))
+        self.info = _info_dict(inf)
+
+    def close(self):
+        if getattr(self, "_g", None):
+            lib.qc_grain_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def steps_per_sweep(self):
+        return self.info["steps_per_sweep"]
+
+    def _dev(self):
+        return _torch().device("cuda", self.device)
+
+    def reset_bc(self):
+        _check(lib.qc_grain_reset_bc(self._g))
+
+    def sweep(self, delta, A, omega_density=False, total=True, stream=None, out=None):
+        """One iteration map: returns (delta_new, j, omega_total[, omega_density])."""
+        torch = _torch()
+        shp_d = (self.ncomp, self.ny, self.nx)
+        dp = _dptr(delta, torch.complex128, shp_d, "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        if out is None:
+            dn = torch.empty(shp_d, dtype=torch.complex128, device=self._dev())
+            j = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=self._dev())
+        else:
+            dn, j = out
+        od = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self._dev()) if omega_density else None
+        tot = ctypes.c_double(0.0)
+        _check(lib.qc_sweep(self._g, dp, ap, ctypes.c_void_p(dn.data_ptr()), ctypes.c_void_p(j.data_ptr()),
+                            ctypes.c_void_p(od.data_ptr()) if od is not None else None,
+                            ctypes.byref(tot) if total else None, _stream(stream)))
+        res = (dn, j, tot.value if total else None)
+        return res + ((od,) if omega_density else ())
+
+    def solve_A(self, j, B=True, stream=None):
+        torch = _torch()
+        jp = _dptr(j, torch.float64, (2, self.ny, self.nx), "j")
+        A = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=self._dev())
+        Bt = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self._dev()) if B else None
+        _check(lib.qc_solve_A(self._g, jp, ctypes.c_void_p(A.data_ptr()),
+                              ctypes.c_void_p(Bt.data_ptr()) if Bt is not None else None, _stream(stream)))
+        return A, Bt
+
+    def scf(self, delta, A, max_iter, min_iter=0, burnin=0, tol=0.0, norm_p=2, alpha=1.0, stream=None):
+        """Picard SCF in place on (delta, A); returns (iters, residuals[iters,5], converged)."""
+        torch = _torch()
+        dp = _dptr(delta, torch.complex128, (self.ncomp, self.ny, self.nx), "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        res = np.zeros((max_iter, 5))
+        it = ctypes.c_int(0)
+        st = _check(lib.qc_scf_run(self._g, dp, ap, int(max_iter), int(min_iter), int(burnin), float(tol),
+                                   int(norm_p), float(alpha), ctypes.byref(it), res.ctypes.data, _stream(stream)))
+        return it.value, res[:it.value], st == QC_OK
+
+    def ldos(self, delta, A, energies, broadening, bc_iters, stream=None):
+        torch = _torch()
+        dp = _dptr(delta, torch.complex128, (self.ncomp, self.ny, self.nx), "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        e = np.ascontiguousarray(energies, dtype=np.float64)
+        out = torch.empty((len(e), self.ny, self.nx), dtype=torch.float64, device=self._dev())
+        _check(lib.qc_ldos(self._g, dp, ap, e.ctypes.data, len(e), float(broadening), int(bc_iters),
+                           ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def get_state(self, stream=None):
+        torch = _torch()
+        n = ctypes.c_size_t(0)
+        _check(lib.qc_get_state(self._g, None, ctypes.byref(n), None))
+        buf = torch.empty(n.value, dtype=torch.uint8, device=self._dev())
+        _check(lib.qc_get_state(self._g, ctypes.c_void_p(buf.data_ptr()), ctypes.byref(n), _stream(stream)))
+        return buf
+
+    def set_state(self, buf, stream=None):
+        _check(lib.qc_set_state(self._g, ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(buf.numel()),
+                                _stream(stream)))
+
+    def profile(self, enable=True):
+        _check(lib.qc_profile_enable(self._g, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib.qc_profile_read(self._g, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

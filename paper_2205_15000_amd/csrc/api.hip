@@ -1,0 +1,982 @@
+// C-ABI of the Riccati-sweep library; see include/qcsweep.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "qcsweep.h"
+#include "sweep.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+qc_status fail(qc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct OomError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+void hcheck(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) throw OomError(std::string(what) + ": out of device memory");
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+qc_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const OomError& e) {
+    return fail(QC_ERR_OOM, e.what());
+  } catch (const HipError& e) {
+    return fail(QC_ERR_HIP, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(QC_ERR_OOM, "host allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(QC_ERR_INVALID, e.what());
+  } catch (const std::range_error& e) {
+    return fail(QC_ERR_NAN, e.what());
+  } catch (const std::exception& e) {
+    return fail(QC_ERR_INVALID, e.what());
+  }
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+template <typename V>
+void* upload(const std::vector<V>& v) {
+  void* p = nullptr;
+  if (v.empty()) return nullptr;
+  hcheck(hipMalloc(&p, v.size() * sizeof(V)), "hipMalloc");
+  hcheck(hipMemcpy(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice), "hipMemcpy");
+  return p;
+}
+
+void* dalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) return nullptr;
+  hcheck(hipMalloc(&p, bytes), "hipMalloc");
+  return p;
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Lanes per segment and energies per lane for n_e energies.
+void lane_shape(int n_e, int& G, int& epl) {
+  epl = n_e >= 64 ? 8 : (n_e >= 16 ? 4 : (n_e >= 4 ? 2 : 1));
+  const int need = (n_e + epl - 1) / epl;
+  G = 1;
+  while (G < need) G <<= 1;
+  if (G > 64) G = 64;
+}
+
+void check_desc(const qc_grain_desc* d) {
+  if (!d) throw std::invalid_argument("desc is NULL");
+  if (d->nx < 2 || d->ny < 2) throw std::invalid_argument("nx and ny must be >= 2");
+  if (static_cast<int64_t>(d->nx) * d->ny > (int64_t(1) << 28)) throw std::invalid_argument("grid too large");
+  if (!(d->h > 0.0) || !std::isfinite(d->h)) throw std::invalid_argument("h must be finite and > 0");
+  if (!std::isfinite(d->x0) || !std::isfinite(d->y0)) throw std::invalid_argument("x0/y0 must be finite");
+  if (!d->shapes || d->n_shapes < 1) throw std::invalid_argument("at least one shape is required");
+  if (d->n_theta < 1 || d->n_theta > 4096) throw std::invalid_argument("n_theta must be in [1, 4096]");
+  if (d->n_poles < 1 || d->n_poles > 512) throw std::invalid_argument("n_poles must be in [1, 512]");
+  if (!(d->t > 0.0) || !std::isfinite(d->t)) throw std::invalid_argument("t must be finite and > 0");
+  if (d->ncomp < 1 || d->ncomp > 4) throw std::invalid_argument("ncomp must be in [1, 4]");
+  if (!d->tc_rel || !d->eta) throw std::invalid_argument("tc_rel and eta are required");
+  for (int g = 0; g < d->ncomp; ++g)
+    if (!(d->tc_rel[g] > 0.0) || !std::isfinite(d->tc_rel[g])) throw std::invalid_argument("tc_rel must be > 0");
+  for (int64_t i = 0; i < 2LL * d->ncomp * d->n_theta; ++i)
+    if (!std::isfinite(d->eta[i])) throw std::invalid_argument("eta must be finite");
+  if (!std::isfinite(d->kappa) || !std::isfinite(d->flux_quanta)) throw std::invalid_argument("kappa/flux must be finite");
+  if (d->gauge < 0 || d->gauge > 2) throw std::invalid_argument("gauge must be 0, 1 or 2");
+  if (d->charge_sign != 1 && d->charge_sign != -1) throw std::invalid_argument("charge_sign must be +1 or -1");
+  if (d->precision != QC_FP64 && d->precision != QC_MIXED) throw std::invalid_argument("precision must be 0 or 1");
+  for (int s = 0; s < d->n_shapes; ++s) {
+    const qc_shape& sh = d->shapes[s];
+    if (sh.kind == QC_SHAPE_DISC) {
+      if (!(sh.radius > 0.0) || !std::isfinite(sh.radius)) throw std::invalid_argument("disc radius must be > 0");
+    } else if (sh.kind == QC_SHAPE_REGULAR_POLYGON) {
+      if (sh.n_edges < 3 || !(sh.side > 0.0)) throw std::invalid_argument("regular polygon needs >= 3 edges, side > 0");
+    } else if (sh.kind == QC_SHAPE_POLYGON) {
+      if (sh.nv < 3 || !sh.vx || !sh.vy) throw std::invalid_argument("polygon needs >= 3 vertices");
+    } else {
+      throw std::invalid_argument("unknown shape kind");
+    }
+  }
+}
+
+void fill_plan_inputs(const qc_grain_desc* d, qc::Plan& p) {
+  p.nx = d->nx;
+  p.ny = d->ny;
+  p.h = d->h;
+  p.x0 = d->x0;
+  p.y0 = d->y0;
+  p.n_theta = d->n_theta;
+  p.n_poles = d->n_poles;
+  p.t = d->t;
+  p.ncomp = d->ncomp;
+  p.tc_rel.assign(d->tc_rel, d->tc_rel + d->ncomp);
+  p.eta.resize(static_cast<size_t>(d->ncomp) * d->n_theta);
+  for (size_t i = 0; i < p.eta.size(); ++i) p.eta[i] = {d->eta[2 * i], d->eta[2 * i + 1]};
+  p.kappa = d->kappa;
+  p.flux = d->flux_quanta;
+  p.gauge = d->gauge;
+  p.q = d->charge_sign;
+  p.precision = d->precision;
+  p.shapes.clear();
+  for (int s = 0; s < d->n_shapes; ++s) {
+    const qc_shape& in = d->shapes[s];
+    qc::Shape sh;
+    sh.add = in.add != 0;
+    if (in.kind == QC_SHAPE_DISC) {
+      sh.kind = 0;
+      sh.cx = in.cx;
+      sh.cy = in.cy;
+      sh.r = in.radius;
+    } else if (in.kind == QC_SHAPE_REGULAR_POLYGON) {
+      // first edge horizontal at the bottom for rotation 0
+      sh.kind = 1;
+      const int n = in.n_edges;
+      const double rc = in.side / (2.0 * std::sin(kPi / n));
+      for (int m = 0; m < n; ++m) {
+        const double a = -0.5 * kPi - kPi / n + 2.0 * kPi * m / n + 2.0 * kPi * in.rotation;
+        sh.vx.push_back(in.cx + rc * std::cos(a));
+        sh.vy.push_back(in.cy + rc * std::sin(a));
+      }
+    } else {
+      sh.kind = 1;
+      sh.vx.assign(in.vx, in.vx + in.nv);
+      sh.vy.assign(in.vy, in.vy + in.nv);
+    }
+    p.shapes.push_back(sh);
+  }
+}
+
+void info_of(const qc::Plan& p, qc_plan_info* o) {
+  o->n_segments = p.nseg;
+  o->n_slots = p.nslot;
+  o->n_nodes = p.nnode;
+  o->n_grain_cells = static_cast<int64_t>(p.grain_cells.size());
+  o->steps_per_sweep = p.steps_per_sweep();
+  o->lattice_m = p.M;
+  o->area = p.area;
+}
+
+// Cell-averaged Green's function of the 2D Laplacian (App. D closed form).
+double green_mn(double m, double n, double h) {
+  auto alpha = [](double a, double b) {
+    return (1 + 2 * a) * (1 + 2 * b) * std::log(0.5 * (1 + 2 * a) * (1 + 2 * a) + 0.5 * (1 + 2 * b) * (1 + 2 * b));
+  };
+  auto beta = [](double a, double b) { return (-2 * a * a + 2 * b * b + 4 * b + 1) * std::atan((1 + 2 * a) / (1 + 2 * b)); };
+  double tot = 0.0;
+  for (int sa = 0; sa < 2; ++sa)
+    for (int sb = 0; sb < 2; ++sb) {
+      const double a = sa ? -m : m, b = sb ? -n : n;
+      tot += alpha(a, b) + beta(a, b) + beta(b, a);
+    }
+  return h * h / (4.0 * kPi) * (2.0 * std::log(h) - std::log(2.0) - 3.0 + 0.25 * tot);
+}
+
+}  // namespace
+
+struct qc_plan {
+  qc::Plan p;
+};
+
+struct qc_grain {
+  int device = 0;
+  qc_plan_info info{};
+  int nx = 0, ny = 0, ncomp = 0, n_theta = 0, n_poles = 0, precision = 0;
+  double h = 0, t = 0, kappa = 0, q = -1, twopi_rz = 0;
+  int64_t ncell = 0, ncg = 0, nseg = 0, nslot = 0;
+  std::vector<double> zp, rp;
+  // static tables
+  int32_t* slot_angle = nullptr;
+  int32_t* dst_idx = nullptr;
+  double* dst_w = nullptr;
+  int32_t* ast_idx = nullptr;
+  double* ast_w = nullptr;
+  double* aext = nullptr;
+  double* eta = nullptr;
+  double* cosk = nullptr;
+  double* sink = nullptr;
+  double* wk = nullptr;
+  int64_t* seg_slot0 = nullptr;
+  int32_t* seg_n = nullptr;
+  double* seg_hfirst = nullptr;
+  double* seg_hlast = nullptr;
+  int32_t* tap_s_seg = nullptr;
+  double* tap_s_w = nullptr;
+  int32_t* tap_e_seg = nullptr;
+  double* tap_e_w = nullptr;
+  int32_t* grain_cells = nullptr;
+  int32_t* rb_idx = nullptr;
+  double* rb_w = nullptr;
+  uint8_t* mask = nullptr;
+  double* eps = nullptr;
+  double* rpd = nullptr;
+  double* den = nullptr;
+  double* logt = nullptr;
+  // work buffers
+  void* dslot = nullptr;
+  void* aslot = nullptr;
+  void* gbuf = nullptr;
+  double* node_out = nullptr;
+  void* bc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int bc_cur = 0;
+  int bc_valid = 0;
+  double* omega_cell = nullptr;
+  double* part = nullptr;
+  double* part_host = nullptr;
+  double* bbuf = nullptr;
+  // A-solve
+  int px = 0, py = 0, lpx = 0, lpy = 0;
+  double2* fw = nullptr;
+  double2* fw2 = nullptr;
+  double2* ghat = nullptr;
+  double2* twx = nullptr;
+  double2* twy = nullptr;
+  // SCF scratch
+  double* dnew = nullptr;
+  double* jcur = nullptr;
+  double* jold = nullptr;
+  double* anew = nullptr;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double prof_ms = 0.0;
+  int64_t prof_n = 0;
+
+  size_t real_bytes() const { return precision == QC_MIXED ? sizeof(float) : sizeof(double); }
+};
+
+static constexpr int kParts = 256;
+
+namespace {
+
+void free_grain(qc_grain* g) {
+  void* ptrs[] = {g->slot_angle, g->dst_idx, g->dst_w, g->ast_idx, g->ast_w, g->aext, g->eta, g->cosk,
+                  g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
+                  g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
+                  g->eps, g->rpd, g->den, g->logt, g->dslot, g->aslot, g->gbuf, g->node_out, g->bc[0][0],
+                  g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->part, g->bbuf, g->fw, g->fw2,
+                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (g->part_host) (void)hipHostFree(g->part_host);
+  for (auto& e : g->ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete g;
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+// Host sum of the first n block partials (fixed order: deterministic).
+double host_sum(qc_grain* g, int n, hipStream_t st) {
+  hcheck(hipMemcpyAsync(g->part_host, g->part, sizeof(double) * n, hipMemcpyDeviceToHost, st), "D2H");
+  hcheck(hipStreamSynchronize(st), "sync");
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += g->part_host[i];
+  return s;
+}
+
+void fft_forward_2d(qc_grain* g, hipStream_t st, int sign) {
+  // rows along x, transpose, rows along y (result in fw2, [px][py] layout)
+  qc::launch_fft_rows(g->fw, g->py, g->lpx, g->twx, sign, st);
+  qc::launch_transpose(g->fw, g->fw2, g->py, g->px, st);
+  qc::launch_fft_rows(g->fw2, g->px, g->lpy, g->twy, sign, st);
+}
+
+void fft_inverse_2d(qc_grain* g, hipStream_t st) {
+  qc::launch_fft_rows(g->fw2, g->px, g->lpy, g->twy, +1, st);
+  qc::launch_transpose(g->fw2, g->fw, g->px, g->py, st);
+  qc::launch_fft_rows(g->fw, g->py, g->lpx, g->twx, +1, st);
+}
+
+std::vector<double2> twiddles(int n) {
+  std::vector<double2> tw(std::max(1, n / 2));
+  for (int k = 0; k < n / 2; ++k) tw[k] = make_double2(std::cos(2.0 * kPi * k / n), -std::sin(2.0 * kPi * k / n));
+  return tw;
+}
+
+void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st) {
+  qc::InterpArgs a;
+  a.nslot = g->nslot;
+  a.ncell = g->ncell;
+  a.ncomp = g->ncomp;
+  a.n_theta = g->n_theta;
+  a.slot_angle = g->slot_angle;
+  a.dst_idx = g->dst_idx;
+  a.dst_w = g->dst_w;
+  a.ast_idx = g->ast_idx;
+  a.ast_w = g->ast_w;
+  a.aext = g->aext;
+  a.eta = g->eta;
+  a.cosk = g->cosk;
+  a.sink = g->sink;
+  a.delta = delta;
+  a.A = A;
+  if (g->precision == QC_MIXED)
+    qc::launch_interp<float>(a, g->dslot, g->aslot, st);
+  else
+    qc::launch_interp<double>(a, g->dslot, g->aslot, st);
+}
+
+qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const double* eps, const double* rp) {
+  qc::SweepArgs a;
+  a.nseg = g->nseg;
+  int epl;
+  lane_shape(n_e, a.G, epl);
+  a.log2g = ilog2(a.G);
+  a.n_e = n_e;
+  a.n_e_tot = n_e_tot;
+  a.e_off = e_off;
+  a.bc_valid = 0;
+  a.h = g->h;
+  a.q = g->q;
+  a.tt = g->t / (2.0 * kPi);
+  a.twopi_tt = g->t;
+  a.seg_slot0 = g->seg_slot0;
+  a.seg_n = g->seg_n;
+  a.seg_hfirst = g->seg_hfirst;
+  a.seg_hlast = g->seg_hlast;
+  a.tap_start_seg = g->tap_s_seg;
+  a.tap_start_w = g->tap_s_w;
+  a.tap_end_seg = g->tap_e_seg;
+  a.tap_end_w = g->tap_e_w;
+  a.eps = eps;
+  a.rp = rp;
+  a.node_out = g->node_out;
+  return a;
+}
+
+void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc::SweepBufs& b, hipStream_t st) {
+  int G, epl;
+  lane_shape(a.n_e, G, epl);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g->prof) {
+    hcheck(hipEventCreate(&e0), "event");
+    hcheck(hipEventCreate(&e1), "event");
+    hcheck(hipEventRecord(e0, st), "event");
+  }
+  if (g->precision == QC_MIXED)
+    qc::launch_sweep<float>(mode, epl, a, b, st);
+  else
+    qc::launch_sweep<double>(mode, epl, a, b, st);
+  hcheck(hipGetLastError(), "sweep launch");
+  if (g->prof) {
+    hcheck(hipEventRecord(e1, st), "event");
+    g->ev.push_back({e0, e1});
+  }
+}
+
+// steps 3-8 of one iteration; omega_total (host) optional
+void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_new, double* j, double* omega,
+              double* omega_total, hipStream_t st) {
+  do_interp(g, delta, A, st);
+  qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
+  a.bc_valid = g->bc_valid;
+  qc::SweepBufs b;
+  b.dslot = g->dslot;
+  b.aslot = g->aslot;
+  b.bc_g_prev = g->bc[g->bc_cur][0];
+  b.bc_gt_prev = g->bc[g->bc_cur][1];
+  b.bc_g_next = g->bc[1 - g->bc_cur][0];
+  b.bc_gt_next = g->bc[1 - g->bc_cur][1];
+  b.gbuf = g->gbuf;
+  b.ebuf = nullptr;
+  launch_sweep_timed(g, 0, a, b, st);
+  g->bc_cur = 1 - g->bc_cur;
+  g->bc_valid = 1;
+
+  qc::launch_fill(delta_new, 2 * g->ncomp * g->ncell, 0.0, st);
+  qc::launch_fill(j, 2 * g->ncell, 0.0, st);
+  if (omega) qc::launch_fill(omega, g->ncell, 0.0, st);
+  qc::BackArgs r;
+  r.ncg = g->ncg;
+  r.ncell = g->ncell;
+  r.ncomp = g->ncomp;
+  r.n_theta = g->n_theta;
+  r.grain_cells = g->grain_cells;
+  r.rb_idx = g->rb_idx;
+  r.rb_w = g->rb_w;
+  r.node_out = g->node_out;
+  r.wk = g->wk;
+  r.cosk = g->cosk;
+  r.sink = g->sink;
+  r.eta = g->eta;
+  r.den = g->den;
+  r.logt = g->logt;
+  r.four_q = 4.0 * g->q;
+  r.twopi_rz = g->twopi_rz;
+  r.delta = delta;
+  r.delta_new = delta_new;
+  r.j = j;
+  r.omega = omega;
+  r.omega_cell = g->omega_cell;
+  qc::launch_rotate_back(r, st);
+  hcheck(hipGetLastError(), "rotate-back launch");
+  if (omega_total) {
+    qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, g->part, kParts, st);
+    double tot = g->h * g->h * host_sum(g, kParts, st);
+    if (g->kappa > 0.0) {
+      qc::launch_curl(A, g->bbuf, g->nx, g->ny, g->h, st);
+      qc::launch_block_sum(g->bbuf, nullptr, g->ncell, 1, g->part, kParts, st);
+      tot += g->h * g->h * 0.5 * g->kappa * g->kappa * host_sum(g, kParts, st);
+    }
+    *omega_total = tot;
+  }
+}
+
+void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipStream_t st);
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+extern "C" {
+
+const char* qc_last_error(void) { return g_err.c_str(); }
+
+int qc_version(void) { return 1; }
+
+qc_status qc_device_count(int* n_out) {
+  if (!n_out) return fail(QC_ERR_INVALID, "n_out is NULL");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) n = 0;
+  *n_out = n;
+  return QC_OK;
+}
+
+qc_status qc_plan_create(const qc_grain_desc* desc, qc_plan** out) {
+  return guarded([&]() -> qc_status {
+    if (!out) throw std::invalid_argument("out is NULL");
+    *out = nullptr;
+    check_desc(desc);
+    auto* pl = new qc_plan();
+    try {
+      fill_plan_inputs(desc, pl->p);
+      qc::build_plan(pl->p);
+    } catch (...) {
+      delete pl;
+      throw;
+    }
+    *out = pl;
+    return QC_OK;
+  });
+}
+
+void qc_plan_destroy(qc_plan* plan) { delete plan; }
+
+qc_status qc_plan_get_info(const qc_plan* plan, qc_plan_info* out) {
+  if (!plan || !out) return fail(QC_ERR_INVALID, "NULL argument");
+  info_of(plan->p, out);
+  return QC_OK;
+}
+
+qc_status qc_plan_get_mask(const qc_plan* plan, uint8_t* mask_out) {
+  if (!plan || !mask_out) return fail(QC_ERR_INVALID, "NULL argument");
+  std::memcpy(mask_out, plan->p.mask.data(), plan->p.mask.size());
+  return QC_OK;
+}
+
+qc_status qc_plan_get_segments(const qc_plan* plan, double* out) {
+  if (!plan || !out) return fail(QC_ERR_INVALID, "NULL argument");
+  const qc::Plan& p = plan->p;
+  for (int64_t g = 0; g < p.nseg; ++g) {
+    double* o = out + g * 8;
+    o[0] = p.seg_angle[g];
+    o[1] = p.seg_line[g];
+    o[2] = p.seg_smin[g];
+    o[3] = p.seg_smax[g];
+    o[4] = p.seg_jfirst[g];
+    o[5] = p.seg_n[g];
+    o[6] = p.seg_tmin[g];
+    o[7] = p.seg_tmax[g];
+  }
+  return QC_OK;
+}
+
+qc_status qc_plan_get_taps(const qc_plan* plan, int at_start, int32_t* seg_out, double* w_out) {
+  if (!plan || !seg_out || !w_out) return fail(QC_ERR_INVALID, "NULL argument");
+  const qc::Plan& p = plan->p;
+  const auto& s = at_start ? p.tap_start_seg : p.tap_end_seg;
+  const auto& w = at_start ? p.tap_start_w : p.tap_end_w;
+  std::memcpy(seg_out, s.data(), s.size() * sizeof(int32_t));
+  std::memcpy(w_out, w.data(), w.size() * sizeof(double));
+  return QC_OK;
+}
+
+qc_status qc_plan_get_poles(const qc_plan* plan, double* z_out, double* r_out) {
+  if (!plan || !z_out || !r_out) return fail(QC_ERR_INVALID, "NULL argument");
+  std::memcpy(z_out, plan->p.zp.data(), plan->p.zp.size() * sizeof(double));
+  std::memcpy(r_out, plan->p.rp.data(), plan->p.rp.size() * sizeof(double));
+  return QC_OK;
+}
+
+qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out) {
+  if (!out) return fail(QC_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(QC_ERR_NO_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(QC_ERR_INVALID, "device index out of range");
+  qc_grain* g = new (std::nothrow) qc_grain();
+  if (!g) return fail(QC_ERR_OOM, "host allocation failed");
+  qc_status st = guarded([&]() -> qc_status {
+    check_desc(desc);
+    hipDeviceProp_t prop;
+    hcheck(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      throw HipError(std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    hcheck(hipSetDevice(device), "hipSetDevice");
+    g->device = device;
+    qc::Plan p;
+    fill_plan_inputs(desc, p);
+    qc::build_plan(p);
+    info_of(p, &g->info);
+    g->nx = p.nx;
+    g->ny = p.ny;
+    g->ncomp = p.ncomp;
+    g->n_theta = p.n_theta;
+    g->n_poles = p.n_poles;
+    g->precision = p.precision;
+    g->h = p.h;
+    g->t = p.t;
+    g->kappa = p.kappa;
+    g->q = p.q;
+    g->ncell = static_cast<int64_t>(p.nx) * p.ny;
+    g->ncg = static_cast<int64_t>(p.grain_cells.size());
+    g->nseg = p.nseg;
+    g->nslot = p.nslot;
+    g->zp = p.zp;
+    g->rp = p.rp;
+    double rz = 0.0;
+    for (int k = 0; k < p.n_poles; ++k) rz += p.rp[k] / p.zp[k];
+    g->twopi_rz = 2.0 * kPi * rz;
+    std::vector<double> den(p.ncomp), logt(p.ncomp);
+    for (int c = 0; c < p.ncomp; ++c) {
+      logt[c] = std::log(p.t / p.tc_rel[c]);
+      den[c] = logt[c] + g->twopi_rz;
+    }
+    std::vector<double> eps(2 * p.n_poles);
+    const double tt = p.t / (2.0 * kPi);
+    for (int k = 0; k < p.n_poles; ++k) {
+      eps[2 * k] = 0.0;
+      eps[2 * k + 1] = p.zp[k] * tt;
+    }
+    std::vector<double> eta(2 * p.eta.size());
+    for (size_t i = 0; i < p.eta.size(); ++i) {
+      eta[2 * i] = p.eta[i].real();
+      eta[2 * i + 1] = p.eta[i].imag();
+    }
+    g->slot_angle = static_cast<int32_t*>(upload(p.slot_angle));
+    g->dst_idx = static_cast<int32_t*>(upload(p.dst_idx));
+    g->dst_w = static_cast<double*>(upload(p.dst_w));
+    g->ast_idx = static_cast<int32_t*>(upload(p.ast_idx));
+    g->ast_w = static_cast<double*>(upload(p.ast_w));
+    g->aext = static_cast<double*>(upload(p.slot_aext));
+    g->eta = static_cast<double*>(upload(eta));
+    g->cosk = static_cast<double*>(upload(p.cosk));
+    g->sink = static_cast<double*>(upload(p.sink));
+    g->wk = static_cast<double*>(upload(p.wk));
+    g->seg_slot0 = static_cast<int64_t*>(upload(p.seg_slot0));
+    g->seg_n = static_cast<int32_t*>(upload(p.seg_n));
+    g->seg_hfirst = static_cast<double*>(upload(p.seg_hfirst));
+    g->seg_hlast = static_cast<double*>(upload(p.seg_hlast));
+    g->tap_s_seg = static_cast<int32_t*>(upload(p.tap_start_seg));
+    g->tap_s_w = static_cast<double*>(upload(p.tap_start_w));
+    g->tap_e_seg = static_cast<int32_t*>(upload(p.tap_end_seg));
+    g->tap_e_w = static_cast<double*>(upload(p.tap_end_w));
+    g->grain_cells = static_cast<int32_t*>(upload(p.grain_cells));
+    g->rb_idx = static_cast<int32_t*>(upload(p.rb_idx));
+    g->rb_w = static_cast<double*>(upload(p.rb_w));
+    g->mask = static_cast<uint8_t*>(upload(p.mask));
+    g->eps = static_cast<double*>(upload(eps));
+    g->rpd = static_cast<double*>(upload(p.rp));
+    g->den = static_cast<double*>(upload(den));
+    g->logt = static_cast<double*>(upload(logt));
+    const size_t rb = g->real_bytes();
+    g->dslot = dalloc(2 * rb * g->nslot);
+    g->aslot = dalloc(rb * g->nslot);
+    g->gbuf = dalloc(2 * rb * g->nslot * p.n_poles);
+    g->node_out = static_cast<double*>(dalloc(4 * sizeof(double) * g->nslot));
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) g->bc[a][b] = dalloc(2 * rb * g->nseg * p.n_poles);
+    g->omega_cell = static_cast<double*>(dalloc(sizeof(double) * g->ncg));
+    g->part = static_cast<double*>(dalloc(sizeof(double) * 2 * kParts));
+    hcheck(hipHostMalloc(reinterpret_cast<void**>(&g->part_host), sizeof(double) * 2 * kParts), "hipHostMalloc");
+    g->bbuf = static_cast<double*>(dalloc(sizeof(double) * g->ncell));
+    g->dnew = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
+    g->jcur = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
+    g->jold = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
+    g->anew = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
+    if (g->kappa > 0.0) {
+      g->px = 1 << ilog2(2 * p.nx);
+      g->py = 1 << ilog2(2 * p.ny);
+      g->lpx = ilog2(g->px);
+      g->lpy = ilog2(g->py);
+      if (g->lpx > 12 || g->lpy > 12) throw std::invalid_argument("grid too large for the A-solve (max 2048)");
+      const int64_t np = static_cast<int64_t>(g->px) * g->py;
+      std::vector<double2> gp(np);
+      for (int y = 0; y < g->py; ++y)
+        for (int x = 0; x < g->px; ++x) {
+          const int m = std::min(x, g->px - x), n = std::min(y, g->py - y);
+          const double v = (m <= p.nx - 1 && n <= p.ny - 1) ? green_mn(m, n, p.h) : 0.0;
+          gp[static_cast<int64_t>(y) * g->px + x] = make_double2(v, 0.0);
+        }
+      g->twx = static_cast<double2*>(upload(twiddles(g->px)));
+      g->twy = static_cast<double2*>(upload(twiddles(g->py)));
+      g->fw = static_cast<double2*>(upload(gp));
+      g->fw2 = static_cast<double2*>(dalloc(sizeof(double2) * np));
+      g->ghat = static_cast<double2*>(dalloc(sizeof(double2) * np));
+      fft_forward_2d(g, nullptr, -1);
+      hcheck(hipMemcpy(g->ghat, g->fw2, sizeof(double2) * np, hipMemcpyDeviceToDevice), "copy");
+    }
+    hcheck(hipDeviceSynchronize(), "grain setup");
+    return QC_OK;
+  });
+  if (st != QC_OK) {
+    free_grain(g);
+    return st;
+  }
+  *out = g;
+  return QC_OK;
+}
+
+void qc_grain_destroy(qc_grain* grain) {
+  if (!grain) return;
+  (void)hipSetDevice(grain->device);
+  (void)hipDeviceSynchronize();
+  free_grain(grain);
+}
+
+qc_status qc_grain_get_info(const qc_grain* grain, qc_plan_info* out) {
+  if (!grain || !out) return fail(QC_ERR_INVALID, "NULL argument");
+  *out = grain->info;
+  return QC_OK;
+}
+
+qc_status qc_grain_reset_bc(qc_grain* grain) {
+  if (!grain) return fail(QC_ERR_INVALID, "grain is NULL");
+  grain->bc_valid = 0;
+  return QC_OK;
+}
+
+qc_status qc_sweep(qc_grain* g, const double* delta, const double* A_ind, double* delta_new, double* j,
+                   double* omega_density, double* omega_total, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !delta_new || !j) return fail(QC_ERR_INVALID, "delta, A_ind, delta_new and j are required");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    do_sweep(g, delta, A_ind, delta_new, j, omega_density, omega_total, S(stream));
+    return QC_OK;
+  });
+}
+
+}  // extern "C"
+
+
+namespace {
+
+void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipStream_t st) {
+  if (g->kappa <= 0.0) {
+    qc::launch_fill(A_out, 2 * g->ncell, 0.0, st);
+    if (B_out) qc::launch_fill(B_out, g->ncell, 0.0, st);
+    return;
+  }
+  // mean current over the grain cells, subtracted before the solve (App. D)
+  double mean[2];
+  for (int c = 0; c < 2; ++c) {
+    qc::launch_block_sum(j + c * g->ncell, g->grain_cells, g->ncg, 0, g->part, kParts, st);
+    mean[c] = host_sum(g, kParts, st) / static_cast<double>(g->ncg);
+  }
+  qc::launch_pad_current(j, g->mask, g->nx, g->ny, g->px, g->py, mean[0], mean[1], g->fw, st);
+  fft_forward_2d(g, st, -1);
+  qc::launch_cmul(g->fw2, g->ghat, static_cast<int64_t>(g->px) * g->py, st);
+  fft_inverse_2d(g, st);
+  const double scale = -1.0 / (g->kappa * g->kappa * static_cast<double>(g->px) * g->py);
+  qc::launch_unpad_A(g->fw, g->nx, g->ny, g->px, scale, A_out, st);
+  if (B_out) qc::launch_curl(A_out, B_out, g->nx, g->ny, g->h, st);
+  hcheck(hipGetLastError(), "A-solve launch");
+}
+
+// relative p-norm difference ||new - old|| / ||old|| over n elements of
+// `stride` doubles, gathered through idx when given, for nrep fields
+double rel_diff(qc_grain* g, const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
+                int64_t field_stride, int stride, int p, hipStream_t st) {
+  qc::DiffNormArgs a;
+  a.xnew = xnew;
+  a.xold = xold;
+  a.idx = idx;
+  a.n = n;
+  a.nrep = nrep;
+  a.field_stride = field_stride;
+  a.stride = stride;
+  a.p = p;
+  a.part = g->part;
+  qc::launch_diff_norm(a, kParts, st);
+  hcheck(hipMemcpyAsync(g->part_host, g->part, sizeof(double) * 2 * kParts, hipMemcpyDeviceToHost, st), "D2H");
+  hcheck(hipStreamSynchronize(st), "sync");
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < kParts; ++i) {
+    if (p == 0) {
+      num = std::max(num, g->part_host[2 * i]);
+      den = std::max(den, g->part_host[2 * i + 1]);
+    } else {
+      num += g->part_host[2 * i];
+      den += g->part_host[2 * i + 1];
+    }
+  }
+  if (p == 2) {
+    num = std::sqrt(num);
+    den = std::sqrt(den);
+  }
+  if (den == 0.0) return num == 0.0 ? 0.0 : INFINITY;
+  return num / den;
+}
+
+}  // namespace
+
+extern "C" {
+
+qc_status qc_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!j || !A_out) return fail(QC_ERR_INVALID, "j and A_out are required");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    do_solve_A(g, j, A_out, B_out, S(stream));
+    return QC_OK;
+  });
+}
+
+qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, int min_iter, int burnin,
+                     double tol, int norm_p, double alpha, int* iters_done, double* residuals_out, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta_io || !A_io) return fail(QC_ERR_INVALID, "delta_io and A_io are required");
+  if (max_iter < 1 || min_iter < 0 || burnin < 0) return fail(QC_ERR_INVALID, "bad iteration counts");
+  if (!(tol >= 0.0) || !(alpha > 0.0) || !std::isfinite(alpha)) return fail(QC_ERR_INVALID, "bad tol or alpha");
+  if (norm_p != 0 && norm_p != 1 && norm_p != 2) return fail(QC_ERR_INVALID, "norm_p must be 0, 1 or 2");
+  return guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    // Delta lives on grain cells only
+    {
+      // zero the off-grain cells of the input once (they stay zero)
+      hcheck(hipMemcpyAsync(g->dnew, delta_io, sizeof(double) * 2 * g->ncomp * g->ncell, hipMemcpyDeviceToDevice,
+                            st),
+             "copy");
+      qc::launch_fill(delta_io, 2 * g->ncomp * g->ncell, 0.0, st);
+      qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, st);
+    }
+    double om_old = 0.0;
+    bool have_old = false;
+    int it = 0;
+    bool conv = false;
+    for (; it < max_iter; ++it) {
+      double om = 0.0;
+      do_sweep(g, delta_io, A_io, g->dnew, g->jcur, nullptr, &om, st);
+      double res[5] = {0.0, 0.0, 0.0, 0.0, om};
+      if (it < burnin) {
+        hcheck(hipMemcpyAsync(g->jold, g->jcur, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+        om_old = om;
+        have_old = true;
+        if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
+        continue;
+      }
+      do_solve_A(g, g->jcur, g->anew, nullptr, st);
+      res[0] = alpha * rel_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, st);
+      res[1] = have_old ? rel_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, st) : INFINITY;
+      res[2] = alpha * rel_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, st);
+      res[3] = (have_old && om_old != 0.0) ? std::fabs(om - om_old) / std::fabs(om_old) : INFINITY;
+      if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
+      if (!std::isfinite(res[0]) || !std::isfinite(om) || (std::isnan(res[2])))
+        throw std::range_error("non-finite residual");
+      qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, alpha, st);
+      qc::launch_picard(A_io, g->anew, nullptr, 2 * g->ncell, 1, 0, 1, alpha, st);
+      hcheck(hipMemcpyAsync(g->jold, g->jcur, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+      om_old = om;
+      have_old = true;
+      if (it + 1 >= min_iter && res[0] < tol && res[1] < tol && res[2] < tol && res[3] < tol) {
+        conv = true;
+        ++it;
+        break;
+      }
+    }
+    hcheck(hipStreamSynchronize(st), "sync");
+    if (iters_done) *iters_done = it;
+    return conv ? QC_OK : QC_NOT_CONVERGED;
+  });
+}
+
+qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const double* energies, int n_e,
+                  double broadening, int bc_iters, double* ldos_out, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !energies || !ldos_out) return fail(QC_ERR_INVALID, "NULL argument");
+  if (n_e < 1 || bc_iters < 0) return fail(QC_ERR_INVALID, "n_e must be >= 1 and bc_iters >= 0");
+  if (!(broadening > 0.0) || !std::isfinite(broadening)) return fail(QC_ERR_INVALID, "broadening must be > 0");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(energies[i])) return fail(QC_ERR_INVALID, "energies must be finite");
+  void* bcl[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  double* deps = nullptr;
+  void* lg = nullptr;
+  void* le = nullptr;
+  qc_status rs = guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    const size_t rb = g->real_bytes();
+    std::vector<double> eps(2 * n_e);
+    for (int i = 0; i < n_e; ++i) {
+      eps[2 * i] = energies[i];
+      eps[2 * i + 1] = broadening;
+    }
+    deps = static_cast<double*>(upload(eps));
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) bcl[a][b] = dalloc(2 * rb * g->nseg * n_e);
+    do_interp(g, delta, A_ind, st);
+    const int blk_all = 512;  // energies of one boundary-only launch (64 lanes x 8)
+    int cur = 0;
+    qc::SweepBufs b;
+    b.dslot = g->dslot;
+    b.aslot = g->aslot;
+    b.gbuf = nullptr;
+    b.ebuf = nullptr;
+    for (int it = 0; it < bc_iters; ++it) {
+      for (int e0 = 0; e0 < n_e; e0 += blk_all) {
+        const int ne = std::min(blk_all, n_e - e0);
+        qc::SweepArgs a = sweep_args(g, ne, n_e, e0, deps, nullptr);
+        a.bc_valid = it > 0;
+        b.bc_g_prev = bcl[cur][0];
+        b.bc_gt_prev = bcl[cur][1];
+        b.bc_g_next = bcl[1 - cur][0];
+        b.bc_gt_next = bcl[1 - cur][1];
+        launch_sweep_timed(g, 2, a, b, st);
+      }
+      cur = 1 - cur;
+    }
+    // output pass in energy blocks bounded by ~8 GiB of node buffers
+    const double per_e = static_cast<double>(g->nslot) * 3.0 * rb;
+    int blk = 64;
+    while (blk > 1 && blk * per_e > 8.0 * (1 << 30)) blk >>= 1;
+    blk = std::min(blk, n_e);
+    lg = dalloc(2 * rb * g->nslot * blk);
+    le = dalloc(rb * g->nslot * blk);
+    qc::launch_fill(ldos_out, static_cast<int64_t>(n_e) * g->ncell, 0.0, st);
+    for (int e0 = 0; e0 < n_e; e0 += blk) {
+      const int ne = std::min(blk, n_e - e0);
+      qc::SweepArgs a = sweep_args(g, ne, n_e, e0, deps, nullptr);
+      a.bc_valid = bc_iters > 0;
+      b.bc_g_prev = bcl[cur][0];
+      b.bc_gt_prev = bcl[cur][1];
+      b.bc_g_next = nullptr;
+      b.bc_gt_next = nullptr;
+      b.gbuf = lg;
+      b.ebuf = le;
+      launch_sweep_timed(g, 1, a, b, st);
+      qc::LdosBackArgs la;
+      la.ncg = g->ncg;
+      la.ncell = g->ncell;
+      la.n_theta = g->n_theta;
+      la.n_e = ne;
+      la.e_off = e0;
+      la.grain_cells = g->grain_cells;
+      la.rb_idx = g->rb_idx;
+      la.rb_w = g->rb_w;
+      la.wk = g->wk;
+      la.out = ldos_out;
+      if (g->precision == QC_MIXED)
+        qc::launch_ldos_back<float>(la, le, st);
+      else
+        qc::launch_ldos_back<double>(la, le, st);
+      hcheck(hipGetLastError(), "ldos launch");
+    }
+    hcheck(hipStreamSynchronize(st), "sync");
+    return QC_OK;
+  });
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      if (bcl[a][b]) (void)hipFree(bcl[a][b]);
+  if (deps) (void)hipFree(deps);
+  if (lg) (void)hipFree(lg);
+  if (le) (void)hipFree(le);
+  return rs;
+}
+
+qc_status qc_get_state(const qc_grain* g, void* state, size_t* bytes, void* stream) {
+  if (!g || !bytes) return fail(QC_ERR_INVALID, "NULL argument");
+  const size_t half = 2 * g->real_bytes() * g->nseg * g->n_poles;
+  if (!state) {
+    *bytes = 2 * half;
+    return QC_OK;
+  }
+  if (*bytes < 2 * half) return fail(QC_ERR_INVALID, "state buffer too small");
+  if (!g->bc_valid) return fail(QC_ERR_INVALID, "no boundary values yet (run a sweep first)");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    hcheck(hipMemcpyAsync(state, g->bc[g->bc_cur][0], half, hipMemcpyDeviceToDevice, S(stream)), "copy");
+    hcheck(hipMemcpyAsync(static_cast<char*>(state) + half, g->bc[g->bc_cur][1], half, hipMemcpyDeviceToDevice,
+                          S(stream)),
+           "copy");
+    *bytes = 2 * half;
+    return QC_OK;
+  });
+}
+
+qc_status qc_set_state(qc_grain* g, const void* state, size_t bytes, void* stream) {
+  if (!g || !state) return fail(QC_ERR_INVALID, "NULL argument");
+  const size_t half = 2 * g->real_bytes() * g->nseg * g->n_poles;
+  if (bytes != 2 * half) return fail(QC_ERR_INVALID, "state size does not match this grain");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    hcheck(hipMemcpyAsync(g->bc[g->bc_cur][0], state, half, hipMemcpyDeviceToDevice, S(stream)), "copy");
+    hcheck(hipMemcpyAsync(g->bc[g->bc_cur][1], static_cast<const char*>(state) + half, half, hipMemcpyDeviceToDevice,
+                          S(stream)),
+           "copy");
+    g->bc_valid = 1;
+    return QC_OK;
+  });
+}
+
+qc_status qc_profile_enable(qc_grain* g, int enable) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  g->prof = enable != 0;
+  return QC_OK;
+}
+
+qc_status qc_profile_read(qc_grain* g, double* sweep_ms, int64_t* sweep_launches) {
+  if (!g || !sweep_ms || !sweep_launches) return fail(QC_ERR_INVALID, "NULL argument");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    double tot = 0.0;
+    for (auto& e : g->ev) {
+      hcheck(hipEventSynchronize(e.second), "event sync");
+      float ms = 0.f;
+      hcheck(hipEventElapsedTime(&ms, e.first, e.second), "event time");
+      tot += ms;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    *sweep_ms = tot;
+    *sweep_launches = static_cast<int64_t>(g->ev.size());
+    g->ev.clear();
+    return QC_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,556 @@
+// Host-side trajectory tables (Sec. III.A of arXiv:2205.15000); see plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <stdexcept>
+#include <utility>
+
+namespace qc {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool inside(const Shape& sh, double x, double y) {
+  if (sh.kind == 0) {
+    const double dx = x - sh.cx, dy = y - sh.cy;
+    return dx * dx + dy * dy <= sh.r * sh.r;
+  }
+  const size_t n = sh.vx.size();
+  for (size_t m = 0; m < n; ++m) {
+    const double ax = sh.vx[m], ay = sh.vy[m];
+    const double bx = sh.vx[(m + 1) % n], by = sh.vy[(m + 1) % n];
+    const double cr = (bx - ax) * (y - ay) - (by - ay) * (x - ax);
+    if (!(cr >= 0.0)) return false;
+  }
+  return true;
+}
+
+// The grain as the ordered fold of its components (App. B).
+bool in_grain(const std::vector<Shape>& shapes, double x, double y) {
+  bool d = false;
+  for (const Shape& sh : shapes) {
+    const bool in = inside(sh, x, y);
+    d = sh.add ? (d || in) : (d && !in);
+  }
+  return d;
+}
+
+struct Hit {
+  double s;
+  double tangent;
+};
+
+// Intersections of the line B + s e with every component boundary.
+std::vector<Hit> boundary_hits(const std::vector<Shape>& shapes, double bx, double by,
+                               double ex, double ey) {
+  std::vector<Hit> hits;
+  for (const Shape& sh : shapes) {
+    if (sh.kind == 0) {
+      const double dx = bx - sh.cx, dy = by - sh.cy;
+      const double bq = dx * ex + dy * ey;
+      const double cq = dx * dx + dy * dy - sh.r * sh.r;
+      const double disc = bq * bq - cq;
+      if (disc > 0.0) {
+        const double rt = std::sqrt(disc);
+        const double ss[2] = {-bq - rt, -bq + rt};
+        for (double s : ss) {
+          const double px = bx + s * ex, py = by + s * ey;
+          hits.push_back({s, std::atan2(py - sh.cy, px - sh.cx) + 0.5 * kPi});
+        }
+      }
+    } else {
+      const size_t n = sh.vx.size();
+      for (size_t m = 0; m < n; ++m) {
+        const double ax = sh.vx[m], ay = sh.vy[m];
+        const double dx = sh.vx[(m + 1) % n] - ax, dy = sh.vy[(m + 1) % n] - ay;
+        const double den = ex * dy - ey * dx;
+        if (den == 0.0) continue;
+        const double wx = ax - bx, wy = ay - by;
+        const double s = (wx * dy - wy * dx) / den;
+        const double tt = (wx * ey - wy * ex) / den;
+        if (tt >= 0.0 && tt <= 1.0) hits.push_back({s, std::atan2(dy, dx)});
+      }
+    }
+  }
+  std::stable_sort(hits.begin(), hits.end(), [](const Hit& a, const Hit& b) { return a.s < b.s; });
+  return hits;
+}
+
+struct Seg {
+  double s0, s1, t0, t1;
+};
+
+// Maximal D-intervals of a line: the sorted hits cut it into pieces, a piece
+// belongs to D when its midpoint does, adjacent D-pieces merge; pieces
+// shorter than 1e-9 h are skipped.
+std::vector<Seg> line_segments(const std::vector<Shape>& shapes, double bx, double by,
+                               double ex, double ey, double h) {
+  const std::vector<Hit> hits = boundary_hits(shapes, bx, by, ex, ey);
+  std::vector<Seg> out;
+  const double tol = 1e-9 * h;
+  bool open = false;
+  Hit start{0, 0}, end{0, 0};
+  for (size_t a = 0; a + 1 < hits.size(); ++a) {
+    const Hit& ha = hits[a];
+    const Hit& hb = hits[a + 1];
+    if (hb.s - ha.s <= tol) continue;
+    const double sm = 0.5 * (ha.s + hb.s);
+    const bool in = in_grain(shapes, bx + sm * ex, by + sm * ey);
+    if (in) {
+      if (!open) {
+        start = ha;
+        open = true;
+      }
+      end = hb;
+    } else if (open) {
+      out.push_back({start.s, end.s, start.tangent, end.tangent});
+      open = false;
+    }
+  }
+  if (open) out.push_back({start.s, end.s, start.tangent, end.tangent});
+  return out;
+}
+
+void external_A(const Plan& p, double x, double y, double& ax, double& ay) {
+  const double dx = x - p.cx, dy = y - p.cy;
+  ax = 0.0;
+  ay = 0.0;
+  if (p.flux == 0.0) return;
+  if (p.gauge == 0) {  // symmetric
+    const double b = kPi * p.flux / p.area;
+    ax = -0.5 * b * dy;
+    ay = 0.5 * b * dx;
+  } else if (p.gauge == 1) {  // landau
+    const double b = kPi * p.flux / p.area;
+    ax = -b * dy;
+    ay = 0.0;
+  } else {  // solenoid
+    const double r2 = dx * dx + dy * dy;
+    if (r2 > 0.0) {
+      ax = -0.5 * p.flux * dy / r2;
+      ay = 0.5 * p.flux * dx / r2;
+    }
+  }
+}
+
+}  // namespace
+
+std::vector<double> fs_weights(int n) {
+  std::vector<double> pat;
+  if (n % 4 == 0)
+    pat = {14.0, 32.0, 12.0, 32.0};
+  else if (n % 3 == 0)
+    pat = {2.0, 3.0, 3.0};
+  else if (n % 2 == 0)
+    pat = {2.0, 4.0};
+  else
+    pat = {1.0};
+  std::vector<double> w(n);
+  double tot = 0.0;
+  for (int k = 0; k < n; ++k) {
+    w[k] = pat[k % pat.size()];
+    tot += w[k];
+  }
+  for (double& v : w) v /= tot;
+  return w;
+}
+
+void ozaki_table(int n_poles, std::vector<double>& z, std::vector<double>& r) {
+  // Continued-fraction matrix of the Fermi function: zero diagonal,
+  // off-diagonal b_m = 1/(2 sqrt((2m-1)(2m+1))).  Its positive eigenvalues
+  // lam_p give the poles z_p = 1/lam_p and, with the first component v0 of
+  // the normalised eigenvector, the residues R_p = v0^2/(4 lam_p^2).
+  // Cyclic Jacobi rotations on the dense symmetric matrix; only row 0 of
+  // the eigenvector matrix is needed and tracked.
+  const int n = 2 * n_poles;
+  std::vector<double> a(static_cast<size_t>(n) * n, 0.0);
+  for (int m = 1; m < n; ++m) {
+    const double b = 1.0 / (2.0 * std::sqrt((2.0 * m - 1.0) * (2.0 * m + 1.0)));
+    a[(m - 1) * n + m] = b;
+    a[m * n + m - 1] = b;
+  }
+  std::vector<double> v0(n, 0.0);
+  v0[0] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += a[p * n + q] * a[p * n + q];
+    if (off < 1e-60) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        const double app = a[p * n + p], aqq = a[q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(tt * tt + 1.0);
+        const double s = tt * c;
+        // A <- J^T A J with J the rotation in the (p, q) plane
+        for (int k = 0; k < n; ++k) {
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - s * akq;
+          a[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - s * aqk;
+          a[q * n + k] = s * apk + c * aqk;
+        }
+        const double vp = v0[p], vq = v0[q];
+        v0[p] = c * vp - s * vq;
+        v0[q] = s * vp + c * vq;
+      }
+    }
+  }
+  std::vector<std::pair<double, double>> ev;  // (lambda, v0)
+  for (int k = 0; k < n; ++k)
+    if (a[k * n + k] > 0.0) ev.push_back({a[k * n + k], v0[k]});
+  std::sort(ev.begin(), ev.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  z.resize(ev.size());
+  r.resize(ev.size());
+  for (size_t k = 0; k < ev.size(); ++k) {
+    const double lam = ev[k].first;
+    z[k] = 1.0 / lam;
+    r[k] = ev[k].second * ev[k].second / (4.0 * lam * lam);
+  }
+}
+
+int64_t Plan::steps_per_sweep() const {
+  int64_t s = 0;
+  for (int64_t k = 0; k < nseg; ++k) s += seg_n[k] + 1;
+  return 2 * static_cast<int64_t>(n_poles) * s;
+}
+
+void build_plan(Plan& p) {
+  if (p.nx < 2 || p.ny < 2) throw std::runtime_error("grid must be at least 2x2");
+  if (!(p.h > 0.0) || !std::isfinite(p.h)) throw std::runtime_error("h must be > 0");
+  if (p.n_theta < 1) throw std::runtime_error("n_theta must be >= 1");
+  if (p.n_poles < 1) throw std::runtime_error("n_poles must be >= 1");
+  if (!(p.t > 0.0)) throw std::runtime_error("t must be > 0");
+  if (p.ncomp < 1) throw std::runtime_error("ncomp must be >= 1");
+  if (p.shapes.empty()) throw std::runtime_error("no geometry component");
+
+  p.cx = p.x0 + 0.5 * p.nx * p.h;
+  p.cy = p.y0 + 0.5 * p.ny * p.h;
+  const int nx = p.nx, ny = p.ny;
+  const double h = p.h;
+
+  // ---- mask
+  p.mask.assign(static_cast<size_t>(nx) * ny, 0);
+  p.grain_cells.clear();
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double x = p.x0 + (i + 0.5) * h, y = p.y0 + (j + 0.5) * h;
+      if (in_grain(p.shapes, x, y)) {
+        p.mask[static_cast<size_t>(j) * nx + i] = 1;
+        p.grain_cells.push_back(j * nx + i);
+      }
+    }
+  if (p.grain_cells.empty()) throw std::runtime_error("the grain covers no cell centre");
+  p.area = h * h * static_cast<double>(p.grain_cells.size());
+
+  // ---- lattice, angles, tables
+  p.M = static_cast<int>(std::ceil(std::sqrt(static_cast<double>(nx) * nx + static_cast<double>(ny) * ny) + 3.0));
+  if ((p.M - nx) % 2 != 0) p.M += 1;
+  const int M = p.M;
+  p.half = 0.5 * (M - 1);
+  const double half = p.half;
+  p.phi.resize(p.n_theta);
+  p.cosk.resize(p.n_theta);
+  p.sink.resize(p.n_theta);
+  for (int k = 0; k < p.n_theta; ++k) {
+    p.phi[k] = 2.0 * kPi * k / p.n_theta;
+    p.cosk[k] = std::cos(p.phi[k]);
+    p.sink[k] = std::sin(p.phi[k]);
+  }
+  p.wk = fs_weights(p.n_theta);
+  ozaki_table(p.n_poles, p.zp, p.rp);
+
+  // ---- segments
+  p.seg_angle.clear(); p.seg_line.clear(); p.seg_jfirst.clear(); p.seg_n.clear();
+  p.seg_smin.clear(); p.seg_smax.clear(); p.seg_tmin.clear(); p.seg_tmax.clear();
+  p.angle_seg0.assign(p.n_theta + 1, 0);
+  p.line_seg0.assign(static_cast<size_t>(p.n_theta) * (M + 1), 0);
+  for (int k = 0; k < p.n_theta; ++k) {
+    p.angle_seg0[k] = static_cast<int64_t>(p.seg_angle.size());
+    const double epx = p.cosk[k], epy = p.sink[k];
+    const double eqx = p.sink[k], eqy = -p.cosk[k];
+    for (int i = 0; i < M; ++i) {
+      p.line_seg0[static_cast<size_t>(k) * (M + 1) + i] = static_cast<int64_t>(p.seg_angle.size());
+      const double u = (i - half) * h;
+      const double bx = p.cx + u * eqx, by = p.cy + u * eqy;
+      for (const Seg& sg : line_segments(p.shapes, bx, by, epx, epy, h)) {
+        const int jf = static_cast<int>(std::floor(sg.s0 / h + half)) + 1;
+        const int jl = static_cast<int>(std::ceil(sg.s1 / h + half)) - 1;
+        p.seg_angle.push_back(k);
+        p.seg_line.push_back(i);
+        p.seg_jfirst.push_back(jf);
+        p.seg_n.push_back(std::max(0, jl - jf + 1));
+        p.seg_smin.push_back(sg.s0);
+        p.seg_smax.push_back(sg.s1);
+        p.seg_tmin.push_back(sg.t0);
+        p.seg_tmax.push_back(sg.t1);
+      }
+    }
+    p.line_seg0[static_cast<size_t>(k) * (M + 1) + M] = static_cast<int64_t>(p.seg_angle.size());
+  }
+  p.angle_seg0[p.n_theta] = static_cast<int64_t>(p.seg_angle.size());
+  p.nseg = static_cast<int64_t>(p.seg_angle.size());
+  if (p.nseg == 0) throw std::runtime_error("no trajectory crosses the grain");
+  if (p.nseg > std::numeric_limits<int32_t>::max() / 2) throw std::runtime_error("too many segments");
+
+  // ---- value slots
+  p.seg_slot0.resize(p.nseg);
+  p.seg_hfirst.resize(p.nseg);
+  p.seg_hlast.resize(p.nseg);
+  int64_t ns = 0, nn = 0;
+  for (int64_t g = 0; g < p.nseg; ++g) {
+    p.seg_slot0[g] = ns;
+    ns += std::max(p.seg_n[g], 1);
+    nn += p.seg_n[g];
+  }
+  if (ns > std::numeric_limits<int32_t>::max()) throw std::runtime_error("too many lattice nodes");
+  p.nslot = ns;
+  p.nnode = nn;
+  p.slot_angle.resize(ns);
+  p.slot_seg.resize(ns);
+  p.dst_idx.assign(static_cast<size_t>(ns) * 4, 0);
+  p.dst_w.assign(static_cast<size_t>(ns) * 4, 0.0);
+  p.ast_idx.assign(static_cast<size_t>(ns) * 4, 0);
+  p.ast_w.assign(static_cast<size_t>(ns) * 4, 0.0);
+  p.slot_aext.assign(ns, 0.0);
+  std::vector<double> gx, gy;  // grain cell centres, for the nearest-cell fallback
+  for (int32_t c : p.grain_cells) {
+    gx.push_back(p.x0 + (c % nx + 0.5) * h);
+    gy.push_back(p.y0 + (c / nx + 0.5) * h);
+  }
+  for (int64_t g = 0; g < p.nseg; ++g) {
+    const int k = p.seg_angle[g];
+    const double epx = p.cosk[k], epy = p.sink[k];
+    const double eqx = p.sink[k], eqy = -p.cosk[k];
+    const int n = p.seg_n[g], jf = p.seg_jfirst[g];
+    const double u = (p.seg_line[g] - half) * h;
+    if (n > 0) {
+      p.seg_hfirst[g] = (jf - half) * h - p.seg_smin[g];
+      p.seg_hlast[g] = p.seg_smax[g] - (jf + n - 1 - half) * h;
+    } else {
+      p.seg_hfirst[g] = p.seg_smax[g] - p.seg_smin[g];
+      p.seg_hlast[g] = 0.0;
+    }
+    const int nsl = std::max(n, 1);
+    for (int t = 0; t < nsl; ++t) {
+      const int64_t sl = p.seg_slot0[g] + t;
+      p.slot_angle[sl] = k;
+      p.slot_seg[sl] = static_cast<int32_t>(g);
+      const double s = n > 0 ? (jf + t - half) * h : 0.5 * (p.seg_smin[g] + p.seg_smax[g]);
+      const double px = p.cx + u * eqx + s * epx;
+      const double py = p.cy + u * eqy + s * epy;
+      // Delta: masked bilinear over the four surrounding cell centres
+      {
+        const double fx = (px - p.x0) / h - 0.5, fy = (py - p.y0) / h - 0.5;
+        const int i0 = static_cast<int>(std::floor(fx)), j0 = static_cast<int>(std::floor(fy));
+        const double wx = fx - i0, wy = fy - j0;
+        const int ci[4] = {i0, i0 + 1, i0, i0 + 1};
+        const int cj[4] = {j0, j0, j0 + 1, j0 + 1};
+        double w[4] = {(1 - wx) * (1 - wy), wx * (1 - wy), (1 - wx) * wy, wx * wy};
+        int idx[4];
+        double tot = 0.0;
+        for (int c = 0; c < 4; ++c) {
+          const bool ok = ci[c] >= 0 && ci[c] < nx && cj[c] >= 0 && cj[c] < ny &&
+                          p.mask[static_cast<size_t>(cj[c]) * nx + ci[c]];
+          idx[c] = ok ? cj[c] * nx + ci[c] : 0;
+          if (!ok) w[c] = 0.0;
+          tot += w[c];
+        }
+        if (tot > 0.0) {
+          for (int c = 0; c < 4; ++c) w[c] /= tot;
+        } else {
+          size_t best = 0;
+          double bd = std::numeric_limits<double>::infinity();
+          for (size_t a = 0; a < gx.size(); ++a) {
+            const double d2 = (gx[a] - px) * (gx[a] - px) + (gy[a] - py) * (gy[a] - py);
+            if (d2 < bd) {
+              bd = d2;
+              best = a;
+            }
+          }
+          idx[0] = p.grain_cells[best];
+          idx[1] = idx[2] = idx[3] = 0;
+          w[0] = 1.0;
+          w[1] = w[2] = w[3] = 0.0;
+        }
+        for (int c = 0; c < 4; ++c) {
+          p.dst_idx[sl * 4 + c] = idx[c];
+          p.dst_w[sl * 4 + c] = w[c];
+        }
+      }
+      // A_ind: plain bilinear, clamped onto the outermost cell centres
+      {
+        const double fx = std::min(std::max((px - p.x0) / h - 0.5, 0.0), nx - 1.0);
+        const double fy = std::min(std::max((py - p.y0) / h - 0.5, 0.0), ny - 1.0);
+        const int i0 = std::min(static_cast<int>(std::floor(fx)), nx - 2);
+        const int j0 = std::min(static_cast<int>(std::floor(fy)), ny - 2);
+        const double wx = fx - i0, wy = fy - j0;
+        const int idx[4] = {j0 * nx + i0, j0 * nx + i0 + 1, (j0 + 1) * nx + i0, (j0 + 1) * nx + i0 + 1};
+        const double w[4] = {(1 - wx) * (1 - wy), wx * (1 - wy), (1 - wx) * wy, wx * wy};
+        for (int c = 0; c < 4; ++c) {
+          p.ast_idx[sl * 4 + c] = idx[c];
+          p.ast_w[sl * 4 + c] = w[c];
+        }
+      }
+      double ax, ay;
+      external_A(p, px, py, ax, ay);
+      p.slot_aext[sl] = epx * ax + epy * ay;
+    }
+  }
+
+  // ---- rotate-back stencils of the grain cells
+  const int64_t nc = static_cast<int64_t>(p.grain_cells.size());
+  p.rb_idx.assign(static_cast<size_t>(p.n_theta) * 4 * nc, 0);
+  p.rb_w.assign(static_cast<size_t>(p.n_theta) * 4 * nc, 0.0);
+  std::vector<int32_t> node(static_cast<size_t>(M) * M);
+  for (int k = 0; k < p.n_theta; ++k) {
+    std::fill(node.begin(), node.end(), -1);
+    for (int64_t g = p.angle_seg0[k]; g < p.angle_seg0[k + 1]; ++g)
+      for (int t = 0; t < p.seg_n[g]; ++t)
+        node[static_cast<size_t>(p.seg_line[g]) * M + p.seg_jfirst[g] + t] =
+            static_cast<int32_t>(p.seg_slot0[g] + t);
+    const double epx = p.cosk[k], epy = p.sink[k];
+    const double eqx = p.sink[k], eqy = -p.cosk[k];
+    for (int64_t a = 0; a < nc; ++a) {
+      const int32_t c = p.grain_cells[a];
+      const double x = p.x0 + (c % nx + 0.5) * h, y = p.y0 + (c / nx + 0.5) * h;
+      const double dx = x - p.cx, dy = y - p.cy;
+      const double u = (dx * eqx + dy * eqy) / h + half;
+      const double v = (dx * epx + dy * epy) / h + half;
+      const int i0 = static_cast<int>(std::floor(u)), j0 = static_cast<int>(std::floor(v));
+      const double wu = u - i0, wv = v - j0;
+      const int li[4] = {i0, i0 + 1, i0, i0 + 1};
+      const int lj[4] = {j0, j0, j0 + 1, j0 + 1};
+      double w[4] = {(1 - wu) * (1 - wv), wu * (1 - wv), (1 - wu) * wv, wu * wv};
+      int32_t idx[4];
+      double tot = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        int32_t s = -1;
+        if (li[q] >= 0 && li[q] < M && lj[q] >= 0 && lj[q] < M) s = node[static_cast<size_t>(li[q]) * M + lj[q]];
+        idx[q] = s >= 0 ? s : 0;
+        if (s < 0) w[q] = 0.0;
+        tot += w[q];
+      }
+      if (tot > 0.0) {
+        for (int q = 0; q < 4; ++q) w[q] /= tot;
+      } else {
+        // nearest interior node (ties -> smallest (line, node)): grow a box
+        // around (u, v) until the best distance is inside the searched box
+        int32_t best = -1;
+        double bd = std::numeric_limits<double>::infinity();
+        for (int R = 1; R <= M; ++R) {
+          best = -1;
+          bd = std::numeric_limits<double>::infinity();
+          for (int i = std::max(0, i0 - R); i <= std::min(M - 1, i0 + 1 + R); ++i)
+            for (int j = std::max(0, j0 - R); j <= std::min(M - 1, j0 + 1 + R); ++j) {
+              const int32_t s = node[static_cast<size_t>(i) * M + j];
+              if (s < 0) continue;
+              const double d2 = (i - u) * (i - u) + (j - v) * (j - v);
+              if (d2 < bd) {
+                bd = d2;
+                best = s;
+              }
+            }
+          if (best >= 0 && bd <= static_cast<double>(R) * R) break;
+        }
+        if (best < 0) throw std::runtime_error("rotate-back: angle without interior node");
+        idx[0] = best;
+        idx[1] = idx[2] = idx[3] = 0;
+        w[0] = 1.0;
+        w[1] = w[2] = w[3] = 0.0;
+      }
+      for (int q = 0; q < 4; ++q) {
+        p.rb_idx[(static_cast<size_t>(k) * 4 + q) * nc + a] = idx[q];
+        p.rb_w[(static_cast<size_t>(k) * 4 + q) * nc + a] = w[q];
+      }
+    }
+  }
+
+  // ---- specular boundary taps
+  p.tap_start_seg.assign(static_cast<size_t>(p.nseg) * 4, 0);
+  p.tap_end_seg.assign(static_cast<size_t>(p.nseg) * 4, 0);
+  p.tap_start_w.assign(static_cast<size_t>(p.nseg) * 4, 0.0);
+  p.tap_end_w.assign(static_cast<size_t>(p.nseg) * 4, 0.0);
+  const double dphi = 2.0 * kPi / p.n_theta;
+  for (int64_t g = 0; g < p.nseg; ++g) {
+    for (int at_start = 1; at_start >= 0; --at_start) {
+      const int k = p.seg_angle[g];
+      const double u = (p.seg_line[g] - half) * h;
+      const double s = at_start ? p.seg_smin[g] : p.seg_smax[g];
+      const double px = p.cx + u * p.sink[k] + s * p.cosk[k];
+      const double py = p.cy + u * (-p.cosk[k]) + s * p.sink[k];
+      const double th = at_start ? p.seg_tmin[g] : p.seg_tmax[g];
+      // reflected direction: mirror of phi_k about the wall tangent
+      double phr = std::fmod(2.0 * th - p.phi[k], 2.0 * kPi);
+      if (phr < 0.0) phr += 2.0 * kPi;
+      const double x = phr / dphi;
+      const int k0 = static_cast<int>(std::floor(x));
+      const double wphi = x - k0;
+      int32_t tseg[4];
+      double tw[4];
+      int nt = 0;
+      const int kks[2] = {((k0 % p.n_theta) + p.n_theta) % p.n_theta, (((k0 + 1) % p.n_theta) + p.n_theta) % p.n_theta};
+      const double wks[2] = {1.0 - wphi, wphi};
+      for (int a = 0; a < 2; ++a) {
+        const int kk = kks[a];
+        const double eqx = p.sink[kk], eqy = -p.cosk[kk];
+        const double uu = ((px - p.cx) * eqx + (py - p.cy) * eqy) / h + half;
+        const int i0 = static_cast<int>(std::floor(uu));
+        const double wu = uu - i0;
+        const double sn = std::fabs(std::sin(p.phi[kk] - th));
+        const double dacc = 2.0 * h / std::max(sn, 0.125);
+        const int iis[2] = {i0, i0 + 1};
+        const double wis[2] = {1.0 - wu, wu};
+        for (int b = 0; b < 2; ++b) {
+          const int ii = iis[b];
+          if (ii < 0 || ii >= M) continue;
+          const int64_t g0 = p.line_seg0[static_cast<size_t>(kk) * (M + 1) + ii];
+          const int64_t g1 = p.line_seg0[static_cast<size_t>(kk) * (M + 1) + ii + 1];
+          if (g1 == g0) continue;
+          int64_t bestg = -1;
+          double bd = std::numeric_limits<double>::infinity();
+          const double uk = (ii - half) * h;
+          for (int64_t gg = g0; gg < g1; ++gg) {
+            const double se = at_start ? p.seg_smax[gg] : p.seg_smin[gg];
+            const double ex = p.cx + uk * p.sink[kk] + se * p.cosk[kk];
+            const double ey = p.cy + uk * (-p.cosk[kk]) + se * p.sink[kk];
+            const double d = std::hypot(ex - px, ey - py);
+            if (d < bd) {
+              bd = d;
+              bestg = gg;
+            }
+          }
+          if (bd <= dacc) {
+            tseg[nt] = static_cast<int32_t>(bestg);
+            tw[nt] = wks[a] * wis[b];
+            ++nt;
+          }
+        }
+      }
+      double tot = 0.0;
+      for (int a = 0; a < nt; ++a) tot += tw[a];
+      int32_t* os = at_start ? &p.tap_start_seg[g * 4] : &p.tap_end_seg[g * 4];
+      double* ow = at_start ? &p.tap_start_w[g * 4] : &p.tap_end_w[g * 4];
+      for (int a = 0; a < 4; ++a) {
+        os[a] = static_cast<int32_t>(g);
+        ow[a] = 0.0;
+      }
+      if (tot > 0.0)
+        for (int a = 0; a < nt; ++a) {
+          os[a] = tseg[a];
+          ow[a] = tw[a] / tot;
+        }
+    }
+  }
+}
+
+}  // namespace qc

@@ -1,0 +1,89 @@
+// Host-side trajectory tables of one grain (Sec. III.A of arXiv:2205.15000).
+//
+// The reference grid carries Delta_G and A_ind at cell centres.  For every
+// Fermi-surface angle phi_k a square lattice of the same spacing h, rotated so
+// that its "node" axis is parallel to v_F(phi_k) and centred on the grid
+// centre, supplies the trajectories: each lattice line is cut by the exact
+// grain boundary into segments [s_min, s_max]; the lattice nodes strictly
+// inside a segment are where gamma, gamma~ and the Green's functions live.
+// A segment without an interior node gets one value slot at its midpoint.
+//
+// Everything here is built once per grain on the host and uploaded.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qc {
+
+struct Shape {
+  int kind = 0;  // 0 disc, 1 convex polygon (regular polygons are converted)
+  bool add = true;
+  double cx = 0, cy = 0, r = 0;
+  std::vector<double> vx, vy;  // counter-clockwise
+};
+
+struct Plan {
+  // ---- inputs
+  int nx = 0, ny = 0;
+  double h = 0, x0 = 0, y0 = 0, cx = 0, cy = 0;
+  int n_theta = 0, n_poles = 0, ncomp = 0;
+  double t = 0;
+  std::vector<double> tc_rel;
+  std::vector<std::complex<double>> eta;  // [ncomp][n_theta]
+  double kappa = 0, flux = 0;
+  int gauge = 0, q = -1, precision = 0;
+  std::vector<Shape> shapes;
+
+  // ---- grid and tables
+  std::vector<uint8_t> mask;           // [ny][nx]
+  std::vector<int32_t> grain_cells;    // flat indices of grain cells, ascending
+  double area = 0;
+  int M = 0;                           // lattice side
+  double half = 0;                     // (M-1)/2
+  std::vector<double> phi, cosk, sink, wk;  // per angle
+  std::vector<double> zp, rp;          // Ozaki poles and residues (ascending z)
+
+  // ---- segments, ordered by (angle, line, s)
+  int64_t nseg = 0;
+  std::vector<int32_t> seg_angle, seg_line, seg_jfirst, seg_n;
+  std::vector<int64_t> seg_slot0;      // first value slot
+  std::vector<double> seg_smin, seg_smax, seg_tmin, seg_tmax;
+  std::vector<double> seg_hfirst, seg_hlast;  // partial end steps (n>0); hfirst = length if n==0
+  std::vector<int64_t> angle_seg0;     // [n_theta+1]
+  std::vector<int64_t> line_seg0;      // [n_theta][M+1]
+
+  // ---- value slots, ordered by segment
+  int64_t nslot = 0, nnode = 0;
+  std::vector<int32_t> slot_angle;
+  std::vector<int32_t> slot_seg;
+  std::vector<int32_t> dst_idx;        // [nslot][4] masked bilinear of Delta
+  std::vector<double> dst_w;
+  std::vector<int32_t> ast_idx;        // [nslot][4] clamped bilinear of A_ind
+  std::vector<double> ast_w;
+  std::vector<double> slot_aext;       // v_k . A_ext(slot)
+
+  // ---- rotate-back stencils of grain cells: [angle][corner][cell]
+  std::vector<int32_t> rb_idx;         // global slot index
+  std::vector<double> rb_w;
+
+  // ---- specular boundary taps: [seg][4]
+  std::vector<int32_t> tap_start_seg, tap_end_seg;
+  std::vector<double> tap_start_w, tap_end_w;
+
+  int64_t steps_per_sweep() const;
+};
+
+// Builds every table; throws std::runtime_error with a message on bad input.
+void build_plan(Plan& p);
+
+// Ozaki poles z_p > 0 and residues R_p (ascending z): eigen-decomposition of
+// the 2N x 2N tridiagonal continued-fraction matrix, Jacobi rotations.
+void ozaki_table(int n_poles, std::vector<double>& z, std::vector<double>& r);
+
+// Normalised periodic Fermi-surface quadrature weights (Sec. III.A).
+std::vector<double> fs_weights(int n_theta);
+
+}  // namespace qc

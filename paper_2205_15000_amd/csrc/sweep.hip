@@ -1,0 +1,598 @@
+// HIP kernels of the Riccati-sweep iteration for gfx950 (arXiv:2205.15000).
+//
+//   interp_kernel       Delta(p_k, slot), a(slot) = v_k.A(slot) on the rotated
+//                       lattices (Sec. III.A bilinear interpolation)
+//   sweep_kernel        gamma forward / gamma~ backward along every segment
+//                       (App. C), Green's functions (Sec. II.A) and per-node
+//                       pole sums; one group of G lanes per segment, EPL
+//                       energies per lane, all angles in one launch
+//   rotate_back_kernel  rotated lattice -> reference cells, angle sums,
+//                       gap update (Eq. gapeq_fixpoint), current
+//                       (Eq. current_density), free-energy density
+//   ldos_back_kernel    rotate-back of the per-energy LDOS values
+//   fft / A-solve / curl / reductions / Picard helpers (App. D, App. E)
+#include "kernels.hpp"
+#include "sweep.hpp"
+
+namespace qc {
+
+// --------------------------------------------------------------------------
+// interpolation pre-pass
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, cpx<T>* __restrict__ dslot,
+                                                     T* __restrict__ aslot) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= a.nslot) return;
+  const int k = a.slot_angle[s];
+  double dx = 0.0, dy = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int idx = a.dst_idx[s * 4 + c];
+    const double w = a.dst_w[s * 4 + c];
+    double vx = 0.0, vy = 0.0;
+    for (int g = 0; g < a.ncomp; ++g) {
+      const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
+      const double fx = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + idx)];
+      const double fy = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + idx) + 1];
+      vx += ex * fx - ey * fy;
+      vy += ex * fy + ey * fx;
+    }
+    dx += vx * w;
+    dy += vy * w;
+  }
+  double ax = 0.0, ay = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int idx = a.ast_idx[s * 4 + c];
+    const double w = a.ast_w[s * 4 + c];
+    ax += a.A[idx] * w;
+    ay += a.A[a.ncell + idx] * w;
+  }
+  dslot[s] = mk(static_cast<T>(dx), static_cast<T>(dy));
+  aslot[s] = static_cast<T>(a.cosk[k] * ax + a.sink[k] * ay + a.aext[s]);
+}
+
+// --------------------------------------------------------------------------
+// Riccati sweep
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void step_values(const cpx<T>* __restrict__ dslot, const T* __restrict__ aslot,
+                                            int64_t slot0, int n, int t, double hfirst, double hlast,
+                                            double hfull, cpx<T>& dm, T& am, T& hs) {
+  // half-step values (App. C): mean of the two end values, a boundary point
+  // taking the value of the nearest slot
+  if (t == 0) {
+    dm = dslot[slot0];
+    am = aslot[slot0];
+    hs = static_cast<T>(hfirst);
+  } else if (t == n) {
+    dm = dslot[slot0 + n - 1];
+    am = aslot[slot0 + n - 1];
+    hs = static_cast<T>(hlast);
+  } else {
+    const cpx<T> d0 = dslot[slot0 + t - 1], d1 = dslot[slot0 + t];
+    dm = mk(T(0.5) * (d0.x + d1.x), T(0.5) * (d0.y + d1.y));
+    am = T(0.5) * (aslot[slot0 + t - 1] + aslot[slot0 + t]);
+    hs = static_cast<T>(hfull);
+  }
+}
+
+template <typename T, int EPL, int MODE>
+__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const cpx<T>* __restrict__ dslot,
+                                                    const T* __restrict__ aslot,
+                                                    const cpx<T>* __restrict__ bc_g_prev,
+                                                    const cpx<T>* __restrict__ bc_gt_prev,
+                                                    cpx<T>* __restrict__ bc_g_next,
+                                                    cpx<T>* __restrict__ bc_gt_next,
+                                                    cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
+  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t seg = gtid >> a.log2g;
+  const int lane = static_cast<int>(gtid & (a.G - 1));
+  if (seg >= a.nseg) return;  // whole lane groups leave together (G | 64)
+  const int64_t slot0 = a.seg_slot0[seg];
+  const int n = a.seg_n[seg];
+  const int nsl = n > 0 ? n : 1;
+  const double hfirst = a.seg_hfirst[seg], hlast = a.seg_hlast[seg];
+  const T q = static_cast<T>(a.q);
+
+  int e[EPL];
+  bool ok[EPL];
+  cpx<T> eps[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    const int ee = lane + a.G * i;
+    ok[i] = ee < a.n_e;
+    e[i] = ok[i] ? ee : a.n_e - 1;
+    eps[i] = mk(static_cast<T>(a.eps[2 * (a.e_off + e[i])]), static_cast<T>(a.eps[2 * (a.e_off + e[i]) + 1]));
+  }
+
+  // ---- gamma: R_min -> R_max
+  cpx<T> g[EPL];
+  {
+    const cpx<T> d0 = dslot[slot0];
+    const T a0 = aslot[slot0];
+    const bool taps = a.bc_valid && a.tap_start_w[seg * 4] + a.tap_start_w[seg * 4 + 1] +
+                                            a.tap_start_w[seg * 4 + 2] + a.tap_start_w[seg * 4 + 3] > 0.0;
+    for (int i = 0; i < EPL; ++i) {
+      if (taps) {
+        cpx<T> acc = mk(T(0), T(0));
+        for (int c = 0; c < 4; ++c) {
+          const T w = static_cast<T>(a.tap_start_w[seg * 4 + c]);
+          const cpx<T> v = bc_g_prev[static_cast<int64_t>(a.tap_start_seg[seg * 4 + c]) * a.n_e_tot + a.e_off + e[i]];
+          acc = acc + w * v;
+        }
+        g[i] = acc;
+      } else {
+        g[i] = bulk_root(mk(eps[i].x + q * a0, eps[i].y), d0);
+      }
+    }
+  }
+  for (int t = 0; t <= n; ++t) {
+    cpx<T> dm;
+    T am, hs;
+    step_values(dslot, aslot, slot0, n, t, hfirst, hlast, a.h, dm, am, hs);
+    for (int i = 0; i < EPL; ++i) g[i] = riccati_step(g[i], dm, mk(eps[i].x + q * am, eps[i].y), hs);
+    if (MODE != 2 && t < n) {
+      for (int i = 0; i < EPL; ++i)
+        if (ok[i]) gbuf[(slot0 + t) * a.n_e + e[i]] = g[i];
+    }
+  }
+  if (MODE != 1) {
+    for (int i = 0; i < EPL; ++i)
+      if (ok[i]) bc_g_next[seg * a.n_e_tot + a.e_off + e[i]] = g[i];
+  }
+
+  // ---- gamma~: R_max -> R_min with D -> -D*, Green's functions at nodes
+  cpx<T> gt[EPL];
+  {
+    const cpx<T> d1 = dslot[slot0 + nsl - 1];
+    const T a1 = aslot[slot0 + nsl - 1];
+    const bool taps = a.bc_valid && a.tap_end_w[seg * 4] + a.tap_end_w[seg * 4 + 1] + a.tap_end_w[seg * 4 + 2] +
+                                            a.tap_end_w[seg * 4 + 3] > 0.0;
+    for (int i = 0; i < EPL; ++i) {
+      if (taps) {
+        cpx<T> acc = mk(T(0), T(0));
+        for (int c = 0; c < 4; ++c) {
+          const T w = static_cast<T>(a.tap_end_w[seg * 4 + c]);
+          const cpx<T> v = bc_gt_prev[static_cast<int64_t>(a.tap_end_seg[seg * 4 + c]) * a.n_e_tot + a.e_off + e[i]];
+          acc = acc + w * v;
+        }
+        gt[i] = acc;
+      } else {
+        gt[i] = bulk_root(mk(eps[i].x + q * a1, eps[i].y), mk(-d1.x, d1.y));  // D -> -D*
+      }
+    }
+  }
+  const T pi = static_cast<T>(3.14159265358979323846);
+  for (int t = n; t >= 0; --t) {
+    cpx<T> dm;
+    T am, hs;
+    step_values(dslot, aslot, slot0, n, t, hfirst, hlast, a.h, dm, am, hs);
+    const cpx<T> md = mk(-dm.x, dm.y);
+    for (int i = 0; i < EPL; ++i) gt[i] = riccati_step(gt[i], md, mk(eps[i].x + q * am, eps[i].y), hs);
+    if (MODE == 2 || t == 0) continue;
+    const int64_t node = slot0 + t - 1;
+    if (MODE == 0) {
+      const cpx<T> dn = dslot[node];
+      double sfx = 0.0, sfy = 0.0, sg = 0.0, si = 0.0;
+      for (int i = 0; i < EPL; ++i) {
+        const cpx<T> gg = gbuf[node * a.n_e + e[i]];
+        const cpx<T> x = gg * gt[i];
+        const cpx<T> inv = cdiv(mk(T(1), T(0)), mk(T(1) + x.x, x.y));
+        const cpx<T> omx = mk(T(1) - x.x, -x.y) * inv;
+        const cpx<T> gr = mk(pi * omx.y, -pi * omx.x);  // -i pi (1-X)/(1+X)
+        const cpx<T> gi = gg * inv, gti = gt[i] * inv;
+        const cpx<T> f = mk(T(2) * pi * gi.y, T(-2) * pi * gi.x);     // -2 i pi gamma/(1+X)
+        const cpx<T> ft = mk(T(-2) * pi * gti.y, T(2) * pi * gti.x);  // 2 i pi gamma~/(1+X)
+        const cpx<T> num = conj(dn) * f + dn * ft;
+        const cpx<T> den = mk(pi - gr.y, gr.x);                       // pi + i g
+        const cpx<T> rat = cdiv(num, den);
+        const double r = ok[i] ? a.rp[a.e_off + e[i]] : 0.0;
+        sfx += r * (static_cast<double>(f.x) + static_cast<double>(ft.x));
+        sfy += r * (static_cast<double>(f.y) - static_cast<double>(ft.y));
+        sg += r * static_cast<double>(gr.x);
+        si += r * static_cast<double>(rat.x);
+      }
+      for (int off = a.G >> 1; off > 0; off >>= 1) {
+        sfx += __shfl_xor(sfx, off, a.G);
+        sfy += __shfl_xor(sfy, off, a.G);
+        sg += __shfl_xor(sg, off, a.G);
+        si += __shfl_xor(si, off, a.G);
+      }
+      if (lane == 0) {
+        double* o = a.node_out + node * 4;
+        o[0] = a.tt * sfx;
+        o[1] = a.tt * sfy;
+        o[2] = a.tt * sg;
+        o[3] = a.twopi_tt * si;
+      }
+    } else {  // MODE 1: -Im g / pi per energy
+      for (int i = 0; i < EPL; ++i) {
+        if (!ok[i]) continue;
+        const cpx<T> gg = gbuf[node * a.n_e + e[i]];
+        const cpx<T> x = gg * gt[i];
+        const cpx<T> inv = cdiv(mk(T(1), T(0)), mk(T(1) + x.x, x.y));
+        const cpx<T> omx = mk(T(1) - x.x, -x.y) * inv;
+        // Im g = Im(-i pi (1-X)/(1+X)) = -pi Re((1-X)/(1+X))
+        ebuf[node * a.n_e + e[i]] = omx.x;
+      }
+    }
+  }
+  if (MODE != 1) {
+    for (int i = 0; i < EPL; ++i)
+      if (ok[i]) bc_gt_next[seg * a.n_e_tot + a.e_off + e[i]] = gt[i];
+  }
+}
+
+// --------------------------------------------------------------------------
+// rotate back + angle sums + gap / current / free energy
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) rotate_back_kernel(BackArgs a) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= a.ncg) return;
+  const int cell = a.grain_cells[c];
+  constexpr int MAXC = 4;
+  double nx_[MAXC], ny_[MAXC], dx_[MAXC], dy_[MAXC];
+  for (int g = 0; g < a.ncomp; ++g) {
+    nx_[g] = 0.0;
+    ny_[g] = 0.0;
+    dx_[g] = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + cell)];
+    dy_[g] = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + cell) + 1];
+  }
+  double jx = 0.0, jy = 0.0, icell = 0.0, d2avg = 0.0;
+  for (int k = 0; k < a.n_theta; ++k) {
+    double cfx = 0.0, cfy = 0.0, cg = 0.0, ci = 0.0;
+    for (int qd = 0; qd < 4; ++qd) {
+      const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
+      const int64_t s = a.rb_idx[o];
+      const double w = a.rb_w[o];
+      const double* v = a.node_out + s * 4;
+      cfx += v[0] * w;
+      cfy += v[1] * w;
+      cg += v[2] * w;
+      ci += v[3] * w;
+    }
+    const double wk = a.wk[k];
+    double dkx = 0.0, dky = 0.0;
+    for (int g = 0; g < a.ncomp; ++g) {
+      const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
+      const double px = wk * ex, py = -wk * ey;  // wk conj(eta)
+      nx_[g] += px * cfx - py * cfy;
+      ny_[g] += px * cfy + py * cfx;
+      dkx += ex * dx_[g] - ey * dy_[g];
+      dky += ex * dy_[g] + ey * dx_[g];
+    }
+    jx += a.four_q * wk * a.cosk[k] * cg;
+    jy += a.four_q * wk * a.sink[k] * cg;
+    icell += wk * ci;
+    d2avg += wk * (dkx * dkx + dky * dky);
+  }
+  double om = 0.0;
+  for (int g = 0; g < a.ncomp; ++g) {
+    a.delta_new[2 * (static_cast<int64_t>(g) * a.ncell + cell)] = nx_[g] / a.den[g];
+    a.delta_new[2 * (static_cast<int64_t>(g) * a.ncell + cell) + 1] = ny_[g] / a.den[g];
+    om += (dx_[g] * dx_[g] + dy_[g] * dy_[g]) * a.logt[g];
+  }
+  om += a.twopi_rz * d2avg - icell;
+  a.j[cell] = jx;
+  a.j[a.ncell + cell] = jy;
+  if (a.omega) a.omega[cell] = om;
+  a.omega_cell[c] = om;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) ldos_back_kernel(LdosBackArgs a, const T* __restrict__ ebuf) {
+  // thread per (grain cell, energy of the block), energy fastest
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t c = tid / a.n_e;
+  const int e = static_cast<int>(tid - c * a.n_e);
+  if (c >= a.ncg) return;
+  double acc = 0.0;
+  for (int k = 0; k < a.n_theta; ++k) {
+    double v = 0.0;
+    for (int qd = 0; qd < 4; ++qd) {
+      const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
+      v += static_cast<double>(ebuf[static_cast<int64_t>(a.rb_idx[o]) * a.n_e + e]) * a.rb_w[o];
+    }
+    acc += a.wk[k] * v;
+  }
+  // N/N_F = -Im g / pi = Re((1-X)/(1+X))
+  a.out[static_cast<int64_t>(a.e_off + e) * a.ncell + a.grain_cells[c]] = acc;
+}
+
+// --------------------------------------------------------------------------
+// grid helpers: zero fill, curl + magnetic energy, block reductions
+// --------------------------------------------------------------------------
+__global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) curl_kernel(const double* __restrict__ A, double* __restrict__ B,
+                                                   int nx, int ny, double h) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= static_cast<int64_t>(nx) * ny) return;
+  const int i = static_cast<int>(c % nx), j = static_cast<int>(c / nx);
+  const double* ax = A;
+  const double* ay = A + static_cast<int64_t>(nx) * ny;
+  double dyx, dxy;  // d_x A_y, d_y A_x
+  if (i == 0)
+    dyx = (ay[c + 1] - ay[c]) / h;
+  else if (i == nx - 1)
+    dyx = (ay[c] - ay[c - 1]) / h;
+  else
+    dyx = (ay[c + 1] - ay[c - 1]) / (2 * h);
+  if (j == 0)
+    dxy = (ax[c + nx] - ax[c]) / h;
+  else if (j == ny - 1)
+    dxy = (ax[c] - ax[c - nx]) / h;
+  else
+    dxy = (ax[c + nx] - ax[c - nx]) / (2 * h);
+  B[c] = dyx - dxy;
+}
+
+// Block partial sums of f(x) (x gathered through idx when given): mode 0
+// sum x, mode 1 sum x^2.  One partial per block written to part[blockIdx.x];
+// the host adds them in order.
+__global__ void __launch_bounds__(256) block_sum_kernel(const double* __restrict__ x,
+                                                        const int32_t* __restrict__ idx, int64_t n, int mode,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double v = x[idx ? idx[i] : i];
+    acc += mode == 1 ? v * v : v;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Partial p-norms of (new - old) and of old over `n` elements of `stride`
+// doubles each (stride 2: complex modulus).  p = 1, 2, or 0 (max).
+// Elements may be gathered through idx (grain cells) when idx != nullptr,
+// for `nrep` consecutive fields of `field_stride` elements.
+__global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
+  __shared__ double s0[256], s1[256];
+  double acc0 = 0.0, acc1 = 0.0;
+  const int64_t total = a.n * a.nrep;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t / a.n, i = t - r * a.n;
+    const int64_t e = r * a.field_stride + (a.idx ? a.idx[i] : i);
+    double dn = 0.0, dd = 0.0;
+    for (int c = 0; c < a.stride; ++c) {
+      const double vn = a.xnew[e * a.stride + c], vo = a.xold[e * a.stride + c];
+      dn += (vn - vo) * (vn - vo);
+      dd += vo * vo;
+    }
+    if (a.p == 2) {
+      acc0 += dn;
+      acc1 += dd;
+    } else if (a.p == 1) {
+      acc0 += __builtin_sqrt(dn);
+      acc1 += __builtin_sqrt(dd);
+    } else {
+      acc0 = fmax(acc0, __builtin_sqrt(dn));
+      acc1 = fmax(acc1, __builtin_sqrt(dd));
+    }
+  }
+  s0[threadIdx.x] = acc0;
+  s1[threadIdx.x] = acc1;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      if (a.p == 0) {
+        s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + s]);
+        s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
+      } else {
+        s0[threadIdx.x] += s0[threadIdx.x + s];
+        s1[threadIdx.x] += s1[threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.part[2 * blockIdx.x] = s0[0];
+    a.part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+// x <- x + alpha (g - x) on n doubles (gathered through idx when given, for
+// nrep fields of field_stride elements with `stride` doubles each)
+__global__ void __launch_bounds__(256) picard_kernel(double* __restrict__ x, const double* __restrict__ gx,
+                                                     const int32_t* __restrict__ idx, int64_t n, int nrep,
+                                                     int64_t field_stride, int stride, double alpha) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrep) return;
+  const int64_t r = t / n, i = t - r * n;
+  const int64_t e = r * field_stride + (idx ? idx[i] : i);
+  for (int c = 0; c < stride; ++c) {
+    const double v = x[e * stride + c];
+    x[e * stride + c] = v + alpha * (gx[e * stride + c] - v);
+  }
+}
+
+// --------------------------------------------------------------------------
+// A-solve (App. D): zero-padded FFT correlation with the cell-averaged
+// Green's function of the 2D Laplacian
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pad_current_kernel(const double* __restrict__ j, const uint8_t* __restrict__ mask,
+                                                          int nx, int ny, int px, int py, double mx, double my,
+                                                          double2* __restrict__ w) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(px) * py) return;
+  const int x = static_cast<int>(t % px), y = static_cast<int>(t / px);
+  double2 v = make_double2(0.0, 0.0);
+  if (x < nx && y < ny) {
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+    if (mask[c]) v = make_double2(j[c] - mx, j[static_cast<int64_t>(nx) * ny + c] - my);
+  }
+  w[t] = v;
+}
+
+// In-place radix-2 FFT of every row (length n = 2^logn) of a [rows][n]
+// complex array, one workgroup per row, staged in LDS.  sign = -1 forward.
+__global__ void __launch_bounds__(256) fft_rows_kernel(double2* __restrict__ w, int logn,
+                                                       const double2* __restrict__ tw, int sign) {
+  extern __shared__ double2 buf[];
+  const int n = 1 << logn;
+  double2* row = w + static_cast<int64_t>(blockIdx.x) * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = static_cast<int>(__builtin_bitreverse32(static_cast<unsigned>(i)) >> (32 - logn));
+    buf[r] = row[i];
+  }
+  __syncthreads();
+  for (int s = 1; s <= logn; ++s) {
+    const int half = 1 << (s - 1);
+    for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
+      const int grp = b / half, pos = b - grp * half;
+      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
+      double2 tf = tw[pos << (logn - s)];  // exp(-2 pi i pos / 2^s)
+      if (sign > 0) tf.y = -tf.y;
+      const double2 u = buf[i0], v = buf[i1];
+      const double2 vt = make_double2(v.x * tf.x - v.y * tf.y, v.x * tf.y + v.y * tf.x);
+      buf[i0] = make_double2(u.x + vt.x, u.y + vt.y);
+      buf[i1] = make_double2(u.x - vt.x, u.y - vt.y);
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = buf[i];
+}
+
+// out[x][y] = in[y][x] for a [rows][cols] complex array, 32x32 LDS tiles
+__global__ void __launch_bounds__(256) transpose_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                                        int rows, int cols) {
+  __shared__ double2 tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int y = by + r, x = bx + threadIdx.x;
+    if (y < rows && x < cols) tile[r][threadIdx.x] = in[static_cast<int64_t>(y) * cols + x];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int x = bx + r, y = by + threadIdx.x;
+    if (x < cols && y < rows) out[static_cast<int64_t>(x) * rows + y] = tile[threadIdx.x][r];
+  }
+}
+
+__global__ void cmul_kernel(double2* __restrict__ w, const double2* __restrict__ g, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = w[i], b = g[i];
+  w[i] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ void __launch_bounds__(256) unpad_A_kernel(const double2* __restrict__ w, int nx, int ny, int px,
+                                                      double scale, double* __restrict__ A) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= static_cast<int64_t>(nx) * ny) return;
+  const int x = static_cast<int>(c % nx), y = static_cast<int>(c / nx);
+  const double2 v = w[static_cast<int64_t>(y) * px + x];
+  A[c] = scale * v.x;
+  A[static_cast<int64_t>(nx) * ny + c] = scale * v.y;
+}
+
+// --------------------------------------------------------------------------
+// launch wrappers
+// --------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
+
+template <typename T>
+void launch_interp(const InterpArgs& a, void* dslot, void* aslot, hipStream_t st) {
+  if (a.nslot == 0) return;
+  hipLaunchKernelGGL(interp_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a,
+                     static_cast<cpx<T>*>(dslot), static_cast<T*>(aslot));
+}
+template void launch_interp<double>(const InterpArgs&, void*, void*, hipStream_t);
+template void launch_interp<float>(const InterpArgs&, void*, void*, hipStream_t);
+
+template <typename T, int EPL, int MODE>
+static void launch_sweep_t(const SweepArgs& a, const SweepBufs& b, hipStream_t st) {
+  const int64_t threads = a.nseg * a.G;
+  hipLaunchKernelGGL((sweep_kernel<T, EPL, MODE>), dim3(nblk(threads)), dim3(256), 0, st, a,
+                     static_cast<const cpx<T>*>(b.dslot), static_cast<const T*>(b.aslot),
+                     static_cast<const cpx<T>*>(b.bc_g_prev), static_cast<const cpx<T>*>(b.bc_gt_prev),
+                     static_cast<cpx<T>*>(b.bc_g_next), static_cast<cpx<T>*>(b.bc_gt_next),
+                     static_cast<cpx<T>*>(b.gbuf), static_cast<T*>(b.ebuf));
+}
+
+template <typename T, int MODE>
+static void launch_sweep_m(int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st) {
+  switch (epl) {
+    case 1: launch_sweep_t<T, 1, MODE>(a, b, st); break;
+    case 2: launch_sweep_t<T, 2, MODE>(a, b, st); break;
+    case 4: launch_sweep_t<T, 4, MODE>(a, b, st); break;
+    default: launch_sweep_t<T, 8, MODE>(a, b, st); break;
+  }
+}
+
+template <typename T>
+void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st) {
+  if (a.nseg == 0) return;
+  if (mode == 0)
+    launch_sweep_m<T, 0>(epl, a, b, st);
+  else if (mode == 1)
+    launch_sweep_m<T, 1>(epl, a, b, st);
+  else
+    launch_sweep_m<T, 2>(epl, a, b, st);
+}
+template void launch_sweep<double>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
+template void launch_sweep<float>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
+
+void launch_rotate_back(const BackArgs& a, hipStream_t st) {
+  if (a.ncg == 0) return;
+  hipLaunchKernelGGL(rotate_back_kernel, dim3(nblk(a.ncg)), dim3(256), 0, st, a);
+}
+
+template <typename T>
+void launch_ldos_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st) {
+  hipLaunchKernelGGL(ldos_back_kernel<T>, dim3(nblk(a.ncg * a.n_e)), dim3(256), 0, st, a,
+                     static_cast<const T*>(ebuf));
+}
+template void launch_ldos_back<double>(const LdosBackArgs&, const void*, hipStream_t);
+template void launch_ldos_back<float>(const LdosBackArgs&, const void*, hipStream_t);
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n, v);
+}
+void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream_t st) {
+  hipLaunchKernelGGL(curl_kernel, dim3(nblk(static_cast<int64_t>(nx) * ny)), dim3(256), 0, st, A, B, nx, ny, h);
+}
+void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(block_sum_kernel, dim3(nparts), dim3(256), 0, st, x, idx, n, mode, part);
+}
+void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(diff_norm_kernel, dim3(nparts), dim3(256), 0, st, a);
+}
+void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, int nrep, int64_t field_stride,
+                   int stride, double alpha, hipStream_t st) {
+  if (n * nrep > 0)
+    hipLaunchKernelGGL(picard_kernel, dim3(nblk(n * nrep)), dim3(256), 0, st, x, gx, idx, n, nrep, field_stride,
+                       stride, alpha);
+}
+void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, double mx, double my,
+                        double2* w, hipStream_t st) {
+  hipLaunchKernelGGL(pad_current_kernel, dim3(nblk(static_cast<int64_t>(px) * py)), dim3(256), 0, st, j, mask, nx,
+                     ny, px, py, mx, my, w);
+}
+void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, hipStream_t st) {
+  hipLaunchKernelGGL(fft_rows_kernel, dim3(rows), dim3(256), sizeof(double2) << logn, st, w, logn, tw, sign);
+}
+void launch_transpose(const double2* in, double2* out, int rows, int cols, hipStream_t st) {
+  hipLaunchKernelGGL(transpose_kernel, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(32, 8), 0, st, in, out, rows,
+                     cols);
+}
+void launch_cmul(double2* w, const double2* g, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(cmul_kernel, dim3(nblk(n)), dim3(256), 0, st, w, g, n);
+}
+void launch_unpad_A(const double2* w, int nx, int ny, int px, double scale, double* A, hipStream_t st) {
+  hipLaunchKernelGGL(unpad_A_kernel, dim3(nblk(static_cast<int64_t>(nx) * ny)), dim3(256), 0, st, w, nx, ny, px,
+                     scale, A);
+}
+
+}  // namespace qc

@@ -1,0 +1,125 @@
+// Kernel argument blocks and launch wrappers of sweep.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qc {
+
+struct InterpArgs {
+  int64_t nslot;
+  int64_t ncell;  // nx * ny
+  int ncomp, n_theta;
+  const int32_t* slot_angle;
+  const int32_t* dst_idx;
+  const double* dst_w;
+  const int32_t* ast_idx;
+  const double* ast_w;
+  const double* aext;   // v_k . A_ext per slot
+  const double* eta;    // complex [ncomp][n_theta]
+  const double* cosk;
+  const double* sink;
+  const double* delta;  // complex [ncomp][ny][nx]
+  const double* A;      // [2][ny][nx]
+};
+
+struct SweepArgs {
+  int64_t nseg;
+  int G, log2g;           // lanes per segment (power of two dividing 64)
+  int n_e;                // energies in this launch (stride of gbuf / ebuf)
+  int n_e_tot;            // stride of the boundary stores
+  int e_off;              // first energy of this launch
+  int bc_valid;           // 0: start at the bulk roots
+  double h, q, tt, twopi_tt;
+  const int64_t* seg_slot0;
+  const int32_t* seg_n;
+  const double* seg_hfirst;
+  const double* seg_hlast;
+  const int32_t* tap_start_seg;
+  const double* tap_start_w;
+  const int32_t* tap_end_seg;
+  const double* tap_end_w;
+  const double* eps;      // complex energies [n_e_tot]: i eps~_p or e + i delta
+  const double* rp;       // pole weights [n_e_tot]
+  double* node_out;       // mode 0: [nslot][4] = t~ sum R f+conj f~ (re, im), t~ sum R Re g, 2 pi t~ sum R Re(..)
+};
+
+struct SweepBufs {
+  const void* dslot;
+  const void* aslot;
+  const void* bc_g_prev;
+  const void* bc_gt_prev;
+  void* bc_g_next;
+  void* bc_gt_next;
+  void* gbuf;
+  void* ebuf;
+};
+
+struct BackArgs {
+  int64_t ncg;     // grain cells
+  int64_t ncell;   // nx * ny
+  int ncomp, n_theta;
+  const int32_t* grain_cells;
+  const int32_t* rb_idx;
+  const double* rb_w;
+  const double* node_out;
+  const double* wk;
+  const double* cosk;
+  const double* sink;
+  const double* eta;
+  const double* den;   // gap denominators per component
+  const double* logt;  // ln(t / t_c,G)
+  double four_q;
+  double twopi_rz;     // 2 pi sum_p R_p / z_p
+  const double* delta;
+  double* delta_new;
+  double* j;
+  double* omega;       // [ny][nx] or nullptr
+  double* omega_cell;  // [ncg] scratch for the total
+};
+
+struct LdosBackArgs {
+  int64_t ncg, ncell;
+  int n_theta, n_e, e_off;
+  const int32_t* grain_cells;
+  const int32_t* rb_idx;
+  const double* rb_w;
+  const double* wk;
+  double* out;  // [n_e_total][ny][nx]
+};
+
+struct DiffNormArgs {
+  const double* xnew;
+  const double* xold;
+  const int32_t* idx;
+  int64_t n;
+  int nrep;
+  int64_t field_stride;
+  int stride;
+  int p;
+  double* part;
+};
+
+template <typename T>
+void launch_interp(const InterpArgs& a, void* dslot, void* aslot, hipStream_t st);
+template <typename T>
+void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
+void launch_rotate_back(const BackArgs& a, hipStream_t st);
+template <typename T>
+void launch_ldos_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st);
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream_t st);
+void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,
+                      hipStream_t st);
+void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st);
+void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, int nrep, int64_t field_stride,
+                   int stride, double alpha, hipStream_t st);
+void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, double mx, double my,
+                        double2* w, hipStream_t st);
+void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, hipStream_t st);
+void launch_transpose(const double2* in, double2* out, int rows, int cols, hipStream_t st);
+void launch_cmul(double2* w, const double2* g, int64_t n, hipStream_t st);
+void launch_unpad_A(const double2* w, int nx, int ny, int px, double scale, double* A, hipStream_t st);
+
+}  // namespace qc

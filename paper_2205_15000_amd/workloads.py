@@ -1,0 +1,136 @@
+"""Seeded synthetic workloads: grain descriptions and starting fields.
+
+This module holds inputs only (shapes, grids, parameters, seeded random
+starting fields), none of the method's arithmetic; the tests, the smoke
+check and the benchmark take their inputs from here so that the HIP path
+and the CPU oracle see identical data.  The paper uses no public dataset:
+its workloads are synthetic grains, which these recipes stand in for.
+
+DELTA0 is the weak-coupling BCS gap at T = 0, pi exp(-gamma_E) k_B Tc, in
+units of 2 pi k_B Tc: the scale of the starting amplitudes and tolerances.
+"""
+import math
+
+import numpy as np
+
+DELTA0 = 0.28072974178344257
+# bulk d-wave gap at t = 0.1 with 64 poles and 64 angles, in units of DELTA0
+# (root of the homogeneous gap equation; used only as a starting amplitude)
+D_BULK_T01 = 0.8577177
+
+
+def _disc(cx, cy, r, add=True):
+    return {"kind": "disc", "cx": cx, "cy": cy, "radius": r, "add": add}
+
+
+def _square(cx, cy, side, rotation=0.0, add=True):
+    return {"kind": "regular_polygon", "cx": cx, "cy": cy, "n_edges": 4, "side": side,
+            "rotation": rotation, "add": add}
+
+
+SPECS = {
+    # s-wave disc R = 10 xi0 on 32x32 (h = 0.625), 32 angles, 16 poles,
+    # t = 0.5, no field (the small Picard case, 50 iterations)
+    "s_disc_32": dict(nx=32, ny=32, h=0.625, shapes=[_disc(0, 0, 10.0)], n_theta=32, n_poles=16, t=0.5,
+                      components=[("s", 1.0)], kappa=0.0, flux_quanta=0.0, gauge="symmetric", charge_sign=-1),
+    # d-wave square of side 40 xi0 on 400x400 (h = 0.1) with crystal axes at
+    # 45 degrees (four pair-breaking [110] edges), 64 angles, 64 poles,
+    # t = 0.1, one flux quantum (symmetric gauge), kappa = 20, one vortex
+    "d110_square_400": dict(nx=400, ny=400, h=0.1, shapes=[_square(0, 0, 40.0)], n_theta=64, n_poles=64,
+                            t=0.1, components=[("dx2y2", 1.0)], crystal_rotation=0.125, kappa=20.0,
+                            flux_quanta=1.0, gauge="symmetric", charge_sign=-1),
+    # d-wave disc R = 20 xi0 on 200x200 (h = 0.2), 64 angles, 48 poles,
+    # t = 0.2, two flux quanta, kappa = 20 (the differentiated map)
+    "d_disc_200": dict(nx=200, ny=200, h=0.2, shapes=[_disc(0, 0, 20.0)], n_theta=64, n_poles=48, t=0.2,
+                       components=[("dx2y2", 1.0)], kappa=20.0, flux_quanta=2.0, gauge="symmetric",
+                       charge_sign=-1),
+    # d-wave square of side 51.2 xi0 on 512x512 (h = 0.1), [110] edges,
+    # t = 0.1, kappa = 100; LDOS with 256 angles
+    "d110_square_512_ldos": dict(nx=512, ny=512, h=0.1, shapes=[_square(0, 0, 51.2)], n_theta=256, n_poles=64,
+                                 t=0.1, components=[("dx2y2", 1.0)], crystal_rotation=0.125, kappa=100.0,
+                                 flux_quanta=0.0, gauge="symmetric", charge_sign=-1),
+    # ---- small parity cases (several tiles, ragged tails, every option) ----
+    # d-wave [110] square with field, finite kappa and an off-centre vortex
+    "small_d110_field": dict(nx=40, ny=40, h=0.5, shapes=[_square(0, 0, 18.3)], n_theta=16, n_poles=8, t=0.3,
+                             components=[("dx2y2", 1.0)], crystal_rotation=0.125, kappa=3.0, flux_quanta=1.5,
+                             gauge="symmetric", charge_sign=-1),
+    # disc with a square hole, s + d_xy components, solenoid gauge
+    "small_holed_mixed": dict(nx=36, ny=36, h=0.5, shapes=[_disc(0, 0, 8.6), _square(1.3, 0.4, 4.0, 0.1, add=False)],
+                              n_theta=24, n_poles=6, t=0.4, components=[("s", 1.0), ("dxy", 0.7)],
+                              kappa=0.0, flux_quanta=0.6, gauge="solenoid", charge_sign=-1),
+    # convex polygon, odd angle count (trapezoid weights), Landau gauge,
+    # positive carriers, kappa for the A-solve, 5 poles (padded lanes)
+    "small_polygon_landau": dict(nx=30, ny=26, h=0.45,
+                                 shapes=[{"kind": "polygon", "vx": [-6.0, 5.5, 6.4, 0.5, -5.8],
+                                          "vy": [-5.0, -5.4, 1.0, 5.5, 3.0], "add": True}],
+                                 n_theta=15, n_poles=5, t=0.6, components=[("s", 1.0)], kappa=2.0,
+                                 flux_quanta=0.8, gauge="landau", charge_sign=1),
+}
+
+
+def spec(name):
+    s = dict(SPECS[name])
+    s["shapes"] = [dict(sh) for sh in s["shapes"]]
+    s["name"] = name
+    return s
+
+
+def centres(sp):
+    """Cell centres x0 + (i + 1/2) h, y0 + (j + 1/2) h as [ny][nx] arrays."""
+    nx, ny, h = sp["nx"], sp["ny"], sp["h"]
+    x0 = sp.get("x0")
+    y0 = sp.get("y0")
+    x0 = -0.5 * nx * h if x0 is None else x0
+    y0 = -0.5 * ny * h if y0 is None else y0
+    xs = x0 + (np.arange(nx) + 0.5) * h
+    ys = y0 + (np.arange(ny) + 0.5) * h
+    return np.meshgrid(xs, ys)
+
+
+def initial_delta(name, sp=None, seed=None):
+    """Seeded starting order parameter, complex [ncomp][ny][nx]
+    (values off the grain are ignored by the method)."""
+    sp = sp or spec(name)
+    nx, ny = sp["nx"], sp["ny"]
+    X, Y = centres(sp)
+    ncomp = len(sp["components"])
+    if name == "s_disc_32":
+        rng = np.random.default_rng(1 if seed is None else seed)
+        u = rng.uniform(-0.05, 0.05, (ny, nx))
+        return (DELTA0 * (1.0 + u))[None].astype(np.complex128)
+    if name in ("d110_square_400", "d110_square_512_ldos"):
+        rng = np.random.default_rng((2 if name == "d110_square_400" else 7) if seed is None else seed)
+        xv, yv = rng.uniform(-5.0, 5.0, 2)
+        phase = -np.arctan2(Y - yv, X - xv)
+        return (D_BULK_T01 * DELTA0 * np.exp(1j * phase))[None].astype(np.complex128)
+    if name == "d_disc_200":
+        rng = np.random.default_rng(4 if seed is None else seed)
+        u = rng.uniform(-0.05, 0.05, (ny, nx))
+        return (DELTA0 * (0.8 + u))[None].astype(np.complex128)
+    # small parity cases: a vortex plus complex noise per component
+    rng = np.random.default_rng(11 if seed is None else seed)
+    xv, yv = rng.uniform(-2.0, 2.0, 2)
+    out = np.empty((ncomp, ny, nx), dtype=np.complex128)
+    for c in range(ncomp):
+        amp = DELTA0 * (0.9 if c == 0 else 0.3)
+        noise = 0.05 * DELTA0 * (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx)))
+        out[c] = amp * np.exp(-1j * np.arctan2(Y - yv, X - xv) + 0.7j * c) + noise
+    return out
+
+
+def initial_A(name, sp=None, seed=None):
+    """Starting induced vector potential [2][ny][nx]: zero for the paper
+    workloads, a small smooth seeded field for the parity cases."""
+    sp = sp or spec(name)
+    nx, ny = sp["nx"], sp["ny"]
+    if name in ("s_disc_32", "d110_square_400", "d_disc_200", "d110_square_512_ldos"):
+        return np.zeros((2, ny, nx))
+    rng = np.random.default_rng(23 if seed is None else seed)
+    X, Y = centres(sp)
+    a, b, c, d = rng.uniform(0.1, 0.4, 4)
+    return 0.02 * np.stack([np.sin(a * X + b * Y), np.cos(c * X - d * Y)])
+
+
+def ldos_energies(n=512):
+    """Real energies -2 DELTA0 + 4 DELTA0 k / n, k = 0..n-1 (includes 0)."""
+    return -2.0 * DELTA0 + 4.0 * DELTA0 * np.arange(n) / n

@@ -1,0 +1,246 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+FP64: <= 1e-10 normwise relative (and elementwise against the field's max).
+Mixed FP32-sweep / FP64-sum: within the bound derived from FP32 rounding
+(checked at 2e-5 * DELTA0 absolute on Delta, about 1e-4 relative).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_2205_15000_amd import workloads as wl  # noqa: E402
+from oracle import fields, scf as oscf  # noqa: E402
+from helpers import oracle_grain, rel_err  # noqa: E402
+
+SMALL = ["s_disc_32", "small_d110_field", "small_holed_mixed", "small_polygon_landau"]
+FP64_TOL = 1e-10
+
+
+def _qs():
+    import paper_2205_15000_amd as qs
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return qs
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _close(a, b, tol):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = max(np.max(np.abs(b)), 1e-300)
+    return rel_err(a, b) <= tol and np.max(np.abs(a - b)) <= tol * scale
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_iteration_map_fp64_matches_oracle(name):
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s fp64: 3 chained sweeps" % name)
+    g = qs.Grain(sp, "fp64")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    bc = None
+    for it in range(3):
+        dn, j, om, od = g.sweep(dd, ad, omega_density=True)
+        ref = og.iterate(d0, a0, bc)
+        bc = ref["bc"]
+        m = og.mask
+        assert _close(dn.cpu().numpy()[:, m], ref["delta_new"][:, m], FP64_TOL), (it, rel_err(dn.cpu().numpy(), ref["delta_new"]))
+        assert np.all(dn.cpu().numpy()[:, ~m] == 0)
+        if np.max(np.abs(ref["j"])) > 1e-12:
+            assert _close(j.cpu().numpy(), ref["j"], FP64_TOL), (it, rel_err(j.cpu().numpy(), ref["j"]))
+        else:
+            assert np.max(np.abs(j.cpu().numpy())) < 1e-13
+        assert _close(od.cpu().numpy(), ref["omega_density"], FP64_TOL)
+        assert abs(om - ref["omega_total"]) <= FP64_TOL * abs(ref["omega_total"])
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["s_disc_32", "small_d110_field", "small_holed_mixed"])
+def test_iteration_map_mixed_precision_error(name):
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s mixed: 3 chained sweeps" % name)
+    g = qs.Grain(sp, "mixed")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    bc = None
+    for it in range(3):
+        dn, j, om = g.sweep(dd, ad)
+        ref = og.iterate(d0, a0, bc)
+        bc = ref["bc"]
+        m = og.mask
+        err = np.max(np.abs(dn.cpu().numpy()[:, m] - ref["delta_new"][:, m]))
+        assert err < 2e-5 * wl.DELTA0, err
+        jerr = np.max(np.abs(j.cpu().numpy() - ref["j"]))
+        assert jerr < 2e-5 * max(np.max(np.abs(ref["j"])), 1e-3), jerr
+        assert abs(om - ref["omega_total"]) < 1e-5 * abs(ref["omega_total"])
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["small_d110_field", "small_polygon_landau"])
+def test_A_solve_matches_oracle(name):
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s: A-solve" % name)
+    g = qs.Grain(sp, "fp64")
+    og = oracle_grain(sp)
+    rng = np.random.default_rng(99)
+    jj = rng.standard_normal((2, sp["ny"], sp["nx"]))
+    A, B = g.solve_A(_dev(jj, torch.float64))
+    ax, ay = fields.solve_A(jj[0], jj[1], og.mask, sp["h"], sp["kappa"], method="direct")
+    assert _close(A.cpu().numpy()[0], ax, FP64_TOL)
+    assert _close(A.cpu().numpy()[1], ay, FP64_TOL)
+    assert _close(B.cpu().numpy(), fields.curl(ax, ay, sp["h"]), FP64_TOL)
+    g.close()
+
+
+def test_scf_50_picard_iterations_match_oracle():
+    qs = _qs()
+    name = "s_disc_32"
+    sp = wl.spec(name)
+    _note("case %s: 50 Picard iterations fp64" % name)
+    g = qs.Grain(sp, "fp64")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    it, res, conv = g.scf(dd, ad, 50)
+    assert it == 50 and not conv
+    dref, aref, hist, _ = oscf.scf(og, d0, a0, 50)
+    m = og.mask
+    assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
+    h = np.array(hist)
+    for c in (0, 3, 4):
+        fin = np.isfinite(h[:, c])
+        assert np.all(np.isfinite(res[:, c]) == fin)
+        assert np.max(np.abs(res[fin, c] - h[fin, c]) / np.maximum(np.abs(h[fin, c]), 1e-300)) < 1e-8
+    g.close()
+
+
+def test_scf_with_A_solve_matches_oracle():
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: 6 Picard iterations with A, fp64" % name)
+    g = qs.Grain(sp, "fp64")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    it, res, conv = g.scf(dd, ad, 6, alpha=0.7, burnin=1)
+    dref, aref, hist, _ = oscf.scf(og, d0, a0, 6, alpha=0.7, burnin=1)
+    m = og.mask
+    assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
+    assert _close(ad.cpu().numpy(), aref, FP64_TOL)
+    h = np.array(hist)
+    fin = np.isfinite(h)
+    assert np.max(np.abs(res[fin] - h[fin]) / np.maximum(np.abs(h[fin]), 1e-12)) < 1e-8
+    g.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 2e-4)])
+def test_ldos_matches_oracle(precision, tol):
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: LDOS %s" % (name, precision))
+    g = qs.Grain(sp, precision)
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    en = np.linspace(-0.4, 0.4, 7)
+    out = g.ldos(_dev(d0, torch.complex128), _dev(a0, torch.float64), en, 0.02, 2)
+    ref = og.ldos(d0, a0, en, 0.02, 2)
+    assert _close(out.cpu().numpy(), ref, tol), rel_err(out.cpu().numpy(), ref)
+    g.close()
+
+
+def test_uniform_s_wave_is_an_exact_fixed_point_on_gpu():
+    qs = _qs()
+    from oracle import bulk
+    sp = wl.spec("s_disc_32")
+    _note("case s_disc_32: bulk fixed point")
+    g = qs.Grain(sp, "fp64")
+    db = bulk.bulk_gap(0.5, 16)
+    d = torch.full((1, 32, 32), db, dtype=torch.complex128, device="cuda")
+    A = torch.zeros((2, 32, 32), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        dn, j, om = g.sweep(d, A)
+    m = oracle_grain(sp).mask
+    assert np.max(np.abs(dn.cpu().numpy()[0][m] - db)) < 1e-13
+    assert np.max(np.abs(j.cpu().numpy())) < 1e-15
+    assert abs(om / (0.625 ** 2 * m.sum()) - bulk.bulk_free_energy(db, 0.5, 16)) < 1e-13
+    g.close()
+
+
+def test_state_roundtrip_and_reset():
+    qs = _qs()
+    name = "small_holed_mixed"
+    sp = wl.spec(name)
+    _note("case %s: boundary-store get/set" % name)
+    g = qs.Grain(sp, "fp64")
+    d0 = _dev(wl.initial_delta(name, sp), torch.complex128)
+    a0 = _dev(wl.initial_A(name, sp), torch.float64)
+    g.sweep(d0, a0)
+    st = g.get_state()
+    r1 = g.sweep(d0, a0)[0].cpu().numpy()
+    g.set_state(st)
+    r2 = g.sweep(d0, a0)[0].cpu().numpy()
+    assert np.array_equal(r1, r2)
+    g.reset_bc()
+    r3 = g.sweep(d0, a0)[0].cpu().numpy()
+    g.reset_bc()
+    r4 = g.sweep(d0, a0)[0].cpu().numpy()
+    assert np.array_equal(r3, r4) and not np.array_equal(r3, r1)
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_d110_square_400_sampled_cells(precision):
+    """The 400x400 [110] square with a vortex, field and kappa = 20 in the
+    launch configuration of the benchmark: the first iteration map from
+    bulk start values checked at sampled grain cells against the oracle,
+    which sweeps only the trajectories feeding those cells."""
+    qs = _qs()
+    name = "d110_square_400"
+    sp = wl.spec(name)
+    _note("case %s %s: full-size first sweep" % (name, precision))
+    g = qs.Grain(sp, precision)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dn, j, om = g.sweep(_dev(d0, torch.complex128), _dev(a0, torch.float64))
+    og = oracle_grain(sp)
+    rng = np.random.default_rng(31)
+    cells = np.sort(rng.choice(np.nonzero(og.mask.ravel())[0], 6, replace=False))
+    cells = np.concatenate([cells, [0, 399, 400 * 200 + 200]])  # two corners and the centre
+    _note("  oracle on cells %s" % cells.tolist())
+    dref, jref = og.iterate_cells(d0, a0, cells)
+    dg = dn.cpu().numpy().reshape(1, -1)[:, cells]
+    jg = j.cpu().numpy().reshape(2, -1)[:, cells]
+    if precision == "fp64":
+        assert np.max(np.abs(dg - dref)) <= FP64_TOL * np.max(np.abs(dref))
+        assert np.max(np.abs(jg - jref)) <= FP64_TOL * np.max(np.abs(jref))
+    else:
+        assert np.max(np.abs(dg - dref)) < 2e-5 * wl.DELTA0
+        assert np.max(np.abs(jg - jref)) < 2e-5 * max(np.max(np.abs(jref)), 1e-3)
+    assert math.isfinite(om)
+    g.close()
