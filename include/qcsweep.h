@@ -245,6 +245,12 @@ qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,
 qc_status qc_get_state(const qc_grain* grain, void* state, size_t* bytes, void* stream);
 qc_status qc_set_state(qc_grain* grain, const void* state, size_t bytes, void* stream);
 
+/* Launch shape of the sweep kernel: energies handled by each lane (1, 2, 4
+ * or 8; 0 = automatic).  The lanes of one trajectory segment share the
+ * per-node energy sums, so fewer energies per lane means more lanes per
+ * segment.  Results are identical up to rounding order. */
+qc_status qc_grain_set_lanes(qc_grain* grain, int energies_per_lane);
+
 /* Kernel timing with HIP events on the launch stream (for roofline
  * reports).  Enable, run, then read the summed milliseconds and launch
  * count of the Riccati sweep kernel; reading resets the counters. */

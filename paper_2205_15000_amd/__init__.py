@@ -17,7 +17,7 @@ __all__ = ["Grain", "Plan", "QcError", "lib", "basis_table", "spec_desc", "PRECI
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqcsweep.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libqcsweep.so is not built: run `python -m paper_2205_15000_amd.build` "
+    raise ImportError("libqcsweep.so is not built: run `python paper_2205_15000_amd/build.py` "
                       "(hipcc for gfx950) before importing paper_2205_15000_amd")
 lib = ctypes.CDLL(LIB_PATH)
 
@@ -64,7 +64,11 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 
 def _sig(name, res, args):
-    f = getattr(lib, name)
+    try:
+        f = getattr(lib, name)
+    except AttributeError as e:
+        raise ImportError("libqcsweep.so is stale (missing %s): rebuild it with "
+                          "`python paper_2205_15000_amd/build.py`" % name) from e
     f.restype = res
     f.argtypes = args
     return f
@@ -92,6 +96,7 @@ _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ct
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_set_state", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P])
 _sig("qc_profile_enable", ctypes.c_int, [_P, ctypes.c_int])
+_sig("qc_grain_set_lanes", ctypes.c_int, [_P, ctypes.c_int])
 _sig("qc_profile_read", ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)])
 
 
@@ -352,6 +357,10 @@ class Grain:
     def set_state(self, buf, stream=None):
         _check(lib.qc_set_state(self._g, ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(buf.numel()),
                                 _stream(stream)))
+
+    def set_lanes(self, energies_per_lane):
+        """Energies per lane of the sweep kernel (1, 2, 4, 8; 0 = automatic)."""
+        _check(lib.qc_grain_set_lanes(self._g, int(energies_per_lane)))
 
     def profile(self, enable=True):
         _check(lib.qc_profile_enable(self._g, 1 if enable else 0))

@@ -1,6 +1,7 @@
 """Build the HIP library libqcsweep.so for gfx950 with hipcc (in-tree).
 
-Usage: python -m paper_2205_15000_amd.build  (or call build()).
+Usage: python paper_2205_15000_amd/build.py  (or __graft_entry__.build()).
+Run it by path: importing the package loads the library it builds.
 """
 import os
 import subprocess

@@ -78,9 +78,14 @@ int ilog2(int v) {
   return l;
 }
 
-// Lanes per segment and energies per lane for n_e energies.
-void lane_shape(int n_e, int& G, int& epl) {
-  epl = n_e >= 64 ? 8 : (n_e >= 16 ? 4 : (n_e >= 4 ? 2 : 1));
+// Lanes per segment G and energies per lane for n_e energies (G * epl >=
+// n_e, G a power of two <= 64); `force` (1, 2, 4, 8) overrides the choice.
+// Two energies per lane measured fastest on gfx950 for both precisions
+// (enough independent recursions per lane, low register use, many waves).
+void lane_shape(int n_e, int force, int& G, int& epl) {
+  epl = n_e >= 4 ? 2 : 1;
+  if (force == 1 || force == 2 || force == 4 || force == 8) epl = force;
+  while (epl < 8 && (n_e + epl - 1) / epl > 64) epl <<= 1;
   const int need = (n_e + epl - 1) / epl;
   G = 1;
   while (G < need) G <<= 1;
@@ -234,8 +239,9 @@ struct qc_grain {
   double* den = nullptr;
   double* logt = nullptr;
   // work buffers
-  void* dslot = nullptr;
-  void* aslot = nullptr;
+  void* nodes = nullptr;
+  int32_t* order = nullptr;
+  int epl_override = 0;
   void* gbuf = nullptr;
   double* node_out = nullptr;
   void* bc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -274,7 +280,7 @@ void free_grain(qc_grain* g) {
   void* ptrs[] = {g->slot_angle, g->dst_idx, g->dst_w, g->ast_idx, g->ast_w, g->aext, g->eta, g->cosk,
                   g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
-                  g->eps, g->rpd, g->den, g->logt, g->dslot, g->aslot, g->gbuf, g->node_out, g->bc[0][0],
+                  g->eps, g->rpd, g->den, g->logt, g->nodes, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew};
   for (void* p : ptrs)
@@ -335,16 +341,17 @@ void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st
   a.delta = delta;
   a.A = A;
   if (g->precision == QC_MIXED)
-    qc::launch_interp<float>(a, g->dslot, g->aslot, st);
+    qc::launch_interp<float>(a, g->nodes, st);
   else
-    qc::launch_interp<double>(a, g->dslot, g->aslot, st);
+    qc::launch_interp<double>(a, g->nodes, st);
 }
 
 qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const double* eps, const double* rp) {
   qc::SweepArgs a;
   a.nseg = g->nseg;
+  a.order = g->order;
   int epl;
-  lane_shape(n_e, a.G, epl);
+  lane_shape(n_e, g->epl_override, a.G, epl);
   a.log2g = ilog2(a.G);
   a.n_e = n_e;
   a.n_e_tot = n_e_tot;
@@ -352,7 +359,6 @@ qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const dou
   a.bc_valid = 0;
   a.h = g->h;
   a.q = g->q;
-  a.tt = g->t / (2.0 * kPi);
   a.twopi_tt = g->t;
   a.seg_slot0 = g->seg_slot0;
   a.seg_n = g->seg_n;
@@ -370,7 +376,7 @@ qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const dou
 
 void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc::SweepBufs& b, hipStream_t st) {
   int G, epl;
-  lane_shape(a.n_e, G, epl);
+  lane_shape(a.n_e, g->epl_override, G, epl);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g->prof) {
     hcheck(hipEventCreate(&e0), "event");
@@ -395,8 +401,7 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
   a.bc_valid = g->bc_valid;
   qc::SweepBufs b;
-  b.dslot = g->dslot;
-  b.aslot = g->aslot;
+  b.nodes = g->nodes;
   b.bc_g_prev = g->bc[g->bc_cur][0];
   b.bc_gt_prev = g->bc[g->bc_cur][1];
   b.bc_g_next = g->bc[1 - g->bc_cur][0];
@@ -613,8 +618,14 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
     g->den = static_cast<double*>(upload(den));
     g->logt = static_cast<double*>(upload(logt));
     const size_t rb = g->real_bytes();
-    g->dslot = dalloc(2 * rb * g->nslot);
-    g->aslot = dalloc(rb * g->nslot);
+    g->nodes = dalloc(4 * rb * g->nslot);
+    {
+      // launch order: longest segments first (least tail, no lane waste)
+      std::vector<int32_t> ord(g->nseg);
+      for (int64_t k = 0; k < g->nseg; ++k) ord[k] = static_cast<int32_t>(k);
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return p.seg_n[x] > p.seg_n[y]; });
+      g->order = static_cast<int32_t*>(upload(ord));
+    }
     g->gbuf = dalloc(2 * rb * g->nslot * p.n_poles);
     g->node_out = static_cast<double*>(dalloc(4 * sizeof(double) * g->nslot));
     for (int a = 0; a < 2; ++a)
@@ -853,8 +864,7 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     const int blk_all = 512;  // energies of one boundary-only launch (64 lanes x 8)
     int cur = 0;
     qc::SweepBufs b;
-    b.dslot = g->dslot;
-    b.aslot = g->aslot;
+    b.nodes = g->nodes;
     b.gbuf = nullptr;
     b.ebuf = nullptr;
     for (int it = 0; it < bc_iters; ++it) {
@@ -951,6 +961,15 @@ qc_status qc_set_state(qc_grain* g, const void* state, size_t bytes, void* strea
     g->bc_valid = 1;
     return QC_OK;
   });
+}
+
+qc_status qc_grain_set_lanes(qc_grain* g, int energies_per_lane) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (energies_per_lane != 0 && energies_per_lane != 1 && energies_per_lane != 2 && energies_per_lane != 4 &&
+      energies_per_lane != 8)
+    return fail(QC_ERR_INVALID, "energies_per_lane must be 0 (auto), 1, 2, 4 or 8");
+  g->epl_override = energies_per_lane;
+  return QC_OK;
 }
 
 qc_status qc_profile_enable(qc_grain* g, int enable) {

@@ -1,8 +1,10 @@
 // Device-side building blocks: complex arithmetic and the Riccati step.
 //
-// Everything here runs in either FP64 or FP32 (the mixed path).  The FP32
-// versions use the hardware square root and reciprocal (1 ulp); the FP64
-// versions use correctly rounded library sqrt and division.
+// Everything here runs in either FP64 or FP32 (the mixed path).  FP32 uses
+// the hardware square root, reciprocal square root and reciprocal (1 ulp).
+// FP64 refines the hardware reciprocal and reciprocal square root with two
+// Newton iterations each (quadratic convergence from the ~2^-23 hardware
+// approximation to full double precision).  All of it is branch-free.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,6 +14,12 @@ namespace qc {
 template <typename T>
 struct cpx {
   T x, y;
+};
+
+// node value slot: Delta(p_k, slot) and a(slot) = v_k . A(slot)
+template <typename T>
+struct __attribute__((aligned(4 * sizeof(T)))) node4 {
+  T dx, dy, a, pad;
 };
 
 template <typename T>
@@ -31,66 +39,128 @@ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return mk(s * a.x, s * a.y); }
-template <typename T>
-__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return mk(a.x, -a.y); }
-template <typename T>
-__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return mk(-a.y, a.x); }  // i * a
 
-__device__ __forceinline__ double dsqrt(double v) { return __builtin_sqrt(v); }
-__device__ __forceinline__ float dsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
-__device__ __forceinline__ double drcp(double v) { return 1.0 / v; }
 __device__ __forceinline__ double dabs(double v) { return __builtin_fabs(v); }
 __device__ __forceinline__ float dabs(float v) { return __builtin_fabsf(v); }
 __device__ __forceinline__ double dsign(double m, double s) { return __builtin_copysign(m, s); }
 __device__ __forceinline__ float dsign(float m, float s) { return __builtin_copysignf(m, s); }
-__device__ __forceinline__ float drcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double dmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float dmax(float a, float b) { return __builtin_fmaxf(a, b); }
 
-// a / b as a * conj(b) / |b|^2 (operands here are O(1): no scaling needed)
-template <typename T>
-__device__ __forceinline__ cpx<T> cdiv(cpx<T> a, cpx<T> b) {
-  const T r = drcp(b.x * b.x + b.y * b.y);
-  return mk((a.x * b.x + a.y * b.y) * r, (a.y * b.x - a.x * b.y) * r);
+// 1/x
+__device__ __forceinline__ float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double drcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, e, y);
 }
+// 1/sqrt(x), x > 0
+__device__ __forceinline__ float drsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double drsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = __builtin_fma(-h * y, y, 0.5);  // y <- y (3/2 - x y^2 / 2)
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-h * y, y, 0.5);
+  return __builtin_fma(y, e, y);
+}
+// sqrt(x), x >= 0
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return x * drsq(dmax(x, 1e-300)); }
+template <typename T>
+__device__ __forceinline__ T tiny();
+template <>
+__device__ __forceinline__ float tiny<float>() { return 1e-30f; }
+template <>
+__device__ __forceinline__ double tiny<double>() { return 1e-300; }
 
-// Principal square root (branch cut on the negative real axis, the sign of
-// a zero imaginary part picks the side): sqrt((|w|+|x|)/2) formula.
+// Principal square root (branch cut on the negative real axis; the sign of
+// a zero imaginary part picks the side), from u = (|w| + |x|)/2:
+// sqrt(w) = (sqrt u, y / (2 sqrt u)) for x >= 0, else (|y| / (2 sqrt u), +-sqrt u).
 template <typename T>
 __device__ __forceinline__ cpx<T> csqrt(cpx<T> w) {
   const T r = dsqrt(w.x * w.x + w.y * w.y);
-  if (r == T(0)) return mk(T(0), T(0));
-  const T t = dsqrt(T(0.5) * (r + dabs(w.x)));
-  const T q = T(0.5) * drcp(t);
-  if (w.x >= T(0)) return mk(t, w.y * q);
-  return mk(dabs(w.y) * q, dsign(t, w.y));
+  const T u = T(0.5) * (r + dabs(w.x));
+  const T rs = drsq(dmax(u, tiny<T>()));
+  const T t = u * rs;
+  const T yq = T(0.5) * w.y * rs;
+  const bool pos = w.x >= T(0);
+  return mk(pos ? t : dabs(yq), pos ? yq : dsign(t, w.y));
 }
 
-// One implicit-midpoint step of d gamma/ds = i[D* g^2 + 2 z g + D]
-// (App. C, v_F = 1) in the closed form g' = 2 c0 / (-c1 + sqrt(c1^2 - 4 c2 c0));
-// the root is flipped if it points away from -c1, so g' -> g as h -> 0.
+// Per-node constants of one implicit-midpoint step (App. C) for the half-step
+// order parameter dm and step length hs: c2 = (i hs/4) conj(dm) and 4 c2.
 template <typename T>
-__device__ __forceinline__ cpx<T> riccati_step(cpx<T> g, cpx<T> dm, cpx<T> zm, T hstep) {
-  const T hq = T(0.25) * hstep;
-  const cpx<T> c2 = mk(hq * dm.y, hq * dm.x);  // (i h/4) conj(dm)
-  const cpx<T> c2g = c2 * g;
-  const cpx<T> ihz = mk(-hstep * zm.y, hstep * zm.x);
-  const cpx<T> c1 = mk(T(2) * c2g.x + ihz.x - T(1), T(2) * c2g.y + ihz.y);
-  const cpx<T> c0 = mk(c1.x - c2g.x + T(2), c1.y - c2g.y) * g - mk(T(4) * c2.x, T(-4) * c2.y);
-  const cpx<T> c1s = c1 * c1;
-  const cpx<T> c20 = c2 * c0;
-  cpx<T> rt = csqrt(mk(c1s.x - T(4) * c20.x, c1s.y - T(4) * c20.y));
-  if (rt.x * c1.x + rt.y * c1.y > T(0)) rt = mk(-rt.x, -rt.y);  // Re(rt conj(-c1)) < 0
-  return cdiv(mk(T(2) * c0.x, T(2) * c0.y), rt - c1);
+struct StepNode {
+  T c2x, c2y, c4x, c4y, hs;
+};
+template <typename T>
+__device__ __forceinline__ StepNode<T> step_node(T dmx, T dmy, T hs) {
+  StepNode<T> s;
+  const T hq = T(0.25) * hs;
+  s.c2x = hq * dmy;
+  s.c2y = hq * dmx;
+  s.c4x = T(4) * s.c2x;
+  s.c4y = T(4) * s.c2y;
+  s.hs = hs;
+  return s;
+}
+
+// One implicit-midpoint step of d gamma/ds = i[D* g^2 + 2 z g + D] (App. C,
+// v_F = 1) with z = (zx, zy): g' = 2 c0 / (-c1 + sqrt(c1^2 - 4 c2 c0)) with
+// c1 = 2 c2 g + i h z - 1 and c0 = (c1 - c2 g + 2) g - 4 conj(c2); the root is
+// flipped if it points away from -c1, so that g' -> g as h -> 0.
+template <typename T>
+__device__ __forceinline__ cpx<T> riccati_step(cpx<T> g, const StepNode<T>& s, T zx, T zy) {
+  const T cgx = s.c2x * g.x - s.c2y * g.y;  // c2 g
+  const T cgy = s.c2x * g.y + s.c2y * g.x;
+  const T kx = -s.hs * zy - T(1);            // i h z - 1
+  const T ky = s.hs * zx;
+  const T c1x = T(2) * cgx + kx, c1y = T(2) * cgy + ky;
+  const T px = cgx + kx + T(2), py = cgy + ky;  // c1 - c2 g + 2
+  const T c0x = px * g.x - py * g.y - s.c4x;
+  const T c0y = px * g.y + py * g.x + s.c4y;
+  const T dx = c1x * c1x - c1y * c1y - (s.c4x * c0x - s.c4y * c0y);
+  const T dy = T(2) * c1x * c1y - (s.c4x * c0y + s.c4y * c0x);
+  cpx<T> rt = csqrt(mk(dx, dy));
+  const bool flip = rt.x * c1x + rt.y * c1y > T(0);  // Re(rt conj(-c1)) < 0
+  rt = mk(flip ? -rt.x : rt.x, flip ? -rt.y : rt.y);
+  const T ex = rt.x - c1x, ey = rt.y - c1y;
+  const T rn = T(2) * drcp(ex * ex + ey * ey);
+  return mk((c0x * ex + c0y * ey) * rn, (c0y * ex - c0x * ey) * rn);
 }
 
 // Stable homogeneous root of D* g^2 + 2 z g + D = 0: -D / (z + s) with
-// s = sqrt(z^2 - |D|^2), Im s > 0.
+// s = sqrt(z^2 - |D|^2) on the branch Im s > 0.
 template <typename T>
-__device__ __forceinline__ cpx<T> bulk_root(cpx<T> z, cpx<T> d) {
-  const cpx<T> z2 = z * z;
-  cpx<T> s = csqrt(mk(z2.x - (d.x * d.x + d.y * d.y), z2.y));
-  if (s.y < T(0)) s = mk(-s.x, -s.y);
-  const cpx<T> num = mk(-d.x, -d.y);
-  return cdiv(num, z + s);
+__device__ __forceinline__ cpx<T> bulk_root(T zx, T zy, T dx, T dy) {
+  cpx<T> s = csqrt(mk(zx * zx - zy * zy - (dx * dx + dy * dy), T(2) * zx * zy));
+  const bool neg = s.y < T(0);
+  const T sx = neg ? -s.x : s.x, sy = neg ? -s.y : s.y;
+  const T bx = zx + sx, by = zy + sy;
+  const T r = drcp(bx * bx + by * by);
+  return mk(-(dx * bx + dy * by) * r, -(dy * bx - dx * by) * r);
+}
+
+// Sum of v over aligned groups of G lanes (G a power of two <= 64); every
+// lane of the group ends with the total.  DPP within rows of 16 lanes,
+// cross-lane permutes beyond.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double group_sum(double v, int G) {
+  if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+  if (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+  if (G >= 32) v += __shfl_xor(v, 16);
+  if (G >= 64) v += __shfl_xor(v, 32);
+  return v;
 }
 
 }  // namespace qc

@@ -20,8 +20,7 @@ namespace qc {
 // interpolation pre-pass
 // --------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, cpx<T>* __restrict__ dslot,
-                                                     T* __restrict__ aslot) {
+__global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, node4<T>* __restrict__ nodes) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= a.nslot) return;
   const int k = a.slot_angle[s];
@@ -47,178 +46,188 @@ __global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, cpx<T>* __res
     ax += a.A[idx] * w;
     ay += a.A[a.ncell + idx] * w;
   }
-  dslot[s] = mk(static_cast<T>(dx), static_cast<T>(dy));
-  aslot[s] = static_cast<T>(a.cosk[k] * ax + a.sink[k] * ay + a.aext[s]);
+  node4<T> v;
+  v.dx = static_cast<T>(dx);
+  v.dy = static_cast<T>(dy);
+  v.a = static_cast<T>(a.cosk[k] * ax + a.sink[k] * ay + a.aext[s]);
+  v.pad = T(0);
+  nodes[s] = v;
 }
 
 // --------------------------------------------------------------------------
 // Riccati sweep
+//
+// Lane group of G lanes per segment, EPL consecutive energies per lane
+// (energy e = lane * EPL + i).  Step t (t = 0..n) joins value slot t-1 and t;
+// a boundary point takes the value of the nearest slot (App. C), so the
+// half-step value is the mean of the two slot values with V(-1) = V(0) and
+// V(n) = V(n-1).  gamma runs t = 0..n, gamma~ t = n..0 with D -> -D*.
+//
+// Per node and pole (Sec. II.A): X = gamma gamma~, g = -i pi (1-X)/(1+X),
+// f = -2 i pi gamma/(1+X), f~ = 2 i pi gamma~/(1+X).  The pole sums use
+//   f + conj f~ = -2 i pi (gamma/(1+X) + conj(gamma~/(1+X))),
+//   Re g = pi Im((1-X)/(1+X)),
+//   (D* f + D f~) / (pi + i g) = i (D gamma~ - D* gamma)  since
+//   pi + i g = 2 pi / (1+X),
+// so the Eilenberger free-energy term needs no division.
 // --------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void step_values(const cpx<T>* __restrict__ dslot, const T* __restrict__ aslot,
-                                            int64_t slot0, int n, int t, double hfirst, double hlast,
-                                            double hfull, cpx<T>& dm, T& am, T& hs) {
-  // half-step values (App. C): mean of the two end values, a boundary point
-  // taking the value of the nearest slot
-  if (t == 0) {
-    dm = dslot[slot0];
-    am = aslot[slot0];
-    hs = static_cast<T>(hfirst);
-  } else if (t == n) {
-    dm = dslot[slot0 + n - 1];
-    am = aslot[slot0 + n - 1];
-    hs = static_cast<T>(hlast);
-  } else {
-    const cpx<T> d0 = dslot[slot0 + t - 1], d1 = dslot[slot0 + t];
-    dm = mk(T(0.5) * (d0.x + d1.x), T(0.5) * (d0.y + d1.y));
-    am = T(0.5) * (aslot[slot0 + t - 1] + aslot[slot0 + t]);
-    hs = static_cast<T>(hfull);
-  }
-}
-
 template <typename T, int EPL, int MODE>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const cpx<T>* __restrict__ dslot,
-                                                    const T* __restrict__ aslot,
+__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
                                                     const cpx<T>* __restrict__ bc_g_prev,
                                                     const cpx<T>* __restrict__ bc_gt_prev,
                                                     cpx<T>* __restrict__ bc_g_next,
                                                     cpx<T>* __restrict__ bc_gt_next,
                                                     cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
   const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t seg = gtid >> a.log2g;
+  const int64_t wseg = gtid >> a.log2g;
   const int lane = static_cast<int>(gtid & (a.G - 1));
-  if (seg >= a.nseg) return;  // whole lane groups leave together (G | 64)
+  if (wseg >= a.nseg) return;  // whole lane groups leave together (G | 64)
+  const int64_t seg = a.order ? static_cast<int64_t>(a.order[wseg]) : wseg;
   const int64_t slot0 = a.seg_slot0[seg];
   const int n = a.seg_n[seg];
-  const int nsl = n > 0 ? n : 1;
-  const double hfirst = a.seg_hfirst[seg], hlast = a.seg_hlast[seg];
+  const int last = n > 0 ? n - 1 : 0;
+  const T hfirst = static_cast<T>(a.seg_hfirst[seg]), hlast = static_cast<T>(a.seg_hlast[seg]);
+  const T hfull = static_cast<T>(a.h);
   const T q = static_cast<T>(a.q);
+  const int e0 = lane * EPL;
 
-  int e[EPL];
-  bool ok[EPL];
-  cpx<T> eps[EPL];
+  T ex[EPL], ey[EPL];
+  double rw[EPL];
   for (int i = 0; i < EPL; ++i) {
-    const int ee = lane + a.G * i;
-    ok[i] = ee < a.n_e;
-    e[i] = ok[i] ? ee : a.n_e - 1;
-    eps[i] = mk(static_cast<T>(a.eps[2 * (a.e_off + e[i])]), static_cast<T>(a.eps[2 * (a.e_off + e[i]) + 1]));
+    const int e = e0 + i < a.n_e ? e0 + i : a.n_e - 1;
+    ex[i] = static_cast<T>(a.eps[2 * (a.e_off + e)]);
+    ey[i] = static_cast<T>(a.eps[2 * (a.e_off + e) + 1]);
+    rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + e] : 0.0;
   }
+  const bool full = e0 + EPL <= a.n_e;
 
   // ---- gamma: R_min -> R_max
   cpx<T> g[EPL];
+  node4<T> prev = nodes[slot0];
   {
-    const cpx<T> d0 = dslot[slot0];
-    const T a0 = aslot[slot0];
-    const bool taps = a.bc_valid && a.tap_start_w[seg * 4] + a.tap_start_w[seg * 4 + 1] +
-                                            a.tap_start_w[seg * 4 + 2] + a.tap_start_w[seg * 4 + 3] > 0.0;
-    for (int i = 0; i < EPL; ++i) {
-      if (taps) {
-        cpx<T> acc = mk(T(0), T(0));
-        for (int c = 0; c < 4; ++c) {
-          const T w = static_cast<T>(a.tap_start_w[seg * 4 + c]);
-          const cpx<T> v = bc_g_prev[static_cast<int64_t>(a.tap_start_seg[seg * 4 + c]) * a.n_e_tot + a.e_off + e[i]];
-          acc = acc + w * v;
+    const int64_t tb = seg * 4;
+    const double wsum = a.tap_start_w[tb] + a.tap_start_w[tb + 1] + a.tap_start_w[tb + 2] + a.tap_start_w[tb + 3];
+    if (a.bc_valid && wsum > 0.0) {
+      for (int i = 0; i < EPL; ++i) g[i] = mk(T(0), T(0));
+      for (int c = 0; c < 4; ++c) {
+        const T w = static_cast<T>(a.tap_start_w[tb + c]);
+        const cpx<T>* src = bc_g_prev + static_cast<int64_t>(a.tap_start_seg[tb + c]) * a.n_e_tot + a.e_off;
+        for (int i = 0; i < EPL; ++i) {
+          const cpx<T> v = src[e0 + i < a.n_e ? e0 + i : a.n_e - 1];
+          g[i] = mk(g[i].x + w * v.x, g[i].y + w * v.y);
         }
-        g[i] = acc;
-      } else {
-        g[i] = bulk_root(mk(eps[i].x + q * a0, eps[i].y), d0);
       }
+    } else {
+      const T qa = q * prev.a;
+      for (int i = 0; i < EPL; ++i) g[i] = bulk_root(qa + ex[i], ey[i], prev.dx, prev.dy);
     }
   }
   for (int t = 0; t <= n; ++t) {
-    cpx<T> dm;
-    T am, hs;
-    step_values(dslot, aslot, slot0, n, t, hfirst, hlast, a.h, dm, am, hs);
-    for (int i = 0; i < EPL; ++i) g[i] = riccati_step(g[i], dm, mk(eps[i].x + q * am, eps[i].y), hs);
+    const node4<T> cur = nodes[slot0 + (t < last ? t : last)];
+    const T hs = t == 0 ? hfirst : (t == n ? hlast : hfull);
+    const StepNode<T> sn = step_node(T(0.5) * (prev.dx + cur.dx), T(0.5) * (prev.dy + cur.dy), hs);
+    const T qam = q * (T(0.5) * (prev.a + cur.a));
+    for (int i = 0; i < EPL; ++i) g[i] = riccati_step(g[i], sn, qam + ex[i], ey[i]);
+    prev = cur;
     if (MODE != 2 && t < n) {
-      for (int i = 0; i < EPL; ++i)
-        if (ok[i]) gbuf[(slot0 + t) * a.n_e + e[i]] = g[i];
+      cpx<T>* dst = gbuf + (slot0 + t) * a.n_e + e0;
+      if (full) {
+        for (int i = 0; i < EPL; ++i) dst[i] = g[i];
+      } else {
+        for (int i = 0; i < EPL; ++i)
+          if (e0 + i < a.n_e) dst[i] = g[i];
+      }
     }
   }
   if (MODE != 1) {
+    cpx<T>* dst = bc_g_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
-      if (ok[i]) bc_g_next[seg * a.n_e_tot + a.e_off + e[i]] = g[i];
+      if (e0 + i < a.n_e) dst[i] = g[i];
   }
 
-  // ---- gamma~: R_max -> R_min with D -> -D*, Green's functions at nodes
+  // ---- gamma~: R_max -> R_min with D -> -D*
   cpx<T> gt[EPL];
+  prev = nodes[slot0 + last];
   {
-    const cpx<T> d1 = dslot[slot0 + nsl - 1];
-    const T a1 = aslot[slot0 + nsl - 1];
-    const bool taps = a.bc_valid && a.tap_end_w[seg * 4] + a.tap_end_w[seg * 4 + 1] + a.tap_end_w[seg * 4 + 2] +
-                                            a.tap_end_w[seg * 4 + 3] > 0.0;
-    for (int i = 0; i < EPL; ++i) {
-      if (taps) {
-        cpx<T> acc = mk(T(0), T(0));
-        for (int c = 0; c < 4; ++c) {
-          const T w = static_cast<T>(a.tap_end_w[seg * 4 + c]);
-          const cpx<T> v = bc_gt_prev[static_cast<int64_t>(a.tap_end_seg[seg * 4 + c]) * a.n_e_tot + a.e_off + e[i]];
-          acc = acc + w * v;
+    const int64_t tb = seg * 4;
+    const double wsum = a.tap_end_w[tb] + a.tap_end_w[tb + 1] + a.tap_end_w[tb + 2] + a.tap_end_w[tb + 3];
+    if (a.bc_valid && wsum > 0.0) {
+      for (int i = 0; i < EPL; ++i) gt[i] = mk(T(0), T(0));
+      for (int c = 0; c < 4; ++c) {
+        const T w = static_cast<T>(a.tap_end_w[tb + c]);
+        const cpx<T>* src = bc_gt_prev + static_cast<int64_t>(a.tap_end_seg[tb + c]) * a.n_e_tot + a.e_off;
+        for (int i = 0; i < EPL; ++i) {
+          const cpx<T> v = src[e0 + i < a.n_e ? e0 + i : a.n_e - 1];
+          gt[i] = mk(gt[i].x + w * v.x, gt[i].y + w * v.y);
         }
-        gt[i] = acc;
-      } else {
-        gt[i] = bulk_root(mk(eps[i].x + q * a1, eps[i].y), mk(-d1.x, d1.y));  // D -> -D*
       }
+    } else {
+      const T qa = q * prev.a;
+      for (int i = 0; i < EPL; ++i) gt[i] = bulk_root(qa + ex[i], ey[i], -prev.dx, prev.dy);
     }
   }
-  const T pi = static_cast<T>(3.14159265358979323846);
   for (int t = n; t >= 0; --t) {
-    cpx<T> dm;
-    T am, hs;
-    step_values(dslot, aslot, slot0, n, t, hfirst, hlast, a.h, dm, am, hs);
-    const cpx<T> md = mk(-dm.x, dm.y);
-    for (int i = 0; i < EPL; ++i) gt[i] = riccati_step(gt[i], md, mk(eps[i].x + q * am, eps[i].y), hs);
+    const node4<T> cur = nodes[slot0 + (t >= 1 ? t - 1 : 0)];
+    const T hs = t == 0 ? hfirst : (t == n ? hlast : hfull);
+    const StepNode<T> sn = step_node(-T(0.5) * (prev.dx + cur.dx), T(0.5) * (prev.dy + cur.dy), hs);
+    const T qam = q * (T(0.5) * (prev.a + cur.a));
+    for (int i = 0; i < EPL; ++i) gt[i] = riccati_step(gt[i], sn, qam + ex[i], ey[i]);
+    prev = cur;
     if (MODE == 2 || t == 0) continue;
     const int64_t node = slot0 + t - 1;
+    const cpx<T>* src = gbuf + node * a.n_e + e0;
     if (MODE == 0) {
-      const cpx<T> dn = dslot[node];
-      double sfx = 0.0, sfy = 0.0, sg = 0.0, si = 0.0;
+      double sfx = 0.0, sfy = 0.0, sg = 0.0, s1 = 0.0, s2 = 0.0;
       for (int i = 0; i < EPL; ++i) {
-        const cpx<T> gg = gbuf[node * a.n_e + e[i]];
+        const cpx<T> gg = src[full ? i : (e0 + i < a.n_e ? i : 0)];
         const cpx<T> x = gg * gt[i];
-        const cpx<T> inv = cdiv(mk(T(1), T(0)), mk(T(1) + x.x, x.y));
-        const cpx<T> omx = mk(T(1) - x.x, -x.y) * inv;
-        const cpx<T> gr = mk(pi * omx.y, -pi * omx.x);  // -i pi (1-X)/(1+X)
-        const cpx<T> gi = gg * inv, gti = gt[i] * inv;
-        const cpx<T> f = mk(T(2) * pi * gi.y, T(-2) * pi * gi.x);     // -2 i pi gamma/(1+X)
-        const cpx<T> ft = mk(T(-2) * pi * gti.y, T(2) * pi * gti.x);  // 2 i pi gamma~/(1+X)
-        const cpx<T> num = conj(dn) * f + dn * ft;
-        const cpx<T> den = mk(pi - gr.y, gr.x);                       // pi + i g
-        const cpx<T> rat = cdiv(num, den);
-        const double r = ok[i] ? a.rp[a.e_off + e[i]] : 0.0;
-        sfx += r * (static_cast<double>(f.x) + static_cast<double>(ft.x));
-        sfy += r * (static_cast<double>(f.y) - static_cast<double>(ft.y));
-        sg += r * static_cast<double>(gr.x);
-        si += r * static_cast<double>(rat.x);
+        const T dxr = T(1) + x.x;
+        const T ri = drcp(dxr * dxr + x.y * x.y);
+        const cpx<T> inv = mk(dxr * ri, -x.y * ri);
+        const cpx<T> u = gg * inv;      // gamma / (1+X)
+        const cpx<T> v = gt[i] * inv;   // gamma~ / (1+X)
+        const T img = inv.y - (gg.x * v.y + gg.y * v.x);  // Im((1-X)/(1+X))
+        const double r = rw[i];
+        sfx += r * static_cast<double>(u.x + v.x);
+        sfy += r * static_cast<double>(u.y - v.y);
+        sg += r * static_cast<double>(img);
+        s1 += r * static_cast<double>(gg.y - gt[i].y);
+        s2 += r * static_cast<double>(gg.x + gt[i].x);
       }
-      for (int off = a.G >> 1; off > 0; off >>= 1) {
-        sfx += __shfl_xor(sfx, off, a.G);
-        sfy += __shfl_xor(sfy, off, a.G);
-        sg += __shfl_xor(sg, off, a.G);
-        si += __shfl_xor(si, off, a.G);
-      }
+      // Im(D* gamma - D gamma~) summed over the lane's poles
+      double si = static_cast<double>(cur.dx) * s1 - static_cast<double>(cur.dy) * s2;
+      sfx = group_sum(sfx, a.G);
+      sfy = group_sum(sfy, a.G);
+      sg = group_sum(sg, a.G);
+      si = group_sum(si, a.G);
       if (lane == 0) {
-        double* o = a.node_out + node * 4;
-        o[0] = a.tt * sfx;
-        o[1] = a.tt * sfy;
-        o[2] = a.tt * sg;
-        o[3] = a.twopi_tt * si;
+        // S_f = t~ sum R (f + conj f~) = -2 i pi t~ (sfx + i sfy), S_g = pi t~ sg,
+        // S_I = 2 pi t~ sum R Re[i (D gamma~ - D* gamma)] = 2 pi t~ si
+        double4 o;
+        o.x = a.twopi_tt * sfy;
+        o.y = -a.twopi_tt * sfx;
+        o.z = 0.5 * a.twopi_tt * sg;
+        o.w = a.twopi_tt * si;
+        reinterpret_cast<double4*>(a.node_out)[node] = o;
       }
-    } else {  // MODE 1: -Im g / pi per energy
+    } else {  // MODE 1: N/N_F = -Im g / pi = Re((1-X)/(1+X)) per energy
+      T* dst = ebuf + node * a.n_e + e0;
       for (int i = 0; i < EPL; ++i) {
-        if (!ok[i]) continue;
-        const cpx<T> gg = gbuf[node * a.n_e + e[i]];
+        if (e0 + i >= a.n_e) continue;
+        const cpx<T> gg = src[i];
         const cpx<T> x = gg * gt[i];
-        const cpx<T> inv = cdiv(mk(T(1), T(0)), mk(T(1) + x.x, x.y));
-        const cpx<T> omx = mk(T(1) - x.x, -x.y) * inv;
-        // Im g = Im(-i pi (1-X)/(1+X)) = -pi Re((1-X)/(1+X))
-        ebuf[node * a.n_e + e[i]] = omx.x;
+        const T dxr = T(1) + x.x;
+        const T ri = drcp(dxr * dxr + x.y * x.y);
+        const cpx<T> inv = mk(dxr * ri, -x.y * ri);
+        const cpx<T> v = gt[i] * inv;
+        dst[i] = inv.x - (gg.x * v.x - gg.y * v.y);
       }
     }
   }
   if (MODE != 1) {
+    cpx<T>* dst = bc_gt_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
-      if (ok[i]) bc_gt_next[seg * a.n_e_tot + a.e_off + e[i]] = gt[i];
+      if (e0 + i < a.n_e) dst[i] = gt[i];
   }
 }
 
@@ -294,7 +303,6 @@ __global__ void __launch_bounds__(256) ldos_back_kernel(LdosBackArgs a, const T*
     }
     acc += a.wk[k] * v;
   }
-  // N/N_F = -Im g / pi = Re((1-X)/(1+X))
   a.out[static_cast<int64_t>(a.e_off + e) * a.ncell + a.grain_cells[c]] = acc;
 }
 
@@ -502,19 +510,18 @@ __global__ void __launch_bounds__(256) unpad_A_kernel(const double2* __restrict_
 static inline unsigned nblk(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
 
 template <typename T>
-void launch_interp(const InterpArgs& a, void* dslot, void* aslot, hipStream_t st) {
+void launch_interp(const InterpArgs& a, void* nodes, hipStream_t st) {
   if (a.nslot == 0) return;
-  hipLaunchKernelGGL(interp_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a,
-                     static_cast<cpx<T>*>(dslot), static_cast<T*>(aslot));
+  hipLaunchKernelGGL(interp_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a, static_cast<node4<T>*>(nodes));
 }
-template void launch_interp<double>(const InterpArgs&, void*, void*, hipStream_t);
-template void launch_interp<float>(const InterpArgs&, void*, void*, hipStream_t);
+template void launch_interp<double>(const InterpArgs&, void*, hipStream_t);
+template void launch_interp<float>(const InterpArgs&, void*, hipStream_t);
 
 template <typename T, int EPL, int MODE>
 static void launch_sweep_t(const SweepArgs& a, const SweepBufs& b, hipStream_t st) {
   const int64_t threads = a.nseg * a.G;
   hipLaunchKernelGGL((sweep_kernel<T, EPL, MODE>), dim3(nblk(threads)), dim3(256), 0, st, a,
-                     static_cast<const cpx<T>*>(b.dslot), static_cast<const T*>(b.aslot),
+                     static_cast<const node4<T>*>(b.nodes),
                      static_cast<const cpx<T>*>(b.bc_g_prev), static_cast<const cpx<T>*>(b.bc_gt_prev),
                      static_cast<cpx<T>*>(b.bc_g_next), static_cast<cpx<T>*>(b.bc_gt_next),
                      static_cast<cpx<T>*>(b.gbuf), static_cast<T*>(b.ebuf));

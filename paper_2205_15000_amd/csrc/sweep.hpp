@@ -26,12 +26,13 @@ struct InterpArgs {
 
 struct SweepArgs {
   int64_t nseg;
+  const int32_t* order;   // launch order of the segments (longest first) or nullptr
   int G, log2g;           // lanes per segment (power of two dividing 64)
   int n_e;                // energies in this launch (stride of gbuf / ebuf)
   int n_e_tot;            // stride of the boundary stores
   int e_off;              // first energy of this launch
   int bc_valid;           // 0: start at the bulk roots
-  double h, q, tt, twopi_tt;
+  double h, q, twopi_tt;
   const int64_t* seg_slot0;
   const int32_t* seg_n;
   const double* seg_hfirst;
@@ -42,12 +43,11 @@ struct SweepArgs {
   const double* tap_end_w;
   const double* eps;      // complex energies [n_e_tot]: i eps~_p or e + i delta
   const double* rp;       // pole weights [n_e_tot]
-  double* node_out;       // mode 0: [nslot][4] = t~ sum R f+conj f~ (re, im), t~ sum R Re g, 2 pi t~ sum R Re(..)
+  double* node_out;       // mode 0: [nslot][4] = S_f (re, im), S_g, S_I per node
 };
 
 struct SweepBufs {
-  const void* dslot;
-  const void* aslot;
+  const void* nodes;      // node4<T> [nslot]
   const void* bc_g_prev;
   const void* bc_gt_prev;
   void* bc_g_next;
@@ -102,7 +102,7 @@ struct DiffNormArgs {
 };
 
 template <typename T>
-void launch_interp(const InterpArgs& a, void* dslot, void* aslot, hipStream_t st);
+void launch_interp(const InterpArgs& a, void* nodes, hipStream_t st);
 template <typename T>
 void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
