@@ -248,6 +248,7 @@ struct qc_grain {
   int bc_cur = 0;
   int bc_valid = 0;
   double* omega_cell = nullptr;
+  double* dmean = nullptr;
   double* part = nullptr;
   double* part_host = nullptr;
   double* bbuf = nullptr;
@@ -273,6 +274,8 @@ struct qc_grain {
 };
 
 static constexpr int kParts = 256;
+// regions of the block-partial buffer (kParts doubles each, diffs 2 kParts)
+enum { kROmega = 0, kRB2 = 1, kRJx = 2, kRJy = 3, kRDiffD = 4, kRDiffJ = 6, kRDiffA = 8, kRegions = 10 };
 
 namespace {
 
@@ -281,7 +284,7 @@ void free_grain(qc_grain* g) {
                   g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->order, g->gbuf, g->node_out, g->bc[0][0],
-                  g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->part, g->bbuf, g->fw, g->fw2,
+                  g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -295,12 +298,19 @@ void free_grain(qc_grain* g) {
 
 hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
-// Host sum of the first n block partials (fixed order: deterministic).
-double host_sum(qc_grain* g, int n, hipStream_t st) {
-  hcheck(hipMemcpyAsync(g->part_host, g->part, sizeof(double) * n, hipMemcpyDeviceToHost, st), "D2H");
+double* region(qc_grain* g, int r) { return g->part + static_cast<int64_t>(r) * kParts; }
+
+// one copy of every block partial to the host, then wait for the stream
+void fetch_parts(qc_grain* g, hipStream_t st) {
+  hcheck(hipMemcpyAsync(g->part_host, g->part, sizeof(double) * kRegions * kParts, hipMemcpyDeviceToHost, st),
+         "D2H");
   hcheck(hipStreamSynchronize(st), "sync");
+}
+
+// host sum of one region (fixed order: deterministic)
+double region_sum(const qc_grain* g, int r) {
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += g->part_host[i];
+  for (int i = 0; i < kParts; ++i) s += g->part_host[static_cast<int64_t>(r) * kParts + i];
   return s;
 }
 
@@ -394,7 +404,13 @@ void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc:
   }
 }
 
-// steps 3-8 of one iteration; omega_total (host) optional
+double omega_from_parts(const qc_grain* g) {
+  double tot = g->h * g->h * region_sum(g, kROmega);
+  if (g->kappa > 0.0) tot += g->h * g->h * 0.5 * g->kappa * g->kappa * region_sum(g, kRB2);
+  return tot;
+}
+
+// steps 3-8 of one iteration; omega_total (host) optional (synchronises)
 void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_new, double* j, double* omega,
               double* omega_total, hipStream_t st) {
   do_interp(g, delta, A, st);
@@ -439,15 +455,15 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   r.omega_cell = g->omega_cell;
   qc::launch_rotate_back(r, st);
   hcheck(hipGetLastError(), "rotate-back launch");
+  // block partials of the free energy (condensation and magnetic parts)
+  qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, region(g, kROmega), kParts, st);
+  if (g->kappa > 0.0) {
+    qc::launch_curl(A, g->bbuf, g->nx, g->ny, g->h, st);
+    qc::launch_block_sum(g->bbuf, nullptr, g->ncell, 1, region(g, kRB2), kParts, st);
+  }
   if (omega_total) {
-    qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, g->part, kParts, st);
-    double tot = g->h * g->h * host_sum(g, kParts, st);
-    if (g->kappa > 0.0) {
-      qc::launch_curl(A, g->bbuf, g->nx, g->ny, g->h, st);
-      qc::launch_block_sum(g->bbuf, nullptr, g->ncell, 1, g->part, kParts, st);
-      tot += g->h * g->h * 0.5 * g->kappa * g->kappa * host_sum(g, kParts, st);
-    }
-    *omega_total = tot;
+    fetch_parts(g, st);
+    *omega_total = omega_from_parts(g);
   }
 }
 
@@ -631,8 +647,10 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) g->bc[a][b] = dalloc(2 * rb * g->nseg * p.n_poles);
     g->omega_cell = static_cast<double*>(dalloc(sizeof(double) * g->ncg));
-    g->part = static_cast<double*>(dalloc(sizeof(double) * 2 * kParts));
-    hcheck(hipHostMalloc(reinterpret_cast<void**>(&g->part_host), sizeof(double) * 2 * kParts), "hipHostMalloc");
+    g->part = static_cast<double*>(dalloc(sizeof(double) * kRegions * kParts));
+    g->dmean = static_cast<double*>(dalloc(sizeof(double) * 2));
+    hcheck(hipHostMalloc(reinterpret_cast<void**>(&g->part_host), sizeof(double) * kRegions * kParts),
+           "hipHostMalloc");
     g->bbuf = static_cast<double*>(dalloc(sizeof(double) * g->ncell));
     g->dnew = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
     g->jcur = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
@@ -713,12 +731,10 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
     return;
   }
   // mean current over the grain cells, subtracted before the solve (App. D)
-  double mean[2];
-  for (int c = 0; c < 2; ++c) {
-    qc::launch_block_sum(j + c * g->ncell, g->grain_cells, g->ncg, 0, g->part, kParts, st);
-    mean[c] = host_sum(g, kParts, st) / static_cast<double>(g->ncg);
-  }
-  qc::launch_pad_current(j, g->mask, g->nx, g->ny, g->px, g->py, mean[0], mean[1], g->fw, st);
+  qc::launch_block_sum(j, g->grain_cells, g->ncg, 0, region(g, kRJx), kParts, st);
+  qc::launch_block_sum(j + g->ncell, g->grain_cells, g->ncg, 0, region(g, kRJy), kParts, st);
+  qc::launch_means(region(g, kRJx), kParts, 1.0 / static_cast<double>(g->ncg), g->dmean, st);
+  qc::launch_pad_current(j, g->mask, g->nx, g->ny, g->px, g->py, g->dmean, g->fw, st);
   fft_forward_2d(g, st, -1);
   qc::launch_cmul(g->fw2, g->ghat, static_cast<int64_t>(g->px) * g->py, st);
   fft_inverse_2d(g, st);
@@ -728,10 +744,10 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
   hcheck(hipGetLastError(), "A-solve launch");
 }
 
-// relative p-norm difference ||new - old|| / ||old|| over n elements of
+// block partials of the p-norms of (new - old) and old over n elements of
 // `stride` doubles, gathered through idx when given, for nrep fields
-double rel_diff(qc_grain* g, const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
-                int64_t field_stride, int stride, int p, hipStream_t st) {
+void enqueue_diff(qc_grain* g, const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
+                  int64_t field_stride, int stride, int p, int reg, hipStream_t st) {
   qc::DiffNormArgs a;
   a.xnew = xnew;
   a.xold = xold;
@@ -741,18 +757,21 @@ double rel_diff(qc_grain* g, const double* xnew, const double* xold, const int32
   a.field_stride = field_stride;
   a.stride = stride;
   a.p = p;
-  a.part = g->part;
+  a.part = region(g, reg);
   qc::launch_diff_norm(a, kParts, st);
-  hcheck(hipMemcpyAsync(g->part_host, g->part, sizeof(double) * 2 * kParts, hipMemcpyDeviceToHost, st), "D2H");
-  hcheck(hipStreamSynchronize(st), "sync");
+}
+
+// ||new - old||_p / ||old||_p from fetched partials (0/0 = 0, x/0 = inf)
+double rel_from_parts(const qc_grain* g, int reg, int p) {
+  const double* q = g->part_host + static_cast<int64_t>(reg) * kParts;
   double num = 0.0, den = 0.0;
   for (int i = 0; i < kParts; ++i) {
     if (p == 0) {
-      num = std::max(num, g->part_host[2 * i]);
-      den = std::max(den, g->part_host[2 * i + 1]);
+      num = std::max(num, q[2 * i]);
+      den = std::max(den, q[2 * i + 1]);
     } else {
-      num += g->part_host[2 * i];
-      den += g->part_host[2 * i + 1];
+      num += q[2 * i];
+      den += q[2 * i + 1];
     }
   }
   if (p == 2) {
@@ -801,27 +820,35 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
     int it = 0;
     bool conv = false;
     for (; it < max_iter; ++it) {
-      double om = 0.0;
-      do_sweep(g, delta_io, A_io, g->dnew, g->jcur, nullptr, &om, st);
-      double res[5] = {0.0, 0.0, 0.0, 0.0, om};
+      do_sweep(g, delta_io, A_io, g->dnew, g->jcur, nullptr, nullptr, st);
       if (it < burnin) {
         hcheck(hipMemcpyAsync(g->jold, g->jcur, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+        fetch_parts(g, st);
+        const double om = omega_from_parts(g);
+        const double res[5] = {0.0, 0.0, 0.0, 0.0, om};
         om_old = om;
         have_old = true;
         if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
         continue;
       }
       do_solve_A(g, g->jcur, g->anew, nullptr, st);
-      res[0] = alpha * rel_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, st);
-      res[1] = have_old ? rel_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, st) : INFINITY;
-      res[2] = alpha * rel_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, st);
-      res[3] = (have_old && om_old != 0.0) ? std::fabs(om - om_old) / std::fabs(om_old) : INFINITY;
-      if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
-      if (!std::isfinite(res[0]) || !std::isfinite(om) || (std::isnan(res[2])))
-        throw std::range_error("non-finite residual");
+      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st);
+      if (have_old) enqueue_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ, st);
+      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st);
       qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, alpha, st);
       qc::launch_picard(A_io, g->anew, nullptr, 2 * g->ncell, 1, 0, 1, alpha, st);
       hcheck(hipMemcpyAsync(g->jold, g->jcur, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+      fetch_parts(g, st);
+      const double om = omega_from_parts(g);
+      double res[5];
+      res[0] = alpha * rel_from_parts(g, kRDiffD, norm_p);
+      res[1] = have_old ? rel_from_parts(g, kRDiffJ, norm_p) : INFINITY;
+      res[2] = alpha * rel_from_parts(g, kRDiffA, norm_p);
+      res[3] = (have_old && om_old != 0.0) ? std::fabs(om - om_old) / std::fabs(om_old) : INFINITY;
+      res[4] = om;
+      if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
+      if (!std::isfinite(res[0]) || !std::isfinite(om) || std::isnan(res[2]))
+        throw std::range_error("non-finite residual (Delta and A hold the failed update)");
       om_old = om;
       have_old = true;
       if (it + 1 >= min_iter && res[0] < tol && res[1] < tol && res[2] < tol && res[3] < tol) {

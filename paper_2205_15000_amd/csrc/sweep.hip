@@ -428,16 +428,27 @@ __global__ void __launch_bounds__(256) picard_kernel(double* __restrict__ x, con
 // A-solve (App. D): zero-padded FFT correlation with the cell-averaged
 // Green's function of the 2D Laplacian
 // --------------------------------------------------------------------------
+// grain means of the two current components from block partials (fixed
+// summation order, the same as a host-side sum of the partials)
+__global__ void means_kernel(const double* __restrict__ part, int nparts, double inv_n, double* __restrict__ mean) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int c = 0; c < 2; ++c) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += part[c * nparts + i];
+    mean[c] = s * inv_n;
+  }
+}
+
 __global__ void __launch_bounds__(256) pad_current_kernel(const double* __restrict__ j, const uint8_t* __restrict__ mask,
-                                                          int nx, int ny, int px, int py, double mx, double my,
-                                                          double2* __restrict__ w) {
+                                                          int nx, int ny, int px, int py,
+                                                          const double* __restrict__ mean, double2* __restrict__ w) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<int64_t>(px) * py) return;
   const int x = static_cast<int>(t % px), y = static_cast<int>(t / px);
   double2 v = make_double2(0.0, 0.0);
   if (x < nx && y < ny) {
     const int64_t c = static_cast<int64_t>(y) * nx + x;
-    if (mask[c]) v = make_double2(j[c] - mx, j[static_cast<int64_t>(nx) * ny + c] - my);
+    if (mask[c]) v = make_double2(j[c] - mean[0], j[static_cast<int64_t>(nx) * ny + c] - mean[1]);
   }
   w[t] = v;
 }
@@ -582,10 +593,13 @@ void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, i
     hipLaunchKernelGGL(picard_kernel, dim3(nblk(n * nrep)), dim3(256), 0, st, x, gx, idx, n, nrep, field_stride,
                        stride, alpha);
 }
-void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, double mx, double my,
+void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st) {
+  hipLaunchKernelGGL(means_kernel, dim3(1), dim3(64), 0, st, part, nparts, inv_n, mean);
+}
+void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, const double* mean,
                         double2* w, hipStream_t st) {
   hipLaunchKernelGGL(pad_current_kernel, dim3(nblk(static_cast<int64_t>(px) * py)), dim3(256), 0, st, j, mask, nx,
-                     ny, px, py, mx, my, w);
+                     ny, px, py, mean, w);
 }
 void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, hipStream_t st) {
   hipLaunchKernelGGL(fft_rows_kernel, dim3(rows), dim3(256), sizeof(double2) << logn, st, w, logn, tw, sign);

@@ -115,7 +115,8 @@ void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, 
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st);
 void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, int nrep, int64_t field_stride,
                    int stride, double alpha, hipStream_t st);
-void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, double mx, double my,
+void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st);
+void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, const double* mean,
                         double2* w, hipStream_t st);
 void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, hipStream_t st);
 void launch_transpose(const double2* in, double2* out, int rows, int cols, hipStream_t st);
