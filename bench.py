@@ -32,6 +32,10 @@ FLOPS_PER_NODE_POLE = 82
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, FP64 and unpacked FP32
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per sweep launch (mixed) from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs scaled by a plain-copy calibration (profiles/sweep_kernel_d110_square_400.md);
+# None whenever the kernel changed after the counters were taken.
+SWEEP_TRAFFIC_BYTES = 11.40e9
 
 
 def parse():
@@ -127,8 +131,8 @@ def main():
                    "steps_per_iteration": steps_iter, "segments": info["n_segments"],
                    "nodes": info["n_nodes"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
-                     "kernel": "sweep_kernel<float,8,0>", "avg_launch_ms": avg_ms,
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": SWEEP_TRAFFIC_BYTES,
+                     "kernel": "sweep_kernel<float,2,0>", "avg_launch_ms": avg_ms,
                      "flops_per_launch": flops_launch,
                      "peak_fp32_packed_published": PEAK_FP32_PACKED_TFLOPS},
         "sweep_only_steps_per_s": steps_iter / (avg_ms * 1e-3),

@@ -239,6 +239,23 @@ qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,
                   const double* energies, int n_e, double broadening, int bc_iters,
                   double* ldos_out, void* stream);
 
+/* Reverse mode of the most recent qc_sweep on this grain (the map with the
+ * boundary store it read held fixed; start values that are bulk roots of
+ * the segment-end values are differentiated).  No qc_sweep may run in
+ * between.  QC_FP64 grains only.  For a real loss L with
+ *   g_delta_new = dL/dRe Delta_new + i dL/dIm Delta_new  (device complex
+ *                 [ncomp][ny][nx], NULL = 0),
+ *   g_j         = dL/dj  (device [2][ny][nx], NULL = 0),
+ *   g_omega     = dL/dOmega_total (host scalar),
+ * writes grad_delta = dL/dRe Delta + i dL/dIm Delta (device complex
+ * [ncomp][ny][nx]) and grad_A = dL/dA_ind (device [2][ny][nx]).
+ * Derivatives of the implicit-midpoint step (App. C) follow from implicit
+ * differentiation of its defining equation.  Scatter-adds use FP64 atomics
+ * (summation order varies at the 1e-16 level).  Memory: three complex
+ * values per (node, pole) on top of the forward buffers. */
+qc_status qc_sweep_adjoint(qc_grain* grain, const double* delta, const double* A_ind, const double* g_delta_new,
+                           const double* g_j, double g_omega, double* grad_delta, double* grad_A, void* stream);
+
 /* Boundary-value store of qc_sweep (resume without burn-in, App. B).
  * bytes: in/out host size_t; with state == NULL only the size is returned.
  * state: device buffer of that size. */

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Grain", "Plan", "QcError", "lib", "basis_table", "spec_desc", "PRECISIONS"]
+__all__ = ["Grain", "Plan", "QcError", "lib", "basis_table", "spec_desc", "PRECISIONS", "sweep_autograd"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqcsweep.so")
@@ -93,6 +93,7 @@ _sig("qc_solve_A", ctypes.c_int, [_P, _P, _P, _P, _P])
 _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int), _P, _P])
 _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
+_sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_set_state", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P])
 _sig("qc_profile_enable", ctypes.c_int, [_P, ctypes.c_int])
@@ -261,6 +262,50 @@ def _dptr(t, dtype, shape, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _sweep_function():
+    torch = _torch()
+
+    class SweepFn(torch.autograd.Function):
+        """(delta, A) -> (delta_new, j, omega_total) through qc_sweep, with the
+        hand-written adjoint sweep as backward.  The boundary store read by
+        the forward is held fixed; call backward before the next sweep on the
+        same grain."""
+
+        @staticmethod
+        def forward(ctx, delta, A, grain):
+            dn, j, om = grain.sweep(delta.detach().contiguous(), A.detach().contiguous())
+            ctx.grain = grain
+            ctx.count = grain._count
+            ctx.save_for_backward(delta.detach().contiguous(), A.detach().contiguous())
+            return dn, j, torch.tensor(om, dtype=torch.float64, device=delta.device)
+
+        @staticmethod
+        def backward(ctx, g_dn, g_j, g_om):
+            grain = ctx.grain
+            if grain._count != ctx.count:
+                raise RuntimeError("another sweep ran on this grain since the forward: backward needs its store")
+            delta, A = ctx.saved_tensors
+            gd, ga = grain.sweep_adjoint(
+                delta, A,
+                g_dn.contiguous() if g_dn is not None else None,
+                g_j.contiguous() if g_j is not None else None,
+                float(g_om) if g_om is not None else 0.0)
+            return gd, ga, None
+
+    return SweepFn
+
+
+_SWEEP_FN = None
+
+
+def sweep_autograd(grain, delta, A):
+    """Differentiable iteration map: returns (delta_new, j, omega_total)."""
+    global _SWEEP_FN
+    if _SWEEP_FN is None:
+        _SWEEP_FN = _sweep_function()
+    return _SWEEP_FN.apply(delta, A, grain)
+
+
 class Grain:
     """A grain resident on one GPU.  spec: grain description dict (see
     paper_2205_15000_amd.workloads); precision "fp64" or "mixed"."""
@@ -278,6 +323,7 @@ class Grain:
         inf = _Info()
         _check(lib.qc_grain_get_info(self._g, ctypes.byref(inf)))
         self.info = _info_dict(inf)
+        self._count = 0
 
     def close(self):
         if getattr(self, "_g", None):
@@ -310,6 +356,7 @@ class Grain:
             dn, j = out
         od = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self._dev()) if omega_density else None
         tot = ctypes.c_double(0.0)
+        self._count += 1
         _check(lib.qc_sweep(self._g, dp, ap, ctypes.c_void_p(dn.data_ptr()), ctypes.c_void_p(j.data_ptr()),
                             ctypes.c_void_p(od.data_ptr()) if od is not None else None,
                             ctypes.byref(tot) if total else None, _stream(stream)))
@@ -345,6 +392,21 @@ class Grain:
         _check(lib.qc_ldos(self._g, dp, ap, e.ctypes.data, len(e), float(broadening), int(bc_iters),
                            ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
+
+    def sweep_adjoint(self, delta, A, g_delta_new=None, g_j=None, g_omega=0.0, stream=None):
+        """Reverse mode of the most recent sweep: returns (grad_delta, grad_A)
+        for a real loss with the given output gradients."""
+        torch = _torch()
+        shp_d = (self.ncomp, self.ny, self.nx)
+        dp = _dptr(delta, torch.complex128, shp_d, "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        gdn = _dptr(g_delta_new, torch.complex128, shp_d, "g_delta_new") if g_delta_new is not None else None
+        gj = _dptr(g_j, torch.float64, (2, self.ny, self.nx), "g_j") if g_j is not None else None
+        gd = torch.empty(shp_d, dtype=torch.complex128, device=self._dev())
+        ga = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=self._dev())
+        _check(lib.qc_sweep_adjoint(self._g, dp, ap, gdn, gj, float(g_omega), ctypes.c_void_p(gd.data_ptr()),
+                                    ctypes.c_void_p(ga.data_ptr()), _stream(stream)))
+        return gd, ga
 
     def get_state(self, stream=None):
         torch = _torch()

@@ -247,6 +247,12 @@ struct qc_grain {
   void* bc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   int bc_cur = 0;
   int bc_valid = 0;
+  int last_bc_valid = -1;  // store validity seen by the latest sweep (-1: no sweep yet)
+  // reverse-mode buffers (allocated on first use)
+  void* gtbuf = nullptr;
+  void* lgt = nullptr;
+  double* gS = nullptr;
+  double* gV = nullptr;
   double* omega_cell = nullptr;
   double* dmean = nullptr;
   double* part = nullptr;
@@ -285,7 +291,7 @@ void free_grain(qc_grain* g) {
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
-                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew};
+                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
@@ -425,6 +431,7 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   b.gbuf = g->gbuf;
   b.ebuf = nullptr;
   launch_sweep_timed(g, 0, a, b, st);
+  g->last_bc_valid = g->bc_valid;
   g->bc_cur = 1 - g->bc_cur;
   g->bc_valid = 1;
 
@@ -986,6 +993,106 @@ qc_status qc_set_state(qc_grain* g, const void* state, size_t bytes, void* strea
                           S(stream)),
            "copy");
     g->bc_valid = 1;
+    return QC_OK;
+  });
+}
+
+qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind, const double* g_delta_new,
+                           const double* g_j, double g_omega, double* grad_delta, double* grad_A, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !grad_delta || !grad_A) return fail(QC_ERR_INVALID, "NULL argument");
+  if (g->precision != QC_FP64) return fail(QC_ERR_INVALID, "the adjoint sweep needs a QC_FP64 grain");
+  if (g->last_bc_valid < 0) return fail(QC_ERR_INVALID, "run qc_sweep first: the adjoint differentiates it");
+  if (!std::isfinite(g_omega)) return fail(QC_ERR_INVALID, "g_omega must be finite");
+  return guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    const size_t nb = sizeof(double) * 2 * g->nslot * g->n_poles;
+    if (!g->gtbuf) g->gtbuf = dalloc(nb);
+    if (!g->lgt) g->lgt = dalloc(nb);
+    if (!g->gS) g->gS = static_cast<double*>(dalloc(sizeof(double) * 4 * g->nslot));
+    if (!g->gV) g->gV = static_cast<double*>(dalloc(sizeof(double) * 3 * g->nslot));
+    do_interp(g, delta, A_ind, st);
+    // gradients of the per-node sums
+    qc::launch_fill(g->gS, 4 * g->nslot, 0.0, st);
+    qc::BackAdjArgs ba;
+    ba.ncg = g->ncg;
+    ba.ncell = g->ncell;
+    ba.ncomp = g->ncomp;
+    ba.n_theta = g->n_theta;
+    ba.grain_cells = g->grain_cells;
+    ba.rb_idx = g->rb_idx;
+    ba.rb_w = g->rb_w;
+    ba.wk = g->wk;
+    ba.cosk = g->cosk;
+    ba.sink = g->sink;
+    ba.eta = g->eta;
+    ba.den = g->den;
+    ba.four_q = 4.0 * g->q;
+    ba.h2 = g->h * g->h;
+    ba.gomega = g_omega;
+    ba.gdn = g_delta_new;
+    ba.gj = g_j;
+    ba.gS = g->gS;
+    qc::launch_back_adjoint(ba, st);
+    // reverse sweep with the store the latest sweep read
+    qc::AdjArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
+    a.bc_valid = g->last_bc_valid;
+    int G, epl;
+    lane_shape(g->n_poles, g->epl_override, G, epl);
+    qc::AdjBufs b;
+    b.nodes = g->nodes;
+    b.bc_g_prev = g->bc[1 - g->bc_cur][0];
+    b.bc_gt_prev = g->bc[1 - g->bc_cur][1];
+    b.gbuf = g->gbuf;
+    b.gtbuf = g->gtbuf;
+    b.lgt = g->lgt;
+    b.gS = g->gS;
+    b.gV = g->gV;
+    qc::launch_adjoint(epl, a, b, st);
+    hcheck(hipGetLastError(), "adjoint launch");
+    // back to the reference grid
+    qc::launch_fill(grad_delta, 2 * g->ncomp * g->ncell, 0.0, st);
+    qc::launch_fill(grad_A, 2 * g->ncell, 0.0, st);
+    qc::InterpAdjArgs ia;
+    ia.nslot = g->nslot;
+    ia.ncell = g->ncell;
+    ia.ncomp = g->ncomp;
+    ia.n_theta = g->n_theta;
+    ia.slot_angle = g->slot_angle;
+    ia.dst_idx = g->dst_idx;
+    ia.dst_w = g->dst_w;
+    ia.ast_idx = g->ast_idx;
+    ia.ast_w = g->ast_w;
+    ia.eta = g->eta;
+    ia.cosk = g->cosk;
+    ia.sink = g->sink;
+    ia.gV = g->gV;
+    ia.gdelta = grad_delta;
+    ia.gA = grad_A;
+    qc::launch_interp_adjoint(ia, st);
+    if (g_omega != 0.0) {
+      qc::OmegaAdjArgs oa;
+      oa.ncg = g->ncg;
+      oa.ncell = g->ncell;
+      oa.ncomp = g->ncomp;
+      oa.n_theta = g->n_theta;
+      oa.grain_cells = g->grain_cells;
+      oa.delta = delta;
+      oa.eta = g->eta;
+      oa.wk = g->wk;
+      oa.logt = g->logt;
+      oa.twopi_rz = g->twopi_rz;
+      oa.h2 = g->h * g->h;
+      oa.gomega = g_omega;
+      oa.gdelta = grad_delta;
+      qc::launch_omega_delta_adjoint(oa, st);
+      if (g->kappa > 0.0) {
+        qc::launch_curl(A_ind, g->bbuf, g->nx, g->ny, g->h, st);
+        qc::launch_curl_adjoint(g->bbuf, grad_A, g->nx, g->ny, g->h, g->h * g->h * g->kappa * g->kappa * g_omega, st);
+      }
+    }
+    hcheck(hipGetLastError(), "adjoint launch");
     return QC_OK;
   });
 }

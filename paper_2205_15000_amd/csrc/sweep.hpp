@@ -101,6 +101,71 @@ struct DiffNormArgs {
   double* part;
 };
 
+// ---- reverse mode (adjoint.hip)
+using AdjArgs = SweepArgs;  // node_out unused; e_off must be 0
+
+struct AdjBufs {
+  const void* nodes;       // node4<double>
+  const void* bc_g_prev;   // boundary store read by the differentiated sweep
+  const void* bc_gt_prev;
+  void* gbuf;              // gamma at nodes  [nslot][n_e]
+  void* gtbuf;             // gamma~ at nodes [nslot][n_e]
+  void* lgt;               // node-local adjoint of gamma~ [nslot][n_e]
+  const void* gS;          // gradients of the per-node sums [nslot][4]
+  double* gV;              // out: gradients of the slot values [nslot][3] (Re D, Im D, a)
+};
+
+struct BackAdjArgs {
+  int64_t ncg, ncell;
+  int ncomp, n_theta;
+  const int32_t* grain_cells;
+  const int32_t* rb_idx;
+  const double* rb_w;
+  const double* wk;
+  const double* cosk;
+  const double* sink;
+  const double* eta;
+  const double* den;
+  double four_q, h2, gomega;
+  const double* gdn;  // complex gradient of Delta_new or nullptr
+  const double* gj;   // gradient of j or nullptr
+  double* gS;         // out (accumulated): [nslot][4]
+};
+
+struct InterpAdjArgs {
+  int64_t nslot, ncell;
+  int ncomp, n_theta;
+  const int32_t* slot_angle;
+  const int32_t* dst_idx;
+  const double* dst_w;
+  const int32_t* ast_idx;
+  const double* ast_w;
+  const double* eta;
+  const double* cosk;
+  const double* sink;
+  const double* gV;
+  double* gdelta;  // accumulated complex [ncomp][ny][nx]
+  double* gA;      // accumulated [2][ny][nx]
+};
+
+struct OmegaAdjArgs {
+  int64_t ncg, ncell;
+  int ncomp, n_theta;
+  const int32_t* grain_cells;
+  const double* delta;
+  const double* eta;
+  const double* wk;
+  const double* logt;
+  double twopi_rz, h2, gomega;
+  double* gdelta;
+};
+
+void launch_adjoint(int epl, const AdjArgs& a, const AdjBufs& b, hipStream_t st);
+void launch_back_adjoint(const BackAdjArgs& a, hipStream_t st);
+void launch_interp_adjoint(const InterpAdjArgs& a, hipStream_t st);
+void launch_omega_delta_adjoint(const OmegaAdjArgs& a, hipStream_t st);
+void launch_curl_adjoint(const double* B, double* gA, int nx, int ny, double h, double s, hipStream_t st);
+
 template <typename T>
 void launch_interp(const InterpArgs& a, void* nodes, hipStream_t st);
 template <typename T>
