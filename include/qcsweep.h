@@ -256,6 +256,40 @@ qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,
 qc_status qc_sweep_adjoint(qc_grain* grain, const double* delta, const double* A_ind, const double* g_delta_new,
                            const double* g_j, double g_omega, double* grad_delta, double* grad_A, void* stream);
 
+/* ---- batched grains ----------------------------------------------------
+ * Many grains of different shape, size, temperature, field, symmetry,
+ * angle and pole counts iterated together: per iteration every grain's
+ * interpolation runs, then ONE persistent sweep launch in which each wave
+ * pulls tiles (a grain and a bundle of 64/G of its segments) from a queue
+ * sorted by cost (longest trajectories first), then every grain's
+ * rotate-back, A-solve and Picard update (alpha = 1).  With use_graph the
+ * iterations are replayed from a captured hipGraph (two iterations per
+ * replay, one per boundary-store parity).  All grains must share device and
+ * precision; each appears once; the batch keeps its own Delta and A per
+ * grain and uses the grains' buffers (do not sweep them separately while
+ * the batch is in use). */
+typedef struct qc_batch qc_batch;
+qc_status qc_batch_create(qc_grain* const* grains, int n, qc_batch** out);
+void qc_batch_destroy(qc_batch* batch);
+/* trajectory steps of one iteration over all grains; energies per lane;
+ * number of tiles.  Any output pointer may be NULL. */
+qc_status qc_batch_get_info(const qc_batch* batch, int64_t* steps_per_iteration, int* energies_per_lane,
+                            int* n_tiles);
+/* set / read grain i's fields: device complex [ncomp][ny][nx] and device
+ * double [2][ny][nx] of that grain (copies; off-grain Delta set to zero). */
+qc_status qc_batch_set_fields(qc_batch* batch, int i, const double* delta, const double* A_ind, void* stream);
+qc_status qc_batch_get_fields(const qc_batch* batch, int i, double* delta_out, double* A_out, void* stream);
+/* n_iter Picard iterations of every grain (stream NULL: the batch's own
+ * stream); returns after they finish.  The first sweep of a grain that has
+ * no boundary values yet runs eagerly (bulk starts). */
+qc_status qc_batch_iterate(qc_batch* batch, int n_iter, int use_graph, void* stream);
+/* wall time of the latest qc_batch_iterate (HIP events on its stream) */
+qc_status qc_batch_last_ms(const qc_batch* batch, double* ms);
+/* autotuner: times iters_per_trial real iterations for each feasible
+ * energies-per-lane choice (1, 2, 4, 8) and keeps the fastest; these
+ * iterations advance the self-consistency like qc_batch_iterate. */
+qc_status qc_batch_autotune(qc_batch* batch, int iters_per_trial, int* best_epl, void* stream);
+
 /* Boundary-value store of qc_sweep (resume without burn-in, App. B).
  * bytes: in/out host size_t; with state == NULL only the size is returned.
  * state: device buffer of that size. */

@@ -95,6 +95,15 @@ _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes
 _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
 _sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
+_sig("qc_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)])
+_sig("qc_batch_destroy", None, [_P])
+_sig("qc_batch_get_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int)])
+_sig("qc_batch_set_fields", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P])
+_sig("qc_batch_get_fields", ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P])
+_sig("qc_batch_iterate", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P])
+_sig("qc_batch_last_ms", ctypes.c_int, [_P, _D])
+_sig("qc_batch_autotune", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _P])
 _sig("qc_set_state", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P])
 _sig("qc_profile_enable", ctypes.c_int, [_P, ctypes.c_int])
 _sig("qc_grain_set_lanes", ctypes.c_int, [_P, ctypes.c_int])
@@ -210,9 +219,11 @@ class Plan:
         self.info = _info_dict(inf)
         self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.qc_plan_destroy):
+        # the destroy function is bound at definition: module globals may
+        # already be cleared when the interpreter finalises objects
         if getattr(self, "_p", None):
-            lib.qc_plan_destroy(self._p)
+            _destroy(self._p)
             self._p = None
 
     def mask(self):
@@ -325,9 +336,9 @@ class Grain:
         self.info = _info_dict(inf)
         self._count = 0
 
-    def close(self):
+    def close(self, _destroy=lib.qc_grain_destroy):
         if getattr(self, "_g", None):
-            lib.qc_grain_destroy(self._g)
+            _destroy(self._g)
             self._g = None
 
     def __del__(self):
@@ -432,3 +443,59 @@ class Grain:
         n = ctypes.c_int64(0)
         _check(lib.qc_profile_read(self._g, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Several grains iterated together: one persistent sweep launch per
+    iteration, optionally replayed from a hipGraph."""
+
+    def __init__(self, grains):
+        self.grains = list(grains)
+        arr = (_P * len(self.grains))(*[g._g for g in self.grains])
+        p = _P()
+        _check(lib.qc_batch_create(arr, len(self.grains), ctypes.byref(p)))
+        self._b = p
+
+    def close(self, _destroy=lib.qc_batch_destroy):
+        if getattr(self, "_b", None):
+            _destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        st = ctypes.c_int64(0)
+        e = ctypes.c_int(0)
+        t = ctypes.c_int(0)
+        _check(lib.qc_batch_get_info(self._b, ctypes.byref(st), ctypes.byref(e), ctypes.byref(t)))
+        return {"steps_per_iteration": st.value, "energies_per_lane": e.value, "tiles": t.value}
+
+    def set_fields(self, i, delta, A, stream=None):
+        torch = _torch()
+        g = self.grains[i]
+        dp = _dptr(delta, torch.complex128, (g.ncomp, g.ny, g.nx), "delta")
+        ap = _dptr(A, torch.float64, (2, g.ny, g.nx), "A")
+        _check(lib.qc_batch_set_fields(self._b, int(i), dp, ap, _stream(stream)))
+
+    def get_fields(self, i, stream=None):
+        torch = _torch()
+        g = self.grains[i]
+        d = torch.empty((g.ncomp, g.ny, g.nx), dtype=torch.complex128, device=g._dev())
+        a = torch.empty((2, g.ny, g.nx), dtype=torch.float64, device=g._dev())
+        _check(lib.qc_batch_get_fields(self._b, int(i), ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                       _stream(stream)))
+        return d, a
+
+    def iterate(self, n_iter, graph=True, stream=None):
+        """Runs n_iter Picard iterations of every grain; returns milliseconds."""
+        _check(lib.qc_batch_iterate(self._b, int(n_iter), 1 if graph else 0,
+                                    _stream(stream) if stream is not None else None))
+        ms = ctypes.c_double(0.0)
+        _check(lib.qc_batch_last_ms(self._b, ctypes.byref(ms)))
+        return ms.value
+
+    def autotune(self, iters_per_trial=2):
+        e = ctypes.c_int(0)
+        _check(lib.qc_batch_autotune(self._b, int(iters_per_trial), ctypes.byref(e), None))
+        return e.value

@@ -347,11 +347,15 @@ __global__ void __launch_bounds__(256) interp_adjoint_kernel(InterpAdjArgs a) {
   if (s >= a.nslot) return;
   const double gx = a.gV[s * 3], gy = a.gV[s * 3 + 1], ga = a.gV[s * 3 + 2];
   const int k = a.slot_angle[s];
+  int di[4], ai[4];
+  double dw[4], aw[4];
+  delta_stencil(a.geom, a.px[s], a.py[s], a.fb[s], di, dw);
+  a_stencil(a.geom, a.px[s], a.py[s], ai, aw);
   if (gx != 0.0 || gy != 0.0) {
     for (int c = 0; c < 4; ++c) {
-      const double w = a.dst_w[s * 4 + c];
+      const double w = dw[c];
       if (w == 0.0) continue;
-      const int idx = a.dst_idx[s * 4 + c];
+      const int idx = di[c];
       for (int g = 0; g < a.ncomp; ++g) {
         // y = eta w x  ->  G_x += conj(eta) w G_y
         const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
@@ -363,8 +367,8 @@ __global__ void __launch_bounds__(256) interp_adjoint_kernel(InterpAdjArgs a) {
   }
   if (ga != 0.0) {
     for (int c = 0; c < 4; ++c) {
-      const double w = a.ast_w[s * 4 + c];
-      const int idx = a.ast_idx[s * 4 + c];
+      const double w = aw[c];
+      const int idx = ai[c];
       unsafeAtomicAdd(a.gA + idx, w * a.cosk[k] * ga);
       unsafeAtomicAdd(a.gA + a.ncell + idx, w * a.sink[k] * ga);
     }

@@ -213,10 +213,10 @@ struct qc_grain {
   std::vector<double> zp, rp;
   // static tables
   int32_t* slot_angle = nullptr;
-  int32_t* dst_idx = nullptr;
-  double* dst_w = nullptr;
-  int32_t* ast_idx = nullptr;
-  double* ast_w = nullptr;
+  double* slot_px = nullptr;
+  double* slot_py = nullptr;
+  int32_t* slot_fb = nullptr;
+  double x0 = 0, y0 = 0;
   double* aext = nullptr;
   double* eta = nullptr;
   double* cosk = nullptr;
@@ -286,7 +286,7 @@ enum { kROmega = 0, kRB2 = 1, kRJx = 2, kRJy = 3, kRDiffD = 4, kRDiffJ = 6, kRDi
 namespace {
 
 void free_grain(qc_grain* g) {
-  void* ptrs[] = {g->slot_angle, g->dst_idx, g->dst_w, g->ast_idx, g->ast_w, g->aext, g->eta, g->cosk,
+  void* ptrs[] = {g->slot_angle, g->slot_px, g->slot_py, g->slot_fb, g->aext, g->eta, g->cosk,
                   g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->order, g->gbuf, g->node_out, g->bc[0][0],
@@ -339,6 +339,17 @@ std::vector<double2> twiddles(int n) {
   return tw;
 }
 
+qc::GridGeom geom_of(const qc_grain* g) {
+  qc::GridGeom gg;
+  gg.nx = g->nx;
+  gg.ny = g->ny;
+  gg.x0 = g->x0;
+  gg.y0 = g->y0;
+  gg.h = g->h;
+  gg.mask = g->mask;
+  return gg;
+}
+
 void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st) {
   qc::InterpArgs a;
   a.nslot = g->nslot;
@@ -346,10 +357,10 @@ void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st
   a.ncomp = g->ncomp;
   a.n_theta = g->n_theta;
   a.slot_angle = g->slot_angle;
-  a.dst_idx = g->dst_idx;
-  a.dst_w = g->dst_w;
-  a.ast_idx = g->ast_idx;
-  a.ast_w = g->ast_w;
+  a.geom = geom_of(g);
+  a.px = g->slot_px;
+  a.py = g->slot_py;
+  a.fb = g->slot_fb;
   a.aext = g->aext;
   a.eta = g->eta;
   a.cosk = g->cosk;
@@ -416,9 +427,21 @@ double omega_from_parts(const qc_grain* g) {
   return tot;
 }
 
+// buffers of the iteration map (gamma at nodes, per-node sums, boundary
+// store), allocated on first use so that LDOS-only grains do not hold them
+void ensure_sweep_buffers(qc_grain* g) {
+  if (g->gbuf) return;
+  const size_t rb = g->real_bytes();
+  g->gbuf = dalloc(2 * rb * g->nslot * g->n_poles);
+  g->node_out = static_cast<double*>(dalloc(4 * sizeof(double) * g->nslot));
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) g->bc[a][b] = dalloc(2 * rb * g->nseg * g->n_poles);
+}
+
 // steps 3-8 of one iteration; omega_total (host) optional (synchronises)
 void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_new, double* j, double* omega,
               double* omega_total, hipStream_t st) {
+  ensure_sweep_buffers(g);
   do_interp(g, delta, A, st);
   qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
   a.bc_valid = g->bc_valid;
@@ -615,10 +638,11 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
       eta[2 * i + 1] = p.eta[i].imag();
     }
     g->slot_angle = static_cast<int32_t*>(upload(p.slot_angle));
-    g->dst_idx = static_cast<int32_t*>(upload(p.dst_idx));
-    g->dst_w = static_cast<double*>(upload(p.dst_w));
-    g->ast_idx = static_cast<int32_t*>(upload(p.ast_idx));
-    g->ast_w = static_cast<double*>(upload(p.ast_w));
+    g->slot_px = static_cast<double*>(upload(p.slot_px));
+    g->slot_py = static_cast<double*>(upload(p.slot_py));
+    g->slot_fb = static_cast<int32_t*>(upload(p.slot_fb));
+    g->x0 = p.x0;
+    g->y0 = p.y0;
     g->aext = static_cast<double*>(upload(p.slot_aext));
     g->eta = static_cast<double*>(upload(eta));
     g->cosk = static_cast<double*>(upload(p.cosk));
@@ -649,10 +673,7 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
       std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return p.seg_n[x] > p.seg_n[y]; });
       g->order = static_cast<int32_t*>(upload(ord));
     }
-    g->gbuf = dalloc(2 * rb * g->nslot * p.n_poles);
-    g->node_out = static_cast<double*>(dalloc(4 * sizeof(double) * g->nslot));
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) g->bc[a][b] = dalloc(2 * rb * g->nseg * p.n_poles);
+    // gbuf, node_out and the boundary store are allocated by the first sweep
     g->omega_cell = static_cast<double*>(dalloc(sizeof(double) * g->ncg));
     g->part = static_cast<double*>(dalloc(sizeof(double) * kRegions * kParts));
     g->dmean = static_cast<double*>(dalloc(sizeof(double) * 2));
@@ -970,7 +991,7 @@ qc_status qc_get_state(const qc_grain* g, void* state, size_t* bytes, void* stre
     return QC_OK;
   }
   if (*bytes < 2 * half) return fail(QC_ERR_INVALID, "state buffer too small");
-  if (!g->bc_valid) return fail(QC_ERR_INVALID, "no boundary values yet (run a sweep first)");
+  if (!g->bc_valid || !g->gbuf) return fail(QC_ERR_INVALID, "no boundary values yet (run a sweep first)");
   return guarded([&]() -> qc_status {
     hcheck(hipSetDevice(g->device), "hipSetDevice");
     hcheck(hipMemcpyAsync(state, g->bc[g->bc_cur][0], half, hipMemcpyDeviceToDevice, S(stream)), "copy");
@@ -988,6 +1009,7 @@ qc_status qc_set_state(qc_grain* g, const void* state, size_t bytes, void* strea
   if (bytes != 2 * half) return fail(QC_ERR_INVALID, "state size does not match this grain");
   return guarded([&]() -> qc_status {
     hcheck(hipSetDevice(g->device), "hipSetDevice");
+    ensure_sweep_buffers(g);
     hcheck(hipMemcpyAsync(g->bc[g->bc_cur][0], state, half, hipMemcpyDeviceToDevice, S(stream)), "copy");
     hcheck(hipMemcpyAsync(g->bc[g->bc_cur][1], static_cast<const char*>(state) + half, half, hipMemcpyDeviceToDevice,
                           S(stream)),
@@ -1060,10 +1082,10 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     ia.ncomp = g->ncomp;
     ia.n_theta = g->n_theta;
     ia.slot_angle = g->slot_angle;
-    ia.dst_idx = g->dst_idx;
-    ia.dst_w = g->dst_w;
-    ia.ast_idx = g->ast_idx;
-    ia.ast_w = g->ast_w;
+    ia.geom = geom_of(g);
+    ia.px = g->slot_px;
+    ia.py = g->slot_py;
+    ia.fb = g->slot_fb;
     ia.eta = g->eta;
     ia.cosk = g->cosk;
     ia.sink = g->sink;
@@ -1130,6 +1152,370 @@ qc_status qc_profile_read(qc_grain* g, double* sweep_ms, int64_t* sweep_launches
     g->ev.clear();
     return QC_OK;
   });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// batched grains
+// ------------------------------------------------------------------------
+struct qc_batch {
+  int device = 0;
+  int precision = 0;
+  std::vector<qc_grain*> grains;
+  std::vector<double*> delta, A;   // per-grain fields owned by the batch
+  int epl = 2;
+  int nblocks = 0;
+  qc::BatchGrainDev* d_args = nullptr;  // [n] for the current launch
+  int2* d_tiles = nullptr;
+  int ntiles = 0;
+  int* d_counter = nullptr;
+  hipStream_t own = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int> graph_parity;   // bc_cur of every grain when the graph was captured
+  int graph_epl = 0;
+  int64_t steps_per_iter = 0;
+  double last_ms = 0.0;
+  std::vector<qc::BatchGrainDev> host_args;
+};
+
+namespace {
+
+// tiles: for every grain, waves of 64/G segments in launch order (longest
+// first); all tiles sorted by their longest segment, longest first
+void build_tiles(qc_batch* b) {
+  struct T3 {
+    int g, w0, cost;
+  };
+  std::vector<T3> all;
+  for (size_t gi = 0; gi < b->grains.size(); ++gi) {
+    qc_grain* g = b->grains[gi];
+    int G, epl;
+    lane_shape(g->n_poles, b->epl, G, epl);
+    std::vector<int32_t> ord(g->nseg), n(g->nseg);
+    hcheck(hipMemcpy(ord.data(), g->order, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
+    hcheck(hipMemcpy(n.data(), g->seg_n, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
+    const int per = 64 / G;
+    for (int64_t w = 0; w < g->nseg; w += per) all.push_back({static_cast<int>(gi), static_cast<int>(w), n[ord[w]] + 1});
+  }
+  std::stable_sort(all.begin(), all.end(), [](const T3& x, const T3& y) { return x.cost > y.cost; });
+  std::vector<int2> t(all.size());
+  for (size_t i = 0; i < all.size(); ++i) t[i] = make_int2(all[i].g, all[i].w0);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  b->d_tiles = static_cast<int2*>(upload(t));
+  b->ntiles = static_cast<int>(t.size());
+}
+
+// per-grain arguments of the next sweep (each grain's current store parity)
+void upload_args(qc_batch* b, hipStream_t st) {
+  std::vector<qc::BatchGrainDev>& v = b->host_args;
+  v.resize(b->grains.size());
+  for (size_t gi = 0; gi < b->grains.size(); ++gi) {
+    qc_grain* g = b->grains[gi];
+    int G, epl;
+    lane_shape(g->n_poles, b->epl, G, epl);
+    qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
+    a.G = G;
+    a.log2g = ilog2(G);
+    a.bc_valid = g->bc_valid;
+    v[gi].a = a;
+    v[gi].b.nodes = g->nodes;
+    v[gi].b.bc_g_prev = g->bc[g->bc_cur][0];
+    v[gi].b.bc_gt_prev = g->bc[g->bc_cur][1];
+    v[gi].b.bc_g_next = g->bc[1 - g->bc_cur][0];
+    v[gi].b.bc_gt_next = g->bc[1 - g->bc_cur][1];
+    v[gi].b.gbuf = g->gbuf;
+    v[gi].b.ebuf = nullptr;
+  }
+  hcheck(hipMemcpyAsync(b->d_args, v.data(), sizeof(qc::BatchGrainDev) * v.size(), hipMemcpyHostToDevice, st),
+         "H2D");
+  hcheck(hipStreamSynchronize(st), "sync");  // the host block is reused by the next upload
+}
+
+void rotate_back_grain(qc_grain* g, const double* delta, double* dnew, double* j, hipStream_t st) {
+  qc::BackArgs r;
+  r.ncg = g->ncg;
+  r.ncell = g->ncell;
+  r.ncomp = g->ncomp;
+  r.n_theta = g->n_theta;
+  r.grain_cells = g->grain_cells;
+  r.rb_idx = g->rb_idx;
+  r.rb_w = g->rb_w;
+  r.node_out = g->node_out;
+  r.wk = g->wk;
+  r.cosk = g->cosk;
+  r.sink = g->sink;
+  r.eta = g->eta;
+  r.den = g->den;
+  r.logt = g->logt;
+  r.four_q = 4.0 * g->q;
+  r.twopi_rz = g->twopi_rz;
+  r.delta = delta;
+  r.delta_new = dnew;
+  r.j = j;
+  r.omega = nullptr;
+  r.omega_cell = g->omega_cell;
+  qc::launch_rotate_back(r, st);
+}
+
+// one Picard iteration (alpha = 1) of every grain: per-grain interpolation,
+// one persistent sweep over all grains, per-grain rotate-back, A-solve and
+// update.  Only kernel launches: it can be captured into a graph.
+void batch_iteration(qc_batch* b, hipStream_t st, bool upload) {
+  for (size_t gi = 0; gi < b->grains.size(); ++gi) do_interp(b->grains[gi], b->delta[gi], b->A[gi], st);
+  if (upload) upload_args(b, st);
+  if (b->precision == QC_MIXED)
+    qc::launch_batch_sweep<float>(b->epl, b->d_args, b->d_tiles, b->ntiles, b->d_counter, b->nblocks, st);
+  else
+    qc::launch_batch_sweep<double>(b->epl, b->d_args, b->d_tiles, b->ntiles, b->d_counter, b->nblocks, st);
+  for (size_t gi = 0; gi < b->grains.size(); ++gi) {
+    qc_grain* g = b->grains[gi];
+    rotate_back_grain(g, b->delta[gi], g->dnew, g->jcur, st);
+    // A from the current (zero for an infinite penetration depth), as in the
+    // single-grain Picard loop
+    do_solve_A(g, g->jcur, g->anew, nullptr, st);
+    qc::launch_picard(b->A[gi], g->anew, nullptr, 2 * g->ncell, 1, 0, 1, 1.0, st);
+    qc::launch_picard(b->delta[gi], g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, st);
+    g->bc_cur = 1 - g->bc_cur;
+    g->bc_valid = 1;
+    g->last_bc_valid = -1;  // batched sweeps are not differentiated
+  }
+  hcheck(hipGetLastError(), "batch launch");
+}
+
+void drop_graph(qc_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->graph_parity.clear();
+}
+
+void free_batch(qc_batch* b) {
+  drop_graph(b);
+  for (double* p : b->delta)
+    if (p) (void)hipFree(p);
+  for (double* p : b->A)
+    if (p) (void)hipFree(p);
+  if (b->d_args) (void)hipFree(b->d_args);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+qc_status qc_batch_create(qc_grain* const* grains, int n, qc_batch** out) {
+  if (!out || !grains || n < 1) return fail(QC_ERR_INVALID, "need at least one grain");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!grains[i]) return fail(QC_ERR_INVALID, "NULL grain in the batch");
+    if (grains[i]->device != grains[0]->device || grains[i]->precision != grains[0]->precision)
+      return fail(QC_ERR_INVALID, "all grains of a batch need the same device and precision");
+    if (grains[i]->n_poles > 512) return fail(QC_ERR_INVALID, "too many poles for a batched sweep");
+    for (int k = 0; k < i; ++k)
+      if (grains[k] == grains[i]) return fail(QC_ERR_INVALID, "a grain appears twice in the batch");
+  }
+  qc_batch* b = new (std::nothrow) qc_batch();
+  if (!b) return fail(QC_ERR_OOM, "host allocation failed");
+  qc_status st = guarded([&]() -> qc_status {
+    b->device = grains[0]->device;
+    b->precision = grains[0]->precision;
+    hcheck(hipSetDevice(b->device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    hcheck(hipGetDeviceProperties(&prop, b->device), "props");
+    b->nblocks = prop.multiProcessorCount * 8;
+    for (int i = 0; i < n; ++i) {
+      qc_grain* g = grains[i];
+      ensure_sweep_buffers(g);
+      b->grains.push_back(g);
+      b->steps_per_iter += g->info.steps_per_sweep;
+      double* d = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
+      double* a = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
+      b->delta.push_back(d);
+      b->A.push_back(a);
+      qc::launch_fill(d, 2 * g->ncomp * g->ncell, 0.0, nullptr);
+      qc::launch_fill(a, 2 * g->ncell, 0.0, nullptr);
+      // off-grain cells of delta_new stay zero: rotate-back writes grain cells only
+      qc::launch_fill(g->dnew, 2 * g->ncomp * g->ncell, 0.0, nullptr);
+    }
+    b->d_args = static_cast<qc::BatchGrainDev*>(dalloc(sizeof(qc::BatchGrainDev) * n));
+    b->d_counter = static_cast<int*>(dalloc(sizeof(int)));
+    hcheck(hipStreamCreate(&b->own), "stream");
+    build_tiles(b);
+    hcheck(hipDeviceSynchronize(), "batch setup");
+    return QC_OK;
+  });
+  if (st != QC_OK) {
+    free_batch(b);
+    return st;
+  }
+  *out = b;
+  return QC_OK;
+}
+
+void qc_batch_destroy(qc_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
+qc_status qc_batch_get_info(const qc_batch* b, int64_t* steps_per_iteration, int* energies_per_lane, int* n_tiles) {
+  if (!b) return fail(QC_ERR_INVALID, "batch is NULL");
+  if (steps_per_iteration) *steps_per_iteration = b->steps_per_iter;
+  if (energies_per_lane) *energies_per_lane = b->epl;
+  if (n_tiles) *n_tiles = b->ntiles;
+  return QC_OK;
+}
+
+qc_status qc_batch_set_fields(qc_batch* b, int i, const double* delta, const double* A_ind, void* stream) {
+  if (!b || i < 0 || i >= static_cast<int>(b->grains.size())) return fail(QC_ERR_INVALID, "bad batch index");
+  if (!delta || !A_ind) return fail(QC_ERR_INVALID, "NULL field");
+  return guarded([&]() -> qc_status {
+    qc_grain* g = b->grains[i];
+    hcheck(hipSetDevice(b->device), "hipSetDevice");
+    hcheck(hipMemcpyAsync(g->dnew, delta, sizeof(double) * 2 * g->ncomp * g->ncell, hipMemcpyDeviceToDevice, S(stream)),
+           "copy");
+    qc::launch_fill(b->delta[i], 2 * g->ncomp * g->ncell, 0.0, S(stream));
+    qc::launch_picard(b->delta[i], g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, S(stream));
+    qc::launch_fill(g->dnew, 2 * g->ncomp * g->ncell, 0.0, S(stream));
+    hcheck(hipMemcpyAsync(b->A[i], A_ind, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, S(stream)), "copy");
+    return QC_OK;
+  });
+}
+
+qc_status qc_batch_get_fields(const qc_batch* b, int i, double* delta_out, double* A_out, void* stream) {
+  if (!b || i < 0 || i >= static_cast<int>(b->grains.size())) return fail(QC_ERR_INVALID, "bad batch index");
+  return guarded([&]() -> qc_status {
+    qc_grain* g = b->grains[i];
+    hcheck(hipSetDevice(b->device), "hipSetDevice");
+    if (delta_out)
+      hcheck(hipMemcpyAsync(delta_out, b->delta[i], sizeof(double) * 2 * g->ncomp * g->ncell, hipMemcpyDeviceToDevice,
+                            S(stream)),
+             "copy");
+    if (A_out)
+      hcheck(hipMemcpyAsync(A_out, b->A[i], sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, S(stream)), "copy");
+    return QC_OK;
+  });
+}
+
+qc_status qc_batch_iterate(qc_batch* b, int n_iter, int use_graph, void* stream) {
+  if (!b || n_iter < 0) return fail(QC_ERR_INVALID, "bad arguments");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(b->device), "hipSetDevice");
+    hipStream_t st = stream ? S(stream) : b->own;
+    hipEvent_t e0, e1;
+    hcheck(hipEventCreate(&e0), "event");
+    hcheck(hipEventCreate(&e1), "event");
+    hcheck(hipEventRecord(e0, st), "event");
+    int left = n_iter;
+    // the first sweep of a fresh grain starts from bulk roots: run it eagerly
+    bool fresh = false;
+    for (qc_grain* g : b->grains) fresh = fresh || !g->bc_valid;
+    if (fresh && left > 0) {
+      batch_iteration(b, st, true);
+      --left;
+    }
+    if (use_graph && left >= 2) {
+      std::vector<int> par;
+      for (qc_grain* g : b->grains) par.push_back(g->bc_cur);
+      if (!b->gexec || par != b->graph_parity || b->graph_epl != b->epl) {
+        drop_graph(b);
+        // the graph holds two iterations (both store parities); the argument
+        // blocks are baked per parity into two device copies
+        hcheck(hipStreamSynchronize(st), "sync");
+        qc::BatchGrainDev* saved = b->d_args;
+        qc::BatchGrainDev* args2 =
+            static_cast<qc::BatchGrainDev*>(dalloc(sizeof(qc::BatchGrainDev) * 2 * b->grains.size()));
+        b->d_args = args2;
+        upload_args(b, st);
+        for (qc_grain* g : b->grains) g->bc_cur = 1 - g->bc_cur;
+        b->d_args = args2 + b->grains.size();
+        upload_args(b, st);
+        for (qc_grain* g : b->grains) g->bc_cur = 1 - g->bc_cur;
+        hcheck(hipStreamSynchronize(st), "sync");
+        hipStream_t cs;
+        hcheck(hipStreamCreate(&cs), "stream");
+        hipGraph_t graph;
+        hcheck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "capture");
+        b->d_args = args2;
+        batch_iteration(b, cs, false);
+        b->d_args = args2 + b->grains.size();
+        batch_iteration(b, cs, false);
+        hcheck(hipStreamEndCapture(cs, &graph), "capture");
+        // the capture flipped the parities twice: back where it started
+        hcheck(hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0), "instantiate");
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (saved) (void)hipFree(saved);
+        b->d_args = args2;  // kept alive for the graph (first half; second half follows)
+        b->graph_parity = par;
+        b->graph_epl = b->epl;
+      }
+      while (left >= 2) {
+        hcheck(hipGraphLaunch(b->gexec, st), "graph launch");
+        left -= 2;
+      }
+    }
+    while (left > 0) {
+      if (b->gexec) {
+        // eager iterations must not overwrite the graph's argument blocks
+        drop_graph(b);
+        (void)hipFree(b->d_args);
+        b->d_args = static_cast<qc::BatchGrainDev*>(dalloc(sizeof(qc::BatchGrainDev) * b->grains.size()));
+      }
+      batch_iteration(b, st, true);
+      --left;
+    }
+    hcheck(hipEventRecord(e1, st), "event");
+    hcheck(hipEventSynchronize(e1), "event");
+    float ms = 0.f;
+    hcheck(hipEventElapsedTime(&ms, e0, e1), "event");
+    b->last_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return QC_OK;
+  });
+}
+
+qc_status qc_batch_last_ms(const qc_batch* b, double* ms) {
+  if (!b || !ms) return fail(QC_ERR_INVALID, "NULL argument");
+  *ms = b->last_ms;
+  return QC_OK;
+}
+
+qc_status qc_batch_autotune(qc_batch* b, int iters_per_trial, int* best_epl, void* stream) {
+  if (!b || iters_per_trial < 1) return fail(QC_ERR_INVALID, "bad arguments");
+  int maxp = 0;
+  for (qc_grain* g : b->grains) maxp = std::max(maxp, g->n_poles);
+  double best = INFINITY;
+  int arg = b->epl;
+  const int cand[4] = {1, 2, 4, 8};
+  for (int e : cand) {
+    if ((maxp + e - 1) / e > 64) continue;
+    b->epl = e;
+    qc_status st = guarded([&]() -> qc_status {
+      drop_graph(b);
+      build_tiles(b);
+      return QC_OK;
+    });
+    if (st != QC_OK) return st;
+    st = qc_batch_iterate(b, iters_per_trial, 0, stream);
+    if (st != QC_OK) return st;
+    if (b->last_ms < best) {
+      best = b->last_ms;
+      arg = e;
+    }
+  }
+  b->epl = arg;
+  qc_status st = guarded([&]() -> qc_status {
+    build_tiles(b);
+    return QC_OK;
+  });
+  if (best_epl) *best_epl = arg;
+  return st;
 }
 
 }  // extern "C"

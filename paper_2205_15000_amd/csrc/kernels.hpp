@@ -144,6 +144,59 @@ __device__ __forceinline__ cpx<T> bulk_root(T zx, T zy, T dx, T dy) {
   return mk(-(dx * bx + dy * by) * r, -(dy * bx - dx * by) * r);
 }
 
+// Bilinear weights of the four cell centres around (px, py) on the
+// reference grid (Sec. III.A), formed with the same IEEE operations as the
+// host tables.  Delta: corners off the array or outside the grain are
+// dropped and the rest renormalised; fb >= 0 names the nearest grain cell
+// used when no corner keeps a positive weight.  A_ind: plain bilinear with
+// the point clamped onto the outermost cell centres.
+struct GridGeom {
+  int nx, ny;
+  double x0, y0, h;
+  const uint8_t* mask;
+};
+__device__ __forceinline__ void delta_stencil(const GridGeom& gg, double px, double py, int fb, int idx[4],
+                                              double w[4]) {
+  const double fx = (px - gg.x0) / gg.h - 0.5, fy = (py - gg.y0) / gg.h - 0.5;
+  const int i0 = static_cast<int>(__builtin_floor(fx)), j0 = static_cast<int>(__builtin_floor(fy));
+  const double wx = fx - i0, wy = fy - j0;
+  w[0] = (1 - wx) * (1 - wy);
+  w[1] = wx * (1 - wy);
+  w[2] = (1 - wx) * wy;
+  w[3] = wx * wy;
+  double tot = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int ci = i0 + (c & 1), cj = j0 + (c >> 1);
+    const bool ok = ci >= 0 && ci < gg.nx && cj >= 0 && cj < gg.ny && gg.mask[cj * gg.nx + ci];
+    idx[c] = ok ? cj * gg.nx + ci : 0;
+    if (!ok) w[c] = 0.0;
+    tot += w[c];
+  }
+  if (fb >= 0) {
+    idx[0] = fb;
+    idx[1] = idx[2] = idx[3] = 0;
+    w[0] = 1.0;
+    w[1] = w[2] = w[3] = 0.0;
+  } else if (tot > 0.0) {
+    for (int c = 0; c < 4; ++c) w[c] /= tot;
+  }
+}
+__device__ __forceinline__ void a_stencil(const GridGeom& gg, double px, double py, int idx[4], double w[4]) {
+  const double fx = __builtin_fmin(__builtin_fmax((px - gg.x0) / gg.h - 0.5, 0.0), gg.nx - 1.0);
+  const double fy = __builtin_fmin(__builtin_fmax((py - gg.y0) / gg.h - 0.5, 0.0), gg.ny - 1.0);
+  const int i0 = min(static_cast<int>(__builtin_floor(fx)), gg.nx - 2);
+  const int j0 = min(static_cast<int>(__builtin_floor(fy)), gg.ny - 2);
+  const double wx = fx - i0, wy = fy - j0;
+  idx[0] = j0 * gg.nx + i0;
+  idx[1] = idx[0] + 1;
+  idx[2] = idx[0] + gg.nx;
+  idx[3] = idx[2] + 1;
+  w[0] = (1 - wx) * (1 - wy);
+  w[1] = wx * (1 - wy);
+  w[2] = (1 - wx) * wy;
+  w[3] = wx * wy;
+}
+
 // Sum of v over aligned groups of G lanes (G a power of two <= 64); every
 // lane of the group ends with the total.  DPP within rows of 16 lanes,
 // cross-lane permutes beyond.
@@ -162,5 +215,6 @@ __device__ __forceinline__ double group_sum(double v, int G) {
   if (G >= 64) v += __shfl_xor(v, 32);
   return v;
 }
+
 
 }  // namespace qc

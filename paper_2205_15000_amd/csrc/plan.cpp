@@ -317,10 +317,9 @@ void build_plan(Plan& p) {
   p.nnode = nn;
   p.slot_angle.resize(ns);
   p.slot_seg.resize(ns);
-  p.dst_idx.assign(static_cast<size_t>(ns) * 4, 0);
-  p.dst_w.assign(static_cast<size_t>(ns) * 4, 0.0);
-  p.ast_idx.assign(static_cast<size_t>(ns) * 4, 0);
-  p.ast_w.assign(static_cast<size_t>(ns) * 4, 0.0);
+  p.slot_px.assign(ns, 0.0);
+  p.slot_py.assign(ns, 0.0);
+  p.slot_fb.assign(ns, -1);
   p.slot_aext.assign(ns, 0.0);
   std::vector<double> gx, gy;  // grain cell centres, for the nearest-cell fallback
   for (int32_t c : p.grain_cells) {
@@ -348,26 +347,25 @@ void build_plan(Plan& p) {
       const double s = n > 0 ? (jf + t - half) * h : 0.5 * (p.seg_smin[g] + p.seg_smax[g]);
       const double px = p.cx + u * eqx + s * epx;
       const double py = p.cy + u * eqy + s * epy;
-      // Delta: masked bilinear over the four surrounding cell centres
+      p.slot_px[sl] = px;
+      p.slot_py[sl] = py;
+      // Delta: masked bilinear over the four surrounding cell centres (the
+      // device forms the weights); only the fallback is decided here: the
+      // nearest grain cell when no masked corner keeps a positive weight
       {
         const double fx = (px - p.x0) / h - 0.5, fy = (py - p.y0) / h - 0.5;
         const int i0 = static_cast<int>(std::floor(fx)), j0 = static_cast<int>(std::floor(fy));
         const double wx = fx - i0, wy = fy - j0;
         const int ci[4] = {i0, i0 + 1, i0, i0 + 1};
         const int cj[4] = {j0, j0, j0 + 1, j0 + 1};
-        double w[4] = {(1 - wx) * (1 - wy), wx * (1 - wy), (1 - wx) * wy, wx * wy};
-        int idx[4];
+        const double w[4] = {(1 - wx) * (1 - wy), wx * (1 - wy), (1 - wx) * wy, wx * wy};
         double tot = 0.0;
         for (int c = 0; c < 4; ++c) {
           const bool ok = ci[c] >= 0 && ci[c] < nx && cj[c] >= 0 && cj[c] < ny &&
                           p.mask[static_cast<size_t>(cj[c]) * nx + ci[c]];
-          idx[c] = ok ? cj[c] * nx + ci[c] : 0;
-          if (!ok) w[c] = 0.0;
-          tot += w[c];
+          if (ok) tot += w[c];
         }
-        if (tot > 0.0) {
-          for (int c = 0; c < 4; ++c) w[c] /= tot;
-        } else {
+        if (!(tot > 0.0)) {
           size_t best = 0;
           double bd = std::numeric_limits<double>::infinity();
           for (size_t a = 0; a < gx.size(); ++a) {
@@ -377,28 +375,7 @@ void build_plan(Plan& p) {
               best = a;
             }
           }
-          idx[0] = p.grain_cells[best];
-          idx[1] = idx[2] = idx[3] = 0;
-          w[0] = 1.0;
-          w[1] = w[2] = w[3] = 0.0;
-        }
-        for (int c = 0; c < 4; ++c) {
-          p.dst_idx[sl * 4 + c] = idx[c];
-          p.dst_w[sl * 4 + c] = w[c];
-        }
-      }
-      // A_ind: plain bilinear, clamped onto the outermost cell centres
-      {
-        const double fx = std::min(std::max((px - p.x0) / h - 0.5, 0.0), nx - 1.0);
-        const double fy = std::min(std::max((py - p.y0) / h - 0.5, 0.0), ny - 1.0);
-        const int i0 = std::min(static_cast<int>(std::floor(fx)), nx - 2);
-        const int j0 = std::min(static_cast<int>(std::floor(fy)), ny - 2);
-        const double wx = fx - i0, wy = fy - j0;
-        const int idx[4] = {j0 * nx + i0, j0 * nx + i0 + 1, (j0 + 1) * nx + i0, (j0 + 1) * nx + i0 + 1};
-        const double w[4] = {(1 - wx) * (1 - wy), wx * (1 - wy), (1 - wx) * wy, wx * wy};
-        for (int c = 0; c < 4; ++c) {
-          p.ast_idx[sl * 4 + c] = idx[c];
-          p.ast_w[sl * 4 + c] = w[c];
+          p.slot_fb[sl] = p.grain_cells[best];
         }
       }
       double ax, ay;

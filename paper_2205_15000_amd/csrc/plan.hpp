@@ -59,10 +59,11 @@ struct Plan {
   int64_t nslot = 0, nnode = 0;
   std::vector<int32_t> slot_angle;
   std::vector<int32_t> slot_seg;
-  std::vector<int32_t> dst_idx;        // [nslot][4] masked bilinear of Delta
-  std::vector<double> dst_w;
-  std::vector<int32_t> ast_idx;        // [nslot][4] clamped bilinear of A_ind
-  std::vector<double> ast_w;
+  std::vector<double> slot_px, slot_py; // slot positions; the device forms the
+                                       // bilinear weights of Delta (masked) and A_ind
+                                       // (clamped) from them
+  std::vector<int32_t> slot_fb;        // nearest grain cell where no masked corner
+                                       // keeps a positive weight, else -1
   std::vector<double> slot_aext;       // v_k . A_ext(slot)
 
   // ---- rotate-back stencils of grain cells: [angle][corner][cell]

@@ -24,10 +24,15 @@ __global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, node4<T>* __r
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= a.nslot) return;
   const int k = a.slot_angle[s];
+  const double px = a.px[s], py = a.py[s];
+  int di[4], ai[4];
+  double dw[4], aw[4];
+  delta_stencil(a.geom, px, py, a.fb[s], di, dw);
+  a_stencil(a.geom, px, py, ai, aw);
   double dx = 0.0, dy = 0.0;
   for (int c = 0; c < 4; ++c) {
-    const int idx = a.dst_idx[s * 4 + c];
-    const double w = a.dst_w[s * 4 + c];
+    const int idx = di[c];
+    const double w = dw[c];
     double vx = 0.0, vy = 0.0;
     for (int g = 0; g < a.ncomp; ++g) {
       const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
@@ -41,10 +46,8 @@ __global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, node4<T>* __r
   }
   double ax = 0.0, ay = 0.0;
   for (int c = 0; c < 4; ++c) {
-    const int idx = a.ast_idx[s * 4 + c];
-    const double w = a.ast_w[s * 4 + c];
-    ax += a.A[idx] * w;
-    ay += a.A[a.ncell + idx] * w;
+    ax += a.A[ai[c]] * aw[c];
+    ay += a.A[a.ncell + ai[c]] * aw[c];
   }
   node4<T> v;
   v.dx = static_cast<T>(dx);
@@ -72,16 +75,12 @@ __global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, node4<T>* __r
 // so the Eilenberger free-energy term needs no division.
 // --------------------------------------------------------------------------
 template <typename T, int EPL, int MODE>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
-                                                    const cpx<T>* __restrict__ bc_g_prev,
-                                                    const cpx<T>* __restrict__ bc_gt_prev,
-                                                    cpx<T>* __restrict__ bc_g_next,
-                                                    cpx<T>* __restrict__ bc_gt_next,
-                                                    cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
-  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t wseg = gtid >> a.log2g;
-  const int lane = static_cast<int>(gtid & (a.G - 1));
-  if (wseg >= a.nseg) return;  // whole lane groups leave together (G | 64)
+__device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, int lane,
+                                              const node4<T>* __restrict__ nodes,
+                                              const cpx<T>* __restrict__ bc_g_prev,
+                                              const cpx<T>* __restrict__ bc_gt_prev,
+                                              cpx<T>* __restrict__ bc_g_next, cpx<T>* __restrict__ bc_gt_next,
+                                              cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
   const int64_t seg = a.order ? static_cast<int64_t>(a.order[wseg]) : wseg;
   const int64_t slot0 = a.seg_slot0[seg];
   const int n = a.seg_n[seg];
@@ -175,11 +174,12 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>*
     prev = cur;
     if (MODE == 2 || t == 0) continue;
     const int64_t node = slot0 + t - 1;
-    const cpx<T>* src = gbuf + node * a.n_e + e0;
+    const cpx<T>* src = gbuf + node * a.n_e;
     if (MODE == 0) {
       double sfx = 0.0, sfy = 0.0, sg = 0.0, s1 = 0.0, s2 = 0.0;
       for (int i = 0; i < EPL; ++i) {
-        const cpx<T> gg = src[full ? i : (e0 + i < a.n_e ? i : 0)];
+        // padded energies (weight 0) read the node's last pole: in range
+        const cpx<T> gg = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
         const cpx<T> x = gg * gt[i];
         const T dxr = T(1) + x.x;
         const T ri = drcp(dxr * dxr + x.y * x.y);
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>*
       T* dst = ebuf + node * a.n_e + e0;
       for (int i = 0; i < EPL; ++i) {
         if (e0 + i >= a.n_e) continue;
-        const cpx<T> gg = src[i];
+        const cpx<T> gg = src[e0 + i];
         const cpx<T> x = gg * gt[i];
         const T dxr = T(1) + x.x;
         const T ri = drcp(dxr * dxr + x.y * x.y);
@@ -229,6 +229,48 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>*
     for (int i = 0; i < EPL; ++i)
       if (e0 + i < a.n_e) dst[i] = gt[i];
   }
+}
+
+template <typename T, int EPL, int MODE>
+__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
+                                                    const cpx<T>* __restrict__ bc_g_prev,
+                                                    const cpx<T>* __restrict__ bc_gt_prev,
+                                                    cpx<T>* __restrict__ bc_g_next,
+                                                    cpx<T>* __restrict__ bc_gt_next,
+                                                    cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
+  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t wseg = gtid >> a.log2g;
+  const int lane = static_cast<int>(gtid & (a.G - 1));
+  if (wseg >= a.nseg) return;  // whole lane groups leave together (G | 64)
+  sweep_segment<T, EPL, MODE>(a, wseg, lane, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, ebuf);
+}
+
+// Batched grains: one persistent launch.  Every wave pulls tiles (a grain
+// and a bundle of 64/G of its segments) from a queue sorted by cost until
+// the queue is empty; every wave reaches that exit.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(256) batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
+                                                          const int2* __restrict__ tiles, int ntiles,
+                                                          int* __restrict__ counter) {
+  const int l64 = threadIdx.x & 63;
+  while (true) {
+    int t = 0;
+    if (l64 == 0) t = atomicAdd(counter, 1);
+    t = __shfl(t, 0, 64);
+    if (t >= ntiles) break;
+    const int2 tile = tiles[t];
+    const BatchGrainDev& gd = grains[tile.x];
+    const int64_t wseg = static_cast<int64_t>(tile.y) + (l64 >> gd.a.log2g);
+    if (wseg < gd.a.nseg)
+      sweep_segment<T, EPL, 0>(gd.a, wseg, l64 & (gd.a.G - 1), static_cast<const node4<T>*>(gd.b.nodes),
+                               static_cast<const cpx<T>*>(gd.b.bc_g_prev), static_cast<const cpx<T>*>(gd.b.bc_gt_prev),
+                               static_cast<cpx<T>*>(gd.b.bc_g_next), static_cast<cpx<T>*>(gd.b.bc_gt_next),
+                               static_cast<cpx<T>*>(gd.b.gbuf), nullptr);
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
 // --------------------------------------------------------------------------
@@ -430,12 +472,26 @@ __global__ void __launch_bounds__(256) picard_kernel(double* __restrict__ x, con
 // --------------------------------------------------------------------------
 // grain means of the two current components from block partials (fixed
 // summation order, the same as a host-side sum of the partials)
-__global__ void means_kernel(const double* __restrict__ part, int nparts, double inv_n, double* __restrict__ mean) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+__global__ void __launch_bounds__(256) means_kernel(const double* __restrict__ part, int nparts, double inv_n,
+                                                    double* __restrict__ mean) {
+  // one block; fixed-order tree over the partials: deterministic
+  __shared__ double sh[2][256];
   for (int c = 0; c < 2; ++c) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[c * nparts + i];
-    mean[c] = s * inv_n;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[c * nparts + i];
+    sh[c][threadIdx.x] = v;
+  }
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mean[0] = sh[0][0] * inv_n;
+    mean[1] = sh[1][0] * inv_n;
   }
 }
 
@@ -561,6 +617,20 @@ void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hip
 template void launch_sweep<double>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
 template void launch_sweep<float>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
 
+template <typename T>
+void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles, int ntiles, int* counter, int nblocks,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
+  switch (epl) {
+    case 1: hipLaunchKernelGGL((batch_sweep_kernel<T, 1>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
+    case 2: hipLaunchKernelGGL((batch_sweep_kernel<T, 2>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
+    case 4: hipLaunchKernelGGL((batch_sweep_kernel<T, 4>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
+    default: hipLaunchKernelGGL((batch_sweep_kernel<T, 8>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
+  }
+}
+template void launch_batch_sweep<double>(int, const BatchGrainDev*, const int2*, int, int*, int, hipStream_t);
+template void launch_batch_sweep<float>(int, const BatchGrainDev*, const int2*, int, int*, int, hipStream_t);
+
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;
   hipLaunchKernelGGL(rotate_back_kernel, dim3(nblk(a.ncg)), dim3(256), 0, st, a);
@@ -594,7 +664,7 @@ void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, i
                        stride, alpha);
 }
 void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st) {
-  hipLaunchKernelGGL(means_kernel, dim3(1), dim3(64), 0, st, part, nparts, inv_n, mean);
+  hipLaunchKernelGGL(means_kernel, dim3(1), dim3(256), 0, st, part, nparts, inv_n, mean);
 }
 void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, const double* mean,
                         double2* w, hipStream_t st) {

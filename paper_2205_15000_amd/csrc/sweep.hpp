@@ -5,17 +5,19 @@
 
 #include <cstdint>
 
+#include "kernels.hpp"
+
 namespace qc {
 
 struct InterpArgs {
   int64_t nslot;
   int64_t ncell;  // nx * ny
   int ncomp, n_theta;
+  GridGeom geom;
   const int32_t* slot_angle;
-  const int32_t* dst_idx;
-  const double* dst_w;
-  const int32_t* ast_idx;
-  const double* ast_w;
+  const double* px;
+  const double* py;
+  const int32_t* fb;
   const double* aext;   // v_k . A_ext per slot
   const double* eta;    // complex [ncomp][n_theta]
   const double* cosk;
@@ -54,6 +56,12 @@ struct SweepBufs {
   void* bc_gt_next;
   void* gbuf;
   void* ebuf;
+};
+
+// one grain of a batched sweep: its arguments and buffers
+struct BatchGrainDev {
+  SweepArgs a;
+  SweepBufs b;
 };
 
 struct BackArgs {
@@ -135,11 +143,11 @@ struct BackAdjArgs {
 struct InterpAdjArgs {
   int64_t nslot, ncell;
   int ncomp, n_theta;
+  GridGeom geom;
   const int32_t* slot_angle;
-  const int32_t* dst_idx;
-  const double* dst_w;
-  const int32_t* ast_idx;
-  const double* ast_w;
+  const double* px;
+  const double* py;
+  const int32_t* fb;
   const double* eta;
   const double* cosk;
   const double* sink;
@@ -171,6 +179,9 @@ void launch_interp(const InterpArgs& a, void* nodes, hipStream_t st);
 template <typename T>
 void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
+template <typename T>
+void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles, int ntiles, int* counter, int nblocks,
+                        hipStream_t st);
 template <typename T>
 void launch_ldos_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st);
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);

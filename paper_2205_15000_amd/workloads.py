@@ -134,3 +134,49 @@ def initial_A(name, sp=None, seed=None):
 def ldos_energies(n=512):
     """Real energies -2 DELTA0 + 4 DELTA0 k / n, k = 0..n-1 (includes 0)."""
     return -2.0 * DELTA0 + 4.0 * DELTA0 * np.arange(n) / n
+
+
+def batch_specs(n=64, seed0=3):
+    """Seeded batch of n grains (grain g uses seed seed0 + g): a disc, a
+    square at a random rotation or a convex polygon of 5-9 vertices with
+    jittered angles, minus 0-2 disc or square holes; grid N x N with N in
+    {64, 80, ..., 512}, h = 0.2, the grain spanning about 80% of the box;
+    t ~ U[0.05, 0.9], flux ~ U[0, 5] quanta (symmetric gauge), s or d_{x2-y2}
+    with probability 1/2, 32/64/96/128 angles, 32..128 poles in steps of 16,
+    infinite penetration depth."""
+    out = []
+    for g in range(n):
+        rng = np.random.default_rng(seed0 + g)
+        N = int(rng.choice(np.arange(64, 513, 16)))
+        h = 0.2
+        L = N * h
+        R = 0.4 * L
+        kind = int(rng.integers(3))
+        if kind == 0:
+            shapes = [_disc(0.0, 0.0, R)]
+        elif kind == 1:
+            shapes = [_square(0.0, 0.0, 0.6 * L, float(rng.uniform(0, 0.25)))]
+        else:
+            nv = int(rng.integers(5, 10))
+            ang = 2 * math.pi * (np.arange(nv) + rng.uniform(-0.3, 0.3, nv)) / nv
+            shapes = [{"kind": "polygon", "vx": list(R * np.cos(ang)), "vy": list(R * np.sin(ang)), "add": True}]
+        for _ in range(int(rng.integers(3))):
+            hr = float(rng.uniform(0.05, 0.12)) * L
+            hx, hy = rng.uniform(-0.2, 0.2, 2) * L
+            if rng.random() < 0.5:
+                shapes.append(_disc(float(hx), float(hy), hr, add=False))
+            else:
+                shapes.append(_square(float(hx), float(hy), 1.4 * hr, float(rng.uniform(0, 0.25)), add=False))
+        sym = "s" if rng.random() < 0.5 else "dx2y2"
+        out.append(dict(nx=N, ny=N, h=h, shapes=shapes, n_theta=int(rng.choice([32, 64, 96, 128])),
+                        n_poles=int(rng.choice(np.arange(32, 129, 16))), t=float(rng.uniform(0.05, 0.9)),
+                        components=[(sym, 1.0)], kappa=0.0, flux_quanta=float(rng.uniform(0, 5)),
+                        gauge="symmetric", charge_sign=-1, name="batch%02d" % g))
+    return out
+
+
+def batch_initial_delta(sp, g):
+    """Starting field of batch grain g: 0.9 DELTA0 with 5% seeded noise."""
+    rng = np.random.default_rng(1000 + g)
+    u = rng.uniform(-0.05, 0.05, (sp["ny"], sp["nx"]))
+    return (0.9 * DELTA0 * (1.0 + u))[None].astype(np.complex128)
