@@ -10,6 +10,17 @@ Inputs are resident in HBM before the timed region.  The reported value is
 the mixed FP32-sweep / FP64-sum path; the FP64 path is timed beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Other measurements of the same library (one JSON line each; not the
+headline):
+    --mode converge [--iters N]   mixed and FP64 Picard runs from the same
+                                  start; difference of the final states
+    --mode ldos [--prior N --bc-iters K]
+                                  LDOS of the 512x512 [110] square, 256 angles,
+                                  512 real energies, K boundary iterations
+    --mode batch [--grains N --iters K]
+                                  N seeded grains iterated together (persistent
+                                  tile-queue sweep, hipGraph replay)
 """
 import argparse
 import json
@@ -46,6 +57,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch"], default="iteration")
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--prior", type=int, default=200)
+    ap.add_argument("--bc-iters", type=int, default=20)
+    ap.add_argument("--grains", type=int, default=64)
     return ap.parse_args()
 
 
@@ -64,6 +80,7 @@ def timed_scf(qs, torch, sp, precision, d0, a0, steps, warmup):
     sweep_ms, launches = g.profile_read()
     g.profile(False)
     info = dict(g.info)
+    info["energies_per_lane"], info["lanes_per_segment"] = g.lanes()
     g.close()
     return dt, it, sweep_ms, launches, info, res
 
@@ -90,6 +107,103 @@ def cpu_baseline(sp, d0, a0, n_angles):
     return steps / dt, dt, steps
 
 
+def mode_converge(qs, torch, wl, iters):
+    """Mixed and FP64 Picard runs of the benchmark workload from the same
+    start: residual histories and the difference of the final fields."""
+    sp = wl.spec(WORKLOAD)
+    d0 = wl.initial_delta(WORKLOAD, sp)
+    a0 = wl.initial_A(WORKLOAD, sp)
+    out, runs = {}, {}
+    for prec in ("mixed", "fp64"):
+        print("bench: converge %s, %d iterations" % (prec, iters), file=sys.stderr, flush=True)
+        g = qs.Grain(sp, prec)
+        dd = torch.as_tensor(d0).cuda()
+        ad = torch.as_tensor(a0).cuda()
+        t0 = time.perf_counter()
+        it, res, conv = g.scf(dd, ad, iters, tol=1e-10)
+        torch.cuda.synchronize()
+        runs[prec] = {"iters": it, "s": time.perf_counter() - t0, "res_first": res[1, :4].tolist(),
+                      "res_last": res[it - 1, :4].tolist()}
+        out[prec] = (dd.cpu().numpy(), ad.cpu().numpy(), res[:it, :4])
+        g.close()
+    m = qs.Plan(dict(sp, n_theta=4)).mask()
+    dm, df = out["mixed"][0][:, m], out["fp64"][0][:, m]
+    hist = np.nanmax(np.abs(out["mixed"][2][1:] - out["fp64"][2][1:]) / np.abs(out["fp64"][2][1:]))
+    return {"metric": "mixed vs FP64 final state after Picard iterations", "workload": WORKLOAD,
+            "iterations": iters, "runs": runs,
+            "max_abs_delta_diff_over_delta0": float(np.max(np.abs(dm - df)) / wl.DELTA0),
+            "rel_l2_delta_diff": float(np.linalg.norm(dm - df) / np.linalg.norm(df)),
+            "A_max_abs_diff": float(np.max(np.abs(out["mixed"][1] - out["fp64"][1]))),
+            "A_max": float(np.max(np.abs(out["fp64"][1]))),
+            "residual_history_max_rel_diff": float(hist)}
+
+
+def mode_ldos(qs, torch, wl, n_prior, bc_iters):
+    """LDOS of the 512x512 [110] square: a mixed Picard prior solve at 64
+    angles, then 256 angles x 512 real energies with bc_iters boundary
+    iterations (Delta and A frozen)."""
+    name = "d110_square_512_ldos"
+    sp = wl.spec(name)
+    d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    print("bench: ldos prior solve, %d iterations" % n_prior, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    g = qs.Grain(dict(sp, n_theta=64), "mixed")
+    g.scf(d0, a0, n_prior, tol=1e-6)
+    torch.cuda.synchronize()
+    g.close()
+    prior_s = time.perf_counter() - t0
+    en = wl.ldos_energies(512)
+    gl = qs.Grain(sp, "mixed")
+    gl.profile(True)
+    print("bench: ldos, %d energies, %d boundary iterations" % (len(en), bc_iters), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o = gl.ldos(d0, a0, en, 0.01 * wl.DELTA0, bc_iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, nl = gl.profile_read()
+    steps = gl.info["steps_per_sweep"] // sp["n_poles"] * len(en) * (bc_iters + 1)
+    o = o.cpu().numpy()
+    gl.close()
+    return {"metric": "LDOS trajectory-steps/s", "workload": name, "energies": len(en), "bc_iters": bc_iters,
+            "value": steps / dt, "unit": "trajectory-steps/s", "seconds": dt, "steps": steps,
+            "sweep_kernel_ms": ms, "sweep_launches": nl, "sweep_only_steps_per_s": steps / (ms * 1e-3),
+            "prior_solve_s": prior_s, "finite": bool(np.isfinite(o).all())}
+
+
+def mode_batch(qs, torch, wl, n, iters):
+    """n seeded grains (64x64 to 512x512, 32-128 angles, 32-128 poles)
+    iterated together in the mixed path: eager and hipGraph timings after
+    the autotuner has picked the energies per lane."""
+    specs = wl.batch_specs(n)
+    t0 = time.perf_counter()
+    grains = []
+    for i, sp in enumerate(specs):
+        grains.append(qs.Grain(sp, "mixed"))
+        if i % 8 == 7:
+            print("bench: created %d grains" % (i + 1), file=sys.stderr, flush=True)
+    b = qs.Batch(grains)
+    for i, sp in enumerate(specs):
+        b.set_fields(i, torch.as_tensor(wl.batch_initial_delta(sp, i)).cuda(),
+                     torch.zeros((2, sp["ny"], sp["nx"]), dtype=torch.float64).cuda())
+    setup_s = time.perf_counter() - t0
+    info = b.info()
+    b.iterate(1, graph=False)
+    epl = b.autotune(1)
+    print("bench: batch autotuned to %d energies per lane" % epl, file=sys.stderr, flush=True)
+    ms_e = b.iterate(2, graph=False)
+    b.iterate(iters, graph=True)  # captures the graphs
+    ms_g = b.iterate(iters, graph=True)
+    d, _ = b.get_fields(0)
+    st = info["steps_per_iteration"]
+    return {"metric": "batched trajectory-steps/s", "grains": n, "unit": "trajectory-steps/s",
+            "value": st * iters / (ms_g * 1e-3), "graph_ms_per_iteration": ms_g / iters,
+            "eager_ms_per_iteration": ms_e / 2, "eager_steps_per_s": st * 2 / (ms_e * 1e-3),
+            "steps_per_iteration": st, "energies_per_lane": epl, "tiles": info["tiles"], "setup_s": setup_s,
+            "finite": bool(torch.isfinite(d).all())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -99,6 +213,16 @@ def main():
     import torch
     import paper_2205_15000_amd as qs
     from paper_2205_15000_amd import workloads as wl
+
+    if args.mode != "iteration":
+        if args.mode == "converge":
+            res = mode_converge(qs, torch, wl, args.iters or 3000)
+        elif args.mode == "ldos":
+            res = mode_ldos(qs, torch, wl, args.prior, args.bc_iters)
+        else:
+            res = mode_batch(qs, torch, wl, args.grains, args.iters or 6)
+        print(json.dumps(res), flush=True)
+        return
 
     sp = wl.spec(WORKLOAD)
     d0 = wl.initial_delta(WORKLOAD, sp)
@@ -132,7 +256,8 @@ def main():
                    "nodes": info["n_nodes"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": SWEEP_TRAFFIC_BYTES,
-                     "kernel": "sweep_kernel<float,2,0>", "avg_launch_ms": avg_ms,
+                     "kernel": "sweep_kernel<float,%d,0>" % info["energies_per_lane"],
+                     "lanes_per_segment": info["lanes_per_segment"], "avg_launch_ms": avg_ms,
                      "flops_per_launch": flops_launch,
                      "peak_fp32_packed_published": PEAK_FP32_PACKED_TFLOPS},
         "sweep_only_steps_per_s": steps_iter / (avg_ms * 1e-3),

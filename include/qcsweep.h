@@ -301,6 +301,10 @@ qc_status qc_set_state(qc_grain* grain, const void* state, size_t bytes, void* s
  * per-node energy sums, so fewer energies per lane means more lanes per
  * segment.  Results are identical up to rounding order. */
 qc_status qc_grain_set_lanes(qc_grain* grain, int energies_per_lane);
+/* The lane shape the next SCF sweep of this grain will use: energies per
+ * lane (1, 2, 4 or 8) and lanes per trajectory segment (a power of two
+ * <= 64).  Both outputs are host ints written on success. */
+qc_status qc_grain_get_lanes(const qc_grain* grain, int* energies_per_lane, int* lanes_per_segment);
 
 /* Kernel timing with HIP events on the launch stream (for roofline
  * reports).  Enable, run, then read the summed milliseconds and launch

@@ -88,6 +88,7 @@ _sig("qc_grain_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_Desc), ctyp
 _sig("qc_grain_destroy", None, [_P])
 _sig("qc_grain_get_info", ctypes.c_int, [_P, ctypes.POINTER(_Info)])
 _sig("qc_grain_reset_bc", ctypes.c_int, [_P])
+_sig("qc_grain_get_lanes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)])
 _sig("qc_sweep", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P])
 _sig("qc_solve_A", ctypes.c_int, [_P, _P, _P, _P, _P])
 _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -434,6 +435,13 @@ class Grain:
     def set_lanes(self, energies_per_lane):
         """Energies per lane of the sweep kernel (1, 2, 4, 8; 0 = automatic)."""
         _check(lib.qc_grain_set_lanes(self._g, int(energies_per_lane)))
+
+    def lanes(self):
+        """(energies per lane, lanes per segment) of the next SCF sweep."""
+        e = ctypes.c_int(0)
+        G = ctypes.c_int(0)
+        _check(lib.qc_grain_get_lanes(self._g, ctypes.byref(e), ctypes.byref(G)))
+        return e.value, G.value
 
     def profile(self, enable=True):
         _check(lib.qc_profile_enable(self._g, 1 if enable else 0))

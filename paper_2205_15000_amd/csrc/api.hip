@@ -240,6 +240,7 @@ struct qc_grain {
   double* logt = nullptr;
   // work buffers
   void* nodes = nullptr;
+  void* cells = nullptr;   // packed Delta / A_ind per cell (single component)
   int32_t* order = nullptr;
   int epl_override = 0;
   void* gbuf = nullptr;
@@ -289,7 +290,7 @@ void free_grain(qc_grain* g) {
   void* ptrs[] = {g->slot_angle, g->slot_px, g->slot_py, g->slot_fb, g->aext, g->eta, g->cosk,
                   g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
-                  g->eps, g->rpd, g->den, g->logt, g->nodes, g->order, g->gbuf, g->node_out, g->bc[0][0],
+                  g->eps, g->rpd, g->den, g->logt, g->nodes, g->cells, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV};
   for (void* p : ptrs)
@@ -367,10 +368,12 @@ void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st
   a.sink = g->sink;
   a.delta = delta;
   a.A = A;
+  if (g->ncomp == 1 && !g->cells) g->cells = dalloc(4 * g->real_bytes() * g->ncell);
+  void* cells = g->ncomp == 1 ? g->cells : nullptr;
   if (g->precision == QC_MIXED)
-    qc::launch_interp<float>(a, g->nodes, st);
+    qc::launch_interp<float>(a, cells, g->nodes, st);
   else
-    qc::launch_interp<double>(a, g->nodes, st);
+    qc::launch_interp<double>(a, cells, g->nodes, st);
 }
 
 qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const double* eps, const double* rp) {
@@ -430,6 +433,8 @@ double omega_from_parts(const qc_grain* g) {
 // buffers of the iteration map (gamma at nodes, per-node sums, boundary
 // store), allocated on first use so that LDOS-only grains do not hold them
 void ensure_sweep_buffers(qc_grain* g) {
+  // the packed interpolation cells are needed before any graph capture
+  if (g->ncomp == 1 && !g->cells) g->cells = dalloc(4 * g->real_bytes() * g->ncell);
   if (g->gbuf) return;
   const size_t rb = g->real_bytes();
   g->gbuf = dalloc(2 * rb * g->nslot * g->n_poles);
@@ -1125,6 +1130,16 @@ qc_status qc_grain_set_lanes(qc_grain* g, int energies_per_lane) {
       energies_per_lane != 8)
     return fail(QC_ERR_INVALID, "energies_per_lane must be 0 (auto), 1, 2, 4 or 8");
   g->epl_override = energies_per_lane;
+  return QC_OK;
+}
+
+qc_status qc_grain_get_lanes(const qc_grain* g, int* energies_per_lane, int* lanes_per_segment) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!energies_per_lane || !lanes_per_segment) return fail(QC_ERR_INVALID, "output pointers are required");
+  int G = 1, epl = 1;
+  lane_shape(g->n_poles, g->epl_override, G, epl);
+  *energies_per_lane = epl;
+  *lanes_per_segment = G;
   return QC_OK;
 }
 

@@ -16,6 +16,21 @@ struct cpx {
   T x, y;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Map the hardware block index to a logical one so that every XCD runs
+// one contiguous range of logical blocks (a bijection of [0, nb)).
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8, x = bid % 8, l = bid / 8;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// one reference-grid cell for the single-component interpolation:
+// Delta (re, im) and A_ind (x, y) side by side
+template <typename T>
+struct __attribute__((aligned(4 * sizeof(T)))) cell4 {
+  T dx, dy, ax, ay;
+};
+
 // node value slot: Delta(p_k, slot) and a(slot) = v_k . A(slot)
 template <typename T>
 struct __attribute__((aligned(4 * sizeof(T)))) node4 {
@@ -215,6 +230,57 @@ __device__ __forceinline__ double group_sum(double v, int G) {
   if (G >= 64) v += __shfl_xor(v, 32);
   return v;
 }
+
+__device__ __forceinline__ double sel(bool c, double a, double b) { return c ? a : b; }
+// v + v of the lane 16 (32) apart: the row (half-wave) swap leaves the
+// partner's value in one of the two results and the lane's own in the other
+__device__ __forceinline__ double xor16_sum(double v) {
+  const unsigned lo = static_cast<unsigned>(__double2loint(v)), hi = static_cast<unsigned>(__double2hiint(v));
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(static_cast<int>(h[0]), static_cast<int>(l[0])) +
+         __hiloint2double(static_cast<int>(h[1]), static_cast<int>(l[1]));
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+  const unsigned lo = static_cast<unsigned>(__double2loint(v)), hi = static_cast<unsigned>(__double2hiint(v));
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(static_cast<int>(h[0]), static_cast<int>(l[0])) +
+         __hiloint2double(static_cast<int>(h[1]), static_cast<int>(l[1]));
+}
+// xor-4 partner inside a 32-lane half (the LDS crossbar swizzle, bit mode)
+__device__ __forceinline__ double swz_xor4(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x101F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x101F);
+  return __hiloint2double(hi, lo);
+}
+
+// Sums of four quantities over aligned groups of G >= 4 lanes (G a power of
+// two <= 64), scattered: every lane ends with the group total of quantity
+// 2 (lane & 1) + ((lane >> 1) & 1), so lanes 0..3 of the group hold all four.
+// Two halving steps inside each quad (each lane keeps half of what it has
+// and adds the partner's matching half), then plain sums across quads:
+// rotations by 4 and 8 inside a 16-lane row, row and half-wave swaps beyond.
+__device__ __forceinline__ double group_sum4_scatter(double q0, double q1, double q2, double q3, int G,
+                                                    int lane) {
+  const bool b0 = lane & 1, b1 = (lane >> 1) & 1;
+  double k0 = sel(b0, q2, q0), k1 = sel(b0, q3, q1);
+  const double s0 = sel(b0, q0, q2), s1 = sel(b0, q1, q3);
+  k0 += dpp_f64<0xB1>(s0);  // quad_perm [1,0,3,2]
+  k1 += dpp_f64<0xB1>(s1);
+  double k = sel(b1, k1, k0);
+  const double s = sel(b1, k0, k1);
+  k += dpp_f64<0x4E>(s);  // quad_perm [2,3,0,1]
+  if (G == 8) k += swz_xor4(k);
+  if (G >= 16) {
+    k += dpp_f64<0x124>(k);  // row_ror:4
+    k += dpp_f64<0x128>(k);  // row_ror:8
+  }
+  if (G >= 32) k = xor16_sum(k);
+  if (G >= 64) k = xor32_sum(k);
+  return k;
+}
+__device__ __forceinline__ int scatter_index(int lane) { return 2 * (lane & 1) + ((lane >> 1) & 1); }
 
 
 }  // namespace qc

@@ -384,6 +384,17 @@ void build_plan(Plan& p) {
     }
   }
 
+  // ---- order of the per-cell kernels: 16 x 16 tiles of the grid, row-major
+  // inside a tile, so that a block of 256 threads covers a compact patch and
+  // neighbouring cells share lattice corners in the rotate-back gathers
+  // (the nearest-cell fallback above broke its ties in ascending order)
+  std::stable_sort(p.grain_cells.begin(), p.grain_cells.end(), [nx](int32_t a, int32_t b) {
+    const int ia = a % nx, ja = a / nx, ib = b % nx, jb = b / nx;
+    if ((ja >> 4) != (jb >> 4)) return (ja >> 4) < (jb >> 4);
+    if ((ia >> 4) != (ib >> 4)) return (ia >> 4) < (ib >> 4);
+    return a < b;
+  });
+
   // ---- rotate-back stencils of the grain cells
   const int64_t nc = static_cast<int64_t>(p.grain_cells.size());
   p.rb_idx.assign(static_cast<size_t>(p.n_theta) * 4 * nc, 0);

@@ -39,7 +39,7 @@ struct Plan {
 
   // ---- grid and tables
   std::vector<uint8_t> mask;           // [ny][nx]
-  std::vector<int32_t> grain_cells;    // flat indices of grain cells, ascending
+  std::vector<int32_t> grain_cells;    // flat indices of grain cells, in 16 x 16 tile order
   double area = 0;
   int M = 0;                           // lattice side
   double half = 0;                     // (M-1)/2

@@ -57,6 +57,108 @@ __global__ void __launch_bounds__(256) interp_kernel(InterpArgs a, node4<T>* __r
   nodes[s] = v;
 }
 
+// Single order-parameter component: Delta and A_ind packed per cell in the
+// sweep precision, so the gathers of a slot touch one 16 B (FP32) or 32 B
+// (FP64) record per corner and the FP32 grid stays resident in L2.  Cells
+// outside the grain carry a NaN in Re Delta: the masked interpolation reads
+// the mask from the same record instead of a separate dependent load.
+template <typename T>
+__global__ void __launch_bounds__(256) pack_cells_kernel(const double* __restrict__ delta,
+                                                         const double* __restrict__ A,
+                                                         const uint8_t* __restrict__ mask, int64_t ncell,
+                                                         cell4<T>* __restrict__ cells) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  cell4<T> c;
+  c.dx = mask[i] ? static_cast<T>(delta[2 * i]) : __builtin_nan("");
+  c.dy = static_cast<T>(delta[2 * i + 1]);
+  c.ax = static_cast<T>(A[i]);
+  c.ay = static_cast<T>(A[ncell + i]);
+  cells[i] = c;
+}
+
+// Same stencils as interp_kernel (identical floating-point operations for the
+// weights): masked bilinear for Delta with the nearest-grain-cell fallback,
+// clamped bilinear for A_ind.  Away from the array edge the two stencils
+// share their corners, and the four records serve both.
+template <typename T>
+__global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<T>* __restrict__ cells,
+                                                      node4<T>* __restrict__ nodes) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= a.nslot) return;
+  const GridGeom& gg = a.geom;
+  const int k = a.slot_angle[s];
+  const double px = a.px[s], py = a.py[s];
+  const int fb = a.fb[s];
+  const double fx = (px - gg.x0) / gg.h - 0.5, fy = (py - gg.y0) / gg.h - 0.5;
+  const int i0 = static_cast<int>(__builtin_floor(fx)), j0 = static_cast<int>(__builtin_floor(fy));
+  const double wx = fx - i0, wy = fy - j0;
+  double w[4];
+  w[0] = (1 - wx) * (1 - wy);
+  w[1] = wx * (1 - wy);
+  w[2] = (1 - wx) * wy;
+  w[3] = wx * wy;
+  cell4<T> v[4];
+  double tot = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int ci = i0 + (c & 1), cj = j0 + (c >> 1);
+    const bool in = ci >= 0 && ci < gg.nx && cj >= 0 && cj < gg.ny;
+    const int lc = min(max(ci, 0), gg.nx - 1), lj = min(max(cj, 0), gg.ny - 1);
+    v[c] = cells[static_cast<int64_t>(lj) * gg.nx + lc];
+    const bool ok = in && v[c].dx == v[c].dx;  // NaN marks cells outside the grain
+    if (!ok) w[c] = 0.0;
+    tot += w[c];
+  }
+  const double ex = a.eta[2 * k], ey = a.eta[2 * k + 1];
+  double dx = 0.0, dy = 0.0;
+  if (fb >= 0) {
+    const cell4<T> f = cells[fb];
+    const double fx0 = static_cast<double>(f.dx), fy0 = static_cast<double>(f.dy);
+    dx = ex * fx0 - ey * fy0;
+    dy = ex * fy0 + ey * fx0;
+  } else {
+    if (tot > 0.0)
+      for (int c = 0; c < 4; ++c) w[c] /= tot;
+    for (int c = 0; c < 4; ++c) {
+      if (w[c] == 0.0) continue;  // a dropped corner may hold the NaN marker
+      const double cx = static_cast<double>(v[c].dx), cy = static_cast<double>(v[c].dy);
+      dx += (ex * cx - ey * cy) * w[c];
+      dy += (ex * cy + ey * cx) * w[c];
+    }
+  }
+  // A_ind: clamped bilinear
+  const double fxa = __builtin_fmin(__builtin_fmax(fx, 0.0), gg.nx - 1.0);
+  const double fya = __builtin_fmin(__builtin_fmax(fy, 0.0), gg.ny - 1.0);
+  const int i0a = min(static_cast<int>(__builtin_floor(fxa)), gg.nx - 2);
+  const int j0a = min(static_cast<int>(__builtin_floor(fya)), gg.ny - 2);
+  const double wxa = fxa - i0a, wya = fya - j0a;
+  double aw[4];
+  aw[0] = (1 - wxa) * (1 - wya);
+  aw[1] = wxa * (1 - wya);
+  aw[2] = (1 - wxa) * wya;
+  aw[3] = wxa * wya;
+  double ax = 0.0, ay = 0.0;
+  if (i0a == i0 && j0a == j0) {
+    for (int c = 0; c < 4; ++c) {
+      ax += static_cast<double>(v[c].ax) * aw[c];
+      ay += static_cast<double>(v[c].ay) * aw[c];
+    }
+  } else {
+    const int64_t b0 = static_cast<int64_t>(j0a) * gg.nx + i0a;
+    for (int c = 0; c < 4; ++c) {
+      const cell4<T> u = cells[b0 + (c & 1) + (c >> 1) * gg.nx];
+      ax += static_cast<double>(u.ax) * aw[c];
+      ay += static_cast<double>(u.ay) * aw[c];
+    }
+  }
+  node4<T> o;
+  o.dx = static_cast<T>(dx);
+  o.dy = static_cast<T>(dy);
+  o.a = static_cast<T>(a.cosk[k] * ax + a.sink[k] * ay + a.aext[s]);
+  o.pad = T(0);
+  nodes[s] = o;
+}
+
 // --------------------------------------------------------------------------
 // Riccati sweep
 //
@@ -195,20 +297,24 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         s2 += r * static_cast<double>(gg.x + gt[i].x);
       }
       // Im(D* gamma - D gamma~) summed over the lane's poles
-      double si = static_cast<double>(cur.dx) * s1 - static_cast<double>(cur.dy) * s2;
-      sfx = group_sum(sfx, a.G);
-      sfy = group_sum(sfy, a.G);
-      sg = group_sum(sg, a.G);
-      si = group_sum(si, a.G);
-      if (lane == 0) {
-        // S_f = t~ sum R (f + conj f~) = -2 i pi t~ (sfx + i sfy), S_g = pi t~ sg,
-        // S_I = 2 pi t~ sum R Re[i (D gamma~ - D* gamma)] = 2 pi t~ si
-        double4 o;
-        o.x = a.twopi_tt * sfy;
-        o.y = -a.twopi_tt * sfx;
-        o.z = 0.5 * a.twopi_tt * sg;
-        o.w = a.twopi_tt * si;
-        reinterpret_cast<double4*>(a.node_out)[node] = o;
+      const double si = static_cast<double>(cur.dx) * s1 - static_cast<double>(cur.dy) * s2;
+      // S_f = t~ sum R (f + conj f~) = -2 i pi t~ (sfx + i sfy), S_g = pi t~ sg,
+      // S_I = 2 pi t~ sum R Re[i (D gamma~ - D* gamma)] = 2 pi t~ si
+      if (a.G >= 4) {
+        // lane q of the group (q < 4) ends with component q of the node's sums
+        const double v = group_sum4_scatter(sfy, -sfx, 0.5 * sg, si, a.G, lane);
+        if (lane < 4) a.node_out[node * 4 + scatter_index(lane)] = a.twopi_tt * v;
+      } else {
+        const double ox = group_sum(sfy, a.G), oy = group_sum(sfx, a.G);
+        const double oz = group_sum(sg, a.G), ow = group_sum(si, a.G);
+        if (lane == 0) {
+          double4 o;
+          o.x = a.twopi_tt * ox;
+          o.y = -a.twopi_tt * oy;
+          o.z = 0.5 * a.twopi_tt * oz;
+          o.w = a.twopi_tt * ow;
+          reinterpret_cast<double4*>(a.node_out)[node] = o;
+        }
       }
     } else {  // MODE 1: N/N_F = -Im g / pi = Re((1-X)/(1+X)) per energy
       T* dst = ebuf + node * a.n_e + e0;
@@ -231,8 +337,17 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
 }
 
+// Occupancy floors (waves per SIMD) that the FP32 variants reach without
+// spills: 8 (<= 64 VGPRs) with two energies per lane, 6 (<= 80) with four;
+// the rest keep the compiler's default.
+template <typename T, int EPL>
+constexpr int sweep_min_waves() {
+  return (sizeof(T) == 4 && EPL == 4) ? 6 : (sizeof(T) == 4 && EPL == 2) ? 8 : 1;
+}
+
 template <typename T, int EPL, int MODE>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL>())))
+sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
                                                     const cpx<T>* __restrict__ bc_g_prev,
                                                     const cpx<T>* __restrict__ bc_gt_prev,
                                                     cpx<T>* __restrict__ bc_g_next,
@@ -249,14 +364,17 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, const node4<T>*
 // and a bundle of 64/G of its segments) from a queue sorted by cost until
 // the queue is empty; every wave reaches that exit.
 template <typename T, int EPL>
-__global__ void __launch_bounds__(256) batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL>())))
+batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
                                                           const int2* __restrict__ tiles, int ntiles,
                                                           int* __restrict__ counter) {
   const int l64 = threadIdx.x & 63;
   while (true) {
     int t = 0;
     if (l64 == 0) t = atomicAdd(counter, 1);
-    t = __shfl(t, 0, 64);
+    // all 64 lanes are active here, so the first active lane is lane 0; the
+    // tile index becomes wave-uniform and the grain's arguments scalar loads
+    t = __builtin_amdgcn_readfirstlane(t);
     if (t >= ntiles) break;
     const int2 tile = tiles[t];
     const BatchGrainDev& gd = grains[tile.x];
@@ -277,7 +395,9 @@ __global__ void reset_counter_kernel(int* counter) {
 // rotate back + angle sums + gap / current / free energy
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) rotate_back_kernel(BackArgs a) {
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  // each XCD takes a contiguous band of grain cells: neighbouring cells share
+  // lattice corners, which then meet in the same L2
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (c >= a.ncg) return;
   const int cell = a.grain_cells[c];
   constexpr int MAXC = 4;
@@ -295,11 +415,11 @@ __global__ void __launch_bounds__(256) rotate_back_kernel(BackArgs a) {
       const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
       const int64_t s = a.rb_idx[o];
       const double w = a.rb_w[o];
-      const double* v = a.node_out + s * 4;
-      cfx += v[0] * w;
-      cfy += v[1] * w;
-      cg += v[2] * w;
-      ci += v[3] * w;
+      const double4 v = reinterpret_cast<const double4*>(a.node_out)[s];
+      cfx += v.x * w;
+      cfy += v.y * w;
+      cg += v.z * w;
+      ci += v.w * w;
     }
     const double wk = a.wk[k];
     double dkx = 0.0, dky = 0.0;
@@ -577,12 +697,19 @@ __global__ void __launch_bounds__(256) unpad_A_kernel(const double2* __restrict_
 static inline unsigned nblk(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
 
 template <typename T>
-void launch_interp(const InterpArgs& a, void* nodes, hipStream_t st) {
+void launch_interp(const InterpArgs& a, void* cells, void* nodes, hipStream_t st) {
   if (a.nslot == 0) return;
-  hipLaunchKernelGGL(interp_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a, static_cast<node4<T>*>(nodes));
+  if (cells && a.ncomp == 1) {
+    hipLaunchKernelGGL(pack_cells_kernel<T>, dim3(nblk(a.ncell)), dim3(256), 0, st, a.delta, a.A, a.geom.mask,
+                       a.ncell, static_cast<cell4<T>*>(cells));
+    hipLaunchKernelGGL(interp1_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a,
+                       static_cast<const cell4<T>*>(cells), static_cast<node4<T>*>(nodes));
+  } else {
+    hipLaunchKernelGGL(interp_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a, static_cast<node4<T>*>(nodes));
+  }
 }
-template void launch_interp<double>(const InterpArgs&, void*, hipStream_t);
-template void launch_interp<float>(const InterpArgs&, void*, hipStream_t);
+template void launch_interp<double>(const InterpArgs&, void*, void*, hipStream_t);
+template void launch_interp<float>(const InterpArgs&, void*, void*, hipStream_t);
 
 template <typename T, int EPL, int MODE>
 static void launch_sweep_t(const SweepArgs& a, const SweepBufs& b, hipStream_t st) {

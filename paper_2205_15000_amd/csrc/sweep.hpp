@@ -174,8 +174,9 @@ void launch_interp_adjoint(const InterpAdjArgs& a, hipStream_t st);
 void launch_omega_delta_adjoint(const OmegaAdjArgs& a, hipStream_t st);
 void launch_curl_adjoint(const double* B, double* gA, int nx, int ny, double h, double s, hipStream_t st);
 
+// cells: workspace of ncell cell4<T> records, used when ncomp == 1 (else nullptr)
 template <typename T>
-void launch_interp(const InterpArgs& a, void* nodes, hipStream_t st);
+void launch_interp(const InterpArgs& a, void* cells, void* nodes, hipStream_t st);
 template <typename T>
 void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
