@@ -147,6 +147,51 @@ __device__ __forceinline__ cpx<T> riccati_step(cpx<T> g, const StepNode<T>& s, T
   return mk((c0x * ex + c0y * ey) * rn, (c0y * ex - c0x * ey) * rn);
 }
 
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Principal square root as csqrt, with u = v/2, v = |w| + |x|: sqrt u = v k and
+// y / (2 sqrt u) = y k for k = 1/sqrt(2 v).
+template <typename T>
+__device__ __forceinline__ cpx<T> csqrt_v(T wx, T wy) {
+  const T r = dsqrt(fmaT(wx, wx, wy * wy));
+  const T v = r + dabs(wx);
+  const T k = drsq(dmax(v + v, tiny<T>()));
+  const T t = v * k;
+  const T yq = wy * k;
+  const bool pos = wx >= T(0);
+  return mk(pos ? t : dabs(yq), pos ? yq : dsign(t, wy));
+}
+
+// The same implicit-midpoint step as riccati_step, rearranged for fewer
+// operations.  Per step (shared by all energies): C2 = 2 c2 and C8 = 8 c2
+// with c2 = (i h/4) conj(dm).  Per energy: kx = -h Im z - 1 and ky = h Re z
+// (k = i h z - 1) and kx4 = kx + 4.  Then
+//   c1 = C2 g + k,   C0 = 2 c0 = (c1 + k + 4) g - 8 conj(c2),
+//   disc = c1^2 - 4 c2 c0 = c1^2 - C2 C0,
+//   g' = 2 c0 / (-c1 + sqrt(disc)) = C0 / (s sqrt(disc) - c1)
+// with the sign s = -1 where the principal root points away from -c1.
+template <typename T>
+struct StepC {
+  T C2x, C2y, C8x, C8y;
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> riccati_step_c(cpx<T> g, const StepC<T>& s, T kx, T kx4, T ky) {
+  const T c1x = fmaT(s.C2x, g.x, fmaT(-s.C2y, g.y, kx));
+  const T c1y = fmaT(s.C2x, g.y, fmaT(s.C2y, g.x, ky));
+  const T p2x = c1x + kx4, p2y = c1y + ky;
+  const T C0x = fmaT(p2x, g.x, fmaT(-p2y, g.y, -s.C8x));
+  const T C0y = fmaT(p2x, g.y, fmaT(p2y, g.x, s.C8y));
+  const T dx = fmaT(c1x, c1x, fmaT(-c1y, c1y, fmaT(-s.C2x, C0x, s.C2y * C0y)));
+  const T tq = fmaT(s.C2x, C0y, s.C2y * C0x);
+  const T dy = fmaT(c1x + c1x, c1y, -tq);
+  const cpx<T> rt = csqrt_v(dx, dy);
+  const T sg = rt.x * c1x + rt.y * c1y > T(0) ? T(-1) : T(1);
+  const T ex = fmaT(sg, rt.x, -c1x), ey = fmaT(sg, rt.y, -c1y);
+  const T rn = drcp(fmaT(ex, ex, ey * ey));
+  return mk(fmaT(C0x, ex, C0y * ey) * rn, fmaT(C0y, ex, -(C0x * ey)) * rn);
+}
+
 // Stable homogeneous root of D* g^2 + 2 z g + D = 0: -D / (z + s) with
 // s = sqrt(z^2 - |D|^2) on the branch Im s > 0.
 template <typename T>

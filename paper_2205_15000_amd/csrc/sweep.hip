@@ -166,15 +166,13 @@ __global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<
 // (energy e = lane * EPL + i).  Step t (t = 0..n) joins value slot t-1 and t;
 // a boundary point takes the value of the nearest slot (App. C), so the
 // half-step value is the mean of the two slot values with V(-1) = V(0) and
-// V(n) = V(n-1).  gamma runs t = 0..n, gamma~ t = n..0 with D -> -D*.
+// V(n) = V(n-1).  gamma runs t = 0..n, gamma~ t = n..0 with D -> -D*.  The
+// partial end steps (t = 0 and t = n) are peeled off the loops, so interior
+// steps use per-energy constants formed once for the full step h.
 //
 // Per node and pole (Sec. II.A): X = gamma gamma~, g = -i pi (1-X)/(1+X),
-// f = -2 i pi gamma/(1+X), f~ = 2 i pi gamma~/(1+X).  The pole sums use
-//   f + conj f~ = -2 i pi (gamma/(1+X) + conj(gamma~/(1+X))),
-//   Re g = pi Im((1-X)/(1+X)),
-//   (D* f + D f~) / (pi + i g) = i (D gamma~ - D* gamma)  since
-//   pi + i g = 2 pi / (1+X),
-// so the Eilenberger free-energy term needs no division.
+// f = -2 i pi gamma/(1+X), f~ = 2 i pi gamma~/(1+X); the pole sums are
+// formed from 1/(1+X) alone (identities at node_sums below).
 // --------------------------------------------------------------------------
 template <typename T, int EPL, int MODE>
 __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, int lane,
@@ -194,13 +192,42 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 
   T ex[EPL], ey[EPL];
   double rw[EPL];
+  // interior steps (length h): kx = -h Im z - 1, kx + 4 and h Re(eps) per energy
+  T kxi[EPL], kx4i[EPL], hexi[EPL];
   for (int i = 0; i < EPL; ++i) {
     const int e = e0 + i < a.n_e ? e0 + i : a.n_e - 1;
     ex[i] = static_cast<T>(a.eps[2 * (a.e_off + e)]);
     ey[i] = static_cast<T>(a.eps[2 * (a.e_off + e) + 1]);
     rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + e] : 0.0;
+    kxi[i] = fmaT(-hfull, ey[i], T(-1));
+    kx4i[i] = fmaT(-hfull, ey[i], T(3));
+    hexi[i] = hfull * ex[i];
   }
   const bool full = e0 + EPL <= a.n_e;
+  const T hq4 = T(0.25) * hfull, hqa = T(0.5) * q * hfull;
+
+  // Step with the half-step values (mean of two slots; sd = -1 applies
+  // D -> -D* for gamma~).  End steps take every constant from their length.
+  auto end_step = [&](cpx<T>* gv, const node4<T>& pv, const node4<T>& cv, T hs, T sd) {
+    const T h4 = T(0.25) * hs;
+    StepC<T> c;
+    c.C2x = h4 * (pv.dy + cv.dy);
+    c.C2y = h4 * (sd * (pv.dx + cv.dx));
+    c.C8x = T(4) * c.C2x;
+    c.C8y = T(4) * c.C2y;
+    const T qa = T(0.5) * q * (pv.a + cv.a);
+    for (int i = 0; i < EPL; ++i)
+      gv[i] = riccati_step_c(gv[i], c, fmaT(-hs, ey[i], T(-1)), fmaT(-hs, ey[i], T(3)), hs * (qa + ex[i]));
+  };
+  auto mid_step = [&](cpx<T>* gv, const node4<T>& pv, const node4<T>& cv, T sd) {
+    StepC<T> c;
+    c.C2x = hq4 * (pv.dy + cv.dy);
+    c.C2y = hq4 * (sd * (pv.dx + cv.dx));
+    c.C8x = T(4) * c.C2x;
+    c.C8y = T(4) * c.C2y;
+    const T hq = hqa * (pv.a + cv.a);
+    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_c(gv[i], c, kxi[i], kx4i[i], hq + hexi[i]);
+  };
 
   // ---- gamma: R_min -> R_max
   cpx<T> g[EPL];
@@ -223,23 +250,22 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
       for (int i = 0; i < EPL; ++i) g[i] = bulk_root(qa + ex[i], ey[i], prev.dx, prev.dy);
     }
   }
-  for (int t = 0; t <= n; ++t) {
-    const node4<T> cur = nodes[slot0 + (t < last ? t : last)];
-    const T hs = t == 0 ? hfirst : (t == n ? hlast : hfull);
-    const StepNode<T> sn = step_node(T(0.5) * (prev.dx + cur.dx), T(0.5) * (prev.dy + cur.dy), hs);
-    const T qam = q * (T(0.5) * (prev.a + cur.a));
-    for (int i = 0; i < EPL; ++i) g[i] = riccati_step(g[i], sn, qam + ex[i], ey[i]);
+  auto store_g = [&](int t) {
+    cpx<T>* dst = gbuf + (slot0 + t) * a.n_e + e0;
+    for (int i = 0; i < EPL; ++i)
+      if (full || e0 + i < a.n_e) dst[i] = g[i];
+  };
+  // step 0 from R_min (the boundary point takes slot 0's values)
+  end_step(g, prev, prev, hfirst, T(1));
+  if (MODE != 2 && n > 0) store_g(0);
+  for (int t = 1; t < n; ++t) {
+    const node4<T> cur = nodes[slot0 + t];
+    mid_step(g, prev, cur, T(1));
     prev = cur;
-    if (MODE != 2 && t < n) {
-      cpx<T>* dst = gbuf + (slot0 + t) * a.n_e + e0;
-      if (full) {
-        for (int i = 0; i < EPL; ++i) dst[i] = g[i];
-      } else {
-        for (int i = 0; i < EPL; ++i)
-          if (e0 + i < a.n_e) dst[i] = g[i];
-      }
-    }
+    if (MODE != 2) store_g(t);
   }
+  // step n to R_max (the boundary point takes slot n-1's values)
+  if (n > 0) end_step(g, prev, prev, hlast, T(1));
   if (MODE != 1) {
     cpx<T>* dst = bc_g_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
@@ -267,42 +293,41 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
       for (int i = 0; i < EPL; ++i) gt[i] = bulk_root(qa + ex[i], ey[i], -prev.dx, prev.dy);
     }
   }
-  for (int t = n; t >= 0; --t) {
-    const node4<T> cur = nodes[slot0 + (t >= 1 ? t - 1 : 0)];
-    const T hs = t == 0 ? hfirst : (t == n ? hlast : hfull);
-    const StepNode<T> sn = step_node(-T(0.5) * (prev.dx + cur.dx), T(0.5) * (prev.dy + cur.dy), hs);
-    const T qam = q * (T(0.5) * (prev.a + cur.a));
-    for (int i = 0; i < EPL; ++i) gt[i] = riccati_step(gt[i], sn, qam + ex[i], ey[i]);
-    prev = cur;
-    if (MODE == 2 || t == 0) continue;
-    const int64_t node = slot0 + t - 1;
+
+  // Per node and pole (Sec. II.A), with X = gamma gamma~ and I = 1/(1+X):
+  //   f + conj f~ = -2 i pi [Re((gamma + gamma~) I) + i Im((gamma - gamma~) I)],
+  //   Re g = pi Im((1-X)/(1+X)) = 2 pi Im I,
+  //   (D* f + D f~) / (pi + i g) = i (D gamma~ - D* gamma)  since pi + i g = 2 pi I,
+  // so the Eilenberger free-energy term needs no division.
+  auto node_sums = [&](int64_t node, const node4<T>& nv) {
     const cpx<T>* src = gbuf + node * a.n_e;
     if (MODE == 0) {
       double sfx = 0.0, sfy = 0.0, sg = 0.0, s1 = 0.0, s2 = 0.0;
       for (int i = 0; i < EPL; ++i) {
         // padded energies (weight 0) read the node's last pole: in range
         const cpx<T> gg = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
-        const cpx<T> x = gg * gt[i];
-        const T dxr = T(1) + x.x;
-        const T ri = drcp(dxr * dxr + x.y * x.y);
-        const cpx<T> inv = mk(dxr * ri, -x.y * ri);
-        const cpx<T> u = gg * inv;      // gamma / (1+X)
-        const cpx<T> v = gt[i] * inv;   // gamma~ / (1+X)
-        const T img = inv.y - (gg.x * v.y + gg.y * v.x);  // Im((1-X)/(1+X))
+        const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
+        const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
+        const T dxr = T(1) + xx;
+        const T ri = drcp(fmaT(dxr, dxr, xy * xy));
+        const T ix = dxr * ri, iy = -xy * ri;  // I = 1/(1+X)
+        const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
+        const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
+        const T ax = fmaT(sxs, ix, -(sys * iy));  // Re((gamma + gamma~) I)
+        const T by = fmaT(dxs, iy, dys * ix);     // Im((gamma - gamma~) I)
         const double r = rw[i];
-        sfx += r * static_cast<double>(u.x + v.x);
-        sfy += r * static_cast<double>(u.y - v.y);
-        sg += r * static_cast<double>(img);
-        s1 += r * static_cast<double>(gg.y - gt[i].y);
-        s2 += r * static_cast<double>(gg.x + gt[i].x);
+        sfx += r * static_cast<double>(ax);
+        sfy += r * static_cast<double>(by);
+        sg += r * static_cast<double>(iy);
+        s1 += r * static_cast<double>(dys);
+        s2 += r * static_cast<double>(sxs);
       }
       // Im(D* gamma - D gamma~) summed over the lane's poles
-      const double si = static_cast<double>(cur.dx) * s1 - static_cast<double>(cur.dy) * s2;
-      // S_f = t~ sum R (f + conj f~) = -2 i pi t~ (sfx + i sfy), S_g = pi t~ sg,
-      // S_I = 2 pi t~ sum R Re[i (D gamma~ - D* gamma)] = 2 pi t~ si
+      const double si = static_cast<double>(nv.dx) * s1 - static_cast<double>(nv.dy) * s2;
+      // S_f = -2 i pi t~ (sfx + i sfy), S_g = 2 pi t~ sg, S_I = 2 pi t~ si
       if (a.G >= 4) {
         // lane q of the group (q < 4) ends with component q of the node's sums
-        const double v = group_sum4_scatter(sfy, -sfx, 0.5 * sg, si, a.G, lane);
+        const double v = group_sum4_scatter(sfy, -sfx, sg, si, a.G, lane);
         if (lane < 4) a.node_out[node * 4 + scatter_index(lane)] = a.twopi_tt * v;
       } else {
         const double ox = group_sum(sfy, a.G), oy = group_sum(sfx, a.G);
@@ -311,25 +336,36 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
           double4 o;
           o.x = a.twopi_tt * ox;
           o.y = -a.twopi_tt * oy;
-          o.z = 0.5 * a.twopi_tt * oz;
+          o.z = a.twopi_tt * oz;
           o.w = a.twopi_tt * ow;
           reinterpret_cast<double4*>(a.node_out)[node] = o;
         }
       }
-    } else {  // MODE 1: N/N_F = -Im g / pi = Re((1-X)/(1+X)) per energy
+    } else {  // MODE 1: N/N_F = -Im g / pi = Re((1-X)/(1+X)) = 2 Re I - 1 per energy
       T* dst = ebuf + node * a.n_e + e0;
       for (int i = 0; i < EPL; ++i) {
         if (e0 + i >= a.n_e) continue;
         const cpx<T> gg = src[e0 + i];
-        const cpx<T> x = gg * gt[i];
-        const T dxr = T(1) + x.x;
-        const T ri = drcp(dxr * dxr + x.y * x.y);
-        const cpx<T> inv = mk(dxr * ri, -x.y * ri);
-        const cpx<T> v = gt[i] * inv;
-        dst[i] = inv.x - (gg.x * v.x - gg.y * v.y);
+        const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
+        const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
+        const T dxr = T(1) + xx;
+        const T ri = drcp(fmaT(dxr, dxr, xy * xy));
+        dst[i] = fmaT(T(2) * dxr, ri, T(-1));
       }
     }
+  };
+
+  // step n from R_max (boundary point = slot n-1; the whole segment if n = 0)
+  end_step(gt, prev, prev, n > 0 ? hlast : hfirst, T(-1));
+  if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev);
+  for (int t = n - 1; t >= 1; --t) {
+    const node4<T> cur = nodes[slot0 + t - 1];
+    mid_step(gt, prev, cur, T(-1));
+    prev = cur;
+    if (MODE != 2) node_sums(slot0 + t - 1, cur);
   }
+  // step 0 to R_min (boundary point = slot 0)
+  if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
   if (MODE != 1) {
     cpx<T>* dst = bc_gt_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)

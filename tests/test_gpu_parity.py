@@ -72,6 +72,35 @@ def test_iteration_map_fp64_matches_oracle(name):
     g.close()
 
 
+@pytest.mark.parametrize("n_poles,epl", [(8, 1), (8, 2), (8, 4), (8, 8), (64, 1), (64, 2), (64, 4)])
+def test_every_lane_shape_matches_oracle(n_poles, epl):
+    """Forced energies per lane cover every lanes-per-segment G of the
+    per-node pole-sum reduction: 8 poles give G = 8, 4, 2, 1 and 64 poles
+    G = 64, 32, 16 (two chained sweeps, FP64, against the oracle)."""
+    qs = _qs()
+    name = "small_d110_field"
+    sp = dict(wl.spec(name), n_poles=n_poles)
+    _note("case %s fp64, %d poles, %d energies per lane" % (name, n_poles, epl))
+    g = qs.Grain(sp, "fp64")
+    g.set_lanes(epl)
+    e, G = g.lanes()
+    assert e == epl and G == max(1, n_poles // epl)
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    bc = None
+    for it in range(2):
+        dn, j, om, od = g.sweep(dd, ad, omega_density=True)
+        ref = og.iterate(d0, a0, bc)
+        bc = ref["bc"]
+        m = og.mask
+        assert _close(dn.cpu().numpy()[:, m], ref["delta_new"][:, m], FP64_TOL), (it, G)
+        assert _close(j.cpu().numpy(), ref["j"], FP64_TOL), (it, G)
+        assert _close(od.cpu().numpy(), ref["omega_density"], FP64_TOL), (it, G)
+    g.close()
+
+
 @pytest.mark.parametrize("name", ["s_disc_32", "small_d110_field", "small_holed_mixed"])
 def test_iteration_map_mixed_precision_error(name):
     qs = _qs()
