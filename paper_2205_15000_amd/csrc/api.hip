@@ -921,7 +921,7 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) bcl[a][b] = dalloc(2 * rb * g->nseg * n_e);
     do_interp(g, delta, A_ind, st);
-    const int blk_all = 512;  // energies of one boundary-only launch (64 lanes x 8)
+    const int blk_all = 256;  // energies of one boundary-only launch (64 lanes x 4)
     int cur = 0;
     qc::SweepBufs b;
     b.nodes = g->nodes;
@@ -940,10 +940,15 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
       }
       cur = 1 - cur;
     }
-    // output pass in energy blocks bounded by ~8 GiB of node buffers
+    // output pass in energy blocks of up to 64 (32 lanes of two energies per
+    // segment: long contiguous gamma and LDOS rows), bounded by half of the
+    // free device memory
+    size_t free_b = 0, total_b = 0;
+    hcheck(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const double budget = std::max(static_cast<double>(1 << 30), 0.5 * static_cast<double>(free_b));
     const double per_e = static_cast<double>(g->nslot) * 3.0 * rb;
     int blk = 64;
-    while (blk > 1 && blk * per_e > 8.0 * (1 << 30)) blk >>= 1;
+    while (blk > 1 && blk * per_e > budget) blk >>= 1;
     blk = std::min(blk, n_e);
     lg = dalloc(2 * rb * g->nslot * blk);
     le = dalloc(rb * g->nslot * blk);

@@ -191,17 +191,14 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   const int e0 = lane * EPL;
 
   T ex[EPL], ey[EPL];
-  double rw[EPL];
-  // interior steps (length h): kx = -h Im z - 1, kx + 4 and h Re(eps) per energy
-  T kxi[EPL], kx4i[EPL], hexi[EPL];
+  // interior steps (length h): kx = -h Im z - 1 and kx + 4 per energy
+  T kxi[EPL], kx4i[EPL];
   for (int i = 0; i < EPL; ++i) {
     const int e = e0 + i < a.n_e ? e0 + i : a.n_e - 1;
     ex[i] = static_cast<T>(a.eps[2 * (a.e_off + e)]);
     ey[i] = static_cast<T>(a.eps[2 * (a.e_off + e) + 1]);
-    rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + e] : 0.0;
     kxi[i] = fmaT(-hfull, ey[i], T(-1));
     kx4i[i] = fmaT(-hfull, ey[i], T(3));
-    hexi[i] = hfull * ex[i];
   }
   const bool full = e0 + EPL <= a.n_e;
   const T hq4 = T(0.25) * hfull, hqa = T(0.5) * q * hfull;
@@ -226,7 +223,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
     c.C8x = T(4) * c.C2x;
     c.C8y = T(4) * c.C2y;
     const T hq = hqa * (pv.a + cv.a);
-    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_c(gv[i], c, kxi[i], kx4i[i], hq + hexi[i]);
+    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_c(gv[i], c, kxi[i], kx4i[i], fmaT(hfull, ex[i], hq));
   };
 
   // ---- gamma: R_min -> R_max
@@ -258,8 +255,11 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // step 0 from R_min (the boundary point takes slot 0's values)
   end_step(g, prev, prev, hfirst, T(1));
   if (MODE != 2 && n > 0) store_g(0);
+  // slot values are loaded one step ahead, so the load overlaps a step
+  node4<T> nxt = nodes[slot0 + min(1, last)];
   for (int t = 1; t < n; ++t) {
-    const node4<T> cur = nodes[slot0 + t];
+    const node4<T> cur = nxt;
+    nxt = nodes[slot0 + min(t + 1, last)];
     mid_step(g, prev, cur, T(1));
     prev = cur;
     if (MODE != 2) store_g(t);
@@ -273,6 +273,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
 
   // ---- gamma~: R_max -> R_min with D -> -D*
+  double rw[EPL];  // pole weights R_p of the lane's energies (0 for padding)
+  for (int i = 0; i < EPL; ++i)
+    rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + min(e0 + i, a.n_e - 1)] : 0.0;
   cpx<T> gt[EPL];
   prev = nodes[slot0 + last];
   {
@@ -299,13 +302,17 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   //   Re g = pi Im((1-X)/(1+X)) = 2 pi Im I,
   //   (D* f + D f~) / (pi + i g) = i (D gamma~ - D* gamma)  since pi + i g = 2 pi I,
   // so the Eilenberger free-energy term needs no division.
-  auto node_sums = [&](int64_t node, const node4<T>& nv) {
+  // gamma of a node for this lane's energies (padded energies read the
+  // node's last pole, in range; their weight is zero)
+  auto load_g = [&](cpx<T>* gv, int64_t node) {
     const cpx<T>* src = gbuf + node * a.n_e;
+    for (int i = 0; i < EPL; ++i) gv[i] = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
+  };
+  auto node_sums = [&](int64_t node, const node4<T>& nv, const cpx<T>* gn) {
     if (MODE == 0) {
       double sfx = 0.0, sfy = 0.0, sg = 0.0, s1 = 0.0, s2 = 0.0;
       for (int i = 0; i < EPL; ++i) {
-        // padded energies (weight 0) read the node's last pole: in range
-        const cpx<T> gg = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
+        const cpx<T> gg = gn[i];
         const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
         const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
         const T dxr = T(1) + xx;
@@ -345,7 +352,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
       T* dst = ebuf + node * a.n_e + e0;
       for (int i = 0; i < EPL; ++i) {
         if (e0 + i >= a.n_e) continue;
-        const cpx<T> gg = src[e0 + i];
+        const cpx<T> gg = gn[i];
         const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
         const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
         const T dxr = T(1) + xx;
@@ -356,13 +363,20 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   };
 
   // step n from R_max (boundary point = slot n-1; the whole segment if n = 0)
+  cpx<T> gn[EPL];
+  if (MODE != 2) load_g(gn, slot0 + last);
   end_step(gt, prev, prev, n > 0 ? hlast : hfirst, T(-1));
-  if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev);
+  if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev, gn);
+  // slot values are loaded one step ahead (gamma is not: the registers
+  // would cost occupancy, and its load is not on the step's critical path)
+  nxt = nodes[slot0 + max(n - 2, 0)];
   for (int t = n - 1; t >= 1; --t) {
-    const node4<T> cur = nodes[slot0 + t - 1];
+    const node4<T> cur = nxt;
+    nxt = nodes[slot0 + max(t - 2, 0)];
+    if (MODE != 2) load_g(gn, slot0 + t - 1);
     mid_step(gt, prev, cur, T(-1));
     prev = cur;
-    if (MODE != 2) node_sums(slot0 + t - 1, cur);
+    if (MODE != 2) node_sums(slot0 + t - 1, cur, gn);
   }
   // step 0 to R_min (boundary point = slot 0)
   if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
@@ -374,11 +388,11 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 }
 
 // Occupancy floors (waves per SIMD) that the FP32 variants reach without
-// spills: 8 (<= 64 VGPRs) with two energies per lane, 6 (<= 80) with four;
+// spills: 7 (<= 72 VGPRs) with two energies per lane, 5 (<= 96) with four;
 // the rest keep the compiler's default.
 template <typename T, int EPL>
 constexpr int sweep_min_waves() {
-  return (sizeof(T) == 4 && EPL == 4) ? 6 : (sizeof(T) == 4 && EPL == 2) ? 8 : 1;
+  return (sizeof(T) == 4 && EPL == 4) ? 5 : (sizeof(T) == 4 && EPL == 2) ? 7 : 1;
 }
 
 template <typename T, int EPL, int MODE>
