@@ -21,6 +21,8 @@ headline):
     --mode batch [--grains N --iters K]
                                   N seeded grains iterated together (persistent
                                   tile-queue sweep, hipGraph replay)
+    --mode adjoint [--iters K]    FP64 sweep and its reverse mode on the 200x200
+                                  d-wave disc (48 poles, 2 flux quanta)
 """
 import argparse
 import json
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch"], default="iteration")
+    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch", "adjoint"], default="iteration")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--prior", type=int, default=200)
     ap.add_argument("--bc-iters", type=int, default=20)
@@ -204,6 +206,40 @@ def mode_batch(qs, torch, wl, n, iters):
             "finite": bool(torch.isfinite(d).all())}
 
 
+def mode_adjoint(qs, torch, wl, iters):
+    """Forward sweep and reverse mode (frozen boundary store) of the FP64
+    d-wave disc, R = 20 xi0 on 200x200, 64 angles, 48 poles: wall time per
+    call with inputs resident, after one warmup each."""
+    name = "d_disc_200"
+    sp = wl.spec(name)
+    g = qs.Grain(sp, "fp64")
+    dd = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    ad = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    rng = np.random.default_rng(5)
+    gdn = torch.as_tensor(rng.standard_normal(dd.shape) + 1j * rng.standard_normal(dd.shape)).cuda()
+    gj = torch.as_tensor(rng.standard_normal((2, sp["ny"], sp["nx"]))).cuda()
+    g.sweep(dd, ad)
+    g.sweep(dd, ad)
+    g.sweep_adjoint(dd, ad, gdn, gj, 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        g.sweep(dd, ad, total=False)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / iters
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        gd, ga = g.sweep_adjoint(dd, ad, gdn, gj, 1.0)
+    torch.cuda.synchronize()
+    adj = (time.perf_counter() - t0) / iters
+    steps = g.steps_per_sweep
+    finite = bool(torch.isfinite(torch.view_as_real(gd)).all() and torch.isfinite(ga).all())
+    g.close()
+    return {"metric": "adjoint sweep time", "workload": name, "precision": "fp64", "iterations": iters,
+            "forward_ms": 1e3 * fwd, "adjoint_ms": 1e3 * adj, "adjoint_over_forward": adj / fwd,
+            "forward_steps": steps, "forward_steps_per_s": steps / fwd, "finite": finite}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -219,6 +255,8 @@ def main():
             res = mode_converge(qs, torch, wl, args.iters or 3000)
         elif args.mode == "ldos":
             res = mode_ldos(qs, torch, wl, args.prior, args.bc_iters)
+        elif args.mode == "adjoint":
+            res = mode_adjoint(qs, torch, wl, args.iters or 5)
         else:
             res = mode_batch(qs, torch, wl, args.grains, args.iters or 6)
         print(json.dumps(res), flush=True)
