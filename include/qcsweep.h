@@ -66,7 +66,8 @@ typedef enum { QC_FP64 = 0, QC_MIXED = 1 } qc_precision;
 typedef enum {
   QC_SHAPE_DISC = 0,             /* cx, cy, radius */
   QC_SHAPE_REGULAR_POLYGON = 1,  /* cx, cy, n_edges, side, rotation (turns) */
-  QC_SHAPE_POLYGON = 2           /* convex, vertices vx/vy counter-clockwise */
+  QC_SHAPE_POLYGON = 2,          /* convex, vertices vx/vy counter-clockwise */
+  QC_SHAPE_MASK = 3              /* cells given by mask (grid of the descriptor) */
 } qc_shape_kind;
 
 typedef enum {
@@ -78,7 +79,13 @@ typedef enum {
 /* One geometry component (App. B).  Components are combined in order:
  * add != 0 unites it with the grain, add == 0 removes it.  Points on a
  * boundary count as inside.  A regular polygon with rotation 0 has a
- * horizontal bottom edge.  vx/vy are host pointers read during the call. */
+ * horizontal bottom edge.  A mask component takes mask[ny][nx] (nonzero =
+ * the cell centre is inside) on the descriptor's grid; its exact boundary
+ * is the marching-squares contour of the mask at level 1/2 over the cell
+ * centres (cells beyond the array outside; a square with only two diagonal
+ * corners inside keeps them apart), and inside is the even-odd rule of
+ * that contour, so the cell centres inside are exactly the mask's.
+ * vx/vy/mask are host pointers read during the call. */
 typedef struct {
   int kind;
   int add;
@@ -90,6 +97,7 @@ typedef struct {
   const double* vx;
   const double* vy;
   int nv;
+  const uint8_t* mask;
 } qc_shape;
 
 /* Grain description.  All pointers are host pointers read during the call.

@@ -62,6 +62,74 @@ def regular_polygon(cx, cy, n_edges, side, rotation=0.0, add=True):
     return Polygon(vx, vy, add)
 
 
+# Contour pieces of one square of four neighbouring cell centres, by which
+# corners are inside (bit 1 lower-left, 2 lower-right, 4 upper-right, 8
+# upper-left); the end points are the midpoints of the square's sides
+# (B bottom, R right, T top, L left), where the level 1/2 crosses.  Squares
+# with only two diagonal corners inside keep those corners apart.
+_MS_CASES = {
+    1: [("L", "B")], 2: [("B", "R")], 3: [("L", "R")], 4: [("R", "T")],
+    5: [("L", "B"), ("R", "T")], 6: [("B", "T")], 7: [("L", "T")], 8: [("T", "L")],
+    9: [("B", "T")], 10: [("B", "R"), ("T", "L")], 11: [("R", "T")], 12: [("L", "R")],
+    13: [("B", "R")], 14: [("L", "B")],
+}
+
+
+class MaskShape:
+    """Component given by a cell mask on the reference grid (App. B allows
+    grains of any shape; this is the reading for a grain given only by its
+    cells).  Its boundary is the marching-squares contour of the mask at
+    level 1/2 over the cell centres, with every cell beyond the array
+    outside; inside is the even-odd rule of that closed polyline.  Edges are
+    listed square by square, rows of squares bottom to top, each row left to
+    right."""
+
+    def __init__(self, mask, grid, add=True):
+        m = np.asarray(mask) != 0
+        ny, nx = m.shape
+        if (nx, ny) != (grid.nx, grid.ny):
+            raise ValueError("mask shape does not match the grid")
+        h, x0, y0 = grid.h, grid.x0, grid.y0
+
+        def val(i, j):
+            return bool(m[j, i]) if 0 <= i < nx and 0 <= j < ny else False
+
+        ax, ay, bx, by = [], [], [], []
+        for j in range(-1, ny):
+            for i in range(-1, nx):
+                case = (1 if val(i, j) else 0) | (2 if val(i + 1, j) else 0) | \
+                       (4 if val(i + 1, j + 1) else 0) | (8 if val(i, j + 1) else 0)
+                if case in (0, 15):
+                    continue
+                pts = {"B": (x0 + (i + 1) * h, y0 + (j + 0.5) * h), "T": (x0 + (i + 1) * h, y0 + (j + 1.5) * h),
+                       "L": (x0 + (i + 0.5) * h, y0 + (j + 1) * h), "R": (x0 + (i + 1.5) * h, y0 + (j + 1) * h)}
+                for a, b in _MS_CASES[case]:
+                    ax.append(pts[a][0])
+                    ay.append(pts[a][1])
+                    bx.append(pts[b][0])
+                    by.append(pts[b][1])
+        self.ax, self.ay = np.array(ax), np.array(ay)
+        self.bx, self.by = np.array(bx), np.array(by)
+        self.add = bool(add)
+
+    def inside(self, x, y):
+        # even-odd rule: crossings of the ray to +x, each edge half-open in y
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        shp = np.broadcast(x, y).shape
+        xf = np.broadcast_to(x, shp).ravel()
+        yf = np.broadcast_to(y, shp).ravel()
+        res = np.zeros(xf.shape, dtype=bool)
+        for c0 in range(0, xf.size, 4096):
+            px = xf[c0:c0 + 4096, None]
+            py = yf[c0:c0 + 4096, None]
+            straddle = (self.ay[None, :] > py) != (self.by[None, :] > py)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                xi = self.ax + (py - self.ay) * (self.bx - self.ax) / (self.by - self.ay)
+            res[c0:c0 + 4096] = (np.count_nonzero(straddle & (px < xi), axis=1) % 2) == 1
+        return res.reshape(shp)
+
+
 def domain(shapes, x, y):
     """The grain D as the ordered fold of its components (App. B):
     an added component is united with D, a subtracted one removed."""
@@ -129,6 +197,17 @@ def _primitive_hits(shapes, bx, by, ex, ey):
                     px, py = bx + s * ex, by + s * ey
                     tang = math.atan2(py - sh.cy, px - sh.cx) + 0.5 * math.pi
                     hits.append((s, tang))
+        elif isinstance(sh, MaskShape):
+            # the same line / edge formula as for polygon edges, per contour edge
+            dx, dy = sh.bx - sh.ax, sh.by - sh.ay
+            den = ex * dy - ey * dx
+            ok = den != 0.0
+            with np.errstate(divide="ignore", invalid="ignore"):
+                wx, wy = sh.ax - bx, sh.ay - by
+                s_all = (wx * dy - wy * dx) / den
+                t_all = (wx * ey - wy * ex) / den
+            for m in np.nonzero(ok & (t_all >= 0.0) & (t_all <= 1.0))[0]:
+                hits.append((float(s_all[m]), math.atan2(float(dy[m]), float(dx[m]))))
         else:
             n = len(sh.vx)
             for m in range(n):

@@ -23,7 +23,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 QC_OK, QC_NOT_CONVERGED = 0, 1
 PRECISIONS = {"fp64": 0, "mixed": 1}
-_SHAPES = {"disc": 0, "regular_polygon": 1, "polygon": 2}
+_SHAPES = {"disc": 0, "regular_polygon": 1, "polygon": 2, "mask": 3}
 _GAUGES = {"symmetric": 0, "landau": 1, "solenoid": 2}
 
 
@@ -38,7 +38,7 @@ class _Shape(ctypes.Structure):
                 ("cy", ctypes.c_double), ("radius", ctypes.c_double), ("n_edges", ctypes.c_int),
                 ("side", ctypes.c_double), ("rotation", ctypes.c_double),
                 ("vx", ctypes.POINTER(ctypes.c_double)), ("vy", ctypes.POINTER(ctypes.c_double)),
-                ("nv", ctypes.c_int)]
+                ("nv", ctypes.c_int), ("mask", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class _Desc(ctypes.Structure):
@@ -173,6 +173,12 @@ class _DescHolder:
                 s.vx = vx.ctypes.data_as(_D)
                 s.vy = vy.ctypes.data_as(_D)
                 s.nv = len(vx)
+            elif sh["kind"] == "mask":
+                mk = np.ascontiguousarray(np.asarray(sh["mask"]) != 0, dtype=np.uint8)
+                if mk.shape != (ny, nx):
+                    raise ValueError("mask shape %s does not match the grid (%d, %d)" % (mk.shape, ny, nx))
+                self.keep.append(mk)
+                s.mask = mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         self.keep.append(shapes)
         n_theta = int(spec["n_theta"])
         eta = spec.get("eta")

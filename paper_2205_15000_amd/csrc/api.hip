@@ -120,6 +120,8 @@ void check_desc(const qc_grain_desc* d) {
       if (sh.n_edges < 3 || !(sh.side > 0.0)) throw std::invalid_argument("regular polygon needs >= 3 edges, side > 0");
     } else if (sh.kind == QC_SHAPE_POLYGON) {
       if (sh.nv < 3 || !sh.vx || !sh.vy) throw std::invalid_argument("polygon needs >= 3 vertices");
+    } else if (sh.kind == QC_SHAPE_MASK) {
+      if (!sh.mask) throw std::invalid_argument("mask shape needs a mask");
     } else {
       throw std::invalid_argument("unknown shape kind");
     }
@@ -164,6 +166,8 @@ void fill_plan_inputs(const qc_grain_desc* d, qc::Plan& p) {
         sh.vx.push_back(in.cx + rc * std::cos(a));
         sh.vy.push_back(in.cy + rc * std::sin(a));
       }
+    } else if (in.kind == QC_SHAPE_MASK) {
+      sh = qc::mask_shape(in.mask, d->nx, d->ny, d->x0, d->y0, d->h, in.add != 0);
     } else {
       sh.kind = 1;
       sh.vx.assign(in.vx, in.vx + in.nv);

@@ -18,6 +18,16 @@ bool inside(const Shape& sh, double x, double y) {
     const double dx = x - sh.cx, dy = y - sh.cy;
     return dx * dx + dy * dy <= sh.r * sh.r;
   }
+  if (sh.kind == 2) {
+    // even-odd rule: crossings of the ray to +x, each edge half-open in y
+    bool in = false;
+    for (size_t m = 0; m < sh.ax.size(); ++m) {
+      if ((sh.ay[m] > y) == (sh.by[m] > y)) continue;
+      const double xi = sh.ax[m] + (y - sh.ay[m]) * (sh.bx[m] - sh.ax[m]) / (sh.by[m] - sh.ay[m]);
+      if (x < xi) in = !in;
+    }
+    return in;
+  }
   const size_t n = sh.vx.size();
   for (size_t m = 0; m < n; ++m) {
     const double ax = sh.vx[m], ay = sh.vy[m];
@@ -60,6 +70,17 @@ std::vector<Hit> boundary_hits(const std::vector<Shape>& shapes, double bx, doub
           const double px = bx + s * ex, py = by + s * ey;
           hits.push_back({s, std::atan2(py - sh.cy, px - sh.cx) + 0.5 * kPi});
         }
+      }
+    } else if (sh.kind == 2) {
+      // the polygon-edge formula, per contour edge
+      for (size_t m = 0; m < sh.ax.size(); ++m) {
+        const double dx = sh.bx[m] - sh.ax[m], dy = sh.by[m] - sh.ay[m];
+        const double den = ex * dy - ey * dx;
+        if (den == 0.0) continue;
+        const double wx = sh.ax[m] - bx, wy = sh.ay[m] - by;
+        const double s = (wx * dy - wy * dx) / den;
+        const double tt = (wx * ey - wy * ex) / den;
+        if (tt >= 0.0 && tt <= 1.0) hits.push_back({s, std::atan2(dy, dx)});
       }
     } else {
       const size_t n = sh.vx.size();
@@ -222,6 +243,36 @@ int64_t Plan::steps_per_sweep() const {
   int64_t s = 0;
   for (int64_t k = 0; k < nseg; ++k) s += seg_n[k] + 1;
   return 2 * static_cast<int64_t>(n_poles) * s;
+}
+
+Shape mask_shape(const uint8_t* mask, int nx, int ny, double x0, double y0, double h, bool add) {
+  // contour pieces per square by inside corners (1 lower-left, 2 lower-right,
+  // 4 upper-right, 8 upper-left); 0..3 = side midpoints B, R, T, L
+  static const int kPieces[16][4] = {
+      {-1, -1, -1, -1}, {3, 0, -1, -1}, {0, 1, -1, -1}, {3, 1, -1, -1},
+      {1, 2, -1, -1},   {3, 0, 1, 2},   {0, 2, -1, -1}, {3, 2, -1, -1},
+      {2, 3, -1, -1},   {0, 2, -1, -1}, {0, 1, 2, 3},   {1, 2, -1, -1},
+      {3, 1, -1, -1},   {0, 1, -1, -1}, {3, 0, -1, -1}, {-1, -1, -1, -1}};
+  auto val = [&](int i, int j) {
+    return i >= 0 && i < nx && j >= 0 && j < ny && mask[static_cast<size_t>(j) * nx + i] != 0;
+  };
+  Shape sh;
+  sh.kind = 2;
+  sh.add = add;
+  for (int j = -1; j < ny; ++j)
+    for (int i = -1; i < nx; ++i) {
+      const int c = (val(i, j) ? 1 : 0) | (val(i + 1, j) ? 2 : 0) | (val(i + 1, j + 1) ? 4 : 0) |
+                    (val(i, j + 1) ? 8 : 0);
+      const double px[4] = {x0 + (i + 1) * h, x0 + (i + 1.5) * h, x0 + (i + 1) * h, x0 + (i + 0.5) * h};
+      const double py[4] = {y0 + (j + 0.5) * h, y0 + (j + 1) * h, y0 + (j + 1.5) * h, y0 + (j + 1) * h};
+      for (int q = 0; q < 4 && kPieces[c][q] >= 0; q += 2) {
+        sh.ax.push_back(px[kPieces[c][q]]);
+        sh.ay.push_back(py[kPieces[c][q]]);
+        sh.bx.push_back(px[kPieces[c][q + 1]]);
+        sh.by.push_back(py[kPieces[c][q + 1]]);
+      }
+    }
+  return sh;
 }
 
 void build_plan(Plan& p) {

@@ -19,11 +19,19 @@
 namespace qc {
 
 struct Shape {
-  int kind = 0;  // 0 disc, 1 convex polygon (regular polygons are converted)
+  int kind = 0;  // 0 disc, 1 convex polygon (regular polygons are converted),
+                 // 2 closed polyline from a cell mask (even-odd inside)
   bool add = true;
   double cx = 0, cy = 0, r = 0;
   std::vector<double> vx, vy;  // counter-clockwise
+  std::vector<double> ax, ay, bx, by;  // kind 2: contour edges a -> b
 };
+
+// Kind-2 component from a cell mask [ny][nx] (nonzero = inside) on the grid
+// with cell centres (x0 + (i + 1/2) h, y0 + (j + 1/2) h): the marching-squares
+// contour at level 1/2 over the cell centres, cells beyond the array outside,
+// diagonal-only squares keeping their two corners apart.
+Shape mask_shape(const uint8_t* mask, int nx, int ny, double x0, double y0, double h, bool add);
 
 struct Plan {
   // ---- inputs

@@ -28,6 +28,27 @@ def _square(cx, cy, side, rotation=0.0, add=True):
             "rotation": rotation, "add": add}
 
 
+def _blob_mask(nx=34, ny=30, h=0.5, seed=17):
+    """Seeded non-convex cell mask: three Gaussian bumps minus a hole,
+    thresholded, with a 2x2 checkerboard carved into its edge so that the
+    contour has squares whose diagonal corners alone are inside."""
+    rng = np.random.default_rng(seed)
+    xs = -0.5 * nx * h + (np.arange(nx) + 0.5) * h
+    ys = -0.5 * ny * h + (np.arange(ny) + 0.5) * h
+    X, Y = np.meshgrid(xs, ys)
+    f = np.zeros_like(X)
+    for _ in range(3):
+        cx, cy = rng.uniform(-2.5, 2.5, 2)
+        f += np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * rng.uniform(3.0, 4.0) ** 2))
+    hole = np.exp(-((X - 1.0) ** 2 + (Y + 0.5) ** 2) / (2 * 1.2 ** 2))
+    m = (f - 1.2 * f.max() * hole) > 0.5
+    # carve a checkerboard at the rightmost inside cell of the middle row
+    j = ny // 2
+    i = int(np.nonzero(m[j])[0].max())
+    m[j, i], m[j, i - 1], m[j + 1, i], m[j + 1, i - 1] = False, True, True, False
+    return m.astype(np.uint8)
+
+
 SPECS = {
     # s-wave disc R = 10 xi0 on 32x32 (h = 0.625), 32 angles, 16 poles,
     # t = 0.5, no field (the small Picard case, 50 iterations)
@@ -58,6 +79,11 @@ SPECS = {
     "small_holed_mixed": dict(nx=36, ny=36, h=0.5, shapes=[_disc(0, 0, 8.6), _square(1.3, 0.4, 4.0, 0.1, add=False)],
                               n_theta=24, n_poles=6, t=0.4, components=[("s", 1.0), ("dxy", 0.7)],
                               kappa=0.0, flux_quanta=0.6, gauge="solenoid", charge_sign=-1),
+    # grain given by its cells only (marching-squares boundary), non-convex
+    # with a hole and a saddle square; d-wave, field, finite kappa
+    "small_mask_blob": dict(nx=34, ny=30, h=0.5, shapes=[{"kind": "mask", "mask": _blob_mask(), "add": True}],
+                            n_theta=16, n_poles=6, t=0.4, components=[("dx2y2", 1.0)], crystal_rotation=0.1,
+                            kappa=2.5, flux_quanta=0.7, gauge="symmetric", charge_sign=-1),
     # convex polygon, odd angle count (trapezoid weights), Landau gauge,
     # positive carriers, kappa for the A-solve, 5 poles (padded lanes)
     "small_polygon_landau": dict(nx=30, ny=26, h=0.45,

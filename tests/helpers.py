@@ -12,6 +12,9 @@ def oracle_shapes(sp):
             out.append(geo.Disc(sh["cx"], sh["cy"], sh["radius"], add))
         elif sh["kind"] == "regular_polygon":
             out.append(geo.regular_polygon(sh["cx"], sh["cy"], sh["n_edges"], sh["side"], sh.get("rotation", 0.0), add))
+        elif sh["kind"] == "mask":
+            grid = geo.Grid(sp["nx"], sp["ny"], sp["h"], sp.get("x0"), sp.get("y0"))
+            out.append(geo.MaskShape(sh["mask"], grid, add))
         else:
             out.append(geo.Polygon(sh["vx"], sh["vy"], add))
     return out

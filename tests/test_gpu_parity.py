@@ -18,7 +18,7 @@ from paper_2205_15000_amd import workloads as wl  # noqa: E402
 from oracle import fields, scf as oscf  # noqa: E402
 from helpers import oracle_grain, rel_err  # noqa: E402
 
-SMALL = ["s_disc_32", "small_d110_field", "small_holed_mixed", "small_polygon_landau"]
+SMALL = ["s_disc_32", "small_d110_field", "small_holed_mixed", "small_polygon_landau", "small_mask_blob"]
 FP64_TOL = 1e-10
 
 
@@ -101,7 +101,7 @@ def test_every_lane_shape_matches_oracle(n_poles, epl):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["s_disc_32", "small_d110_field", "small_holed_mixed"])
+@pytest.mark.parametrize("name", ["s_disc_32", "small_d110_field", "small_holed_mixed", "small_mask_blob"])
 def test_iteration_map_mixed_precision_error(name):
     qs = _qs()
     sp = wl.spec(name)

@@ -15,7 +15,7 @@ from oracle import tables
 from helpers import oracle_grain
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SMALL = ["s_disc_32", "small_d110_field", "small_holed_mixed", "small_polygon_landau"]
+SMALL = ["s_disc_32", "small_d110_field", "small_holed_mixed", "small_polygon_landau", "small_mask_blob"]
 
 
 def test_library_exports_every_declared_symbol():
