@@ -298,6 +298,18 @@ qc_status qc_batch_last_ms(const qc_batch* batch, double* ms);
  * iterations advance the self-consistency like qc_batch_iterate. */
 qc_status qc_batch_autotune(qc_batch* batch, int iters_per_trial, int* best_epl, void* stream);
 
+/* Fermi-surface average of the quasiclassical Green's function at the
+ * positive poles of the energy sums (Sec. II.A: g = -i pi (1 - gamma
+ * gamma~)/(1 + gamma gamma~) along each trajectory; rotate-back and angle
+ * weights as for the gap, Sec. III.A): g_out = <g>(R, i eps~_p), complex
+ * interleaved [n_poles][ny][nx] in pole order (ascending eps~_p), zero off
+ * the grain.  delta, A_ind, g_out are device pointers as for qc_sweep.  The
+ * start values are the ones the next qc_sweep would use (the boundary store
+ * left by the latest sweep, bulk roots before the first); the store is not
+ * changed.  Works in pole blocks with temporary device buffers (allocates
+ * and frees; QC_ERR_OOM when they do not fit).  Synchronises the stream. */
+qc_status qc_green_average(qc_grain* grain, const double* delta, const double* A_ind, double* g_out, void* stream);
+
 /* Boundary-value store of qc_sweep (resume without burn-in, App. B).
  * bytes: in/out host size_t; with state == NULL only the size is returned.
  * state: device buffer of that size. */

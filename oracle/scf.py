@@ -155,6 +155,32 @@ class Grain:
             icell += wk * ci
         return self._finish(delta, A_ind, num, jx, jy, icell, (gend, gtend))
 
+    def green_average(self, delta, A_ind, bc_prev=None):
+        """Fermi-surface average <g>(R, i eps~_p) of the quasiclassical
+        Green's function g = -i pi (1 - gamma gamma~)/(1 + gamma gamma~)
+        (Sec. II.A) at each positive pole, from the same marches as
+        iterate() with the given start values; the angle average rotates
+        the per-node g back with the gap's stencils and weights (Sec. III.A).
+        Returns complex [n_poles, ny, nx], zero off the grain."""
+        ny, nx = self.grid.ny, self.grid.nx
+        delta = np.asarray(delta, dtype=np.complex128).reshape(self.ncomp, ny, nx)
+        A_ind = np.asarray(A_ind, dtype=np.float64).reshape(2, ny, nx)
+        m = self.mask
+        eps = 1j * self.zp * self.tt
+        out = np.zeros((len(eps), int(m.sum())), dtype=np.complex128)
+        for k in range(self.n_theta):
+            data = self.data(k)
+            dnode, anode = self.node_values(k, data, delta, A_ind)
+            g0, gt0 = self.start_values(k, data, dnode, anode, eps, bc_prev)
+            gn, gtn, _, _ = sweep.march(data, dnode, anode, eps, self.q, g0, gt0)
+            g, _, _ = sweep.green(gn, gtn)                 # [S, W, E]
+            seg, pos, w = self.rb_stencil(k)
+            cell = np.sum(g[seg, pos, :] * w[:, :, None], axis=1)   # [ncell, E]
+            out += self.wk[k] * cell.T
+        res = np.zeros((len(eps), ny, nx), dtype=np.complex128)
+        res[:, m] = out
+        return res
+
     def _finish(self, delta, A_ind, num, jx, jy, icell, bc):
         ny, nx = self.grid.ny, self.grid.nx
         m = self.mask

@@ -95,6 +95,7 @@ _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes
                                    ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int), _P, _P])
 _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
 _sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
+_sig("qc_green_average", ctypes.c_int, [_P, _P, _P, _P, _P])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)])
 _sig("qc_batch_destroy", None, [_P])
@@ -335,6 +336,7 @@ class Grain:
         self.device = device
         self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
         self.ncomp = len(spec.get("components", [("s", 1.0)]))
+        self.n_poles = int(spec["n_poles"])
         p = _P()
         _check(lib.qc_grain_create(int(device), ctypes.byref(self._h.desc), ctypes.byref(p)))
         self._g = p
@@ -425,6 +427,17 @@ class Grain:
         _check(lib.qc_sweep_adjoint(self._g, dp, ap, gdn, gj, float(g_omega), ctypes.c_void_p(gd.data_ptr()),
                                     ctypes.c_void_p(ga.data_ptr()), _stream(stream)))
         return gd, ga
+
+    def green_average(self, delta, A, stream=None):
+        """<g>(R, i eps_p) at the positive poles, complex [n_poles, ny, nx],
+        with the start values the next sweep would use."""
+        torch = _torch()
+        shp_d = (self.ncomp, self.ny, self.nx)
+        dp = _dptr(delta, torch.complex128, shp_d, "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        out = torch.empty((self.n_poles, self.ny, self.nx), dtype=torch.complex128, device=self._dev())
+        _check(lib.qc_green_average(self._g, dp, ap, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
 
     def get_state(self, stream=None):
         torch = _torch()

@@ -997,6 +997,65 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
   return rs;
 }
 
+qc_status qc_green_average(qc_grain* g, const double* delta, const double* A_ind, double* g_out, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !g_out) return fail(QC_ERR_INVALID, "delta, A_ind and g_out are required");
+  void* lg = nullptr;
+  void* le = nullptr;
+  qc_status rs = guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    const size_t rb = g->real_bytes();
+    do_interp(g, delta, A_ind, st);
+    // poles in blocks of up to 64, bounded by half of the free device memory
+    size_t free_b = 0, total_b = 0;
+    hcheck(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const double budget = std::max(static_cast<double>(1 << 30), 0.5 * static_cast<double>(free_b));
+    const double per_e = static_cast<double>(g->nslot) * 4.0 * rb;
+    int blk = 64;
+    while (blk > 1 && blk * per_e > budget) blk >>= 1;
+    blk = std::min(blk, g->n_poles);
+    lg = dalloc(2 * rb * g->nslot * blk);
+    le = dalloc(2 * rb * g->nslot * blk);
+    qc::launch_fill(g_out, 2LL * g->n_poles * g->ncell, 0.0, st);
+    qc::SweepBufs b;
+    b.nodes = g->nodes;
+    b.bc_g_prev = g->bc[g->bc_cur][0];
+    b.bc_gt_prev = g->bc[g->bc_cur][1];
+    b.bc_g_next = nullptr;
+    b.bc_gt_next = nullptr;
+    b.gbuf = lg;
+    b.ebuf = le;
+    for (int e0 = 0; e0 < g->n_poles; e0 += blk) {
+      const int ne = std::min(blk, g->n_poles - e0);
+      qc::SweepArgs a = sweep_args(g, ne, g->n_poles, e0, g->eps, nullptr);
+      a.bc_valid = g->bc_valid;  // the start values the next sweep would use
+      launch_sweep_timed(g, 3, a, b, st);
+      qc::LdosBackArgs la;
+      la.ncg = g->ncg;
+      la.ncell = g->ncell;
+      la.n_theta = g->n_theta;
+      la.n_e = ne;
+      la.e_off = e0;
+      la.grain_cells = g->grain_cells;
+      la.rb_idx = g->rb_idx;
+      la.rb_w = g->rb_w;
+      la.wk = g->wk;
+      la.out = g_out;
+      if (g->precision == QC_MIXED)
+        qc::launch_green_back<float>(la, le, st);
+      else
+        qc::launch_green_back<double>(la, le, st);
+      hcheck(hipGetLastError(), "green launch");
+    }
+    hcheck(hipStreamSynchronize(st), "sync");
+    return QC_OK;
+  });
+  if (lg) (void)hipFree(lg);
+  if (le) (void)hipFree(le);
+  return rs;
+}
+
 qc_status qc_get_state(const qc_grain* g, void* state, size_t* bytes, void* stream) {
   if (!g || !bytes) return fail(QC_ERR_INVALID, "NULL argument");
   const size_t half = 2 * g->real_bytes() * g->nseg * g->n_poles;

@@ -266,7 +266,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
   // step n to R_max (the boundary point takes slot n-1's values)
   if (n > 0) end_step(g, prev, prev, hlast, T(1));
-  if (MODE != 1) {
+  if (MODE == 0 || MODE == 2) {
     cpx<T>* dst = bc_g_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
       if (e0 + i < a.n_e) dst[i] = g[i];
@@ -348,7 +348,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
           reinterpret_cast<double4*>(a.node_out)[node] = o;
         }
       }
-    } else {  // MODE 1: N/N_F = -Im g / pi = Re((1-X)/(1+X)) = 2 Re I - 1 per energy
+    } else if (MODE == 1) {  // N/N_F = -Im g / pi = Re((1-X)/(1+X)) = 2 Re I - 1 per energy
       T* dst = ebuf + node * a.n_e + e0;
       for (int i = 0; i < EPL; ++i) {
         if (e0 + i >= a.n_e) continue;
@@ -358,6 +358,18 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         const T dxr = T(1) + xx;
         const T ri = drcp(fmaT(dxr, dxr, xy * xy));
         dst[i] = fmaT(T(2) * dxr, ri, T(-1));
+      }
+    } else {  // MODE 3: (1-X)/(1+X) = 2 I - 1 per energy, complex (g = -i pi times it)
+      T* dst = ebuf + 2 * (node * a.n_e + e0);
+      for (int i = 0; i < EPL; ++i) {
+        if (e0 + i >= a.n_e) continue;
+        const cpx<T> gg = gn[i];
+        const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
+        const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
+        const T dxr = T(1) + xx;
+        const T ri = drcp(fmaT(dxr, dxr, xy * xy));
+        dst[2 * i] = fmaT(T(2) * dxr, ri, T(-1));
+        dst[2 * i + 1] = T(-2) * xy * ri;
       }
     }
   };
@@ -380,7 +392,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
   // step 0 to R_min (boundary point = slot 0)
   if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
-  if (MODE != 1) {
+  if (MODE == 0 || MODE == 2) {
     cpx<T>* dst = bc_gt_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
       if (e0 + i < a.n_e) dst[i] = gt[i];
@@ -516,6 +528,32 @@ __global__ void __launch_bounds__(256) ldos_back_kernel(LdosBackArgs a, const T*
     acc += a.wk[k] * v;
   }
   a.out[static_cast<int64_t>(a.e_off + e) * a.ncell + a.grain_cells[c]] = acc;
+}
+
+// Fermi-surface average of g = -i pi (1-X)/(1+X) per cell and energy of the
+// block: the rotate-back of the complex per-node values of sweep mode 3
+template <typename T>
+__global__ void __launch_bounds__(256) green_back_kernel(LdosBackArgs a, const T* __restrict__ ebuf) {
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t c = tid / a.n_e;
+  const int e = static_cast<int>(tid - c * a.n_e);
+  if (c >= a.ncg) return;
+  double ax = 0.0, ay = 0.0;
+  for (int k = 0; k < a.n_theta; ++k) {
+    double vx = 0.0, vy = 0.0;
+    for (int qd = 0; qd < 4; ++qd) {
+      const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
+      const int64_t src = 2 * (static_cast<int64_t>(a.rb_idx[o]) * a.n_e + e);
+      vx += static_cast<double>(ebuf[src]) * a.rb_w[o];
+      vy += static_cast<double>(ebuf[src + 1]) * a.rb_w[o];
+    }
+    ax += a.wk[k] * vx;
+    ay += a.wk[k] * vy;
+  }
+  const double pi = 3.14159265358979323846;
+  double* o = a.out + 2 * (static_cast<int64_t>(a.e_off + e) * a.ncell + a.grain_cells[c]);
+  o[0] = pi * ay;   // -i pi (ax + i ay)
+  o[1] = -pi * ax;
 }
 
 // --------------------------------------------------------------------------
@@ -788,8 +826,10 @@ void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hip
     launch_sweep_m<T, 0>(epl, a, b, st);
   else if (mode == 1)
     launch_sweep_m<T, 1>(epl, a, b, st);
-  else
+  else if (mode == 2)
     launch_sweep_m<T, 2>(epl, a, b, st);
+  else
+    launch_sweep_m<T, 3>(epl, a, b, st);
 }
 template void launch_sweep<double>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
 template void launch_sweep<float>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
@@ -820,6 +860,14 @@ void launch_ldos_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st) {
 }
 template void launch_ldos_back<double>(const LdosBackArgs&, const void*, hipStream_t);
 template void launch_ldos_back<float>(const LdosBackArgs&, const void*, hipStream_t);
+
+template <typename T>
+void launch_green_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st) {
+  hipLaunchKernelGGL(green_back_kernel<T>, dim3(nblk(a.ncg * a.n_e)), dim3(256), 0, st, a,
+                     static_cast<const T*>(ebuf));
+}
+template void launch_green_back<double>(const LdosBackArgs&, const void*, hipStream_t);
+template void launch_green_back<float>(const LdosBackArgs&, const void*, hipStream_t);
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n, v);

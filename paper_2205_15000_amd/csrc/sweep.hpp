@@ -185,6 +185,9 @@ void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles,
                         hipStream_t st);
 template <typename T>
 void launch_ldos_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st);
+// complex counterpart for sweep mode 3: out = -i pi <(1-X)/(1+X)>, interleaved
+template <typename T>
+void launch_green_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st);
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream_t st);
 void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,

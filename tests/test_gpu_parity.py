@@ -273,3 +273,33 @@ def test_full_size_d110_square_400_sampled_cells(precision):
         assert np.max(np.abs(jg - jref)) < 2e-5 * max(np.max(np.abs(jref)), 1e-3)
     assert math.isfinite(om)
     g.close()
+
+
+@pytest.mark.parametrize("name,precision", [("small_d110_field", "fp64"), ("small_mask_blob", "fp64"),
+                                            ("small_holed_mixed", "fp64"), ("small_d110_field", "mixed")])
+def test_green_average_matches_oracle(name, precision):
+    """<g>(R, i eps~_p) per pole: from bulk starts, then with the boundary
+    store of one sweep; the call must leave the store unchanged."""
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s %s: green average" % (name, precision))
+    g = qs.Grain(sp, precision)
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    tol = FP64_TOL if precision == "fp64" else 2e-5
+    m = og.mask
+    got = g.green_average(dd, ad).cpu().numpy()
+    ref = og.green_average(d0, a0, None)
+    assert got.shape == ref.shape
+    assert _close(got[:, m], ref[:, m], tol), rel_err(got[:, m], ref[:, m])
+    assert np.all(got[:, ~m] == 0)
+    g.sweep(dd, ad)
+    bc = og.iterate(d0, a0, None)["bc"]
+    st0 = g.get_state().cpu().numpy().copy()
+    got = g.green_average(dd, ad).cpu().numpy()
+    ref = og.green_average(d0, a0, bc)
+    assert _close(got[:, m], ref[:, m], tol), rel_err(got[:, m], ref[:, m])
+    assert np.array_equal(g.get_state().cpu().numpy(), st0)
+    g.close()

@@ -351,3 +351,47 @@ def test_A_solve_azimuthal_current_gives_radial_field_integral():
         sel = np.abs(r - r0) < 0.06
         pred = np.interp(r0, rr, tail) / kappa ** 2
         assert abs(np.mean(B[sel]) / pred - 1) < 1e-2
+
+
+def test_green_average_uniform_s_wave_is_bulk_closed_form():
+    """Uniform s-wave, no field, bulk start values: every trajectory carries
+    the bulk root, so each pole's Fermi-surface average is the bulk
+    g = -i pi eps~ / sqrt(eps~^2 + |Delta|^2) (Sec. II.A) at every cell."""
+    from oracle import scf as oscf, geometry as geo
+    d = 0.9 * 0.28072974178344257
+    g = oscf.Grain(24, 22, 0.6, [geo.Disc(0.3, -0.2, 5.1)], 16, 7, 0.5)
+    delta = np.full((1, 22, 24), d * np.exp(0.4j))
+    ga = g.green_average(delta, np.zeros((2, 22, 24)))
+    eps = g.zp * g.tt
+    ref = -1j * np.pi * eps / np.sqrt(eps ** 2 + d * d)
+    m = g.mask
+    err = np.max(np.abs(ga[:, m] - ref[:, None]))
+    assert err < 1e-12, err
+    assert np.all(ga[:, ~m] == 0)
+
+
+def test_green_average_matches_the_pole_sum_of_g():
+    """S_g = t~ sum_p R_p Re g_p per node (Sec. II) and the rotate-back is
+    linear, so t~ sum_p R_p Re <g>_p must equal the angle average of the
+    rotated-back S_g (same stencils and weights) on a grain with field."""
+    from paper_2205_15000_amd import workloads as wl
+    from helpers import oracle_grain
+    sp = wl.spec("small_polygon_landau")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta("small_polygon_landau", sp)
+    a0 = wl.initial_A("small_polygon_landau", sp)
+    ga = og.green_average(d0, a0)
+    # angle-averaged S_g from the oracle's own node sums, without v_F
+    m = og.mask
+    eps = 1j * og.zp * og.tt
+    acc = np.zeros(int(m.sum()))
+    for k in range(og.n_theta):
+        data = og.data(k)
+        dn, an = og.node_values(k, data, d0, a0)
+        g0, gt0 = og.start_values(k, data, dn, an, eps, None)
+        gn, gtn, _, _ = sweep.march(data, dn, an, eps, og.q, g0, gt0)
+        _, sg, _ = sweep.node_sums(gn, gtn, dn, og.rp, og.tt)
+        seg, pos, w = og.rb_stencil(k)
+        acc += og.wk[k] * np.sum(sg[seg, pos] * w, axis=1)
+    lhs = og.tt * np.sum(og.rp[:, None] * ga[:, m].real, axis=0)
+    assert np.max(np.abs(lhs - acc)) <= 1e-13 * max(1.0, np.max(np.abs(acc)))
