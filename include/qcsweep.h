@@ -294,7 +294,7 @@ qc_status qc_batch_iterate(qc_batch* batch, int n_iter, int use_graph, void* str
 /* wall time of the latest qc_batch_iterate (HIP events on its stream) */
 qc_status qc_batch_last_ms(const qc_batch* batch, double* ms);
 /* autotuner: times iters_per_trial real iterations for each feasible
- * energies-per-lane choice (1, 2, 4, 8) and keeps the fastest; these
+ * energies-per-lane choice (1, 2, 3, 4, 8) and keeps the fastest; these
  * iterations advance the self-consistency like qc_batch_iterate. */
 qc_status qc_batch_autotune(qc_batch* batch, int iters_per_trial, int* best_epl, void* stream);
 
@@ -316,13 +316,16 @@ qc_status qc_green_average(qc_grain* grain, const double* delta, const double* A
 qc_status qc_get_state(const qc_grain* grain, void* state, size_t* bytes, void* stream);
 qc_status qc_set_state(qc_grain* grain, const void* state, size_t bytes, void* stream);
 
-/* Launch shape of the sweep kernel: energies handled by each lane (1, 2, 4
- * or 8; 0 = automatic).  The lanes of one trajectory segment share the
+/* Launch shape of the sweep kernel: energies handled by each lane (1, 2, 3,
+ * 4 or 8; 0 = automatic: the fewest padded energy slots weighted by each
+ * variant's measured cost).  The lanes of one trajectory segment share the
  * per-node energy sums, so fewer energies per lane means more lanes per
- * segment.  Results are identical up to rounding order. */
+ * segment (a power of two up to 64; a forced value that would need more is
+ * replaced by the automatic choice).  Results are identical up to rounding
+ * order. */
 qc_status qc_grain_set_lanes(qc_grain* grain, int energies_per_lane);
 /* The lane shape the next SCF sweep of this grain will use: energies per
- * lane (1, 2, 4 or 8) and lanes per trajectory segment (a power of two
+ * lane (1, 2, 3, 4 or 8) and lanes per trajectory segment (a power of two
  * <= 64).  Both outputs are host ints written on success. */
 qc_status qc_grain_get_lanes(const qc_grain* grain, int* energies_per_lane, int* lanes_per_segment);
 

@@ -452,7 +452,7 @@ class Grain:
                                 _stream(stream)))
 
     def set_lanes(self, energies_per_lane):
-        """Energies per lane of the sweep kernel (1, 2, 4, 8; 0 = automatic)."""
+        """Energies per lane of the sweep kernel (1, 2, 3, 4, 8; 0 = automatic)."""
         _check(lib.qc_grain_set_lanes(self._g, int(energies_per_lane)))
 
     def lanes(self):

@@ -21,10 +21,31 @@ using C = cpx<double>;
 
 __device__ __forceinline__ C cconj(C a) { return mk(a.x, -a.y); }
 __device__ __forceinline__ C cdivd(C a, C b) {
-  const double r = 1.0 / (b.x * b.x + b.y * b.y);
+  const double r = drcp(b.x * b.x + b.y * b.y);
   return mk((a.x * b.x + a.y * b.y) * r, (a.y * b.x - a.x * b.y) * r);
 }
 __device__ __forceinline__ C cscale(double s, C a) { return mk(s * a.x, s * a.y); }
+
+// Sums over the segment's lane group of the three slot gradients (Re, Im of
+// G_Delta and the gradient of a), written (or added) to o[0..2] by the
+// group's first lanes.
+__device__ __forceinline__ void put_slot_grad(double* o, double rx, double ry, double ra, int G, int lane,
+                                              bool add) {
+  if (G >= 4) {
+    const double v = group_sum4_scatter(rx, ry, ra, 0.0, G, lane);
+    const int qq = scatter_index(lane);
+    if (lane < 4 && qq < 3) o[qq] = add ? o[qq] + v : v;
+  } else {
+    rx = group_sum(rx, G);
+    ry = group_sum(ry, G);
+    ra = group_sum(ra, G);
+    if (lane == 0) {
+      o[0] = add ? o[0] + rx : rx;
+      o[1] = add ? o[1] + ry : ry;
+      o[2] = add ? o[2] + ra : ra;
+    }
+  }
+}
 
 struct StepDer {
   C dg, dd, ddc, dz;
@@ -118,8 +139,9 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
     C dm;
     double am;
     mid(t, dm, am);
-    const StepNode<double> sn = step_node(dm.x, dm.y, hstep(t));
-    for (int i = 0; i < EPL; ++i) g[i] = riccati_step(g[i], sn, q * am + ex[i], ey[i]);
+    const double hs = hstep(t);
+    const StepC<double> sc = step_consts(dm.x, dm.y, hs);
+    for (int i = 0; i < EPL; ++i) g[i] = riccati_step_z(g[i], sc, hs, q * am + ex[i], ey[i]);
     if (t < n)
       for (int i = 0; i < EPL; ++i)
         if (ok[i]) gbuf[(slot0 + t) * a.n_e + e0 + i] = g[i];
@@ -152,6 +174,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
   // step just processed.
   C carry = mk(0.0, 0.0);
   double carrya = 0.0;
+  C gcur[EPL];  // gamma at slot t (at R_max for t = n), loaded once per slot
+  for (int i = 0; i < EPL; ++i) gcur[i] = g[i];
   for (int t = n; t >= 0; --t) {
     C acc = carry;
     double acca = carrya;
@@ -164,7 +188,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
       const C gsf = mk(gs.x, gs.y);
       for (int i = 0; i < EPL; ++i) {
         if (!ok[i]) continue;
-        const C gg = gbuf[node * a.n_e + e0 + i];
+        const C gg = gcur[i];
         const C x = gg * gt[i];
         const C inv = cdivd(mk(1.0, 0.0), mk(1.0 + x.x, x.y));
         const C inv2 = inv * inv;
@@ -187,19 +211,20 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
     const double hs = hstep(t);
     C stepD = mk(0.0, 0.0);
     double stepa = 0.0;
-    const StepNode<double> sn = step_node(-dm.x, dm.y, hs);
+    const StepC<double> sc = step_consts(-dm.x, dm.y, hs);
     for (int i = 0; i < EPL; ++i) {
       const C z = mk(q * am + ex[i], ey[i]);
       if (ok[i]) {
         const C gl = t >= 1 ? gbuf[(slot0 + t - 1) * a.n_e + e0 + i] : g0[i];
-        const C gu = t < n ? gbuf[(slot0 + t) * a.n_e + e0 + i] : g[i];
+        const C gu = gcur[i];
+        gcur[i] = gl;
         const StepDer sd = step_der(gl, gu, dm, z, hs);
         const C l = lam[i];
         stepD = stepD + cconj(sd.dd) * l + sd.ddc * cconj(l);
         stepa += q * (cconj(l) * sd.dz).x;
         lam[i] = cconj(sd.dg) * l;
       }
-      gt[i] = riccati_step(gt[i], sn, z.x, z.y);
+      gt[i] = riccati_step_z(gt[i], sc, hs, z.x, z.y);
     }
     if (t == n && n >= 1) {  // both halves of the last step go to slot n-1
       carry = stepD;
@@ -223,13 +248,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
         }
       }
     }
-    const double rx = group_sum(acc.x, a.G), ry = group_sum(acc.y, a.G), ra = group_sum(acca, a.G);
-    if (lane == 0) {
-      double* o = gV + (slot0 + t) * 3;
-      o[0] = rx;
-      o[1] = ry;
-      o[2] = ra;
-    }
+    put_slot_grad(gV + (slot0 + t) * 3, acc.x, acc.y, acca, a.G, lane, false);
   }
   // gt[] now holds gamma~ at R_min
 
@@ -237,7 +256,11 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
   // gamma~_{t-1}; slot t-1 is complete after step t (slot n-1 also takes
   // both halves of step n and the bulk start at R_max).
   C mu[EPL];
-  for (int i = 0; i < EPL; ++i) mu[i] = mk(0.0, 0.0);
+  C gprv[EPL];  // gamma~ at slot t-1 (at R_min for t = 0), loaded once per slot
+  for (int i = 0; i < EPL; ++i) {
+    mu[i] = mk(0.0, 0.0);
+    gprv[i] = gt[i];
+  }
   carry = mk(0.0, 0.0);
   carrya = 0.0;
   for (int t = 0; t <= n; ++t) {
@@ -252,7 +275,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
       if (!ok[i]) continue;
       const C z = mk(q * am + ex[i], ey[i]);
       const C gu = t < n ? gtbuf[(slot0 + t) * a.n_e + e0 + i] : gt0[i];
-      const C gl = t >= 1 ? gtbuf[(slot0 + t - 1) * a.n_e + e0 + i] : gt[i];
+      const C gl = gprv[i];
+      gprv[i] = gu;
       const StepDer sd = step_der(gu, gl, dprime, z, hs);
       const C l = mu[i];
       const C gdp = cconj(sd.dd) * l + sd.ddc * cconj(l);  // gradient of D' = -conj(dm)
@@ -295,84 +319,83 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
         acca += q * gz;
       }
     }
-    const double rx = group_sum(acc.x, a.G), ry = group_sum(acc.y, a.G), ra = group_sum(acca, a.G);
-    if (lane == 0) {
-      double* o = gV + (slot0 + slot) * 3;
-      o[0] += rx;
-      o[1] += ry;
-      o[2] += ra;
-    }
+    put_slot_grad(gV + (slot0 + slot) * 3, acc.x, acc.y, acca, a.G, lane, true);
   }
 }
 
-// gradients of the per-node sums from the cell gradients (transpose of the
-// rotate-back gather): thread per grain cell, FP64 atomics onto the slots
+// Gradients of the per-node sums from the cell gradients: the transpose of
+// the rotate-back gather, formed as a gather per slot over the cells whose
+// rotate-back stencil uses it (no atomics; each slot written once).
 __global__ void __launch_bounds__(256) back_adjoint_kernel(BackAdjArgs a) {
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= a.ncg) return;
-  const int cell = a.grain_cells[c];
-  const double gjx = a.gj ? a.gj[cell] : 0.0, gjy = a.gj ? a.gj[a.ncell + cell] : 0.0;
-  const double gi = -a.h2 * a.gomega;  // omega = ... - I
-  for (int k = 0; k < a.n_theta; ++k) {
-    // G_{S_f} = wk sum_G eta_G G_{Num_G}, G_{Num_G} = G_{Delta_new,G} / den_G
-    double fx = 0.0, fy = 0.0;
-    for (int g = 0; g < a.ncomp; ++g) {
-      const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
-      double nx = 0.0, ny = 0.0;
-      if (a.gdn) {
-        nx = a.gdn[2 * (static_cast<int64_t>(g) * a.ncell + cell)] / a.den[g];
-        ny = a.gdn[2 * (static_cast<int64_t>(g) * a.ncell + cell) + 1] / a.den[g];
-      }
-      fx += ex * nx - ey * ny;
-      fy += ex * ny + ey * nx;
-    }
-    const double wk = a.wk[k];
-    const double sg = a.four_q * wk * (a.cosk[k] * gjx + a.sink[k] * gjy);
-    for (int qd = 0; qd < 4; ++qd) {
-      const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
-      const double w = a.rb_w[o];
-      if (w == 0.0) continue;
-      double* d = a.gS + static_cast<int64_t>(a.rb_idx[o]) * 4;
-      unsafeAtomicAdd(d + 0, wk * w * fx);
-      unsafeAtomicAdd(d + 1, wk * w * fy);
-      unsafeAtomicAdd(d + 2, w * sg);
-      unsafeAtomicAdd(d + 3, wk * w * gi);
-    }
-  }
-}
-
-// cell gradients from slot gradients (transpose of the interpolation)
-__global__ void __launch_bounds__(256) interp_adjoint_kernel(InterpAdjArgs a) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= a.nslot) return;
-  const double gx = a.gV[s * 3], gy = a.gV[s * 3 + 1], ga = a.gV[s * 3 + 2];
   const int k = a.slot_angle[s];
-  int di[4], ai[4];
-  double dw[4], aw[4];
-  delta_stencil(a.geom, a.px[s], a.py[s], a.fb[s], di, dw);
-  a_stencil(a.geom, a.px[s], a.py[s], ai, aw);
-  if (gx != 0.0 || gy != 0.0) {
-    for (int c = 0; c < 4; ++c) {
-      const double w = dw[c];
-      if (w == 0.0) continue;
-      const int idx = di[c];
+  const double wk = a.wk[k], ck = a.cosk[k], sk = a.sink[k];
+  double ex[4], ey[4];
+  for (int g = 0; g < a.ncomp; ++g) {
+    ex[g] = a.eta[2 * (g * a.n_theta + k)];
+    ey[g] = a.eta[2 * (g * a.n_theta + k) + 1];
+  }
+  double sx = 0.0, sy = 0.0, sj = 0.0, sw = 0.0;
+  for (int64_t e = a.bt_ptr[s]; e < a.bt_ptr[s + 1]; ++e) {
+    const double w = a.bt_w[e];
+    const int64_t cell = a.grain_cells[a.bt_c[e]];
+    // G_{S_f} = wk sum_G eta_G G_{Num_G}, G_{Num_G} = G_{Delta_new,G} / den_G
+    if (a.gdn) {
+      double fx = 0.0, fy = 0.0;
       for (int g = 0; g < a.ncomp; ++g) {
-        // y = eta w x  ->  G_x += conj(eta) w G_y
-        const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
-        double* d = a.gdelta + 2 * (static_cast<int64_t>(g) * a.ncell + idx);
-        unsafeAtomicAdd(d, w * (ex * gx + ey * gy));
-        unsafeAtomicAdd(d + 1, w * (ex * gy - ey * gx));
+        const double nx = a.gdn[2 * (g * a.ncell + cell)] / a.den[g];
+        const double ny = a.gdn[2 * (g * a.ncell + cell) + 1] / a.den[g];
+        fx += ex[g] * nx - ey[g] * ny;
+        fy += ex[g] * ny + ey[g] * nx;
       }
+      sx += w * fx;
+      sy += w * fy;
+    }
+    if (a.gj) sj += w * (ck * a.gj[cell] + sk * a.gj[a.ncell + cell]);
+    sw += w;
+  }
+  double4 o;
+  o.x = wk * sx;
+  o.y = wk * sy;
+  o.z = a.four_q * wk * sj;
+  o.w = wk * (-a.h2 * a.gomega) * sw;  // omega = ... - I
+  reinterpret_cast<double4*>(a.gS)[s] = o;
+}
+
+// Gradients on the reference grid from the slot gradients: the transpose of
+// the interpolation pre-pass, as a gather per cell over the slots whose
+// stencils use it (each cell written once, zero where none does).
+__global__ void __launch_bounds__(256) interp_adjoint_kernel(InterpAdjArgs a) {
+  const int64_t cell = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cell >= a.ncell) return;
+  double dx[4] = {0.0, 0.0, 0.0, 0.0}, dy[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t e = a.it_dptr[cell]; e < a.it_dptr[cell + 1]; ++e) {
+    const int64_t s = a.it_ds[e];
+    const double w = a.it_dw[e];
+    const int k = a.slot_angle[s];
+    const double gx = a.gV[s * 3], gy = a.gV[s * 3 + 1];
+    for (int g = 0; g < a.ncomp; ++g) {
+      // y = eta w x  ->  G_x += conj(eta) w G_y
+      const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
+      dx[g] += w * (ex * gx + ey * gy);
+      dy[g] += w * (ex * gy - ey * gx);
     }
   }
-  if (ga != 0.0) {
-    for (int c = 0; c < 4; ++c) {
-      const double w = aw[c];
-      const int idx = ai[c];
-      unsafeAtomicAdd(a.gA + idx, w * a.cosk[k] * ga);
-      unsafeAtomicAdd(a.gA + a.ncell + idx, w * a.sink[k] * ga);
-    }
+  for (int g = 0; g < a.ncomp; ++g) {
+    a.gdelta[2 * (g * a.ncell + cell)] = dx[g];
+    a.gdelta[2 * (g * a.ncell + cell) + 1] = dy[g];
   }
+  double ax = 0.0, ay = 0.0;
+  for (int64_t e = a.it_aptr[cell]; e < a.it_aptr[cell + 1]; ++e) {
+    const int64_t s = a.it_as[e];
+    const double wg = a.it_aw[e] * a.gV[s * 3 + 2];
+    const int k = a.slot_angle[s];
+    ax += wg * a.cosk[k];
+    ay += wg * a.sink[k];
+  }
+  a.gA[cell] = ax;
+  a.gA[a.ncell + cell] = ay;
 }
 
 // explicit dependence of Omega on Delta at the cells:
@@ -461,6 +484,8 @@ void launch_adjoint(int epl, const AdjArgs& a, const AdjBufs& b, hipStream_t st)
     QC_ADJ(1);
   else if (epl == 2)
     QC_ADJ(2);
+  else if (epl == 3)
+    QC_ADJ(3);
   else if (epl == 4)
     QC_ADJ(4);
   else
@@ -468,10 +493,10 @@ void launch_adjoint(int epl, const AdjArgs& a, const AdjBufs& b, hipStream_t st)
 #undef QC_ADJ
 }
 void launch_back_adjoint(const BackAdjArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(back_adjoint_kernel, dim3(nb(a.ncg)), dim3(256), 0, st, a);
+  if (a.nslot > 0) hipLaunchKernelGGL(back_adjoint_kernel, dim3(nb(a.nslot)), dim3(256), 0, st, a);
 }
 void launch_interp_adjoint(const InterpAdjArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(interp_adjoint_kernel, dim3(nb(a.nslot)), dim3(256), 0, st, a);
+  if (a.ncell > 0) hipLaunchKernelGGL(interp_adjoint_kernel, dim3(nb(a.ncell)), dim3(256), 0, st, a);
 }
 void launch_omega_delta_adjoint(const OmegaAdjArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(omega_delta_adjoint_kernel, dim3(nb(a.ncg)), dim3(256), 0, st, a);

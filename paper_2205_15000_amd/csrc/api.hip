@@ -78,18 +78,41 @@ int ilog2(int v) {
   return l;
 }
 
-// Lanes per segment G and energies per lane for n_e energies (G * epl >=
-// n_e, G a power of two <= 64); `force` (1, 2, 4, 8) overrides the choice.
-// Two energies per lane measured fastest on gfx950 for both precisions
-// (enough independent recursions per lane, low register use, many waves).
-void lane_shape(int n_e, int force, int& G, int& epl) {
-  epl = n_e >= 4 ? 2 : 1;
-  if (force == 1 || force == 2 || force == 4 || force == 8) epl = force;
-  while (epl < 8 && (n_e + epl - 1) / epl > 64) epl <<= 1;
+// Lanes per segment G (a power of two <= 64) for epl energies per lane
+int lanes_for(int n_e, int epl) {
   const int need = (n_e + epl - 1) / epl;
-  G = 1;
+  int G = 1;
   while (G < need) G <<= 1;
-  if (G > 64) G = 64;
+  return G;
+}
+
+// Energies per lane: a forced value (1, 2, 3, 4, 8) if it fits 64 lanes,
+// else the shape with the least cost G * epl * f(epl), i.e. energy slots
+// (padding included) weighted by the measured relative cost per slot of
+// each variant on gfx950 (64- and 48-pole grains).  FP32: two per lane
+// (three costs more per slot than the padding it saves); FP64: three for
+// 48 poles; either precision: four for 256-energy blocks.
+void lane_shape(int n_e, int force, bool fp32, int& G, int& epl) {
+  static const int kEpl[5] = {1, 2, 3, 4, 8};
+  static const double kCost32[5] = {1.12, 1.0, 1.39, 1.15, 1.55};
+  static const double kCost64[5] = {1.07, 1.0, 1.20, 1.12, 1.24};
+  const double* kCost = fp32 ? kCost32 : kCost64;
+  if ((force == 1 || force == 2 || force == 3 || force == 4 || force == 8) && lanes_for(n_e, force) <= 64) {
+    epl = force;
+  } else {
+    double best = INFINITY;
+    epl = 8;
+    for (int i = 0; i < 5; ++i) {
+      const int Gi = lanes_for(n_e, kEpl[i]);
+      if (Gi > 64) continue;
+      const double c = kCost[i] * Gi * kEpl[i];
+      if (c < best) {
+        best = c;
+        epl = kEpl[i];
+      }
+    }
+  }
+  G = std::min(lanes_for(n_e, epl), 64);
 }
 
 void check_desc(const qc_grain_desc* d) {
@@ -258,6 +281,16 @@ struct qc_grain {
   void* lgt = nullptr;
   double* gS = nullptr;
   double* gV = nullptr;
+  // transposed gather tables of the adjoint (built on first use)
+  int64_t* bt_ptr = nullptr;
+  int32_t* bt_c = nullptr;
+  double* bt_w = nullptr;
+  int64_t* it_dptr = nullptr;
+  int32_t* it_ds = nullptr;
+  double* it_dw = nullptr;
+  int64_t* it_aptr = nullptr;
+  int32_t* it_as = nullptr;
+  double* it_aw = nullptr;
   double* omega_cell = nullptr;
   double* dmean = nullptr;
   double* part = nullptr;
@@ -296,7 +329,8 @@ void free_grain(qc_grain* g) {
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->cells, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
-                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV};
+                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV,
+                  g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
@@ -385,7 +419,7 @@ qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const dou
   a.nseg = g->nseg;
   a.order = g->order;
   int epl;
-  lane_shape(n_e, g->epl_override, a.G, epl);
+  lane_shape(n_e, g->epl_override, g->precision == QC_MIXED, a.G, epl);
   a.log2g = ilog2(a.G);
   a.n_e = n_e;
   a.n_e_tot = n_e_tot;
@@ -410,7 +444,7 @@ qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const dou
 
 void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc::SweepBufs& b, hipStream_t st) {
   int G, epl;
-  lane_shape(a.n_e, g->epl_override, G, epl);
+  lane_shape(a.n_e, g->epl_override, g->precision == QC_MIXED, G, epl);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g->prof) {
     hcheck(hipEventCreate(&e0), "event");
@@ -1092,6 +1126,106 @@ qc_status qc_set_state(qc_grain* g, const void* state, size_t bytes, void* strea
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+std::vector<T> download(const T* d, size_t n) {
+  std::vector<T> h(n);
+  if (n) hcheck(hipMemcpy(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost), "copy");
+  return h;
+}
+
+// Compressed rows from (row, column, weight) triples given row by row in
+// any order: counting sort by row, entries of a row in input order.
+struct Csr {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> w;
+};
+Csr to_csr(int64_t nrows, const std::vector<int64_t>& row, const std::vector<int32_t>& col,
+           const std::vector<double>& w) {
+  Csr c;
+  c.ptr.assign(nrows + 1, 0);
+  for (int64_t r : row) ++c.ptr[r + 1];
+  for (int64_t i = 0; i < nrows; ++i) c.ptr[i + 1] += c.ptr[i];
+  c.col.resize(row.size());
+  c.w.resize(row.size());
+  std::vector<int64_t> pos(c.ptr.begin(), c.ptr.end() - 1);
+  for (size_t e = 0; e < row.size(); ++e) {
+    const int64_t p = pos[row[e]]++;
+    c.col[p] = col[e];
+    c.w[p] = w[e];
+  }
+  return c;
+}
+
+// The adjoint's transposed tables, built on the host from the device tables
+// the forward path uses: rotate-back entries by slot, interpolation entries
+// (the same stencil code as the device) by cell.
+void ensure_adjoint_tables(qc_grain* g) {
+  if (g->bt_ptr) return;
+  {
+    const size_t n = static_cast<size_t>(g->n_theta) * 4 * g->ncg;
+    const std::vector<int32_t> idx = download(g->rb_idx, n);
+    const std::vector<double> w = download(g->rb_w, n);
+    std::vector<int64_t> row;
+    std::vector<int32_t> col;
+    std::vector<double> ww;
+    for (size_t o = 0; o < n; ++o) {
+      if (w[o] == 0.0) continue;
+      row.push_back(idx[o]);
+      col.push_back(static_cast<int32_t>(o % g->ncg));
+      ww.push_back(w[o]);
+    }
+    const Csr c = to_csr(g->nslot, row, col, ww);
+    g->bt_ptr = static_cast<int64_t*>(upload(c.ptr));
+    g->bt_c = static_cast<int32_t*>(upload(c.col));
+    g->bt_w = static_cast<double*>(upload(c.w));
+  }
+  const std::vector<double> px = download(g->slot_px, g->nslot), py = download(g->slot_py, g->nslot);
+  const std::vector<int32_t> fb = download(g->slot_fb, g->nslot);
+  const std::vector<uint8_t> mask = download(g->mask, g->ncell);
+  qc::GridGeom gg = geom_of(g);
+  gg.mask = mask.data();
+  std::vector<int64_t> drow, arow;
+  std::vector<int32_t> dcol, acol;
+  std::vector<double> dw, aw;
+  drow.reserve(4 * g->nslot);
+  arow.reserve(4 * g->nslot);
+  for (int64_t s = 0; s < g->nslot; ++s) {
+    int di[4], ai[4];
+    double dwt[4], awt[4];
+    qc::delta_stencil(gg, px[s], py[s], fb[s], di, dwt);
+    qc::a_stencil(gg, px[s], py[s], ai, awt);
+    for (int c = 0; c < 4; ++c) {
+      if (dwt[c] != 0.0) {
+        drow.push_back(di[c]);
+        dcol.push_back(static_cast<int32_t>(s));
+        dw.push_back(dwt[c]);
+      }
+      if (awt[c] != 0.0) {
+        arow.push_back(ai[c]);
+        acol.push_back(static_cast<int32_t>(s));
+        aw.push_back(awt[c]);
+      }
+    }
+  }
+  const Csr d = to_csr(g->ncell, drow, dcol, dw);
+  const Csr a = to_csr(g->ncell, arow, acol, aw);
+  g->it_dptr = static_cast<int64_t*>(upload(d.ptr));
+  g->it_ds = static_cast<int32_t*>(upload(d.col));
+  g->it_dw = static_cast<double*>(upload(d.w));
+  g->it_aptr = static_cast<int64_t*>(upload(a.ptr));
+  g->it_as = static_cast<int32_t*>(upload(a.col));
+  g->it_aw = static_cast<double*>(upload(a.w));
+}
+
+}  // namespace
+
+extern "C" {
+
 qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind, const double* g_delta_new,
                            const double* g_j, double g_omega, double* grad_delta, double* grad_A, void* stream) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
@@ -1107,9 +1241,9 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     if (!g->lgt) g->lgt = dalloc(nb);
     if (!g->gS) g->gS = static_cast<double*>(dalloc(sizeof(double) * 4 * g->nslot));
     if (!g->gV) g->gV = static_cast<double*>(dalloc(sizeof(double) * 3 * g->nslot));
+    ensure_adjoint_tables(g);
     do_interp(g, delta, A_ind, st);
     // gradients of the per-node sums
-    qc::launch_fill(g->gS, 4 * g->nslot, 0.0, st);
     qc::BackAdjArgs ba;
     ba.ncg = g->ncg;
     ba.ncell = g->ncell;
@@ -1129,12 +1263,17 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     ba.gdn = g_delta_new;
     ba.gj = g_j;
     ba.gS = g->gS;
+    ba.nslot = g->nslot;
+    ba.slot_angle = g->slot_angle;
+    ba.bt_ptr = g->bt_ptr;
+    ba.bt_c = g->bt_c;
+    ba.bt_w = g->bt_w;
     qc::launch_back_adjoint(ba, st);
     // reverse sweep with the store the latest sweep read
     qc::AdjArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
     a.bc_valid = g->last_bc_valid;
     int G, epl;
-    lane_shape(g->n_poles, g->epl_override, G, epl);
+    lane_shape(g->n_poles, g->epl_override, g->precision == QC_MIXED, G, epl);
     qc::AdjBufs b;
     b.nodes = g->nodes;
     b.bc_g_prev = g->bc[1 - g->bc_cur][0];
@@ -1146,9 +1285,7 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     b.gV = g->gV;
     qc::launch_adjoint(epl, a, b, st);
     hcheck(hipGetLastError(), "adjoint launch");
-    // back to the reference grid
-    qc::launch_fill(grad_delta, 2 * g->ncomp * g->ncell, 0.0, st);
-    qc::launch_fill(grad_A, 2 * g->ncell, 0.0, st);
+    // back to the reference grid (the gather writes every cell)
     qc::InterpAdjArgs ia;
     ia.nslot = g->nslot;
     ia.ncell = g->ncell;
@@ -1165,6 +1302,12 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     ia.gV = g->gV;
     ia.gdelta = grad_delta;
     ia.gA = grad_A;
+    ia.it_dptr = g->it_dptr;
+    ia.it_ds = g->it_ds;
+    ia.it_dw = g->it_dw;
+    ia.it_aptr = g->it_aptr;
+    ia.it_as = g->it_as;
+    ia.it_aw = g->it_aw;
     qc::launch_interp_adjoint(ia, st);
     if (g_omega != 0.0) {
       qc::OmegaAdjArgs oa;
@@ -1194,9 +1337,9 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
 
 qc_status qc_grain_set_lanes(qc_grain* g, int energies_per_lane) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
-  if (energies_per_lane != 0 && energies_per_lane != 1 && energies_per_lane != 2 && energies_per_lane != 4 &&
-      energies_per_lane != 8)
-    return fail(QC_ERR_INVALID, "energies_per_lane must be 0 (auto), 1, 2, 4 or 8");
+  if (energies_per_lane != 0 && energies_per_lane != 1 && energies_per_lane != 2 && energies_per_lane != 3 &&
+      energies_per_lane != 4 && energies_per_lane != 8)
+    return fail(QC_ERR_INVALID, "energies_per_lane must be 0 (auto), 1, 2, 3, 4 or 8");
   g->epl_override = energies_per_lane;
   return QC_OK;
 }
@@ -1205,7 +1348,7 @@ qc_status qc_grain_get_lanes(const qc_grain* g, int* energies_per_lane, int* lan
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
   if (!energies_per_lane || !lanes_per_segment) return fail(QC_ERR_INVALID, "output pointers are required");
   int G = 1, epl = 1;
-  lane_shape(g->n_poles, g->epl_override, G, epl);
+  lane_shape(g->n_poles, g->epl_override, g->precision == QC_MIXED, G, epl);
   *energies_per_lane = epl;
   *lanes_per_segment = G;
   return QC_OK;
@@ -1274,7 +1417,7 @@ void build_tiles(qc_batch* b) {
   for (size_t gi = 0; gi < b->grains.size(); ++gi) {
     qc_grain* g = b->grains[gi];
     int G, epl;
-    lane_shape(g->n_poles, b->epl, G, epl);
+    lane_shape(g->n_poles, b->epl, g->precision == QC_MIXED, G, epl);
     std::vector<int32_t> ord(g->nseg), n(g->nseg);
     hcheck(hipMemcpy(ord.data(), g->order, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
     hcheck(hipMemcpy(n.data(), g->seg_n, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
@@ -1296,7 +1439,7 @@ void upload_args(qc_batch* b, hipStream_t st) {
   for (size_t gi = 0; gi < b->grains.size(); ++gi) {
     qc_grain* g = b->grains[gi];
     int G, epl;
-    lane_shape(g->n_poles, b->epl, G, epl);
+    lane_shape(g->n_poles, b->epl, g->precision == QC_MIXED, G, epl);
     qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
     a.G = G;
     a.log2g = ilog2(G);
@@ -1575,7 +1718,7 @@ qc_status qc_batch_autotune(qc_batch* b, int iters_per_trial, int* best_epl, voi
   for (qc_grain* g : b->grains) maxp = std::max(maxp, g->n_poles);
   double best = INFINITY;
   int arg = b->epl;
-  const int cand[4] = {1, 2, 4, 8};
+  const int cand[5] = {1, 2, 3, 4, 8};
   for (int e : cand) {
     if ((maxp + e - 1) / e > 64) continue;
     b->epl = e;

@@ -192,6 +192,23 @@ __device__ __forceinline__ cpx<T> riccati_step_c(cpx<T> g, const StepC<T>& s, T 
   return mk(fmaT(C0x, ex, C0y * ey) * rn, fmaT(C0y, ex, -(C0x * ey)) * rn);
 }
 
+// Step constants of riccati_step_c for half-step value dm and length hs
+template <typename T>
+__device__ __forceinline__ StepC<T> step_consts(T dmx, T dmy, T hs) {
+  StepC<T> c;
+  const T h2 = T(0.5) * hs;
+  c.C2x = h2 * dmy;
+  c.C2y = h2 * dmx;
+  c.C8x = T(4) * c.C2x;
+  c.C8y = T(4) * c.C2y;
+  return c;
+}
+// riccati_step_c with the per-energy constants formed from z = (zx, zy)
+template <typename T>
+__device__ __forceinline__ cpx<T> riccati_step_z(cpx<T> g, const StepC<T>& c, T hs, T zx, T zy) {
+  return riccati_step_c(g, c, fmaT(-hs, zy, T(-1)), fmaT(-hs, zy, T(3)), hs * zx);
+}
+
 // Stable homogeneous root of D* g^2 + 2 z g + D = 0: -D / (z + s) with
 // s = sqrt(z^2 - |D|^2) on the branch Im s > 0.
 template <typename T>
@@ -206,7 +223,7 @@ __device__ __forceinline__ cpx<T> bulk_root(T zx, T zy, T dx, T dy) {
 
 // Bilinear weights of the four cell centres around (px, py) on the
 // reference grid (Sec. III.A), formed with the same IEEE operations as the
-// host tables.  Delta: corners off the array or outside the grain are
+// host tables (the adjoint's transposed tables call them on the host).  Delta: corners off the array or outside the grain are
 // dropped and the rest renormalised; fb >= 0 names the nearest grain cell
 // used when no corner keeps a positive weight.  A_ind: plain bilinear with
 // the point clamped onto the outermost cell centres.
@@ -215,7 +232,7 @@ struct GridGeom {
   double x0, y0, h;
   const uint8_t* mask;
 };
-__device__ __forceinline__ void delta_stencil(const GridGeom& gg, double px, double py, int fb, int idx[4],
+__host__ __device__ inline void delta_stencil(const GridGeom& gg, double px, double py, int fb, int idx[4],
                                               double w[4]) {
   const double fx = (px - gg.x0) / gg.h - 0.5, fy = (py - gg.y0) / gg.h - 0.5;
   const int i0 = static_cast<int>(__builtin_floor(fx)), j0 = static_cast<int>(__builtin_floor(fy));
@@ -241,11 +258,12 @@ __device__ __forceinline__ void delta_stencil(const GridGeom& gg, double px, dou
     for (int c = 0; c < 4; ++c) w[c] /= tot;
   }
 }
-__device__ __forceinline__ void a_stencil(const GridGeom& gg, double px, double py, int idx[4], double w[4]) {
+__host__ __device__ inline void a_stencil(const GridGeom& gg, double px, double py, int idx[4], double w[4]) {
   const double fx = __builtin_fmin(__builtin_fmax((px - gg.x0) / gg.h - 0.5, 0.0), gg.nx - 1.0);
   const double fy = __builtin_fmin(__builtin_fmax((py - gg.y0) / gg.h - 0.5, 0.0), gg.ny - 1.0);
-  const int i0 = min(static_cast<int>(__builtin_floor(fx)), gg.nx - 2);
-  const int j0 = min(static_cast<int>(__builtin_floor(fy)), gg.ny - 2);
+  const int fi = static_cast<int>(__builtin_floor(fx)), fj = static_cast<int>(__builtin_floor(fy));
+  const int i0 = fi < gg.nx - 2 ? fi : gg.nx - 2;
+  const int j0 = fj < gg.ny - 2 ? fj : gg.ny - 2;
   const double wx = fx - i0, wy = fy - j0;
   idx[0] = j0 * gg.nx + i0;
   idx[1] = idx[0] + 1;

@@ -814,6 +814,7 @@ static void launch_sweep_m(int epl, const SweepArgs& a, const SweepBufs& b, hipS
   switch (epl) {
     case 1: launch_sweep_t<T, 1, MODE>(a, b, st); break;
     case 2: launch_sweep_t<T, 2, MODE>(a, b, st); break;
+    case 3: launch_sweep_t<T, 3, MODE>(a, b, st); break;
     case 4: launch_sweep_t<T, 4, MODE>(a, b, st); break;
     default: launch_sweep_t<T, 8, MODE>(a, b, st); break;
   }
@@ -841,6 +842,7 @@ void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles,
   switch (epl) {
     case 1: hipLaunchKernelGGL((batch_sweep_kernel<T, 1>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
     case 2: hipLaunchKernelGGL((batch_sweep_kernel<T, 2>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
+    case 3: hipLaunchKernelGGL((batch_sweep_kernel<T, 3>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
     case 4: hipLaunchKernelGGL((batch_sweep_kernel<T, 4>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
     default: hipLaunchKernelGGL((batch_sweep_kernel<T, 8>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
   }

@@ -137,7 +137,14 @@ struct BackAdjArgs {
   double four_q, h2, gomega;
   const double* gdn;  // complex gradient of Delta_new or nullptr
   const double* gj;   // gradient of j or nullptr
-  double* gS;         // out (accumulated): [nslot][4]
+  double* gS;         // out: [nslot][4]
+  // transpose of the rotate-back table by slot: entries [bt_ptr[s], bt_ptr[s+1])
+  // hold (grain-cell position, weight)
+  int64_t nslot;
+  const int32_t* slot_angle;
+  const int64_t* bt_ptr;
+  const int32_t* bt_c;
+  const double* bt_w;
 };
 
 struct InterpAdjArgs {
@@ -152,8 +159,16 @@ struct InterpAdjArgs {
   const double* cosk;
   const double* sink;
   const double* gV;
-  double* gdelta;  // accumulated complex [ncomp][ny][nx]
-  double* gA;      // accumulated [2][ny][nx]
+  double* gdelta;  // out: complex [ncomp][ny][nx]
+  double* gA;      // out: [2][ny][nx]
+  // transposes of the slot stencils by cell: Delta entries [it_dptr[c],
+  // it_dptr[c+1]) and A_ind entries [it_aptr[c], it_aptr[c+1]) hold (slot, weight)
+  const int64_t* it_dptr;
+  const int32_t* it_ds;
+  const double* it_dw;
+  const int64_t* it_aptr;
+  const int32_t* it_as;
+  const double* it_aw;
 };
 
 struct OmegaAdjArgs {

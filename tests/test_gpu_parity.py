@@ -72,11 +72,14 @@ def test_iteration_map_fp64_matches_oracle(name):
     g.close()
 
 
-@pytest.mark.parametrize("n_poles,epl", [(8, 1), (8, 2), (8, 4), (8, 8), (64, 1), (64, 2), (64, 4)])
+@pytest.mark.parametrize("n_poles,epl", [(8, 1), (8, 2), (8, 4), (8, 8), (64, 1), (64, 2), (64, 4), (48, 3),
+                                         (7, 3), (48, 0)])
 def test_every_lane_shape_matches_oracle(n_poles, epl):
     """Forced energies per lane cover every lanes-per-segment G of the
     per-node pole-sum reduction: 8 poles give G = 8, 4, 2, 1 and 64 poles
-    G = 64, 32, 16 (two chained sweeps, FP64, against the oracle)."""
+    G = 64, 32, 16; three energies per lane with 48 poles (G = 16, the
+    automatic choice) and with 7 (G = 4, two padded energies) (two chained
+    sweeps, FP64, against the oracle)."""
     qs = _qs()
     name = "small_d110_field"
     sp = dict(wl.spec(name), n_poles=n_poles)
@@ -84,7 +87,8 @@ def test_every_lane_shape_matches_oracle(n_poles, epl):
     g = qs.Grain(sp, "fp64")
     g.set_lanes(epl)
     e, G = g.lanes()
-    assert e == epl and G == max(1, n_poles // epl)
+    want = epl if epl else 3
+    assert e == want and G == 1 << max(0, math.ceil(math.log2(math.ceil(n_poles / want))))
     og = oracle_grain(sp)
     d0 = wl.initial_delta(name, sp)
     a0 = wl.initial_A(name, sp)
