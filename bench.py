@@ -23,6 +23,9 @@ headline):
                                   tile-queue sweep, hipGraph replay)
     --mode adjoint [--iters K]    FP64 sweep and its reverse mode on the 200x200
                                   d-wave disc (48 poles, 2 flux quanta)
+    --mode lanes [--workload NAME]
+                                  sweep time at every energies-per-lane setting,
+                                  both precisions (default: the 48-pole disc)
 """
 import argparse
 import json
@@ -59,7 +62,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch", "adjoint"], default="iteration")
+    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch", "adjoint", "lanes"],
+                    default="iteration")
+    ap.add_argument("--workload", default="d_disc_200")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--prior", type=int, default=200)
     ap.add_argument("--bc-iters", type=int, default=20)
@@ -240,6 +245,35 @@ def mode_adjoint(qs, torch, wl, iters):
             "forward_steps": steps, "forward_steps_per_s": steps / fwd, "finite": finite}
 
 
+def mode_lanes(qs, torch, wl, name, iters):
+    """Average sweep-kernel time (HIP events) at each energies-per-lane
+    setting and at the automatic choice, mixed and FP64, same inputs."""
+    sp = wl.spec(name)
+    d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    rows = []
+    for prec in ("mixed", "fp64"):
+        g = qs.Grain(sp, prec)
+        g.sweep(d0, a0)  # warm-up of the grain's buffers and clocks
+        for epl in (1, 2, 3, 4, 8, 0):
+            g.set_lanes(epl)
+            g.reset_bc()
+            g.sweep(d0, a0)
+            g.sweep(d0, a0)
+            torch.cuda.synchronize()
+            g.profile(True)
+            for _ in range(iters):
+                g.sweep(d0, a0, total=False)
+            torch.cuda.synchronize()
+            ms, n = g.profile_read()
+            g.profile(False)
+            e, G = g.lanes()
+            rows.append({"precision": prec, "requested": epl, "energies_per_lane": e, "lanes_per_segment": G,
+                         "sweep_ms": ms / max(n, 1)})
+        g.close()
+    return {"metric": "sweep time per lane shape", "workload": name, "n_poles": sp["n_poles"], "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -257,6 +291,8 @@ def main():
             res = mode_ldos(qs, torch, wl, args.prior, args.bc_iters)
         elif args.mode == "adjoint":
             res = mode_adjoint(qs, torch, wl, args.iters or 5)
+        elif args.mode == "lanes":
+            res = mode_lanes(qs, torch, wl, args.workload, args.iters or 8)
         else:
             res = mode_batch(qs, torch, wl, args.grains, args.iters or 6)
         print(json.dumps(res), flush=True)
