@@ -307,3 +307,57 @@ def test_green_average_matches_oracle(name, precision):
     assert _close(got[:, m], ref[:, m], tol), rel_err(got[:, m], ref[:, m])
     assert np.array_equal(g.get_state().cpu().numpy(), st0)
     g.close()
+
+
+def _degenerate(case):
+    base = wl.spec("small_d110_field")
+    if case == "tiny_disc":
+        return dict(base, nx=10, ny=10, h=0.5, n_theta=8, n_poles=4,
+                    shapes=[{"kind": "disc", "cx": 0.1, "cy": -0.05, "radius": 0.9, "add": True}])
+    if case == "square_fills_array":
+        return dict(base, nx=24, ny=24, h=0.5,
+                    shapes=[{"kind": "regular_polygon", "cx": 0.0, "cy": 0.0, "n_edges": 4, "side": 12.0,
+                             "rotation": 0.0, "add": True}])
+    if case == "thin_sliver":
+        c, s = math.cos(0.3), math.sin(0.3)
+        pts = [(-6.0, -0.15), (6.0, -0.15), (6.0, 0.15), (-6.0, 0.15)]
+        return dict(base, shapes=[{"kind": "polygon", "vx": [c * x - s * y for x, y in pts],
+                                   "vy": [s * x + c * y for x, y in pts], "add": True}])
+    if case in ("normal_state", "single_pole"):
+        return dict(base, n_poles=1) if case == "single_pole" else dict(base)
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["tiny_disc", "square_fills_array", "thin_sliver", "normal_state", "single_pole"])
+def test_degenerate_inputs_match_oracle(case):
+    """A disc of a few cells, a sliver a fraction of a cell wide (segments
+    without interior nodes), a grain reaching the array edge on all sides,
+    Delta = 0 (normal state: no current, no condensation energy) and a
+    single pole (one lane per segment): two chained FP64 sweeps against
+    the oracle."""
+    qs = _qs()
+    sp = _degenerate(case)
+    sp["name"] = case
+    _note("degenerate case %s" % case)
+    og = oracle_grain(sp)
+    m = og.mask
+    assert m.sum() > 0
+    d0 = wl.initial_delta(case, sp)
+    if case == "normal_state":
+        d0 = np.zeros_like(d0)
+    a0 = wl.initial_A(case, sp)
+    g = qs.Grain(sp, "fp64")
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    bc = None
+    for it in range(2):
+        dn, j, om, od = g.sweep(dd, ad, omega_density=True)
+        ref = og.iterate(d0, a0, bc)
+        bc = ref["bc"]
+        if case == "normal_state":
+            assert np.max(np.abs(dn.cpu().numpy())) == 0.0
+        else:
+            assert _close(dn.cpu().numpy()[:, m], ref["delta_new"][:, m], FP64_TOL), (case, it)
+        assert _close(j.cpu().numpy(), ref["j"], FP64_TOL), (case, it)
+        assert _close(od.cpu().numpy(), ref["omega_density"], FP64_TOL), (case, it)
+        assert abs(om - ref["omega_total"]) <= FP64_TOL * abs(ref["omega_total"])
+    g.close()
