@@ -1,0 +1,168 @@
+"""Checks at the full sizes of the benchmark configurations, in the launch
+configurations bench.py uses: the adjoint of the 200x200 disc against
+central differences at 32 random points, the 512x512 LDOS through
+properties that hold at any size plus mixed against FP64, and the
+64-grain batch against stand-alone iterations of sampled grains.  (The
+400x400 sweep is checked against the oracle cell by cell in
+test_gpu_parity.py.)"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2205_15000_amd import workloads as wl  # noqa: E402
+
+
+def _qs():
+    import paper_2205_15000_amd as qs
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return qs
+
+
+def _note(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def test_adjoint_full_disc_free_energy_and_current_loss():
+    """L = Omega + h^2 sum |j - j_target|^2 (seeded target) on the 200x200
+    d-wave disc, boundary store frozen: the reverse mode against central
+    differences (step 1e-6) at 32 random (cell, component) points."""
+    qs = _qs()
+    name = "d_disc_200"
+    sp = wl.spec(name)
+    _note("full size: adjoint of %s vs central differences" % name)
+    g = qs.Grain(sp, "fp64")
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp) + 1e-3 * np.random.default_rng(3).standard_normal((2, sp["ny"], sp["nx"]))
+    rng = np.random.default_rng(9)
+    jt = 0.05 * rng.standard_normal((2, sp["ny"], sp["nx"]))
+    h2 = sp["h"] ** 2
+    dd, ad = torch.as_tensor(d0).cuda(), torch.as_tensor(a0).cuda()
+    g.sweep(dd, ad)
+    st = g.get_state().clone()
+
+    def loss(d, a):
+        g.set_state(st)
+        _, j, om = g.sweep(torch.as_tensor(d).cuda(), torch.as_tensor(a).cuda())
+        j = j.cpu().numpy()
+        return om + h2 * float(np.sum((j - jt) ** 2)), j
+
+    _, j0 = loss(d0, a0)
+    gd, ga = g.sweep_adjoint(dd, ad, None, torch.as_tensor(2.0 * h2 * (j0 - jt)).cuda(), 1.0)
+    gd, ga = gd.cpu().numpy(), ga.cpu().numpy()
+    mask = qs.Plan(dict(sp, n_theta=4)).mask()
+    cells = rng.choice(np.nonzero(mask.ravel())[0], 32, replace=False)
+    kinds = rng.integers(0, 4, 32)
+    eps = 1e-6
+    worst, scale = 0.0, 0.0
+    for c, kd in zip(cells, kinds):
+        dp, dm, ap, am = d0.copy(), d0.copy(), a0.copy(), a0.copy()
+        if kd < 2:
+            step = eps if kd == 0 else 1j * eps
+            dp.reshape(1, -1)[0, c] += step
+            dm.reshape(1, -1)[0, c] -= step
+            an = gd.reshape(1, -1)[0, c].real if kd == 0 else gd.reshape(1, -1)[0, c].imag
+        else:
+            ap.reshape(2, -1)[kd - 2, c] += eps
+            am.reshape(2, -1)[kd - 2, c] -= eps
+            an = ga.reshape(2, -1)[kd - 2, c]
+        fd = (loss(dp, ap)[0] - loss(dm, am)[0]) / (2 * eps)
+        worst = max(worst, abs(an - fd))
+        scale = max(scale, abs(fd))
+    assert scale > 0.0
+    assert worst <= 1e-5 * scale, (worst, scale)
+    g.close()
+
+
+def test_ldos_full_grid_properties_and_precisions():
+    """512x512 [110] square, 256 angles, 512 energies, 20 boundary
+    iterations after a 64-angle Picard prior solve (bench.py --mode ldos):
+    N >= 0 and finite everywhere; zero-energy states on the pair-breaking
+    edges (N(0) well above the normal value 1) and a gapped interior
+    (N(0) well below 1); N -> about 1 at |e| = 2 Delta0; mixed against
+    FP64 at sampled energies."""
+    qs = _qs()
+    name = "d110_square_512_ldos"
+    sp = wl.spec(name)
+    _note("full size: LDOS of %s" % name)
+    d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    pg = qs.Grain(dict(sp, n_theta=64), "mixed")
+    pg.scf(d0, a0, 200, tol=1e-6)
+    pg.close()
+    en = wl.ldos_energies(512)
+    gm = qs.Grain(sp, "mixed")
+    out = gm.ldos(d0, a0, en, 0.01 * wl.DELTA0, 20).cpu().numpy()
+    gm.close()
+    m = qs.Plan(dict(sp, n_theta=4)).mask()
+    assert np.isfinite(out).all()
+    assert out[:, m].min() >= -1e-6
+    e0 = int(np.argmin(np.abs(en)))
+    # edge cells: grain cells with a neighbour outside the grain or the array
+    pad = np.pad(m, 1)
+    inner = pad[1:-1, 1:-1] & pad[:-2, 1:-1] & pad[2:, 1:-1] & pad[1:-1, :-2] & pad[1:-1, 2:]
+    edge = out[e0][m & ~inner].max()
+    # cells at least 10 xi0 (100 cells) from the grain's edges: somewhere
+    # there the d-wave gap suppresses N(0) (a starting vortex may survive)
+    deep = m.copy()
+    for _ in range(100):
+        p2 = np.pad(deep, 1)
+        deep = p2[1:-1, 1:-1] & p2[:-2, 1:-1] & p2[2:, 1:-1] & p2[1:-1, :-2] & p2[1:-1, 2:]
+    centre = out[e0][deep].min()
+    assert edge > 3.0, edge
+    assert centre < 0.5, centre
+    far = out[0][m].mean()  # e = -2 Delta0
+    assert 0.8 < far < 1.5, far
+    # the same LDOS in FP64 at 8 energies (every 64th)
+    sel = np.arange(0, 512, 64)
+    gf = qs.Grain(sp, "fp64")
+    ref = gf.ldos(d0, a0, en[sel], 0.01 * wl.DELTA0, 20).cpu().numpy()
+    gf.close()
+    diff = np.abs(out[sel][:, m] - ref[:, m])
+    assert diff.max() <= 2e-3 * max(1.0, np.abs(ref[:, m]).max()), diff.max()
+
+
+def test_batch_of_64_grains_matches_single_grains():
+    """The 64-grain batch (bench.py --mode batch: persistent tile-queue
+    sweep, autotuned lanes, hipGraph replay) against the same Picard
+    iterations run grain by grain, for the smallest, a middle and the
+    largest grain."""
+    qs = _qs()
+    specs = wl.batch_specs(64)
+    _note("full size: batch of %d grains" % len(specs))
+    grains = [qs.Grain(sp, "mixed") for sp in specs]
+    b = qs.Batch(grains)
+    starts = []
+    for i, sp in enumerate(specs):
+        d = torch.as_tensor(wl.batch_initial_delta(sp, i)).cuda()
+        a = torch.zeros((2, sp["ny"], sp["nx"]), dtype=torch.float64).cuda()
+        b.set_fields(i, d, a)
+        starts.append((d.clone(), a.clone()))
+    b.autotune(1)
+    epl = b.info()["energies_per_lane"]
+    # the autotuner's trials advanced the state: restart every grain
+    for i in range(len(specs)):
+        b.set_fields(i, *starts[i])
+        grains[i].reset_bc()
+    b.iterate(2, graph=False)
+    b.iterate(2, graph=True)
+    sizes = [sp["nx"] for sp in specs]
+    picks = [int(np.argmin(sizes)), len(specs) // 2, int(np.argmax(sizes))]
+    got = {i: b.get_fields(i)[0].cpu().numpy() for i in picks}
+    b.close()
+    for g in grains:
+        g.close()
+    for i in picks:
+        g1 = qs.Grain(specs[i], "mixed")
+        g1.set_lanes(epl)
+        d, a = starts[i][0].clone(), starts[i][1].clone()
+        g1.scf(d, a, 4)
+        ref = d.cpu().numpy()
+        g1.close()
+        err = np.max(np.abs(got[i] - ref))
+        assert err <= 1e-6 * np.max(np.abs(ref)), (i, err)
