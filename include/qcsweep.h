@@ -316,6 +316,15 @@ qc_status qc_green_average(qc_grain* grain, const double* delta, const double* A
 qc_status qc_get_state(const qc_grain* grain, void* state, size_t* bytes, void* stream);
 qc_status qc_set_state(qc_grain* grain, const void* state, size_t bytes, void* stream);
 
+/* Memory mode of qc_sweep_adjoint.  every = C > 0 (default 32):
+ * checkpoints every C slots of each trajectory (32 B per C nodes and pole)
+ * plus a per-thread scratch of 2 C slots; each block is recomputed from its
+ * checkpoint (three extra marches per node) with the same steps on the same
+ * inputs.  every = 0: gamma~ and the node-local gamma~ adjoint are stored
+ * at every (node, pole) instead (32 B in FP64).  Both modes give the same
+ * gradients to rounding. */
+qc_status qc_grain_set_adjoint_checkpoint(qc_grain* grain, int every);
+
 /* Launch shape of the sweep kernel: energies handled by each lane (1, 2, 3,
  * 4 or 8; 0 = automatic: the fewest padded energy slots weighted by each
  * variant's measured cost).  The lanes of one trajectory segment share the

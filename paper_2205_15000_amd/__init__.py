@@ -96,6 +96,7 @@ _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes
 _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
 _sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
 _sig("qc_green_average", ctypes.c_int, [_P, _P, _P, _P, _P])
+_sig("qc_grain_set_adjoint_checkpoint", ctypes.c_int, [_P, ctypes.c_int])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)])
 _sig("qc_batch_destroy", None, [_P])
@@ -450,6 +451,11 @@ class Grain:
     def set_state(self, buf, stream=None):
         _check(lib.qc_set_state(self._g, ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(buf.numel()),
                                 _stream(stream)))
+
+    def set_adjoint_checkpoint(self, every):
+        """Reverse mode with checkpoints every `every` slots (default 32;
+        0 stores gamma~ and its adjoint terms at every node)."""
+        _check(lib.qc_grain_set_adjoint_checkpoint(self._g, int(every)))
 
     def set_lanes(self, energies_per_lane):
         """Energies per lane of the sweep kernel (1, 2, 3, 4, 8; 0 = automatic)."""

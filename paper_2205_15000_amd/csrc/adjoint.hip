@@ -79,6 +79,26 @@ __device__ __forceinline__ void bulk_adj(C y, C z, C d, C gy, C& gd, double& gzr
   gzr += (cconj(gy) * dz).x;
 }
 
+// Node-local gradients of the per-node sums at one pole (Sec. II.A, Sec. II)
+// for gamma = gg, gamma~ = gv, node order parameter dn, sum gradients gs and
+// pole weight r: the adjoint of gamma (added to lam), of gamma~ (returned
+// in lgt) and of D through S_I (added to acc).
+__device__ __forceinline__ void node_adj(C gg, C gv, C dn, const double4& gs, double r, double pt, C& lam, C& lgt,
+                                         C& acc) {
+  const C gsf = mk(gs.x, gs.y);
+  const C x = gg * gv;
+  const C inv = cdivd(mk(1.0, 0.0), mk(1.0 + x.x, x.y));
+  const C inv2 = inv * inv;
+  const C kf = cconj(gsf) * mk(0.0, -pt * r);        // S_f = -i 2pi t~ R (u + conj v)
+  const C kg = mk(0.0, -0.5 * pt * r * gs.z);        // S_g = pi t~ R Im((1-X)/(1+X))
+  const C ki = mk(0.0, -pt * r * gs.w);              // S_I = 2pi t~ R Im(D* g - D g~)
+  const C agam = kf * inv2 - cconj(kf) * (gv * gv) * inv2 - cscale(2.0, kg * gv * inv2) + ki * cconj(dn);
+  const C agt = cconj(kf) * inv2 - kf * (gg * gg) * inv2 - cscale(2.0, kg * gg * inv2) - ki * dn;
+  lam = lam + cconj(agam);
+  lgt = cconj(agt);
+  acc = acc + ki * gg - cconj(ki * gv);  // G_D through S_I
+}
+
 template <int EPL>
 __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<double>* __restrict__ nodes,
                                                       const C* __restrict__ bc_g_prev,
@@ -185,23 +205,12 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
       const node4<double> v = nodes[node];
       const C dn = mk(v.dx, v.dy);
       const double4 gs = gS[node];
-      const C gsf = mk(gs.x, gs.y);
       for (int i = 0; i < EPL; ++i) {
         if (!ok[i]) continue;
-        const C gg = gcur[i];
-        const C x = gg * gt[i];
-        const C inv = cdivd(mk(1.0, 0.0), mk(1.0 + x.x, x.y));
-        const C inv2 = inv * inv;
-        const double r = rw[i];
-        const C kf = cconj(gsf) * mk(0.0, -pt * r);        // S_f = -i 2pi t~ R (u + conj v)
-        const C kg = mk(0.0, -0.5 * pt * r * gs.z);        // S_g = pi t~ R Im((1-X)/(1+X))
-        const C ki = mk(0.0, -pt * r * gs.w);              // S_I = 2pi t~ R Im(D* g - D g~)
-        const C agam = kf * inv2 - cconj(kf) * (gt[i] * gt[i]) * inv2 - cscale(2.0, kg * gt[i] * inv2) + ki * cconj(dn);
-        const C agt = cconj(kf) * inv2 - kf * (gg * gg) * inv2 - cscale(2.0, kg * gg * inv2) - ki * dn;
-        lam[i] = lam[i] + cconj(agam);
-        lgt[node * a.n_e + e0 + i] = cconj(agt);
+        C lv;
+        node_adj(gcur[i], gt[i], dn, gs, rw[i], pt, lam[i], lv, acc);
+        lgt[node * a.n_e + e0 + i] = lv;
         gtbuf[node * a.n_e + e0 + i] = gt[i];
-        acc = acc + ki * gg - cconj(ki * gt[i]);  // G_D through S_I
       }
     }
     // step t: adjoint of gamma_{t-1} -> gamma_t; primal gamma~_t -> gamma~_{t-1}
@@ -309,6 +318,293 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a, const node4<dou
       slot = last;
     }
     if (t == n && !etaps) {  // gamma~ started at the bulk root of the last slot
+      const node4<double> v1 = nodes[slot0 + last];
+      for (int i = 0; i < EPL; ++i) {
+        if (!ok[i]) continue;
+        double gz = 0.0;
+        C gdp = mk(0.0, 0.0);
+        bulk_adj(gt0[i], mk(q * v1.a + ex[i], ey[i]), mk(-v1.dx, v1.dy), mu[i], gdp, gz);
+        acc = acc - cconj(gdp);
+        acca += q * gz;
+      }
+    }
+    put_slot_grad(gV + (slot0 + slot) * 3, acc.x, acc.y, acca, a.G, lane, true);
+  }
+}
+
+// The same reverse mode with checkpoints every CK slots instead of gamma,
+// gamma~ and the gamma~ adjoint terms at every node: pass 1 keeps gamma
+// entering each block; pass 2 (backward) recomputes each block's gamma
+// forward from its checkpoint into a per-thread scratch and keeps gamma~ at
+// each block's first slot; pass 3 (forward) recomputes a block's gamma
+// forward and gamma~ backward (from the next block's checkpoint) and forms
+// the node-local gamma~ adjoint terms again.  The recomputation runs the same
+// steps on the same inputs as the stored variant.
+template <int EPL>
+__global__ void __launch_bounds__(256) adjoint_ckpt_kernel(AdjArgs a, const node4<double>* __restrict__ nodes,
+                                                           const C* __restrict__ bc_g_prev,
+                                                           const C* __restrict__ bc_gt_prev,
+                                                           const double4* __restrict__ gS, double* __restrict__ gV,
+                                                           int CK, const int64_t* __restrict__ ckbase,
+                                                           C* __restrict__ ckg, C* __restrict__ ckgt,
+                                                           C* __restrict__ scr, int64_t nthr) {
+  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t wseg = gtid >> a.log2g;
+  const int lane = static_cast<int>(gtid & (a.G - 1));
+  if (wseg >= a.nseg) return;
+  const int64_t seg = a.order ? static_cast<int64_t>(a.order[wseg]) : wseg;
+  const int64_t slot0 = a.seg_slot0[seg];
+  const int n = a.seg_n[seg];
+  const int last = n > 0 ? n - 1 : 0;
+  const double hfirst = a.seg_hfirst[seg], hlast = a.seg_hlast[seg], hfull = a.h;
+  const double q = a.q;
+  const int e0 = lane * EPL;
+  const int64_t cb = ckbase[seg];
+  double ex[EPL], ey[EPL], rw[EPL];
+  bool ok[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    ok[i] = e0 + i < a.n_e;
+    const int e = ok[i] ? e0 + i : a.n_e - 1;
+    ex[i] = a.eps[2 * e];
+    ey[i] = a.eps[2 * e + 1];
+    rw[i] = ok[i] ? a.rp[e] : 0.0;
+  }
+  auto hstep = [&](int t) { return t == 0 ? hfirst : (t == n ? hlast : hfull); };
+  auto mid = [&](int t, C& dm, double& am) {
+    const node4<double> lo = nodes[slot0 + (t >= 1 ? t - 1 : 0)];
+    const node4<double> up = nodes[slot0 + (t < last ? t : last)];
+    dm = mk(0.5 * (lo.dx + up.dx), 0.5 * (lo.dy + up.dy));
+    am = 0.5 * (lo.a + up.a);
+  };
+  // scratch: region 0 gamma, region 1 gamma~, lane-interleaved
+  auto sc_at = [&](int region, int pos, int i) -> C& {
+    return scr[((static_cast<int64_t>(region) * CK + pos) * EPL + i) * nthr + gtid];
+  };
+  auto ck_at = [&](C* base, int kb, int i) -> C& { return base[(cb + kb) * a.n_e + e0 + i]; };
+
+  const int64_t tb = seg * 4;
+  const bool staps = a.bc_valid && a.tap_start_w[tb] + a.tap_start_w[tb + 1] + a.tap_start_w[tb + 2] +
+                                           a.tap_start_w[tb + 3] > 0.0;
+  const bool etaps = a.bc_valid && a.tap_end_w[tb] + a.tap_end_w[tb + 1] + a.tap_end_w[tb + 2] +
+                                           a.tap_end_w[tb + 3] > 0.0;
+  C g0[EPL], g[EPL];
+  {
+    const node4<double> v0 = nodes[slot0];
+    for (int i = 0; i < EPL; ++i) {
+      if (staps) {
+        C acc = mk(0.0, 0.0);
+        for (int c = 0; c < 4; ++c)
+          acc = acc + cscale(a.tap_start_w[tb + c],
+                             bc_g_prev[static_cast<int64_t>(a.tap_start_seg[tb + c]) * a.n_e_tot + (ok[i] ? e0 + i : a.n_e - 1)]);
+        g0[i] = acc;
+      } else {
+        g0[i] = bulk_root(q * v0.a + ex[i], ey[i], v0.dx, v0.dy);
+      }
+      g[i] = g0[i];
+    }
+  }
+  auto gamma_step = [&](C* gv, int t) {
+    C dm;
+    double am;
+    mid(t, dm, am);
+    const double hs = hstep(t);
+    const StepC<double> sc = step_consts(dm.x, dm.y, hs);
+    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_z(gv[i], sc, hs, q * am + ex[i], ey[i]);
+  };
+  auto gammat_step = [&](C* gv, int t) {
+    C dm;
+    double am;
+    mid(t, dm, am);
+    const double hs = hstep(t);
+    const StepC<double> sc = step_consts(-dm.x, dm.y, hs);
+    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_z(gv[i], sc, hs, q * am + ex[i], ey[i]);
+  };
+  // gamma at the slots of block kb (slots kb*CK .. min((kb+1)*CK, n) - 1)
+  auto recompute_gamma = [&](int kb) {
+    C gr[EPL];
+    for (int i = 0; i < EPL; ++i) gr[i] = kb == 0 ? g0[i] : (ok[i] ? ck_at(ckg, kb, i) : g0[i]);
+    const int s0 = kb * CK, s1 = min(s0 + CK, n);
+    for (int s = s0; s < s1; ++s) {
+      gamma_step(gr, s);
+      for (int i = 0; i < EPL; ++i) sc_at(0, s - s0, i) = gr[i];
+    }
+  };
+
+  // ---- pass 1: gamma forward, kept entering each block
+  for (int t = 0; t <= n; ++t) {
+    gamma_step(g, t);
+    if (t + 1 < n && (t + 1) % CK == 0)
+      for (int i = 0; i < EPL; ++i)
+        if (ok[i]) ck_at(ckg, (t + 1) / CK, i) = g[i];
+  }
+
+  // ---- pass 2: gamma~ backward; node-local gradients; adjoint of gamma
+  C gt0[EPL], gt[EPL], lam[EPL];
+  {
+    const node4<double> v1 = nodes[slot0 + last];
+    for (int i = 0; i < EPL; ++i) {
+      if (etaps) {
+        C acc = mk(0.0, 0.0);
+        for (int c = 0; c < 4; ++c)
+          acc = acc + cscale(a.tap_end_w[tb + c],
+                             bc_gt_prev[static_cast<int64_t>(a.tap_end_seg[tb + c]) * a.n_e_tot + (ok[i] ? e0 + i : a.n_e - 1)]);
+        gt0[i] = acc;
+      } else {
+        gt0[i] = bulk_root(q * v1.a + ex[i], ey[i], -v1.dx, v1.dy);
+      }
+      gt[i] = gt0[i];
+      lam[i] = mk(0.0, 0.0);
+    }
+  }
+  const double pt = a.twopi_tt;  // 2 pi t~
+  C carry = mk(0.0, 0.0);
+  double carrya = 0.0;
+  C gcur[EPL];  // gamma at slot t (at R_max for t = n)
+  for (int i = 0; i < EPL; ++i) gcur[i] = g[i];
+  int loaded = -1;
+  for (int t = n; t >= 0; --t) {
+    C acc = carry;
+    double acca = carrya;
+    if (t < n) {
+      const int64_t node = slot0 + t;
+      const node4<double> v = nodes[node];
+      const C dn = mk(v.dx, v.dy);
+      const double4 gs = gS[node];
+      for (int i = 0; i < EPL; ++i) {
+        if (!ok[i]) continue;
+        C lv;
+        node_adj(gcur[i], gt[i], dn, gs, rw[i], pt, lam[i], lv, acc);
+        if (t > 0 && t % CK == 0) ck_at(ckgt, t / CK, i) = gt[i];
+      }
+    }
+    if (t >= 1 && (t - 1) / CK != loaded) {
+      loaded = (t - 1) / CK;
+      recompute_gamma(loaded);
+    }
+    C dm;
+    double am;
+    mid(t, dm, am);
+    const double hs = hstep(t);
+    C stepD = mk(0.0, 0.0);
+    double stepa = 0.0;
+    const StepC<double> sc = step_consts(-dm.x, dm.y, hs);
+    for (int i = 0; i < EPL; ++i) {
+      const C z = mk(q * am + ex[i], ey[i]);
+      if (ok[i]) {
+        const C gl = t >= 1 ? sc_at(0, (t - 1) - loaded * CK, i) : g0[i];
+        const C gu = gcur[i];
+        gcur[i] = gl;
+        const StepDer sd = step_der(gl, gu, dm, z, hs);
+        const C l = lam[i];
+        stepD = stepD + cconj(sd.dd) * l + sd.ddc * cconj(l);
+        stepa += q * (cconj(l) * sd.dz).x;
+        lam[i] = cconj(sd.dg) * l;
+      }
+      gt[i] = riccati_step_z(gt[i], sc, hs, z.x, z.y);
+    }
+    if (t == n && n >= 1) {
+      carry = stepD;
+      carrya = stepa;
+      continue;
+    }
+    acc = acc + cscale(0.5, stepD);
+    acca += 0.5 * stepa;
+    carry = cscale(0.5, stepD);
+    carrya = 0.5 * stepa;
+    if (t == 0) {
+      acc = acc + carry;
+      acca += carrya;
+      if (!staps) {
+        const node4<double> v0 = nodes[slot0];
+        for (int i = 0; i < EPL; ++i) {
+          if (!ok[i]) continue;
+          double gz = 0.0;
+          bulk_adj(g0[i], mk(q * v0.a + ex[i], ey[i]), mk(v0.dx, v0.dy), lam[i], acc, gz);
+          acca += q * gz;
+        }
+      }
+    }
+    put_slot_grad(gV + (slot0 + t) * 3, acc.x, acc.y, acca, a.G, lane, false);
+  }
+
+  // ---- pass 3: adjoint of gamma~, forward, block by block
+  C mu[EPL];
+  C gprv[EPL];
+  for (int i = 0; i < EPL; ++i) {
+    mu[i] = mk(0.0, 0.0);
+    gprv[i] = gt[i];
+  }
+  carry = mk(0.0, 0.0);
+  carrya = 0.0;
+  loaded = -1;
+  for (int t = 0; t <= n; ++t) {
+    if (t < n && t / CK != loaded) {
+      loaded = t / CK;
+      recompute_gamma(loaded);
+      // gamma~ over the block, backward from the next block's first slot
+      const int s0 = loaded * CK, s1 = min(s0 + CK, n);
+      C gv[EPL];
+      for (int i = 0; i < EPL; ++i) gv[i] = s1 == n ? gt0[i] : (ok[i] ? ck_at(ckgt, s1 / CK, i) : gt0[i]);
+      for (int s = s1; s > s0; --s) {
+        gammat_step(gv, s);
+        for (int i = 0; i < EPL; ++i) sc_at(1, s - 1 - s0, i) = gv[i];
+      }
+    }
+    C dm;
+    double am;
+    mid(t, dm, am);
+    const double hs = hstep(t);
+    const C dprime = mk(-dm.x, dm.y);
+    C stepD = mk(0.0, 0.0);
+    double stepa = 0.0;
+    node4<double> v;
+    double4 gs;
+    if (t < n) {
+      v = nodes[slot0 + t];
+      gs = gS[slot0 + t];
+    }
+    for (int i = 0; i < EPL; ++i) {
+      if (!ok[i]) continue;
+      const C z = mk(q * am + ex[i], ey[i]);
+      const C gu = t < n ? sc_at(1, t - loaded * CK, i) : gt0[i];
+      const C gl = gprv[i];
+      gprv[i] = gu;
+      const StepDer sd = step_der(gu, gl, dprime, z, hs);
+      const C l = mu[i];
+      const C gdp = cconj(sd.dd) * l + sd.ddc * cconj(l);
+      stepD = stepD - cconj(gdp);
+      stepa += q * (cconj(l) * sd.dz).x;
+      mu[i] = cconj(sd.dg) * l;
+      if (t < n) {
+        C lamd = mk(0.0, 0.0), accd = mk(0.0, 0.0), lv;
+        node_adj(sc_at(0, t - loaded * CK, i), gu, mk(v.dx, v.dy), gs, rw[i], pt, lamd, lv, accd);
+        mu[i] = mu[i] + lv;
+      }
+    }
+    if (t == 0) {
+      carry = stepD;
+      carrya = stepa;
+      if (n >= 1) continue;
+    }
+    C acc;
+    double acca;
+    int slot;
+    if (t == 0) {
+      acc = carry;
+      acca = carrya;
+      slot = 0;
+    } else if (t < n) {
+      acc = carry + cscale(0.5, stepD);
+      acca = carrya + 0.5 * stepa;
+      carry = cscale(0.5, stepD);
+      carrya = 0.5 * stepa;
+      slot = t - 1;
+    } else {
+      acc = carry + stepD;
+      acca = carrya + stepa;
+      slot = last;
+    }
+    if (t == n && !etaps) {
       const node4<double> v1 = nodes[slot0 + last];
       for (int i = 0; i < EPL; ++i) {
         if (!ok[i]) continue;
@@ -475,6 +771,25 @@ static inline unsigned nb(int64_t n) { return static_cast<unsigned>((n + 255) / 
 
 void launch_adjoint(int epl, const AdjArgs& a, const AdjBufs& b, hipStream_t st) {
   const int64_t threads = a.nseg * a.G;
+  if (b.ck > 0) {
+#define QC_ADJC(E)                                                                                        \
+  hipLaunchKernelGGL(adjoint_ckpt_kernel<E>, dim3(nb(threads)), dim3(256), 0, st, a,                      \
+                     static_cast<const node4<double>*>(b.nodes), static_cast<const C*>(b.bc_g_prev),      \
+                     static_cast<const C*>(b.bc_gt_prev), static_cast<const double4*>(b.gS), b.gV, b.ck,   \
+                     b.ckbase, static_cast<C*>(b.ckg), static_cast<C*>(b.ckgt), static_cast<C*>(b.scr), b.nthr)
+    if (epl == 1)
+      QC_ADJC(1);
+    else if (epl == 2)
+      QC_ADJC(2);
+    else if (epl == 3)
+      QC_ADJC(3);
+    else if (epl == 4)
+      QC_ADJC(4);
+    else
+      QC_ADJC(8);
+#undef QC_ADJC
+    return;
+  }
 #define QC_ADJ(E)                                                                                        \
   hipLaunchKernelGGL(adjoint_kernel<E>, dim3(nb(threads)), dim3(256), 0, st, a,                          \
                      static_cast<const node4<double>*>(b.nodes), static_cast<const C*>(b.bc_g_prev),      \

@@ -281,6 +281,14 @@ struct qc_grain {
   void* lgt = nullptr;
   double* gS = nullptr;
   double* gV = nullptr;
+  // checkpointed reverse mode (adj_ck > 0): offsets and buffers for that ck
+  int adj_ck = 32;
+  int ck_built = 0;
+  int64_t* ckbase = nullptr;
+  void* ckg = nullptr;
+  void* ckgt = nullptr;
+  void* ckscr = nullptr;
+  size_t ckscr_bytes = 0;
   // transposed gather tables of the adjoint (built on first use)
   int64_t* bt_ptr = nullptr;
   int32_t* bt_c = nullptr;
@@ -330,7 +338,8 @@ void free_grain(qc_grain* g) {
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->cells, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV,
-                  g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw};
+                  g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw,
+                  g->ckbase, g->ckg, g->ckgt, g->ckscr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
@@ -1237,8 +1246,35 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     hipStream_t st = S(stream);
     hcheck(hipSetDevice(g->device), "hipSetDevice");
     const size_t nb = sizeof(double) * 2 * g->nslot * g->n_poles;
-    if (!g->gtbuf) g->gtbuf = dalloc(nb);
-    if (!g->lgt) g->lgt = dalloc(nb);
+    int G, epl;
+    lane_shape(g->n_poles, g->epl_override, g->precision == QC_MIXED, G, epl);
+    if (g->adj_ck == 0) {
+      if (!g->gtbuf) g->gtbuf = dalloc(nb);
+      if (!g->lgt) g->lgt = dalloc(nb);
+    } else {
+      const int ck = g->adj_ck;
+      if (g->ck_built != ck) {
+        // checkpoint blocks of each segment: ceil(n / ck)
+        const std::vector<int32_t> n = download(g->seg_n, g->nseg);
+        std::vector<int64_t> base(g->nseg + 1, 0);
+        for (int64_t sg = 0; sg < g->nseg; ++sg) base[sg + 1] = base[sg] + (n[sg] + ck - 1) / ck;
+        for (void* p : {static_cast<void*>(g->ckbase), g->ckg, g->ckgt})
+          if (p) (void)hipFree(p);
+        g->ckbase = static_cast<int64_t*>(upload(base));
+        const size_t cbytes = sizeof(double) * 2 * std::max<int64_t>(base[g->nseg], 1) * g->n_poles;
+        g->ckg = dalloc(cbytes);
+        g->ckgt = dalloc(cbytes);
+        g->ck_built = ck;
+      }
+      const size_t sbytes = sizeof(double) * 2 * 2 * static_cast<size_t>(ck) * epl * g->nseg * G;
+      if (sbytes > g->ckscr_bytes) {
+        if (g->ckscr) (void)hipFree(g->ckscr);
+        g->ckscr = nullptr;
+        g->ckscr_bytes = 0;
+        g->ckscr = dalloc(sbytes);
+        g->ckscr_bytes = sbytes;
+      }
+    }
     if (!g->gS) g->gS = static_cast<double*>(dalloc(sizeof(double) * 4 * g->nslot));
     if (!g->gV) g->gV = static_cast<double*>(dalloc(sizeof(double) * 3 * g->nslot));
     ensure_adjoint_tables(g);
@@ -1272,8 +1308,6 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     // reverse sweep with the store the latest sweep read
     qc::AdjArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
     a.bc_valid = g->last_bc_valid;
-    int G, epl;
-    lane_shape(g->n_poles, g->epl_override, g->precision == QC_MIXED, G, epl);
     qc::AdjBufs b;
     b.nodes = g->nodes;
     b.bc_g_prev = g->bc[1 - g->bc_cur][0];
@@ -1283,6 +1317,14 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     b.lgt = g->lgt;
     b.gS = g->gS;
     b.gV = g->gV;
+    if (g->adj_ck > 0) {
+      b.ck = g->adj_ck;
+      b.ckbase = g->ckbase;
+      b.ckg = g->ckg;
+      b.ckgt = g->ckgt;
+      b.scr = g->ckscr;
+      b.nthr = g->nseg * G;
+    }
     qc::launch_adjoint(epl, a, b, st);
     hcheck(hipGetLastError(), "adjoint launch");
     // back to the reference grid (the gather writes every cell)
@@ -1333,6 +1375,13 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     hcheck(hipGetLastError(), "adjoint launch");
     return QC_OK;
   });
+}
+
+qc_status qc_grain_set_adjoint_checkpoint(qc_grain* g, int every) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (every < 0 || every > 4096) return fail(QC_ERR_INVALID, "checkpoint interval must be in [0, 4096]");
+  g->adj_ck = every;
+  return QC_OK;
 }
 
 qc_status qc_grain_set_lanes(qc_grain* g, int energies_per_lane) {

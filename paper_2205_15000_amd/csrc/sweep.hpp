@@ -121,6 +121,14 @@ struct AdjBufs {
   void* lgt;               // node-local adjoint of gamma~ [nslot][n_e]
   const void* gS;          // gradients of the per-node sums [nslot][4]
   double* gV;              // out: gradients of the slot values [nslot][3] (Re D, Im D, a)
+  // checkpointed variant (ck > 0): gamma and gamma~ kept every ck slots, each
+  // block of ck slots recomputed into a per-thread scratch
+  int ck = 0;
+  const int64_t* ckbase = nullptr;  // first checkpoint block of each segment
+  void* ckg = nullptr;              // gamma entering block k: [block][n_e]
+  void* ckgt = nullptr;             // gamma~ at the first slot of block k: [block][n_e]
+  void* scr = nullptr;              // [2][ck][EPL][nthreads] complex
+  int64_t nthr = 0;                 // nseg * G
 };
 
 struct BackAdjArgs {

@@ -59,11 +59,13 @@ def _samples(mask, ncomp, rng, n):
     return cells
 
 
-@pytest.mark.parametrize("name,frozen", [("small_d110_field", True), ("small_holed_mixed", True),
-                                         ("small_d110_field", False)])
-def test_adjoint_matches_gpu_finite_differences(name, frozen):
+@pytest.mark.parametrize("name,frozen,ck", [("small_d110_field", True, 0), ("small_holed_mixed", True, 0),
+                                            ("small_d110_field", False, 0), ("small_d110_field", True, 3),
+                                            ("small_holed_mixed", False, 32)])
+def test_adjoint_matches_gpu_finite_differences(name, frozen, ck):
     qs, sp, g, d0, a0, c1, c2, c3 = _setup(name)
-    _note("case %s frozen=%s: adjoint vs GPU FD" % (name, frozen))
+    g.set_adjoint_checkpoint(ck)
+    _note("case %s frozen=%s checkpoint=%d: adjoint vs GPU FD" % (name, frozen, ck))
     dd, ad = torch.as_tensor(d0).cuda(), torch.as_tensor(a0).cuda()
     st = None
     if frozen:
@@ -156,3 +158,28 @@ def test_autograd_function_matches_adjoint():
     assert torch.allclose(dd.grad, gd, rtol=1e-12, atol=1e-12 * float(gd.abs().max()))
     assert torch.allclose(ad.grad, ga, rtol=1e-12, atol=1e-12 * float(ga.abs().max()))
     g.close()
+
+
+@pytest.mark.parametrize("name", ["small_d110_field", "small_mask_blob", "small_polygon_landau"])
+def test_checkpointed_adjoint_equals_stored_adjoint(name):
+    """Checkpoints every 1, 3 and 32 slots recompute the same marches as the
+    stored mode, so the gradients agree to rounding (frozen store and bulk
+    starts)."""
+    qs, sp, g, d0, a0, c1, c2, c3 = _setup(name)
+    _note("case %s: checkpointed vs stored adjoint" % name)
+    dd, ad = torch.as_tensor(d0).cuda(), torch.as_tensor(a0).cuda()
+    c1d, c2d = torch.as_tensor(c1).cuda(), torch.as_tensor(c2).cuda()
+    for frozen in (False, True):
+        g.reset_bc()
+        g.sweep(dd, ad)
+        if frozen:
+            g.sweep(dd, ad)
+        g.set_adjoint_checkpoint(0)
+        rd, ra = [x.cpu().numpy() for x in g.sweep_adjoint(dd, ad, c1d, c2d, c3)]
+        for ck in (1, 3, 32):
+            g.set_adjoint_checkpoint(ck)
+            gd, ga = [x.cpu().numpy() for x in g.sweep_adjoint(dd, ad, c1d, c2d, c3)]
+            assert np.max(np.abs(gd - rd)) <= 1e-12 * np.max(np.abs(rd)), (frozen, ck)
+            assert np.max(np.abs(ga - ra)) <= 1e-12 * np.max(np.abs(ra)), (frozen, ck)
+    g.close()
+

@@ -30,7 +30,8 @@ def _note(m):
 
 def test_adjoint_full_disc_free_energy_and_current_loss():
     """L = Omega + h^2 sum |j - j_target|^2 (seeded target) on the 200x200
-    d-wave disc, boundary store frozen: the reverse mode against central
+    d-wave disc, boundary store frozen: the reverse mode with checkpoints
+    every 32 steps against the stored mode and against central
     differences (step 1e-6) at 32 random (cell, component) points."""
     qs = _qs()
     name = "d_disc_200"
@@ -53,8 +54,15 @@ def test_adjoint_full_disc_free_energy_and_current_loss():
         return om + h2 * float(np.sum((j - jt) ** 2)), j
 
     _, j0 = loss(d0, a0)
-    gd, ga = g.sweep_adjoint(dd, ad, None, torch.as_tensor(2.0 * h2 * (j0 - jt)).cuda(), 1.0)
-    gd, ga = gd.cpu().numpy(), ga.cpu().numpy()
+    gjt = torch.as_tensor(2.0 * h2 * (j0 - jt)).cuda()
+    # checkpoint every 32 steps, as the configuration asks; the stored mode
+    # must give the same gradients
+    g.set_adjoint_checkpoint(32)
+    gd, ga = [x.cpu().numpy() for x in g.sweep_adjoint(dd, ad, None, gjt, 1.0)]
+    g.set_adjoint_checkpoint(0)
+    rd, ra = [x.cpu().numpy() for x in g.sweep_adjoint(dd, ad, None, gjt, 1.0)]
+    assert np.max(np.abs(gd - rd)) <= 1e-12 * np.max(np.abs(rd))
+    assert np.max(np.abs(ga - ra)) <= 1e-12 * np.max(np.abs(ra))
     mask = qs.Plan(dict(sp, n_theta=4)).mask()
     cells = rng.choice(np.nonzero(mask.ravel())[0], 32, replace=False)
     kinds = rng.integers(0, 4, 32)
