@@ -267,9 +267,10 @@ qc_status qc_sweep_adjoint(qc_grain* grain, const double* delta, const double* A
 /* ---- batched grains ----------------------------------------------------
  * Many grains of different shape, size, temperature, field, symmetry,
  * angle and pole counts iterated together: per iteration every grain's
- * interpolation runs, then ONE persistent sweep launch in which each wave
- * pulls tiles (a grain and a bundle of 64/G of its segments) from a queue
- * sorted by cost (longest trajectories first), then every grain's
+ * interpolation runs, then one persistent sweep launch per lane shape in
+ * use (usually one or two) in which each wave pulls tiles (a grain and a
+ * bundle of 64/G of its segments) from a queue sorted by cost (longest
+ * trajectories first), then every grain's
  * rotate-back, A-solve and Picard update (alpha = 1).  With use_graph the
  * iterations are replayed from a captured hipGraph (two iterations per
  * replay, one per boundary-store parity).  All grains must share device and
@@ -279,8 +280,9 @@ qc_status qc_sweep_adjoint(qc_grain* grain, const double* delta, const double* A
 typedef struct qc_batch qc_batch;
 qc_status qc_batch_create(qc_grain* const* grains, int n, qc_batch** out);
 void qc_batch_destroy(qc_batch* batch);
-/* trajectory steps of one iteration over all grains; energies per lane;
- * number of tiles.  Any output pointer may be NULL. */
+/* trajectory steps of one iteration over all grains; energies per lane
+ * (0: each grain its own automatic choice, the default); number of tiles.
+ * Any output pointer may be NULL. */
 qc_status qc_batch_get_info(const qc_batch* batch, int64_t* steps_per_iteration, int* energies_per_lane,
                             int* n_tiles);
 /* set / read grain i's fields: device complex [ncomp][ny][nx] and device
@@ -294,8 +296,9 @@ qc_status qc_batch_iterate(qc_batch* batch, int n_iter, int use_graph, void* str
 /* wall time of the latest qc_batch_iterate (HIP events on its stream) */
 qc_status qc_batch_last_ms(const qc_batch* batch, double* ms);
 /* autotuner: times iters_per_trial real iterations for each feasible
- * energies-per-lane choice (1, 2, 3, 4, 8) and keeps the fastest; these
- * iterations advance the self-consistency like qc_batch_iterate. */
+ * energies-per-lane choice (0 = per grain, 1, 2, 3, 4, 8) and keeps the
+ * fastest; these iterations advance the self-consistency like
+ * qc_batch_iterate. */
 qc_status qc_batch_autotune(qc_batch* batch, int iters_per_trial, int* best_epl, void* stream);
 
 /* Fermi-surface average of the quasiclassical Green's function at the

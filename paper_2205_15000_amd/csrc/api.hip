@@ -1439,12 +1439,14 @@ struct qc_batch {
   int precision = 0;
   std::vector<qc_grain*> grains;
   std::vector<double*> delta, A;   // per-grain fields owned by the batch
-  int epl = 2;
+  int epl = 0;  // energies per lane of every grain; 0: each grain's automatic choice
   int nblocks = 0;
   qc::BatchGrainDev* d_args = nullptr;  // [n] for the current launch
   int2* d_tiles = nullptr;
   int ntiles = 0;
-  int* d_counter = nullptr;
+  // tiles grouped by the grains' lane shapes: one persistent launch per group
+  std::vector<int> grp_epl, grp_off, grp_n;
+  int* d_counter = nullptr;  // one tile counter per group
   hipStream_t own = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<int> graph_parity;   // bc_cur of every grain when the graph was captured
@@ -1458,11 +1460,15 @@ namespace {
 
 // tiles: for every grain, waves of 64/G segments in launch order (longest
 // first); all tiles sorted by their longest segment, longest first
+// Tiles: for every grain, waves of 64/G segments in launch order (longest
+// first).  Grains are grouped by lane shape (energies per lane: the batch's
+// setting, or each grain's automatic choice when it is 0); within a group
+// the tiles are sorted by their longest segment, longest first.
 void build_tiles(qc_batch* b) {
   struct T3 {
     int g, w0, cost;
   };
-  std::vector<T3> all;
+  std::vector<std::vector<T3>> groups(9);
   for (size_t gi = 0; gi < b->grains.size(); ++gi) {
     qc_grain* g = b->grains[gi];
     int G, epl;
@@ -1471,11 +1477,22 @@ void build_tiles(qc_batch* b) {
     hcheck(hipMemcpy(ord.data(), g->order, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
     hcheck(hipMemcpy(n.data(), g->seg_n, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
     const int per = 64 / G;
-    for (int64_t w = 0; w < g->nseg; w += per) all.push_back({static_cast<int>(gi), static_cast<int>(w), n[ord[w]] + 1});
+    for (int64_t w = 0; w < g->nseg; w += per)
+      groups[epl].push_back({static_cast<int>(gi), static_cast<int>(w), n[ord[w]] + 1});
   }
-  std::stable_sort(all.begin(), all.end(), [](const T3& x, const T3& y) { return x.cost > y.cost; });
-  std::vector<int2> t(all.size());
-  for (size_t i = 0; i < all.size(); ++i) t[i] = make_int2(all[i].g, all[i].w0);
+  std::vector<int2> t;
+  b->grp_epl.clear();
+  b->grp_off.clear();
+  b->grp_n.clear();
+  for (int e = 1; e <= 8; ++e) {
+    std::vector<T3>& all = groups[e];
+    if (all.empty()) continue;
+    std::stable_sort(all.begin(), all.end(), [](const T3& x, const T3& y) { return x.cost > y.cost; });
+    b->grp_epl.push_back(e);
+    b->grp_off.push_back(static_cast<int>(t.size()));
+    b->grp_n.push_back(static_cast<int>(all.size()));
+    for (const T3& x : all) t.push_back(make_int2(x.g, x.w0));
+  }
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   b->d_tiles = static_cast<int2*>(upload(t));
   b->ntiles = static_cast<int>(t.size());
@@ -1539,10 +1556,14 @@ void rotate_back_grain(qc_grain* g, const double* delta, double* dnew, double* j
 void batch_iteration(qc_batch* b, hipStream_t st, bool upload) {
   for (size_t gi = 0; gi < b->grains.size(); ++gi) do_interp(b->grains[gi], b->delta[gi], b->A[gi], st);
   if (upload) upload_args(b, st);
-  if (b->precision == QC_MIXED)
-    qc::launch_batch_sweep<float>(b->epl, b->d_args, b->d_tiles, b->ntiles, b->d_counter, b->nblocks, st);
-  else
-    qc::launch_batch_sweep<double>(b->epl, b->d_args, b->d_tiles, b->ntiles, b->d_counter, b->nblocks, st);
+  for (size_t k = 0; k < b->grp_epl.size(); ++k) {
+    if (b->precision == QC_MIXED)
+      qc::launch_batch_sweep<float>(b->grp_epl[k], b->d_args, b->d_tiles + b->grp_off[k], b->grp_n[k],
+                                    b->d_counter + k, b->nblocks, st);
+    else
+      qc::launch_batch_sweep<double>(b->grp_epl[k], b->d_args, b->d_tiles + b->grp_off[k], b->grp_n[k],
+                                     b->d_counter + k, b->nblocks, st);
+  }
   for (size_t gi = 0; gi < b->grains.size(); ++gi) {
     qc_grain* g = b->grains[gi];
     rotate_back_grain(g, b->delta[gi], g->dnew, g->jcur, st);
@@ -1616,7 +1637,7 @@ qc_status qc_batch_create(qc_grain* const* grains, int n, qc_batch** out) {
       qc::launch_fill(g->dnew, 2 * g->ncomp * g->ncell, 0.0, nullptr);
     }
     b->d_args = static_cast<qc::BatchGrainDev*>(dalloc(sizeof(qc::BatchGrainDev) * n));
-    b->d_counter = static_cast<int*>(dalloc(sizeof(int)));
+    b->d_counter = static_cast<int*>(dalloc(8 * sizeof(int)));
     hcheck(hipStreamCreate(&b->own), "stream");
     build_tiles(b);
     hcheck(hipDeviceSynchronize(), "batch setup");
@@ -1767,9 +1788,10 @@ qc_status qc_batch_autotune(qc_batch* b, int iters_per_trial, int* best_epl, voi
   for (qc_grain* g : b->grains) maxp = std::max(maxp, g->n_poles);
   double best = INFINITY;
   int arg = b->epl;
-  const int cand[5] = {1, 2, 3, 4, 8};
+  // 0: every grain its own automatic lane shape (one launch per shape)
+  const int cand[6] = {0, 1, 2, 3, 4, 8};
   for (int e : cand) {
-    if ((maxp + e - 1) / e > 64) continue;
+    if (e > 0 && (maxp + e - 1) / e > 64) continue;
     b->epl = e;
     qc_status st = guarded([&]() -> qc_status {
       drop_graph(b);
