@@ -180,7 +180,8 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
                                               const cpx<T>* __restrict__ bc_g_prev,
                                               const cpx<T>* __restrict__ bc_gt_prev,
                                               cpx<T>* __restrict__ bc_g_next, cpx<T>* __restrict__ bc_gt_next,
-                                              cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
+                                              cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf,
+                                              double* __restrict__ lsum) {
   const int64_t seg = a.order ? static_cast<int64_t>(a.order[wseg]) : wseg;
   const int64_t slot0 = a.seg_slot0[seg];
   const int n = a.seg_n[seg];
@@ -308,7 +309,34 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
     const cpx<T>* src = gbuf + node * a.n_e;
     for (int i = 0; i < EPL; ++i) gv[i] = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
   };
-  auto node_sums = [&](int64_t node, const node4<T>& nv, const cpx<T>* gn) {
+  // Node sums through LDS (MODE 0, G >= 8).  The wave's buffer holds two
+  // nodes x four components x 64 lanes; slot b of component c of lane l is
+  // lsum[b * 256 + c * 64 + l].  Lanes of one wave see each other's LDS
+  // writes in issue order; the fences keep the compiler from moving the
+  // accesses across each other.  Every lane of a group then takes one
+  // (node, component) output and a block of 8 partials, and P = G / 8
+  // neighbouring lanes finish it with quad moves.
+  auto lds_reduce = [&](int64_t node0, int cnt) {
+    const int l64 = threadIdx.x & 63;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const int lp = a.log2g - 3;  // log2 P
+    const int o = lane >> lp, r = lane & ((1 << lp) - 1);
+    const double2* src = reinterpret_cast<const double2*>(lsum + o * 64 + (l64 - lane));
+    double v = 0.0;
+    for (int j = 0; j < 4; ++j) {  // partials of lanes 8 r .. 8 r + 7 of the group
+      const double2 x = src[(r << 2) + j];
+      v += x.x + x.y;
+    }
+    if (lp >= 1) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    if (lp >= 2) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if (lp >= 3) v += dpp_f64<0x141>(v);  // row_half_mirror: lane 0 of 8 adds lane 7
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // slot b = o >> 2 holds node0 - b; component o & 3
+    if (r == 0 && (o >> 2) < cnt) a.node_out[(node0 - (o >> 2)) * 4 + (o & 3)] = a.twopi_tt * v;
+  };
+  // k counts the nodes visited before this one (the same for every group of
+  // the wave, since all groups start their march together)
+  auto node_sums = [&](int64_t node, const node4<T>& nv, const cpx<T>* gn, int k) {
     if (MODE == 0) {
       double sfx = 0.0, sfy = 0.0, sg = 0.0, s1 = 0.0, s2 = 0.0;
       for (int i = 0; i < EPL; ++i) {
@@ -332,7 +360,17 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
       // Im(D* gamma - D gamma~) summed over the lane's poles
       const double si = static_cast<double>(nv.dx) * s1 - static_cast<double>(nv.dy) * s2;
       // S_f = -2 i pi t~ (sfx + i sfy), S_g = 2 pi t~ sg, S_I = 2 pi t~ si
-      if (a.G >= 4) {
+      if (a.G >= 8) {
+        // the lane's four partials go to LDS; every second node the group
+        // sums the pair (this node and the one before it, node + 1)
+        const int b = k & 1;
+        double* w = lsum + b * 256 + (threadIdx.x & 63);
+        w[0] = sfy;
+        w[64] = -sfx;
+        w[128] = sg;
+        w[192] = si;
+        if (b) lds_reduce(node + 1, 2);
+      } else if (a.G >= 4) {
         // lane q of the group (q < 4) ends with component q of the node's sums
         const double v = group_sum4_scatter(sfy, -sfx, sg, si, a.G, lane);
         if (lane < 4) a.node_out[node * 4 + scatter_index(lane)] = a.twopi_tt * v;
@@ -378,7 +416,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   cpx<T> gn[EPL];
   if (MODE != 2) load_g(gn, slot0 + last);
   end_step(gt, prev, prev, n > 0 ? hlast : hfirst, T(-1));
-  if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev, gn);
+  if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev, gn, 0);
   // slot values are loaded one step ahead (gamma is not: the registers
   // would cost occupancy, and its load is not on the step's critical path)
   nxt = nodes[slot0 + max(n - 2, 0)];
@@ -388,8 +426,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
     if (MODE != 2) load_g(gn, slot0 + t - 1);
     mid_step(gt, prev, cur, T(-1));
     prev = cur;
-    if (MODE != 2) node_sums(slot0 + t - 1, cur, gn);
+    if (MODE != 2) node_sums(slot0 + t - 1, cur, gn, n - t);
   }
+  // with an odd node count, node 0 is left alone in slot 0
+  if (MODE == 0 && a.G >= 8 && (n & 1)) lds_reduce(slot0, 1);
   // step 0 to R_min (boundary point = slot 0)
   if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
   if (MODE == 0 || MODE == 2) {
@@ -419,7 +459,13 @@ sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
   const int64_t wseg = gtid >> a.log2g;
   const int lane = static_cast<int>(gtid & (a.G - 1));
   if (wseg >= a.nseg) return;  // whole lane groups leave together (G | 64)
-  sweep_segment<T, EPL, MODE>(a, wseg, lane, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, ebuf);
+  double* lsum = nullptr;
+  if constexpr (MODE == 0) {
+    __shared__ double red[4 * 512];  // two nodes x four sums x 64 lanes per wave
+    lsum = red + (threadIdx.x >> 6) * 512;
+  }
+  sweep_segment<T, EPL, MODE>(a, wseg, lane, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, ebuf,
+                              lsum);
 }
 
 // Batched grains: one persistent launch.  Every wave pulls tiles (a grain
@@ -431,6 +477,7 @@ batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
                                                           const int2* __restrict__ tiles, int ntiles,
                                                           int* __restrict__ counter) {
   const int l64 = threadIdx.x & 63;
+  __shared__ double red[4 * 512];  // node-sum exchange, two nodes x four sums x 64 lanes per wave
   while (true) {
     int t = 0;
     if (l64 == 0) t = atomicAdd(counter, 1);
@@ -445,7 +492,7 @@ batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
       sweep_segment<T, EPL, 0>(gd.a, wseg, l64 & (gd.a.G - 1), static_cast<const node4<T>*>(gd.b.nodes),
                                static_cast<const cpx<T>*>(gd.b.bc_g_prev), static_cast<const cpx<T>*>(gd.b.bc_gt_prev),
                                static_cast<cpx<T>*>(gd.b.bc_g_next), static_cast<cpx<T>*>(gd.b.bc_gt_next),
-                               static_cast<cpx<T>*>(gd.b.gbuf), nullptr);
+                               static_cast<cpx<T>*>(gd.b.gbuf), nullptr, red + (threadIdx.x >> 6) * 512);
   }
 }
 
