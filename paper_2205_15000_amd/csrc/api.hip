@@ -243,6 +243,10 @@ struct qc_grain {
   double* slot_px = nullptr;
   double* slot_py = nullptr;
   int32_t* slot_fb = nullptr;
+  int2* slot_sf = nullptr;           // per slot: segment, fallback cell
+  qc::SegGeo* seg_geo = nullptr;
+  double cx = 0, cy = 0, half = 0, flux = 0, bfield = 0;
+  int gauge = 0;
   double x0 = 0, y0 = 0;
   double* aext = nullptr;
   double* eta = nullptr;
@@ -260,6 +264,7 @@ struct qc_grain {
   int32_t* grain_cells = nullptr;
   int32_t* rb_idx = nullptr;
   double* rb_w = nullptr;
+  int4* rb4 = nullptr;
   uint8_t* mask = nullptr;
   double* eps = nullptr;
   double* rpd = nullptr;
@@ -332,9 +337,9 @@ enum { kROmega = 0, kRB2 = 1, kRJx = 2, kRJy = 3, kRDiffD = 4, kRDiffJ = 6, kRDi
 namespace {
 
 void free_grain(qc_grain* g) {
-  void* ptrs[] = {g->slot_angle, g->slot_px, g->slot_py, g->slot_fb, g->aext, g->eta, g->cosk,
+  void* ptrs[] = {g->slot_angle, g->slot_px, g->slot_py, g->slot_fb, g->slot_sf, g->seg_geo, g->aext, g->eta, g->cosk,
                   g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
-                  g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->mask,
+                  g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->rb4, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->cells, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV,
@@ -398,6 +403,39 @@ qc::GridGeom geom_of(const qc_grain* g) {
   return gg;
 }
 
+// rotate-back of the node sums into Delta_new, j and the free energy
+qc::BackArgs back_args(qc_grain* g, const double* delta, double* dnew, double* j, double* omega) {
+  qc::BackArgs r;
+  r.ncg = g->ncg;
+  r.ncell = g->ncell;
+  r.ncomp = g->ncomp;
+  r.n_theta = g->n_theta;
+  r.grain_cells = g->grain_cells;
+  r.rb4 = g->rb4;
+  r.nx = g->nx;
+  r.x0 = g->x0;
+  r.y0 = g->y0;
+  r.h = g->h;
+  r.cx = g->cx;
+  r.cy = g->cy;
+  r.half = g->half;
+  r.node_out = g->node_out;
+  r.wk = g->wk;
+  r.cosk = g->cosk;
+  r.sink = g->sink;
+  r.eta = g->eta;
+  r.den = g->den;
+  r.logt = g->logt;
+  r.four_q = 4.0 * g->q;
+  r.twopi_rz = g->twopi_rz;
+  r.delta = delta;
+  r.delta_new = dnew;
+  r.j = j;
+  r.omega = omega;
+  r.omega_cell = g->omega_cell;
+  return r;
+}
+
 void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st) {
   qc::InterpArgs a;
   a.nslot = g->nslot;
@@ -415,6 +453,14 @@ void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st
   a.sink = g->sink;
   a.delta = delta;
   a.A = A;
+  a.slot_sf = g->slot_sf;
+  a.seg_geo = g->seg_geo;
+  a.cx = g->cx;
+  a.cy = g->cy;
+  a.half = g->half;
+  a.gauge = g->gauge;
+  a.flux = g->flux;
+  a.bfield = g->bfield;
   if (g->ncomp == 1 && !g->cells) g->cells = dalloc(4 * g->real_bytes() * g->ncell);
   void* cells = g->ncomp == 1 ? g->cells : nullptr;
   if (g->precision == QC_MIXED)
@@ -513,29 +559,7 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   qc::launch_fill(delta_new, 2 * g->ncomp * g->ncell, 0.0, st);
   qc::launch_fill(j, 2 * g->ncell, 0.0, st);
   if (omega) qc::launch_fill(omega, g->ncell, 0.0, st);
-  qc::BackArgs r;
-  r.ncg = g->ncg;
-  r.ncell = g->ncell;
-  r.ncomp = g->ncomp;
-  r.n_theta = g->n_theta;
-  r.grain_cells = g->grain_cells;
-  r.rb_idx = g->rb_idx;
-  r.rb_w = g->rb_w;
-  r.node_out = g->node_out;
-  r.wk = g->wk;
-  r.cosk = g->cosk;
-  r.sink = g->sink;
-  r.eta = g->eta;
-  r.den = g->den;
-  r.logt = g->logt;
-  r.four_q = 4.0 * g->q;
-  r.twopi_rz = g->twopi_rz;
-  r.delta = delta;
-  r.delta_new = delta_new;
-  r.j = j;
-  r.omega = omega;
-  r.omega_cell = g->omega_cell;
-  qc::launch_rotate_back(r, st);
+  qc::launch_rotate_back(back_args(g, delta, delta_new, j, omega), st);
   hcheck(hipGetLastError(), "rotate-back launch");
   // block partials of the free energy (condensation and magnetic parts)
   qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, region(g, kROmega), kParts, st);
@@ -693,6 +717,28 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
     g->slot_px = static_cast<double*>(upload(p.slot_px));
     g->slot_py = static_cast<double*>(upload(p.slot_py));
     g->slot_fb = static_cast<int32_t*>(upload(p.slot_fb));
+    {
+      std::vector<int2> sf(p.slot_seg.size());
+      for (size_t i = 0; i < sf.size(); ++i) sf[i] = make_int2(p.slot_seg[i], p.slot_fb[i]);
+      std::vector<qc::SegGeo> sg(static_cast<size_t>(p.nseg));
+      for (int64_t i = 0; i < p.nseg; ++i) {
+        sg[i].slot0 = p.seg_slot0[i];
+        sg[i].u = (p.seg_line[i] - p.half) * p.h;  // the plan's expression
+        sg[i].smid = 0.5 * (p.seg_smin[i] + p.seg_smax[i]);
+        sg[i].jf = p.seg_jfirst[i];
+        sg[i].n = p.seg_n[i];
+        sg[i].k = p.seg_angle[i];
+        sg[i].pad = 0;
+      }
+      g->slot_sf = static_cast<int2*>(upload(sf));
+      g->seg_geo = static_cast<qc::SegGeo*>(upload(sg));
+      g->cx = p.cx;
+      g->cy = p.cy;
+      g->half = p.half;
+      g->gauge = p.gauge;
+      g->flux = p.flux;
+      g->bfield = p.area > 0.0 ? kPi * p.flux / p.area : 0.0;
+    }
     g->x0 = p.x0;
     g->y0 = p.y0;
     g->aext = static_cast<double*>(upload(p.slot_aext));
@@ -711,6 +757,7 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
     g->grain_cells = static_cast<int32_t*>(upload(p.grain_cells));
     g->rb_idx = static_cast<int32_t*>(upload(p.rb_idx));
     g->rb_w = static_cast<double*>(upload(p.rb_w));
+    g->rb4 = static_cast<int4*>(upload(p.rb4));
     g->mask = static_cast<uint8_t*>(upload(p.mask));
     g->eps = static_cast<double*>(upload(eps));
     g->rpd = static_cast<double*>(upload(p.rp));
@@ -1525,29 +1572,7 @@ void upload_args(qc_batch* b, hipStream_t st) {
 }
 
 void rotate_back_grain(qc_grain* g, const double* delta, double* dnew, double* j, hipStream_t st) {
-  qc::BackArgs r;
-  r.ncg = g->ncg;
-  r.ncell = g->ncell;
-  r.ncomp = g->ncomp;
-  r.n_theta = g->n_theta;
-  r.grain_cells = g->grain_cells;
-  r.rb_idx = g->rb_idx;
-  r.rb_w = g->rb_w;
-  r.node_out = g->node_out;
-  r.wk = g->wk;
-  r.cosk = g->cosk;
-  r.sink = g->sink;
-  r.eta = g->eta;
-  r.den = g->den;
-  r.logt = g->logt;
-  r.four_q = 4.0 * g->q;
-  r.twopi_rz = g->twopi_rz;
-  r.delta = delta;
-  r.delta_new = dnew;
-  r.j = j;
-  r.omega = nullptr;
-  r.omega_cell = g->omega_cell;
-  qc::launch_rotate_back(r, st);
+  qc::launch_rotate_back(back_args(g, delta, dnew, j, nullptr), st);
 }
 
 // one Picard iteration (alpha = 1) of every grain: per-grain interpolation,

@@ -221,6 +221,27 @@ __device__ __forceinline__ cpx<T> bulk_root(T zx, T zy, T dx, T dy) {
   return mk(-(dx * bx + dy * by) * r, -(dy * bx - dx * by) * r);
 }
 
+// Lattice and cell positions rounded operation by operation, in the order
+// written, as the host plan forms them (its host code has no fused
+// multiply-add): floor() of these values then picks the plan's corners even
+// where a coordinate sits exactly on a lattice line.
+__device__ __forceinline__ double rn_point(double c0, double u, double eu, double s, double es) {
+#pragma clang fp contract(off)
+  return c0 + u * eu + s * es;
+}
+__device__ __forceinline__ double rn_node_s(double j, double half, double h) {
+#pragma clang fp contract(off)
+  return (j - half) * h;
+}
+__device__ __forceinline__ double rn_cell_offset(double x0, double i, double h, double c) {
+#pragma clang fp contract(off)
+  return x0 + (i + 0.5) * h - c;
+}
+__device__ __forceinline__ double rn_lattice(double rx, double ex, double ry, double ey, double h, double half) {
+#pragma clang fp contract(off)
+  return (rx * ex + ry * ey) / h + half;
+}
+
 // Bilinear weights of the four cell centres around (px, py) on the
 // reference grid (Sec. III.A), formed with the same IEEE operations as the
 // host tables (the adjoint's transposed tables call them on the host).  Delta: corners off the array or outside the grain are

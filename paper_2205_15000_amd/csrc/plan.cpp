@@ -450,6 +450,7 @@ void build_plan(Plan& p) {
   const int64_t nc = static_cast<int64_t>(p.grain_cells.size());
   p.rb_idx.assign(static_cast<size_t>(p.n_theta) * 4 * nc, 0);
   p.rb_w.assign(static_cast<size_t>(p.n_theta) * 4 * nc, 0.0);
+  p.rb4.assign(static_cast<size_t>(p.n_theta) * 4 * nc, -1);
   std::vector<int32_t> node(static_cast<size_t>(M) * M);
   for (int k = 0; k < p.n_theta; ++k) {
     std::fill(node.begin(), node.end(), -1);
@@ -471,10 +472,12 @@ void build_plan(Plan& p) {
       const int lj[4] = {j0, j0, j0 + 1, j0 + 1};
       double w[4] = {(1 - wu) * (1 - wv), wu * (1 - wv), (1 - wu) * wv, wu * wv};
       int32_t idx[4];
+      int32_t* c4 = &p.rb4[(static_cast<size_t>(k) * nc + a) * 4];
       double tot = 0.0;
       for (int q = 0; q < 4; ++q) {
         int32_t s = -1;
         if (li[q] >= 0 && li[q] < M && lj[q] >= 0 && lj[q] < M) s = node[static_cast<size_t>(li[q]) * M + lj[q]];
+        c4[q] = s;
         idx[q] = s >= 0 ? s : 0;
         if (s < 0) w[q] = 0.0;
         tot += w[q];
@@ -502,6 +505,8 @@ void build_plan(Plan& p) {
           if (best >= 0 && bd <= static_cast<double>(R) * R) break;
         }
         if (best < 0) throw std::runtime_error("rotate-back: angle without interior node");
+        c4[0] = best;
+        c4[1] = c4[2] = c4[3] = -2;
         idx[0] = best;
         idx[1] = idx[2] = idx[3] = 0;
         w[0] = 1.0;

@@ -77,6 +77,9 @@ struct Plan {
   // ---- rotate-back stencils of grain cells: [angle][corner][cell]
   std::vector<int32_t> rb_idx;         // global slot index
   std::vector<double> rb_w;
+  // compact form [n_theta][ncg][4]: slot of each corner or -1; a cell that
+  // takes its nearest node instead holds {slot, -2, -2, -2}
+  std::vector<int32_t> rb4;
 
   // ---- specular boundary taps: [seg][4]
   std::vector<int32_t> tap_start_seg, tap_end_seg;

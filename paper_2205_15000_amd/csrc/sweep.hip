@@ -87,9 +87,17 @@ __global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= a.nslot) return;
   const GridGeom& gg = a.geom;
-  const int k = a.slot_angle[s];
-  const double px = a.px[s], py = a.py[s];
-  const int fb = a.fb[s];
+  const int2 sf = a.slot_sf[s];
+  const SegGeo sgeo = a.seg_geo[sf.x];
+  const int k = sgeo.k;
+  const int fb = sf.y;
+  // the slot position as the plan forms it, so the corner choice below is
+  // the one the nearest-cell fallback was decided on
+  const double epx = a.cosk[k], epy = a.sink[k];
+  const double sp = sgeo.n > 0 ? rn_node_s(static_cast<double>(sgeo.jf + static_cast<int>(s - sgeo.slot0)), a.half, gg.h)
+                               : sgeo.smid;
+  const double px = rn_point(a.cx, sgeo.u, epy, sp, epx);
+  const double py = rn_point(a.cy, sgeo.u, -epx, sp, epy);
   const double fx = (px - gg.x0) / gg.h - 0.5, fy = (py - gg.y0) / gg.h - 0.5;
   const int i0 = static_cast<int>(__builtin_floor(fx)), j0 = static_cast<int>(__builtin_floor(fy));
   const double wx = fx - i0, wy = fy - j0;
@@ -154,7 +162,22 @@ __global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<
   node4<T> o;
   o.dx = static_cast<T>(dx);
   o.dy = static_cast<T>(dy);
-  o.a = static_cast<T>(a.cosk[k] * ax + a.sink[k] * ay + a.aext[s]);
+  // external field (analytic, Sec. III.C gauges)
+  double ex_x = 0.0, ex_y = 0.0;
+  const double rx = px - a.cx, ry = py - a.cy;
+  if (a.gauge == 0) {
+    ex_x = -0.5 * a.bfield * ry;
+    ex_y = 0.5 * a.bfield * rx;
+  } else if (a.gauge == 1) {
+    ex_x = -a.bfield * ry;
+  } else {
+    const double r2 = rx * rx + ry * ry;
+    if (r2 > 0.0) {
+      ex_x = -0.5 * a.flux * ry / r2;
+      ex_y = 0.5 * a.flux * rx / r2;
+    }
+  }
+  o.a = static_cast<T>(epx * (ax + ex_x) + epy * (ay + ex_y));
   o.pad = T(0);
   nodes[s] = o;
 }
@@ -503,12 +526,21 @@ __global__ void reset_counter_kernel(int* counter) {
 // --------------------------------------------------------------------------
 // rotate back + angle sums + gap / current / free energy
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) rotate_back_kernel(BackArgs a) {
+// A block of kBackWaves waves shares 64 grain cells: wave w takes the angles
+// k = w, w + kBackWaves, ... for all of them, so each load of a wave gathers
+// the lattice corners of 64 neighbouring cells at one angle; the waves'
+// partial angle sums meet in LDS.
+constexpr int kBackWaves = 4;
+constexpr int kBackFields = 12;  // 2 x (up to 4 components) + jx, jy, I, <|Delta|^2>
+
+__global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a) {
+  __shared__ double part[kBackWaves - 1][kBackFields][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // each XCD takes a contiguous band of grain cells: neighbouring cells share
   // lattice corners, which then meet in the same L2
-  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (c >= a.ncg) return;
-  const int cell = a.grain_cells[c];
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
+  const bool live = c < a.ncg;
+  const int cell = live ? a.grain_cells[c] : 0;
   constexpr int MAXC = 4;
   double nx_[MAXC], ny_[MAXC], dx_[MAXC], dy_[MAXC];
   for (int g = 0; g < a.ncomp; ++g) {
@@ -517,18 +549,43 @@ __global__ void __launch_bounds__(256) rotate_back_kernel(BackArgs a) {
     dx_[g] = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + cell)];
     dy_[g] = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + cell) + 1];
   }
+  // cell centre relative to the grid centre, as the plan forms it
+  const double rx = rn_cell_offset(a.x0, static_cast<double>(cell % a.nx), a.h, a.cx);
+  const double ry = rn_cell_offset(a.y0, static_cast<double>(cell / a.nx), a.h, a.cy);
+  const double4* nsum = reinterpret_cast<const double4*>(a.node_out);
   double jx = 0.0, jy = 0.0, icell = 0.0, d2avg = 0.0;
-  for (int k = 0; k < a.n_theta; ++k) {
+  for (int k = live ? wv : a.n_theta; k < a.n_theta; k += kBackWaves) {
+    const int4 ix = a.rb4[static_cast<int64_t>(k) * a.ncg + c];
+    const double epx = a.cosk[k], epy = a.sink[k];
+    // lattice coordinates (line u, node v) of the cell centre
+    const double u = rn_lattice(rx, epy, ry, -epx, a.h, a.half);
+    const double v = rn_lattice(rx, epx, ry, epy, a.h, a.half);
+    const double wu = u - __builtin_floor(u), wv = v - __builtin_floor(v);
+    double w[4] = {(1 - wu) * (1 - wv), wu * (1 - wv), (1 - wu) * wv, wu * wv};
+    int sl[4] = {ix.x, ix.y, ix.z, ix.w};
+    if (ix.y == -2) {  // no lattice corner is a node: the nearest node alone
+      w[0] = 1.0;
+      w[1] = w[2] = w[3] = 0.0;
+    }
+    // corners that are not nodes read slot 0 with weight 0, so the four
+    // gathers issue together
+    double tot = 0.0;
+    for (int qd = 0; qd < 4; ++qd) {
+      if (sl[qd] < 0) {
+        w[qd] = 0.0;
+        sl[qd] = 0;
+      }
+      tot += w[qd];
+    }
+    const double rt = (ix.x | ix.y | ix.z | ix.w) < 0 ? 1.0 / tot : 1.0;
     double cfx = 0.0, cfy = 0.0, cg = 0.0, ci = 0.0;
     for (int qd = 0; qd < 4; ++qd) {
-      const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
-      const int64_t s = a.rb_idx[o];
-      const double w = a.rb_w[o];
-      const double4 v = reinterpret_cast<const double4*>(a.node_out)[s];
-      cfx += v.x * w;
-      cfy += v.y * w;
-      cg += v.z * w;
-      ci += v.w * w;
+      const double4 vv = nsum[sl[qd]];
+      const double wq = w[qd] * rt;
+      cfx += vv.x * wq;
+      cfy += vv.y * wq;
+      cg += vv.z * wq;
+      ci += vv.w * wq;
     }
     const double wk = a.wk[k];
     double dkx = 0.0, dky = 0.0;
@@ -540,10 +597,34 @@ __global__ void __launch_bounds__(256) rotate_back_kernel(BackArgs a) {
       dkx += ex * dx_[g] - ey * dy_[g];
       dky += ex * dy_[g] + ey * dx_[g];
     }
-    jx += a.four_q * wk * a.cosk[k] * cg;
-    jy += a.four_q * wk * a.sink[k] * cg;
+    jx += a.four_q * wk * epx * cg;
+    jy += a.four_q * wk * epy * cg;
     icell += wk * ci;
     d2avg += wk * (dkx * dkx + dky * dky);
+  }
+  if (wv > 0) {
+    double* p = &part[wv - 1][0][lane];
+    for (int g = 0; g < a.ncomp; ++g) {
+      p[64 * (2 * g)] = nx_[g];
+      p[64 * (2 * g + 1)] = ny_[g];
+    }
+    p[64 * 8] = jx;
+    p[64 * 9] = jy;
+    p[64 * 10] = icell;
+    p[64 * 11] = d2avg;
+  }
+  __syncthreads();
+  if (wv > 0 || !live) return;
+  for (int w = 0; w < kBackWaves - 1; ++w) {
+    const double* p = &part[w][0][lane];
+    for (int g = 0; g < a.ncomp; ++g) {
+      nx_[g] += p[64 * (2 * g)];
+      ny_[g] += p[64 * (2 * g + 1)];
+    }
+    jx += p[64 * 8];
+    jy += p[64 * 9];
+    icell += p[64 * 10];
+    d2avg += p[64 * 11];
   }
   double om = 0.0;
   for (int g = 0; g < a.ncomp; ++g) {
@@ -899,7 +980,7 @@ template void launch_batch_sweep<float>(int, const BatchGrainDev*, const int2*, 
 
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;
-  hipLaunchKernelGGL(rotate_back_kernel, dim3(nblk(a.ncg)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(rotate_back_kernel, dim3((a.ncg + 63) / 64), dim3(64 * kBackWaves), 0, st, a);
 }
 
 template <typename T>

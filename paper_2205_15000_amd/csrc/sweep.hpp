@@ -9,6 +9,16 @@
 
 namespace qc {
 
+// Lattice geometry of one segment: its slots are slot0 .. slot0 + max(n, 1) - 1
+// and slot t sits at s = (jf + t - half) h along the line u (n > 0), or at
+// the segment midpoint smid (n = 0).
+struct SegGeo {
+  int64_t slot0;
+  double u;     // (line - half) h
+  double smid;  // (s_min + s_max) / 2
+  int32_t jf, n, k, pad;
+};
+
 struct InterpArgs {
   int64_t nslot;
   int64_t ncell;  // nx * ny
@@ -24,6 +34,12 @@ struct InterpArgs {
   const double* sink;
   const double* delta;  // complex [ncomp][ny][nx]
   const double* A;      // [2][ny][nx]
+  // single-component path: slot positions and A_ext formed on the fly
+  const int2* slot_sf;     // per slot: segment, nearest-cell fallback (-1: none)
+  const SegGeo* seg_geo;
+  double cx, cy, half;     // grid centre and (M - 1) / 2
+  int gauge;               // 0 symmetric, 1 Landau, 2 solenoid
+  double flux, bfield;     // flux quanta; pi flux / area
 };
 
 struct SweepArgs {
@@ -69,8 +85,11 @@ struct BackArgs {
   int64_t ncell;   // nx * ny
   int ncomp, n_theta;
   const int32_t* grain_cells;
-  const int32_t* rb_idx;
-  const double* rb_w;
+  // [n_theta][ncg] corner slots (-1: not a node; {s, -2, -2, -2}: nearest
+  // node s alone); the bilinear weights are formed from the cell position
+  const int4* rb4;
+  int nx;
+  double x0, y0, h, cx, cy, half;
   const double* node_out;
   const double* wk;
   const double* cosk;
