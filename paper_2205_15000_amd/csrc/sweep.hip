@@ -462,12 +462,13 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
 }
 
-// Occupancy floors (waves per SIMD) that the FP32 variants reach without
-// spills: 7 (<= 72 VGPRs) with two energies per lane, 5 (<= 96) with four;
-// the rest keep the compiler's default.
+// Occupancy floors (waves per SIMD) for the FP32 variants: 7 (<= 72 VGPRs)
+// with two energies per lane (a few spills outside the loops), 4 (<= 128,
+// no spills; 5 spilled in the loops) with four; the rest keep the
+// compiler's default.
 template <typename T, int EPL>
 constexpr int sweep_min_waves() {
-  return (sizeof(T) == 4 && EPL == 4) ? 5 : (sizeof(T) == 4 && EPL == 2) ? 7 : 1;
+  return (sizeof(T) == 4 && EPL == 4) ? 4 : (sizeof(T) == 4 && EPL == 2) ? 7 : 1;
 }
 
 template <typename T, int EPL, int MODE>
