@@ -237,6 +237,7 @@ struct qc_grain {
   int nx = 0, ny = 0, ncomp = 0, n_theta = 0, n_poles = 0, precision = 0;
   double h = 0, t = 0, kappa = 0, q = -1, twopi_rz = 0;
   int64_t ncell = 0, ncg = 0, nseg = 0, nslot = 0;
+  int maxn = 1;  // most nodes of any segment
   std::vector<double> zp, rp;
   // static tables
   int32_t* slot_angle = nullptr;
@@ -494,6 +495,7 @@ qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const dou
   a.eps = eps;
   a.rp = rp;
   a.node_out = g->node_out;
+  a.maxn = g->maxn;
   return a;
 }
 
@@ -525,12 +527,14 @@ double omega_from_parts(const qc_grain* g) {
 
 // buffers of the iteration map (gamma at nodes, per-node sums, boundary
 // store), allocated on first use so that LDOS-only grains do not hold them
-void ensure_sweep_buffers(qc_grain* g) {
+// spill: also the gamma spill of single-grain sweeps (batched sweeps keep it
+// in per-wave scratch instead)
+void ensure_sweep_buffers(qc_grain* g, bool spill = true) {
   // the packed interpolation cells are needed before any graph capture
   if (g->ncomp == 1 && !g->cells) g->cells = dalloc(4 * g->real_bytes() * g->ncell);
-  if (g->gbuf) return;
   const size_t rb = g->real_bytes();
-  g->gbuf = dalloc(2 * rb * g->nslot * g->n_poles);
+  if (spill && !g->gbuf) g->gbuf = dalloc(2 * rb * g->nslot * g->n_poles);
+  if (g->node_out) return;
   g->node_out = static_cast<double*>(dalloc(4 * sizeof(double) * g->nslot));
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) g->bc[a][b] = dalloc(2 * rb * g->nseg * g->n_poles);
@@ -692,6 +696,7 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
     g->ncg = static_cast<int64_t>(p.grain_cells.size());
     g->nseg = p.nseg;
     g->nslot = p.nslot;
+    for (int32_t n : p.seg_n) g->maxn = std::max(g->maxn, static_cast<int>(n));
     g->zp = p.zp;
     g->rp = p.rp;
     double rz = 0.0;
@@ -1154,7 +1159,7 @@ qc_status qc_get_state(const qc_grain* g, void* state, size_t* bytes, void* stre
     return QC_OK;
   }
   if (*bytes < 2 * half) return fail(QC_ERR_INVALID, "state buffer too small");
-  if (!g->bc_valid || !g->gbuf) return fail(QC_ERR_INVALID, "no boundary values yet (run a sweep first)");
+  if (!g->bc_valid || !g->bc[0][0]) return fail(QC_ERR_INVALID, "no boundary values yet (run a sweep first)");
   return guarded([&]() -> qc_status {
     hcheck(hipSetDevice(g->device), "hipSetDevice");
     hcheck(hipMemcpyAsync(state, g->bc[g->bc_cur][0], half, hipMemcpyDeviceToDevice, S(stream)), "copy");
@@ -1490,6 +1495,11 @@ struct qc_batch {
   int nblocks = 0;
   qc::BatchGrainDev* d_args = nullptr;  // [n] for the current launch
   int2* d_tiles = nullptr;
+  // gamma spill of the persistent sweep: wave_elems records per resident
+  // wave slot (nblocks x 4 slots), sized for the largest tile of any grain
+  void* spill = nullptr;
+  size_t spill_bytes = 0;
+  int64_t wave_elems = 0;
   int ntiles = 0;
   // tiles grouped by the grains' lane shapes: one persistent launch per group
   std::vector<int> grp_epl, grp_off, grp_n;
@@ -1511,6 +1521,8 @@ namespace {
 // first).  Grains are grouped by lane shape (energies per lane: the batch's
 // setting, or each grain's automatic choice when it is 0); within a group
 // the tiles are sorted by their longest segment, longest first.
+void drop_graph(qc_batch* b);
+
 void build_tiles(qc_batch* b) {
   struct T3 {
     int g, w0, cost;
@@ -1543,6 +1555,23 @@ void build_tiles(qc_batch* b) {
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   b->d_tiles = static_cast<int2*>(upload(t));
   b->ntiles = static_cast<int>(t.size());
+  // per-wave spill: 64/G segments of up to maxn nodes and n_e poles each
+  int64_t we = 1;
+  for (qc_grain* g : b->grains) {
+    int G, epl;
+    lane_shape(g->n_poles, b->epl, g->precision == QC_MIXED, G, epl);
+    we = std::max(we, static_cast<int64_t>(64 / G) * g->maxn * g->n_poles);
+  }
+  b->wave_elems = we;
+  const size_t need = static_cast<size_t>(b->nblocks) * 4 * we * 2 * b->grains[0]->real_bytes();
+  if (need > b->spill_bytes) {
+    drop_graph(b);  // a captured graph holds the old pointer
+    if (b->spill) (void)hipFree(b->spill);
+    b->spill = nullptr;
+    b->spill_bytes = 0;
+    b->spill = dalloc(need);
+    b->spill_bytes = need;
+  }
 }
 
 // per-grain arguments of the next sweep (each grain's current store parity)
@@ -1584,10 +1613,10 @@ void batch_iteration(qc_batch* b, hipStream_t st, bool upload) {
   for (size_t k = 0; k < b->grp_epl.size(); ++k) {
     if (b->precision == QC_MIXED)
       qc::launch_batch_sweep<float>(b->grp_epl[k], b->d_args, b->d_tiles + b->grp_off[k], b->grp_n[k],
-                                    b->d_counter + k, b->nblocks, st);
+                                    b->d_counter + k, b->nblocks, b->spill, b->wave_elems, st);
     else
       qc::launch_batch_sweep<double>(b->grp_epl[k], b->d_args, b->d_tiles + b->grp_off[k], b->grp_n[k],
-                                     b->d_counter + k, b->nblocks, st);
+                                     b->d_counter + k, b->nblocks, b->spill, b->wave_elems, st);
   }
   for (size_t gi = 0; gi < b->grains.size(); ++gi) {
     qc_grain* g = b->grains[gi];
@@ -1619,6 +1648,7 @@ void free_batch(qc_batch* b) {
   if (b->d_args) (void)hipFree(b->d_args);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->spill) (void)hipFree(b->spill);
   if (b->own) (void)hipStreamDestroy(b->own);
   delete b;
 }
@@ -1649,7 +1679,7 @@ qc_status qc_batch_create(qc_grain* const* grains, int n, qc_batch** out) {
     b->nblocks = prop.multiProcessorCount * 8;
     for (int i = 0; i < n; ++i) {
       qc_grain* g = grains[i];
-      ensure_sweep_buffers(g);
+      ensure_sweep_buffers(g, false);
       b->grains.push_back(g);
       b->steps_per_iter += g->info.steps_per_sweep;
       double* d = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));

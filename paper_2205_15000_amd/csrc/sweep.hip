@@ -203,7 +203,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
                                               const cpx<T>* __restrict__ bc_g_prev,
                                               const cpx<T>* __restrict__ bc_gt_prev,
                                               cpx<T>* __restrict__ bc_g_next, cpx<T>* __restrict__ bc_gt_next,
-                                              cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf,
+                                              cpx<T>* __restrict__ gbase, int64_t gmul, T* __restrict__ ebuf,
                                               double* __restrict__ lsum) {
   const int64_t seg = a.order ? static_cast<int64_t>(a.order[wseg]) : wseg;
   const int64_t slot0 = a.seg_slot0[seg];
@@ -271,8 +271,11 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
       for (int i = 0; i < EPL; ++i) g[i] = bulk_root(qa + ex[i], ey[i], prev.dx, prev.dy);
     }
   }
+  // gamma spill of this segment, node t at gseg[t * n_e]: the grain's array
+  // (gmul = n_e) or a wave's own scratch (gmul = 0)
+  cpx<T>* const gseg = gbase + slot0 * gmul;
   auto store_g = [&](int t) {
-    cpx<T>* dst = gbuf + (slot0 + t) * a.n_e + e0;
+    cpx<T>* dst = gseg + static_cast<int64_t>(t) * a.n_e + e0;
     for (int i = 0; i < EPL; ++i)
       if (full || e0 + i < a.n_e) dst[i] = g[i];
   };
@@ -328,8 +331,8 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // so the Eilenberger free-energy term needs no division.
   // gamma of a node for this lane's energies (padded energies read the
   // node's last pole, in range; their weight is zero)
-  auto load_g = [&](cpx<T>* gv, int64_t node) {
-    const cpx<T>* src = gbuf + node * a.n_e;
+  auto load_g = [&](cpx<T>* gv, int t) {
+    const cpx<T>* src = gseg + static_cast<int64_t>(t) * a.n_e;
     for (int i = 0; i < EPL; ++i) gv[i] = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
   };
   // Node sums through LDS (MODE 0, G >= 8).  The wave's buffer holds two
@@ -437,7 +440,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 
   // step n from R_max (boundary point = slot n-1; the whole segment if n = 0)
   cpx<T> gn[EPL];
-  if (MODE != 2) load_g(gn, slot0 + last);
+  if (MODE != 2) load_g(gn, last);
   end_step(gt, prev, prev, n > 0 ? hlast : hfirst, T(-1));
   if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev, gn, 0);
   // slot values are loaded one step ahead (gamma is not: the registers
@@ -446,7 +449,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   for (int t = n - 1; t >= 1; --t) {
     const node4<T> cur = nxt;
     nxt = nodes[slot0 + max(t - 2, 0)];
-    if (MODE != 2) load_g(gn, slot0 + t - 1);
+    if (MODE != 2) load_g(gn, t - 1);
     mid_step(gt, prev, cur, T(-1));
     prev = cur;
     if (MODE != 2) node_sums(slot0 + t - 1, cur, gn, n - t);
@@ -488,19 +491,25 @@ sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
     __shared__ double red[4 * 512];  // two nodes x four sums x 64 lanes per wave
     lsum = red + (threadIdx.x >> 6) * 512;
   }
-  sweep_segment<T, EPL, MODE>(a, wseg, lane, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, ebuf,
-                              lsum);
+  sweep_segment<T, EPL, MODE>(a, wseg, lane, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, a.n_e,
+                              ebuf, lsum);
 }
 
 // Batched grains: one persistent launch.  Every wave pulls tiles (a grain
 // and a bundle of 64/G of its segments) from a queue sorted by cost until
-// the queue is empty; every wave reaches that exit.
+// the queue is empty; every wave reaches that exit.  The gamma spill of a
+// tile lives only between its two marches, so each wave keeps it in its own
+// slice of `spill` (wave_elems records; segment k of the tile at
+// k * maxn * n_e), reused tile after tile: the spill memory is set by the
+// resident waves, not by the number or size of the grains.
 template <typename T, int EPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL>())))
 batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
                                                           const int2* __restrict__ tiles, int ntiles,
-                                                          int* __restrict__ counter) {
+                                                          int* __restrict__ counter, cpx<T>* __restrict__ spill,
+                                                          int64_t wave_elems) {
   const int l64 = threadIdx.x & 63;
+  cpx<T>* const wspill = spill + (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * wave_elems;
   __shared__ double red[4 * 512];  // node-sum exchange, two nodes x four sums x 64 lanes per wave
   while (true) {
     int t = 0;
@@ -516,7 +525,8 @@ batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
       sweep_segment<T, EPL, 0>(gd.a, wseg, l64 & (gd.a.G - 1), static_cast<const node4<T>*>(gd.b.nodes),
                                static_cast<const cpx<T>*>(gd.b.bc_g_prev), static_cast<const cpx<T>*>(gd.b.bc_gt_prev),
                                static_cast<cpx<T>*>(gd.b.bc_g_next), static_cast<cpx<T>*>(gd.b.bc_gt_next),
-                               static_cast<cpx<T>*>(gd.b.gbuf), nullptr, red + (threadIdx.x >> 6) * 512);
+                               wspill + static_cast<int64_t>(l64 >> gd.a.log2g) * gd.a.maxn * gd.a.n_e, 0, nullptr,
+                               red + (threadIdx.x >> 6) * 512);
   }
 }
 
@@ -966,18 +976,25 @@ template void launch_sweep<float>(int, int, const SweepArgs&, const SweepBufs&, 
 
 template <typename T>
 void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles, int ntiles, int* counter, int nblocks,
-                        hipStream_t st) {
+                        void* spill, int64_t wave_elems, hipStream_t st) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
+  cpx<T>* sp = static_cast<cpx<T>*>(spill);
+#define QC_BATCH(E)                                                                                                  \
+  hipLaunchKernelGGL((batch_sweep_kernel<T, E>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter, sp, \
+                     wave_elems)
   switch (epl) {
-    case 1: hipLaunchKernelGGL((batch_sweep_kernel<T, 1>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
-    case 2: hipLaunchKernelGGL((batch_sweep_kernel<T, 2>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
-    case 3: hipLaunchKernelGGL((batch_sweep_kernel<T, 3>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
-    case 4: hipLaunchKernelGGL((batch_sweep_kernel<T, 4>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
-    default: hipLaunchKernelGGL((batch_sweep_kernel<T, 8>), dim3(nblocks), dim3(256), 0, st, grains, tiles, ntiles, counter); break;
+    case 1: QC_BATCH(1); break;
+    case 2: QC_BATCH(2); break;
+    case 3: QC_BATCH(3); break;
+    case 4: QC_BATCH(4); break;
+    default: QC_BATCH(8); break;
   }
+#undef QC_BATCH
 }
-template void launch_batch_sweep<double>(int, const BatchGrainDev*, const int2*, int, int*, int, hipStream_t);
-template void launch_batch_sweep<float>(int, const BatchGrainDev*, const int2*, int, int*, int, hipStream_t);
+template void launch_batch_sweep<double>(int, const BatchGrainDev*, const int2*, int, int*, int, void*, int64_t,
+                                         hipStream_t);
+template void launch_batch_sweep<float>(int, const BatchGrainDev*, const int2*, int, int*, int, void*, int64_t,
+                                        hipStream_t);
 
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;

@@ -62,6 +62,7 @@ struct SweepArgs {
   const double* eps;      // complex energies [n_e_tot]: i eps~_p or e + i delta
   const double* rp;       // pole weights [n_e_tot]
   double* node_out;       // mode 0: [nslot][4] = S_f (re, im), S_g, S_I per node
+  int maxn;               // most nodes of any segment (batched spill layout)
 };
 
 struct SweepBufs {
@@ -70,7 +71,7 @@ struct SweepBufs {
   const void* bc_gt_prev;
   void* bc_g_next;
   void* bc_gt_next;
-  void* gbuf;
+  void* gbuf;             // gamma spill [nslot][n_e] (single-grain launches)
   void* ebuf;
 };
 
@@ -224,6 +225,7 @@ void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hip
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
 template <typename T>
 void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles, int ntiles, int* counter, int nblocks,
+                        void* spill, int64_t wave_elems,
                         hipStream_t st);
 template <typename T>
 void launch_ldos_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st);
