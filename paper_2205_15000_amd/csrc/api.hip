@@ -541,8 +541,11 @@ void ensure_sweep_buffers(qc_grain* g, bool spill = true) {
 }
 
 // steps 3-8 of one iteration; omega_total (host) optional (synchronises)
+// zero_out: clear delta_new, j (and omega) first; the rotate-back writes
+// grain cells only, so a caller that keeps the off-grain cells at zero itself
+// may skip it
 void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_new, double* j, double* omega,
-              double* omega_total, hipStream_t st) {
+              double* omega_total, hipStream_t st, bool zero_out = true) {
   ensure_sweep_buffers(g);
   do_interp(g, delta, A, st);
   qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
@@ -560,9 +563,11 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   g->bc_cur = 1 - g->bc_cur;
   g->bc_valid = 1;
 
-  qc::launch_fill(delta_new, 2 * g->ncomp * g->ncell, 0.0, st);
-  qc::launch_fill(j, 2 * g->ncell, 0.0, st);
-  if (omega) qc::launch_fill(omega, g->ncell, 0.0, st);
+  if (zero_out) {
+    qc::launch_fill(delta_new, 2 * g->ncomp * g->ncell, 0.0, st);
+    qc::launch_fill(j, 2 * g->ncell, 0.0, st);
+    if (omega) qc::launch_fill(omega, g->ncell, 0.0, st);
+  }
   qc::launch_rotate_back(back_args(g, delta, delta_new, j, omega), st);
   hcheck(hipGetLastError(), "rotate-back launch");
   // block partials of the free energy (condensation and magnetic parts)
@@ -878,8 +883,11 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
 
 // block partials of the p-norms of (new - old) and old over n elements of
 // `stride` doubles, gathered through idx when given, for nrep fields
-void enqueue_diff(qc_grain* g, const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
-                  int64_t field_stride, int stride, int p, int reg, hipStream_t st) {
+// block partials of ||xnew - xold||_p and ||xold||_p; with update, also the
+// Picard step xold += alpha (xnew - xold) in the same pass
+void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* idx, int64_t n, int nrep,
+                  int64_t field_stride, int stride, int p, int reg, hipStream_t st, bool update = false,
+                  double alpha = 1.0) {
   qc::DiffNormArgs a;
   a.xnew = xnew;
   a.xold = xold;
@@ -890,6 +898,8 @@ void enqueue_diff(qc_grain* g, const double* xnew, const double* xold, const int
   a.stride = stride;
   a.p = p;
   a.part = region(g, reg);
+  a.update = update ? xold : nullptr;
+  a.alpha = alpha;
   qc::launch_diff_norm(a, kParts, st);
 }
 
@@ -947,14 +957,19 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       qc::launch_fill(delta_io, 2 * g->ncomp * g->ncell, 0.0, st);
       qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, st);
     }
+    // the sweeps write grain cells only: off-grain j stays zero in both
+    // current buffers, and off-grain Delta_new is never read here
+    ensure_sweep_buffers(g);
+    qc::launch_fill(g->jcur, 2 * g->ncell, 0.0, st);
+    qc::launch_fill(g->jold, 2 * g->ncell, 0.0, st);
     double om_old = 0.0;
     bool have_old = false;
     int it = 0;
     bool conv = false;
     for (; it < max_iter; ++it) {
-      do_sweep(g, delta_io, A_io, g->dnew, g->jcur, nullptr, nullptr, st);
+      do_sweep(g, delta_io, A_io, g->dnew, g->jcur, nullptr, nullptr, st, false);
       if (it < burnin) {
-        hcheck(hipMemcpyAsync(g->jold, g->jcur, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+        std::swap(g->jold, g->jcur);
         fetch_parts(g, st);
         const double om = omega_from_parts(g);
         const double res[5] = {0.0, 0.0, 0.0, 0.0, om};
@@ -964,12 +979,12 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
         continue;
       }
       do_solve_A(g, g->jcur, g->anew, nullptr, st);
-      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st);
+      // residuals of Delta and A with their Picard steps fused in
+      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st, true,
+                   alpha);
       if (have_old) enqueue_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ, st);
-      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st);
-      qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, alpha, st);
-      qc::launch_picard(A_io, g->anew, nullptr, 2 * g->ncell, 1, 0, 1, alpha, st);
-      hcheck(hipMemcpyAsync(g->jold, g->jcur, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, true, alpha);
+      std::swap(g->jold, g->jcur);
       fetch_parts(g, st);
       const double om = omega_from_parts(g);
       double res[5];

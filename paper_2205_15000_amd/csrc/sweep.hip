@@ -765,6 +765,7 @@ __global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
       const double vn = a.xnew[e * a.stride + c], vo = a.xold[e * a.stride + c];
       dn += (vn - vo) * (vn - vo);
       dd += vo * vo;
+      if (a.update) a.update[e * a.stride + c] = vo + a.alpha * (vn - vo);  // the Picard step
     }
     if (a.p == 2) {
       acc0 += dn;

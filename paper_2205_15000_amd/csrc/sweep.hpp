@@ -127,6 +127,8 @@ struct DiffNormArgs {
   int stride;
   int p;
   double* part;
+  double* update;  // nullptr, or xold itself: then xold += alpha (xnew - xold) in the same pass
+  double alpha;
 };
 
 // ---- reverse mode (adjoint.hip)
