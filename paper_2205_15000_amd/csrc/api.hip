@@ -374,17 +374,20 @@ double region_sum(const qc_grain* g, int r) {
   return s;
 }
 
-void fft_forward_2d(qc_grain* g, hipStream_t st, int sign) {
-  // rows along x, transpose, rows along y (result in fw2, [px][py] layout)
-  qc::launch_fft_rows(g->fw, g->py, g->lpx, g->twx, sign, st);
+// rows along x, transpose, rows along y (result in fw2, [px][py] layout);
+// rows y >= nz_rows of fw are zero and keep a zero transform
+void fft_forward_2d(qc_grain* g, hipStream_t st, int sign, int nz_rows) {
+  qc::launch_fft_rows(g->fw, nz_rows, g->lpx, g->twx, sign, nullptr, st);
   qc::launch_transpose(g->fw, g->fw2, g->py, g->px, st);
-  qc::launch_fft_rows(g->fw2, g->px, g->lpy, g->twy, sign, st);
+  qc::launch_fft_rows(g->fw2, g->px, g->lpy, g->twy, sign, nullptr, st);
 }
 
-void fft_inverse_2d(qc_grain* g, hipStream_t st) {
-  qc::launch_fft_rows(g->fw2, g->px, g->lpy, g->twy, +1, st);
+// inverse of fw2 times pre (elementwise, [px][py]) into fw; only rows
+// y < out_rows of fw are transformed along x
+void fft_inverse_2d(qc_grain* g, hipStream_t st, const double2* pre, int out_rows) {
+  qc::launch_fft_rows(g->fw2, g->px, g->lpy, g->twy, +1, pre, st);
   qc::launch_transpose(g->fw2, g->fw, g->px, g->py, st);
-  qc::launch_fft_rows(g->fw, g->py, g->lpx, g->twx, +1, st);
+  qc::launch_fft_rows(g->fw, out_rows, g->lpx, g->twx, +1, nullptr, st);
 }
 
 std::vector<double2> twiddles(int n) {
@@ -812,7 +815,7 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
       g->fw = static_cast<double2*>(upload(gp));
       g->fw2 = static_cast<double2*>(dalloc(sizeof(double2) * np));
       g->ghat = static_cast<double2*>(dalloc(sizeof(double2) * np));
-      fft_forward_2d(g, nullptr, -1);
+      fft_forward_2d(g, nullptr, -1, g->py);
       hcheck(hipMemcpy(g->ghat, g->fw2, sizeof(double2) * np, hipMemcpyDeviceToDevice), "copy");
     }
     hcheck(hipDeviceSynchronize(), "grain setup");
@@ -872,9 +875,11 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
   qc::launch_block_sum(j + g->ncell, g->grain_cells, g->ncg, 0, region(g, kRJy), kParts, st);
   qc::launch_means(region(g, kRJx), kParts, 1.0 / static_cast<double>(g->ncg), g->dmean, st);
   qc::launch_pad_current(j, g->mask, g->nx, g->ny, g->px, g->py, g->dmean, g->fw, st);
-  fft_forward_2d(g, st, -1);
-  qc::launch_cmul(g->fw2, g->ghat, static_cast<int64_t>(g->px) * g->py, st);
-  fft_inverse_2d(g, st);
+  // the padded current is zero beyond row ny, and only rows < ny of the
+  // correlation are kept; the product with the kernel's transform is taken
+  // as the inverse pass loads its rows
+  fft_forward_2d(g, st, -1, g->ny);
+  fft_inverse_2d(g, st, g->ghat, g->ny);
   const double scale = -1.0 / (g->kappa * g->kappa * static_cast<double>(g->px) * g->py);
   qc::launch_unpad_A(g->fw, g->nx, g->ny, g->px, scale, A_out, st);
   if (B_out) qc::launch_curl(A_out, B_out, g->nx, g->ny, g->h, st);

@@ -859,14 +859,21 @@ __global__ void __launch_bounds__(256) pad_current_kernel(const double* __restri
 
 // In-place radix-2 FFT of every row (length n = 2^logn) of a [rows][n]
 // complex array, one workgroup per row, staged in LDS.  sign = -1 forward.
+// pre (optional, same layout): the input is multiplied by it on the way in.
 __global__ void __launch_bounds__(256) fft_rows_kernel(double2* __restrict__ w, int logn,
-                                                       const double2* __restrict__ tw, int sign) {
+                                                       const double2* __restrict__ tw, int sign,
+                                                       const double2* __restrict__ pre) {
   extern __shared__ double2 buf[];
   const int n = 1 << logn;
   double2* row = w + static_cast<int64_t>(blockIdx.x) * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int r = static_cast<int>(__builtin_bitreverse32(static_cast<unsigned>(i)) >> (32 - logn));
-    buf[r] = row[i];
+    double2 v = row[i];
+    if (pre) {
+      const double2 b = pre[static_cast<int64_t>(blockIdx.x) * n + i];
+      v = make_double2(v.x * b.x - v.y * b.y, v.x * b.y + v.y * b.x);
+    }
+    buf[r] = v;
   }
   __syncthreads();
   for (int s = 1; s <= logn; ++s) {
@@ -900,13 +907,6 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double2* __restric
     const int x = bx + r, y = by + threadIdx.x;
     if (x < cols && y < rows) out[static_cast<int64_t>(x) * rows + y] = tile[threadIdx.x][r];
   }
-}
-
-__global__ void cmul_kernel(double2* __restrict__ w, const double2* __restrict__ g, int64_t n) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double2 a = w[i], b = g[i];
-  w[i] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 __global__ void __launch_bounds__(256) unpad_A_kernel(const double2* __restrict__ w, int nx, int ny, int px,
@@ -1045,15 +1045,12 @@ void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, in
   hipLaunchKernelGGL(pad_current_kernel, dim3(nblk(static_cast<int64_t>(px) * py)), dim3(256), 0, st, j, mask, nx,
                      ny, px, py, mean, w);
 }
-void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, hipStream_t st) {
-  hipLaunchKernelGGL(fft_rows_kernel, dim3(rows), dim3(256), sizeof(double2) << logn, st, w, logn, tw, sign);
+void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, const double2* pre, hipStream_t st) {
+  hipLaunchKernelGGL(fft_rows_kernel, dim3(rows), dim3(256), sizeof(double2) << logn, st, w, logn, tw, sign, pre);
 }
 void launch_transpose(const double2* in, double2* out, int rows, int cols, hipStream_t st) {
   hipLaunchKernelGGL(transpose_kernel, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(32, 8), 0, st, in, out, rows,
                      cols);
-}
-void launch_cmul(double2* w, const double2* g, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(cmul_kernel, dim3(nblk(n)), dim3(256), 0, st, w, g, n);
 }
 void launch_unpad_A(const double2* w, int nx, int ny, int px, double scale, double* A, hipStream_t st) {
   hipLaunchKernelGGL(unpad_A_kernel, dim3(nblk(static_cast<int64_t>(nx) * ny)), dim3(256), 0, st, w, nx, ny, px,

@@ -244,9 +244,8 @@ void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, i
 void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st);
 void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, const double* mean,
                         double2* w, hipStream_t st);
-void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, hipStream_t st);
+void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, const double2* pre, hipStream_t st);
 void launch_transpose(const double2* in, double2* out, int rows, int cols, hipStream_t st);
-void launch_cmul(double2* w, const double2* g, int64_t n, hipStream_t st);
 void launch_unpad_A(const double2* w, int nx, int ny, int px, double scale, double* A, hipStream_t st);
 
 }  // namespace qc
