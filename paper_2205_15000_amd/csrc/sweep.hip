@@ -466,16 +466,16 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 }
 
 // Occupancy floors (waves per SIMD) for the FP32 variants: 7 (<= 72 VGPRs)
-// with two energies per lane (a few spills outside the loops), 4 (<= 128,
-// no spills; 5 spilled in the loops) with four; the rest keep the
-// compiler's default.
-template <typename T, int EPL>
+// with two energies per lane (a few spills outside the loops); with four,
+// 4 (<= 128) for the pole-sum sweep, which spills in its loops at 5, and 5
+// for the other modes; the rest keep the compiler's default.
+template <typename T, int EPL, int MODE>
 constexpr int sweep_min_waves() {
-  return (sizeof(T) == 4 && EPL == 4) ? 4 : (sizeof(T) == 4 && EPL == 2) ? 7 : 1;
+  return (sizeof(T) == 4 && EPL == 4) ? (MODE == 0 ? 4 : 5) : (sizeof(T) == 4 && EPL == 2) ? 7 : 1;
 }
 
 template <typename T, int EPL, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL, MODE>())))
 sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
                                                     const cpx<T>* __restrict__ bc_g_prev,
                                                     const cpx<T>* __restrict__ bc_gt_prev,
@@ -503,7 +503,7 @@ sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
 // k * maxn * n_e), reused tile after tile: the spill memory is set by the
 // resident waves, not by the number or size of the grains.
 template <typename T, int EPL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<T, EPL, 0>())))
 batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
                                                           const int2* __restrict__ tiles, int ntiles,
                                                           int* __restrict__ counter, cpx<T>* __restrict__ spill,
