@@ -244,7 +244,6 @@ struct qc_grain {
   double* slot_px = nullptr;
   double* slot_py = nullptr;
   int32_t* slot_fb = nullptr;
-  int2* slot_sf = nullptr;           // per slot: segment, fallback cell
   qc::SegGeo* seg_geo = nullptr;
   double cx = 0, cy = 0, half = 0, flux = 0, bfield = 0;
   int gauge = 0;
@@ -338,7 +337,7 @@ enum { kROmega = 0, kRB2 = 1, kRJx = 2, kRJy = 3, kRDiffD = 4, kRDiffJ = 6, kRDi
 namespace {
 
 void free_grain(qc_grain* g) {
-  void* ptrs[] = {g->slot_angle, g->slot_px, g->slot_py, g->slot_fb, g->slot_sf, g->seg_geo, g->aext, g->eta, g->cosk,
+  void* ptrs[] = {g->slot_angle, g->slot_px, g->slot_py, g->slot_fb, g->seg_geo, g->aext, g->eta, g->cosk,
                   g->sink, g->wk, g->seg_slot0, g->seg_n, g->seg_hfirst, g->seg_hlast, g->tap_s_seg,
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->rb4, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->cells, g->order, g->gbuf, g->node_out, g->bc[0][0],
@@ -443,6 +442,7 @@ qc::BackArgs back_args(qc_grain* g, const double* delta, double* dnew, double* j
 void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st) {
   qc::InterpArgs a;
   a.nslot = g->nslot;
+  a.nseg = g->nseg;
   a.ncell = g->ncell;
   a.ncomp = g->ncomp;
   a.n_theta = g->n_theta;
@@ -457,7 +457,6 @@ void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st
   a.sink = g->sink;
   a.delta = delta;
   a.A = A;
-  a.slot_sf = g->slot_sf;
   a.seg_geo = g->seg_geo;
   a.cx = g->cx;
   a.cy = g->cy;
@@ -731,8 +730,6 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
     g->slot_py = static_cast<double*>(upload(p.slot_py));
     g->slot_fb = static_cast<int32_t*>(upload(p.slot_fb));
     {
-      std::vector<int2> sf(p.slot_seg.size());
-      for (size_t i = 0; i < sf.size(); ++i) sf[i] = make_int2(p.slot_seg[i], p.slot_fb[i]);
       std::vector<qc::SegGeo> sg(static_cast<size_t>(p.nseg));
       for (int64_t i = 0; i < p.nseg; ++i) {
         sg[i].slot0 = p.seg_slot0[i];
@@ -743,7 +740,6 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
         sg[i].k = p.seg_angle[i];
         sg[i].pad = 0;
       }
-      g->slot_sf = static_cast<int2*>(upload(sf));
       g->seg_geo = static_cast<qc::SegGeo*>(upload(sg));
       g->cx = p.cx;
       g->cy = p.cy;

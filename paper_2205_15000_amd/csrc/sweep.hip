@@ -84,102 +84,106 @@ __global__ void __launch_bounds__(256) pack_cells_kernel(const double* __restric
 template <typename T>
 __global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<T>* __restrict__ cells,
                                                       node4<T>* __restrict__ nodes) {
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= a.nslot) return;
+  // one wave per segment: its record is read once (scalar loads), and each
+  // lane takes every 64th slot of the segment
+  const int64_t seg = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6));
+  if (seg >= a.nseg) return;
+  const SegGeo sgeo = a.seg_geo[seg];
+  const int nsl = sgeo.n > 0 ? sgeo.n : 1;
   const GridGeom& gg = a.geom;
-  const int2 sf = a.slot_sf[s];
-  const SegGeo sgeo = a.seg_geo[sf.x];
   const int k = sgeo.k;
-  const int fb = sf.y;
-  // the slot position as the plan forms it, so the corner choice below is
-  // the one the nearest-cell fallback was decided on
   const double epx = a.cosk[k], epy = a.sink[k];
-  const double sp = sgeo.n > 0 ? rn_node_s(static_cast<double>(sgeo.jf + static_cast<int>(s - sgeo.slot0)), a.half, gg.h)
-                               : sgeo.smid;
-  const double px = rn_point(a.cx, sgeo.u, epy, sp, epx);
-  const double py = rn_point(a.cy, sgeo.u, -epx, sp, epy);
-  const double fx = (px - gg.x0) / gg.h - 0.5, fy = (py - gg.y0) / gg.h - 0.5;
-  const int i0 = static_cast<int>(__builtin_floor(fx)), j0 = static_cast<int>(__builtin_floor(fy));
-  const double wx = fx - i0, wy = fy - j0;
-  double w[4];
-  w[0] = (1 - wx) * (1 - wy);
-  w[1] = wx * (1 - wy);
-  w[2] = (1 - wx) * wy;
-  w[3] = wx * wy;
-  cell4<T> v[4];
-  double tot = 0.0;
-  for (int c = 0; c < 4; ++c) {
-    const int ci = i0 + (c & 1), cj = j0 + (c >> 1);
-    const bool in = ci >= 0 && ci < gg.nx && cj >= 0 && cj < gg.ny;
-    const int lc = min(max(ci, 0), gg.nx - 1), lj = min(max(cj, 0), gg.ny - 1);
-    v[c] = cells[static_cast<int64_t>(lj) * gg.nx + lc];
-    const bool ok = in && v[c].dx == v[c].dx;  // NaN marks cells outside the grain
-    if (!ok) w[c] = 0.0;
-    tot += w[c];
-  }
-  const double ex = a.eta[2 * k], ey = a.eta[2 * k + 1];
-  double dx = 0.0, dy = 0.0;
-  if (fb >= 0) {
-    const cell4<T> f = cells[fb];
-    const double fx0 = static_cast<double>(f.dx), fy0 = static_cast<double>(f.dy);
-    dx = ex * fx0 - ey * fy0;
-    dy = ex * fy0 + ey * fx0;
-  } else {
-    if (tot > 0.0)
-      for (int c = 0; c < 4; ++c) w[c] /= tot;
+  for (int t = static_cast<int>(threadIdx.x & 63); t < nsl; t += 64) {
+    const int64_t s = sgeo.slot0 + t;
+    const int fb = a.fb[s];
+    // the slot position as the plan forms it, so the corner choice below is
+    // the one the nearest-cell fallback was decided on
+    const double sp = sgeo.n > 0 ? rn_node_s(static_cast<double>(sgeo.jf + t), a.half, gg.h) : sgeo.smid;
+    const double px = rn_point(a.cx, sgeo.u, epy, sp, epx);
+    const double py = rn_point(a.cy, sgeo.u, -epx, sp, epy);
+    const double fx = (px - gg.x0) / gg.h - 0.5, fy = (py - gg.y0) / gg.h - 0.5;
+    const int i0 = static_cast<int>(__builtin_floor(fx)), j0 = static_cast<int>(__builtin_floor(fy));
+    const double wx = fx - i0, wy = fy - j0;
+    double w[4];
+    w[0] = (1 - wx) * (1 - wy);
+    w[1] = wx * (1 - wy);
+    w[2] = (1 - wx) * wy;
+    w[3] = wx * wy;
+    cell4<T> v[4];
+    double tot = 0.0;
     for (int c = 0; c < 4; ++c) {
-      if (w[c] == 0.0) continue;  // a dropped corner may hold the NaN marker
-      const double cx = static_cast<double>(v[c].dx), cy = static_cast<double>(v[c].dy);
-      dx += (ex * cx - ey * cy) * w[c];
-      dy += (ex * cy + ey * cx) * w[c];
+      const int ci = i0 + (c & 1), cj = j0 + (c >> 1);
+      const bool in = ci >= 0 && ci < gg.nx && cj >= 0 && cj < gg.ny;
+      const int lc = min(max(ci, 0), gg.nx - 1), lj = min(max(cj, 0), gg.ny - 1);
+      v[c] = cells[static_cast<int64_t>(lj) * gg.nx + lc];
+      const bool ok = in && v[c].dx == v[c].dx;  // NaN marks cells outside the grain
+      if (!ok) w[c] = 0.0;
+      tot += w[c];
     }
+    const double ex = a.eta[2 * k], ey = a.eta[2 * k + 1];
+    double dx = 0.0, dy = 0.0;
+    if (fb >= 0) {
+      const cell4<T> f = cells[fb];
+      const double fx0 = static_cast<double>(f.dx), fy0 = static_cast<double>(f.dy);
+      dx = ex * fx0 - ey * fy0;
+      dy = ex * fy0 + ey * fx0;
+    } else {
+      if (tot > 0.0)
+        for (int c = 0; c < 4; ++c) w[c] /= tot;
+      for (int c = 0; c < 4; ++c) {
+        if (w[c] == 0.0) continue;  // a dropped corner may hold the NaN marker
+        const double cx = static_cast<double>(v[c].dx), cy = static_cast<double>(v[c].dy);
+        dx += (ex * cx - ey * cy) * w[c];
+        dy += (ex * cy + ey * cx) * w[c];
+      }
+    }
+    // A_ind: clamped bilinear
+    const double fxa = __builtin_fmin(__builtin_fmax(fx, 0.0), gg.nx - 1.0);
+    const double fya = __builtin_fmin(__builtin_fmax(fy, 0.0), gg.ny - 1.0);
+    const int i0a = min(static_cast<int>(__builtin_floor(fxa)), gg.nx - 2);
+    const int j0a = min(static_cast<int>(__builtin_floor(fya)), gg.ny - 2);
+    const double wxa = fxa - i0a, wya = fya - j0a;
+    double aw[4];
+    aw[0] = (1 - wxa) * (1 - wya);
+    aw[1] = wxa * (1 - wya);
+    aw[2] = (1 - wxa) * wya;
+    aw[3] = wxa * wya;
+    double ax = 0.0, ay = 0.0;
+    if (i0a == i0 && j0a == j0) {
+      for (int c = 0; c < 4; ++c) {
+        ax += static_cast<double>(v[c].ax) * aw[c];
+        ay += static_cast<double>(v[c].ay) * aw[c];
+      }
+    } else {
+      const int64_t b0 = static_cast<int64_t>(j0a) * gg.nx + i0a;
+      for (int c = 0; c < 4; ++c) {
+        const cell4<T> u = cells[b0 + (c & 1) + (c >> 1) * gg.nx];
+        ax += static_cast<double>(u.ax) * aw[c];
+        ay += static_cast<double>(u.ay) * aw[c];
+      }
+    }
+    node4<T> o;
+    o.dx = static_cast<T>(dx);
+    o.dy = static_cast<T>(dy);
+    // external field (analytic, Sec. III.C gauges)
+    double ex_x = 0.0, ex_y = 0.0;
+    const double rx = px - a.cx, ry = py - a.cy;
+    if (a.gauge == 0) {
+      ex_x = -0.5 * a.bfield * ry;
+      ex_y = 0.5 * a.bfield * rx;
+    } else if (a.gauge == 1) {
+      ex_x = -a.bfield * ry;
+    } else {
+      const double r2 = rx * rx + ry * ry;
+      if (r2 > 0.0) {
+        ex_x = -0.5 * a.flux * ry / r2;
+        ex_y = 0.5 * a.flux * rx / r2;
+      }
+    }
+    o.a = static_cast<T>(epx * (ax + ex_x) + epy * (ay + ex_y));
+    o.pad = T(0);
+    nodes[s] = o;
   }
-  // A_ind: clamped bilinear
-  const double fxa = __builtin_fmin(__builtin_fmax(fx, 0.0), gg.nx - 1.0);
-  const double fya = __builtin_fmin(__builtin_fmax(fy, 0.0), gg.ny - 1.0);
-  const int i0a = min(static_cast<int>(__builtin_floor(fxa)), gg.nx - 2);
-  const int j0a = min(static_cast<int>(__builtin_floor(fya)), gg.ny - 2);
-  const double wxa = fxa - i0a, wya = fya - j0a;
-  double aw[4];
-  aw[0] = (1 - wxa) * (1 - wya);
-  aw[1] = wxa * (1 - wya);
-  aw[2] = (1 - wxa) * wya;
-  aw[3] = wxa * wya;
-  double ax = 0.0, ay = 0.0;
-  if (i0a == i0 && j0a == j0) {
-    for (int c = 0; c < 4; ++c) {
-      ax += static_cast<double>(v[c].ax) * aw[c];
-      ay += static_cast<double>(v[c].ay) * aw[c];
-    }
-  } else {
-    const int64_t b0 = static_cast<int64_t>(j0a) * gg.nx + i0a;
-    for (int c = 0; c < 4; ++c) {
-      const cell4<T> u = cells[b0 + (c & 1) + (c >> 1) * gg.nx];
-      ax += static_cast<double>(u.ax) * aw[c];
-      ay += static_cast<double>(u.ay) * aw[c];
-    }
-  }
-  node4<T> o;
-  o.dx = static_cast<T>(dx);
-  o.dy = static_cast<T>(dy);
-  // external field (analytic, Sec. III.C gauges)
-  double ex_x = 0.0, ex_y = 0.0;
-  const double rx = px - a.cx, ry = py - a.cy;
-  if (a.gauge == 0) {
-    ex_x = -0.5 * a.bfield * ry;
-    ex_y = 0.5 * a.bfield * rx;
-  } else if (a.gauge == 1) {
-    ex_x = -a.bfield * ry;
-  } else {
-    const double r2 = rx * rx + ry * ry;
-    if (r2 > 0.0) {
-      ex_x = -0.5 * a.flux * ry / r2;
-      ex_y = 0.5 * a.flux * rx / r2;
-    }
-  }
-  o.a = static_cast<T>(epx * (ax + ex_x) + epy * (ay + ex_y));
-  o.pad = T(0);
-  nodes[s] = o;
 }
 
 // --------------------------------------------------------------------------
@@ -930,7 +934,7 @@ void launch_interp(const InterpArgs& a, void* cells, void* nodes, hipStream_t st
   if (cells && a.ncomp == 1) {
     hipLaunchKernelGGL(pack_cells_kernel<T>, dim3(nblk(a.ncell)), dim3(256), 0, st, a.delta, a.A, a.geom.mask,
                        a.ncell, static_cast<cell4<T>*>(cells));
-    hipLaunchKernelGGL(interp1_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a,
+    hipLaunchKernelGGL(interp1_kernel<T>, dim3(static_cast<unsigned>((a.nseg + 3) / 4)), dim3(256), 0, st, a,
                        static_cast<const cell4<T>*>(cells), static_cast<node4<T>*>(nodes));
   } else {
     hipLaunchKernelGGL(interp_kernel<T>, dim3(nblk(a.nslot)), dim3(256), 0, st, a, static_cast<node4<T>*>(nodes));

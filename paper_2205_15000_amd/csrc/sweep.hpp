@@ -21,6 +21,7 @@ struct SegGeo {
 
 struct InterpArgs {
   int64_t nslot;
+  int64_t nseg;
   int64_t ncell;  // nx * ny
   int ncomp, n_theta;
   GridGeom geom;
@@ -35,7 +36,6 @@ struct InterpArgs {
   const double* delta;  // complex [ncomp][ny][nx]
   const double* A;      // [2][ny][nx]
   // single-component path: slot positions and A_ext formed on the fly
-  const int2* slot_sf;     // per slot: segment, nearest-cell fallback (-1: none)
   const SegGeo* seg_geo;
   double cx, cy, half;     // grid centre and (M - 1) / 2
   int gauge;               // 0 symmetric, 1 Landau, 2 solenoid
