@@ -661,12 +661,17 @@ __global__ void __launch_bounds__(256) back_adjoint_kernel(BackAdjArgs a) {
 
 // Gradients on the reference grid from the slot gradients: the transpose of
 // the interpolation pre-pass, as a gather per cell over the slots whose
-// stencils use it (each cell written once, zero where none does).
+// stencils use it (each cell written once, zero where none does).  Sixteen
+// lanes share a cell, lane q taking every 16th entry of its lists; their
+// partial sums are combined with DPP moves.
+constexpr int kItLanes = 16;
 __global__ void __launch_bounds__(256) interp_adjoint_kernel(InterpAdjArgs a) {
-  const int64_t cell = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (cell >= a.ncell) return;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t cell = t / kItLanes;
+  const int q = static_cast<int>(t & (kItLanes - 1));
+  if (cell >= a.ncell) return;  // whole groups of sixteen leave together
   double dx[4] = {0.0, 0.0, 0.0, 0.0}, dy[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t e = a.it_dptr[cell]; e < a.it_dptr[cell + 1]; ++e) {
+  for (int64_t e = a.it_dptr[cell] + q; e < a.it_dptr[cell + 1]; e += kItLanes) {
     const int64_t s = a.it_ds[e];
     const double w = a.it_dw[e];
     const int k = a.slot_angle[s];
@@ -678,17 +683,24 @@ __global__ void __launch_bounds__(256) interp_adjoint_kernel(InterpAdjArgs a) {
       dy[g] += w * (ex * gy - ey * gx);
     }
   }
-  for (int g = 0; g < a.ncomp; ++g) {
-    a.gdelta[2 * (g * a.ncell + cell)] = dx[g];
-    a.gdelta[2 * (g * a.ncell + cell) + 1] = dy[g];
-  }
   double ax = 0.0, ay = 0.0;
-  for (int64_t e = a.it_aptr[cell]; e < a.it_aptr[cell + 1]; ++e) {
+  for (int64_t e = a.it_aptr[cell] + q; e < a.it_aptr[cell + 1]; e += kItLanes) {
     const int64_t s = a.it_as[e];
     const double wg = a.it_aw[e] * a.gV[s * 3 + 2];
     const int k = a.slot_angle[s];
     ax += wg * a.cosk[k];
     ay += wg * a.sink[k];
+  }
+  for (int g = 0; g < a.ncomp; ++g) {
+    dx[g] = group_sum(dx[g], kItLanes);
+    dy[g] = group_sum(dy[g], kItLanes);
+  }
+  ax = group_sum(ax, kItLanes);
+  ay = group_sum(ay, kItLanes);
+  if (q != 0) return;
+  for (int g = 0; g < a.ncomp; ++g) {
+    a.gdelta[2 * (g * a.ncell + cell)] = dx[g];
+    a.gdelta[2 * (g * a.ncell + cell) + 1] = dy[g];
   }
   a.gA[cell] = ax;
   a.gA[a.ncell + cell] = ay;
@@ -811,7 +823,7 @@ void launch_back_adjoint(const BackAdjArgs& a, hipStream_t st) {
   if (a.nslot > 0) hipLaunchKernelGGL(back_adjoint_kernel, dim3(nb(a.nslot)), dim3(256), 0, st, a);
 }
 void launch_interp_adjoint(const InterpAdjArgs& a, hipStream_t st) {
-  if (a.ncell > 0) hipLaunchKernelGGL(interp_adjoint_kernel, dim3(nb(a.ncell)), dim3(256), 0, st, a);
+  if (a.ncell > 0) hipLaunchKernelGGL(interp_adjoint_kernel, dim3(nb(a.ncell * kItLanes)), dim3(256), 0, st, a);
 }
 void launch_omega_delta_adjoint(const OmegaAdjArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(omega_delta_adjoint_kernel, dim3(nb(a.ncg)), dim3(256), 0, st, a);
