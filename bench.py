@@ -26,6 +26,8 @@ headline):
     --mode lanes [--workload NAME]
                                   sweep time at every energies-per-lane setting,
                                   both precisions (default: the 48-pole disc)
+    --mode valu                   sustained FP32 fma / rsq / sqrt / rcp rates of
+                                  the device (the issue ceiling of the sweep)
 """
 import argparse
 import json
@@ -62,7 +64,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch", "adjoint", "lanes"],
+    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch", "adjoint", "lanes", "valu"],
                     default="iteration")
     ap.add_argument("--workload", default="d_disc_200")
     ap.add_argument("--iters", type=int, default=None)
@@ -287,6 +289,18 @@ def mode_lanes(qs, torch, wl, name, iters):
     return {"metric": "sweep time per lane shape", "workload": name, "n_poles": sp["n_poles"], "rows": rows}
 
 
+def mode_valu(qs):
+    """Sustained rate of single FP32 VALU operations with every CU busy:
+    the issue ceiling the sweep kernels run against (a wave64 instruction
+    issues 16 lanes per cycle per SIMD, 1024 SIMDs)."""
+    r = {op: qs.valu_rate(op) for op in ("fma", "rsq", "sqrt", "rcp")}
+    return {"metric": "sustained FP32 VALU rate", "unit": "lane ops/s",
+            "fma": r["fma"], "rsq": r["rsq"], "sqrt": r["sqrt"], "rcp": r["rcp"],
+            "fma_tflops": 2 * r["fma"] / 1e12, "fma_over_published_78_6": 2 * r["fma"] / 1e12 / PEAK_VALU_TFLOPS,
+            "implied_clock_ghz": r["fma"] / (1024 * 16) / 1e9,
+            "transcendental_over_fma": {op: r[op] / r["fma"] for op in ("rsq", "sqrt", "rcp")}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -306,6 +320,8 @@ def main():
             res = mode_adjoint(qs, torch, wl, args.iters or 5)
         elif args.mode == "lanes":
             res = mode_lanes(qs, torch, wl, args.workload, args.iters or 8)
+        elif args.mode == "valu":
+            res = mode_valu(qs)
         else:
             res = mode_batch(qs, torch, wl, args.grains, args.iters or 6)
         print(json.dumps(res), flush=True)
@@ -349,6 +365,11 @@ def main():
                      "peak_fp32_packed_published": PEAK_FP32_PACKED_TFLOPS},
         "sweep_only_steps_per_s": steps_iter / (avg_ms * 1e-3),
     }
+    # the ceiling the device sustains under a full VALU load (same run, same
+    # device): FP32 fma rate with every CU busy
+    fma = qs.valu_rate("fma")
+    out["roofline"]["sustained_fma_tflops"] = 2 * fma / 1e12
+    out["roofline"]["frac_of_sustained"] = achieved / (2 * fma / 1e12)
     if not args.skip_fp64:
         print("bench: %s fp64" % WORKLOAD, file=sys.stderr, flush=True)
         dt64, it64, sms64, l64, _, _ = timed_scf(qs, torch, sp, "fp64", d0, a0, args.steps, args.warmup)

@@ -347,6 +347,14 @@ qc_status qc_grain_get_lanes(const qc_grain* grain, int* energies_per_lane, int*
 qc_status qc_profile_enable(qc_grain* grain, int enable);
 qc_status qc_profile_read(qc_grain* grain, double* sweep_ms, int64_t* sweep_launches);
 
+/* Measurement aid for the roofline of the sweep kernels (not an operation
+ * of the method): the sustained rate, in lane operations per second, of one
+ * FP32 VALU operation on `device` with every CU busy (8 independent chains
+ * per lane, 8 blocks of 256 lanes per CU, timed with HIP events after one
+ * warm-up launch).  op: 0 fma, 1 rsq, 2 sqrt, 3 rcp.  Allocates and frees
+ * its own small buffer; QC_ERR_NO_DEVICE without the device. */
+qc_status qc_valu_rate(int device, int op, double* lane_ops_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,7 @@ def _sig(name, res, args):
 _sig("qc_last_error", ctypes.c_char_p, [])
 _sig("qc_version", ctypes.c_int, [])
 _sig("qc_device_count", ctypes.c_int, [ctypes.POINTER(ctypes.c_int)])
+_sig("qc_valu_rate", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)])
 _sig("qc_plan_create", ctypes.c_int, [ctypes.POINTER(_Desc), ctypes.POINTER(_P)])
 _sig("qc_plan_destroy", None, [_P])
 _sig("qc_plan_get_info", ctypes.c_int, [_P, ctypes.POINTER(_Info)])
@@ -123,6 +124,14 @@ def device_count():
     n = ctypes.c_int(0)
     _check(lib.qc_device_count(ctypes.byref(n)))
     return n.value
+
+
+def valu_rate(op, device=0):
+    """Sustained lane operations per second of one FP32 VALU operation
+    (op: "fma", "rsq", "sqrt" or "rcp") with every CU busy."""
+    v = ctypes.c_double()
+    _check(lib.qc_valu_rate(int(device), ["fma", "rsq", "sqrt", "rcp"].index(op), ctypes.byref(v)))
+    return v.value
 
 
 def basis_table(components, n_theta, crystal_rotation=0.0):

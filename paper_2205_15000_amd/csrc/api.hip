@@ -595,6 +595,41 @@ const char* qc_last_error(void) { return g_err.c_str(); }
 
 int qc_version(void) { return 1; }
 
+qc_status qc_valu_rate(int device, int op, double* lane_ops_per_s) {
+  if (!lane_ops_per_s) return fail(QC_ERR_INVALID, "lane_ops_per_s is NULL");
+  if (op < 0 || op > 3) return fail(QC_ERR_INVALID, "op must be 0 (fma), 1 (rsq), 2 (sqrt) or 3 (rcp)");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(QC_ERR_NO_DEVICE, "no such HIP device");
+  float* out = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const qc_status rs = guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    hcheck(hipGetDeviceProperties(&prop, device), "properties");
+    const int nblocks = prop.multiProcessorCount * 8, iters = 4096;
+    out = static_cast<float*>(dalloc(sizeof(float) * 256 * static_cast<size_t>(nblocks)));
+    hcheck(hipStreamCreate(&st), "stream");
+    hcheck(hipEventCreate(&e0), "event");
+    hcheck(hipEventCreate(&e1), "event");
+    qc::launch_valu_rate(op, out, nblocks, iters, st);  // warm-up
+    hcheck(hipEventRecord(e0, st), "event");
+    qc::launch_valu_rate(op, out, nblocks, iters, st);
+    hcheck(hipEventRecord(e1, st), "event");
+    hcheck(hipEventSynchronize(e1), "event");
+    float ms = 0.f;
+    hcheck(hipEventElapsedTime(&ms, e0, e1), "event");
+    *lane_ops_per_s = 256.0 * nblocks * iters * 8.0 / (1e-3 * ms);
+    return QC_OK;
+  });
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  if (out) (void)hipFree(out);
+  return rs;
+}
+
 qc_status qc_device_count(int* n_out) {
   if (!n_out) return fail(QC_ERR_INVALID, "n_out is NULL");
   int n = 0;

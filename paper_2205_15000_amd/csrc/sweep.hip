@@ -924,6 +924,28 @@ __global__ void __launch_bounds__(256) unpad_A_kernel(const double2* __restrict_
 }
 
 // --------------------------------------------------------------------------
+// issue-rate probe: eight independent chains of one FP32 operation per lane
+// (op 0 fma, 1 rsq, 2 sqrt, 3 rcp), for the roofline of the sweep kernels
+// --------------------------------------------------------------------------
+template <int OP>
+__device__ __forceinline__ float rate_op(float a, float s) {
+  if (OP == 0) return __builtin_fmaf(a, s, 0.5f);
+  if (OP == 1) return __builtin_amdgcn_rsqf(a);
+  if (OP == 2) return __builtin_amdgcn_sqrtf(a);
+  return __builtin_amdgcn_rcpf(a);
+}
+template <int OP>
+__global__ void __launch_bounds__(256) valu_rate_kernel(float* __restrict__ out, int iters, float s) {
+  float v[8];
+  for (int i = 0; i < 8; ++i) v[i] = 1.0f + 1e-3f * static_cast<float>(threadIdx.x) + 0.1f * static_cast<float>(i);
+  for (int k = 0; k < iters; ++k)
+    for (int i = 0; i < 8; ++i) v[i] = rate_op<OP>(v[i], s);
+  float t = 0.0f;
+  for (int i = 0; i < 8; ++i) t += v[i];
+  out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = t;
+}
+
+// --------------------------------------------------------------------------
 // launch wrappers
 // --------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
@@ -1000,6 +1022,15 @@ template void launch_batch_sweep<double>(int, const BatchGrainDev*, const int2*,
                                          hipStream_t);
 template void launch_batch_sweep<float>(int, const BatchGrainDev*, const int2*, int, int*, int, void*, int64_t,
                                         hipStream_t);
+
+void launch_valu_rate(int op, float* out, int nblocks, int iters, hipStream_t st) {
+  switch (op) {
+    case 0: hipLaunchKernelGGL(valu_rate_kernel<0>, dim3(nblocks), dim3(256), 0, st, out, iters, 0.999f); break;
+    case 1: hipLaunchKernelGGL(valu_rate_kernel<1>, dim3(nblocks), dim3(256), 0, st, out, iters, 0.999f); break;
+    case 2: hipLaunchKernelGGL(valu_rate_kernel<2>, dim3(nblocks), dim3(256), 0, st, out, iters, 0.999f); break;
+    default: hipLaunchKernelGGL(valu_rate_kernel<3>, dim3(nblocks), dim3(256), 0, st, out, iters, 0.999f); break;
+  }
+}
 
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;

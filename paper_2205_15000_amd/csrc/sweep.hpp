@@ -225,6 +225,8 @@ void launch_interp(const InterpArgs& a, void* cells, void* nodes, hipStream_t st
 template <typename T>
 void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
+// blocks of 256 lanes, each lane writes out[lane]: out holds nblocks * 256 floats
+void launch_valu_rate(int op, float* out, int nblocks, int iters, hipStream_t st);
 template <typename T>
 void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles, int ntiles, int* counter, int nblocks,
                         void* spill, int64_t wave_elems,

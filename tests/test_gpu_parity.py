@@ -361,3 +361,4 @@ def test_degenerate_inputs_match_oracle(case):
         assert _close(od.cpu().numpy(), ref["omega_density"], FP64_TOL), (case, it)
         assert abs(om - ref["omega_total"]) <= FP64_TOL * abs(ref["omega_total"])
     g.close()
+
