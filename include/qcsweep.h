@@ -258,9 +258,12 @@ qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,
  * writes grad_delta = dL/dRe Delta + i dL/dIm Delta (device complex
  * [ncomp][ny][nx]) and grad_A = dL/dA_ind (device [2][ny][nx]).
  * Derivatives of the implicit-midpoint step (App. C) follow from implicit
- * differentiation of its defining equation.  Scatter-adds use FP64 atomics
- * (summation order varies at the 1e-16 level).  Memory: three complex
- * values per (node, pole) on top of the forward buffers. */
+ * differentiation of its defining equation.  The transposes of the
+ * interpolation and of the rotate-back are gathers over transposed tables
+ * (built on the first call), so every output element is written once: no
+ * atomics, and repeated calls give identical gradients.  Memory: by default
+ * trajectory checkpoints every 32 slots plus a per-thread scratch; see
+ * qc_grain_set_adjoint_checkpoint for the fully stored mode. */
 qc_status qc_sweep_adjoint(qc_grain* grain, const double* delta, const double* A_ind, const double* g_delta_new,
                            const double* g_j, double g_omega, double* grad_delta, double* grad_A, void* stream);
 
@@ -276,7 +279,10 @@ qc_status qc_sweep_adjoint(qc_grain* grain, const double* delta, const double* A
  * replay, one per boundary-store parity).  All grains must share device and
  * precision; each appears once; the batch keeps its own Delta and A per
  * grain and uses the grains' buffers (do not sweep them separately while
- * the batch is in use). */
+ * the batch is in use).  The gamma values between a tile's two marches live
+ * in one scratch array with a slice per resident wave (reused tile after
+ * tile), sized for the largest tile of the batch: the spill memory depends
+ * on the longest trajectory and the pole count, not on the number of grains. */
 typedef struct qc_batch qc_batch;
 qc_status qc_batch_create(qc_grain* const* grains, int n, qc_batch** out);
 void qc_batch_destroy(qc_batch* batch);
