@@ -447,13 +447,22 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   if (MODE != 2) load_g(gn, last);
   end_step(gt, prev, prev, n > 0 ? hlast : hfirst, T(-1));
   if (MODE != 2 && n > 0) node_sums(slot0 + n - 1, prev, gn, 0);
-  // slot values are loaded one step ahead (gamma is not: the registers
-  // would cost occupancy, and its load is not on the step's critical path)
+  // slot values and gamma are loaded one step ahead, so the loads overlap
+  // a step (gamma comes back from HBM: it was written a whole march ago)
+  // (FP32 only: in FP64 the registers would cost a wave per SIMD)
+  constexpr bool gpre = MODE != 2 && sizeof(T) == 4;
   nxt = nodes[slot0 + max(n - 2, 0)];
+  cpx<T> gnx[EPL];
+  if (gpre) load_g(gnx, max(n - 2, 0));
   for (int t = n - 1; t >= 1; --t) {
     const node4<T> cur = nxt;
     nxt = nodes[slot0 + max(t - 2, 0)];
-    if (MODE != 2) load_g(gn, t - 1);
+    if (gpre) {
+      for (int i = 0; i < EPL; ++i) gn[i] = gnx[i];
+      load_g(gnx, max(t - 2, 0));
+    } else if (MODE != 2) {
+      load_g(gn, t - 1);
+    }
     mid_step(gt, prev, cur, T(-1));
     prev = cur;
     if (MODE != 2) node_sums(slot0 + t - 1, cur, gn, n - t);
@@ -470,7 +479,8 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 }
 
 // Occupancy floors (waves per SIMD) for the FP32 variants: 7 (<= 72 VGPRs)
-// with two energies per lane (a few spills outside the loops); with four,
+// with two energies per lane (the spills, gamma look-ahead included, stay
+// outside the loops; 6 waves without spills ran slower); with four,
 // 4 (<= 128) for the pole-sum sweep, which spills in its loops at 5, and 5
 // for the other modes; the rest keep the compiler's default.
 template <typename T, int EPL, int MODE>
