@@ -89,12 +89,11 @@ int lanes_for(int n_e, int epl) {
 // Energies per lane: a forced value (1, 2, 3, 4, 8) if it fits 64 lanes,
 // else the shape with the least cost G * epl * f(epl), i.e. energy slots
 // (padding included) weighted by the measured relative cost per slot of
-// each variant on gfx950 (64- and 48-pole grains).  FP32: two per lane
-// (three costs more per slot than the padding it saves); FP64: three for
-// 48 poles; either precision: four for 256-energy blocks.
+// each variant on gfx950 (64- and 48-pole grains).  Two per lane for 64
+// poles, three for 48, four for 256-energy blocks (both precisions).
 void lane_shape(int n_e, int force, bool fp32, int& G, int& epl) {
   static const int kEpl[5] = {1, 2, 3, 4, 8};
-  static const double kCost32[5] = {1.12, 1.0, 1.39, 1.15, 1.55};
+  static const double kCost32[5] = {1.13, 1.0, 1.28, 1.15, 1.55};
   static const double kCost64[5] = {1.07, 1.0, 1.20, 1.12, 1.24};
   const double* kCost = fp32 ? kCost32 : kCost64;
   if ((force == 1 || force == 2 || force == 3 || force == 4 || force == 8) && lanes_for(n_e, force) <= 64) {
