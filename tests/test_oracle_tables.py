@@ -1,5 +1,6 @@
 """Pins of the oracle's tables against what mathematics fixes."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -70,6 +71,38 @@ def test_basis_rotation_in_turns():
     a = tables.basis("dx2y2", phi, crystal_rotation=1.0 / 8.0)
     b = tables.basis("dxy", phi)
     assert np.allclose(a, b, atol=1e-14)
+
+def _golden_basis_rows():
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "basis_functions.txt")
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _eval_expr(expr, **names):
+    env = {"__builtins__": {}, "sqrt": np.sqrt, "sin": np.sin, "cos": np.cos}
+    env.update(names)
+    return np.broadcast_to(np.asarray(eval(expr, env), dtype=np.float64), names["phi"].shape)
+
+
+@pytest.mark.parametrize("row", _golden_basis_rows(), ids=lambda r: r[0])
+def test_basis_matches_the_tabulated_polynomials(row):
+    # both columns of the table: Delta(k) normalised to unit Fermi-surface
+    # mean square gives eta(phi) with a positive factor, and the oracle's
+    # basis is that eta
+    _, name, poly, eta = row
+    phi = tables.fs_angles(64)
+    w = tables.fs_weights(64)
+    pk = _eval_expr(poly, kx=np.cos(phi), ky=np.sin(phi), phi=phi)
+    et = _eval_expr(eta, phi=phi)
+    assert np.allclose(pk / math.sqrt(np.sum(w * pk * pk)), et, atol=1e-14)
+    ob = tables.basis(name, phi)
+    assert np.max(np.abs(ob.imag)) == 0.0
+    assert np.allclose(ob.real, et, atol=1e-14)
 
 
 @pytest.mark.parametrize("m,n,h", [(0, 0, 1.0), (1, 0, 1.0), (2, 3, 1.0), (5, 1, 1.0), (3, 2, 0.25), (0, 4, 0.1)])
