@@ -278,23 +278,36 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // gamma spill of this segment, node t at gseg[t * n_e]: the grain's array
   // (gmul = n_e) or a wave's own scratch (gmul = 0)
   cpx<T>* const gseg = gbase + slot0 * gmul;
+  // Every lane stores every element: a padded energy repeats the last pole's
+  // march (same constants, same start) and writes the same value to that
+  // pole's entry.  With no conditional stores the compiler knows how many
+  // stores were issued after a prefetch and waits for the prefetch alone.
   auto store_g = [&](int t) {
-    cpx<T>* dst = gseg + static_cast<int64_t>(t) * a.n_e + e0;
-    for (int i = 0; i < EPL; ++i)
-      if (full || e0 + i < a.n_e) dst[i] = g[i];
+    cpx<T>* dst = gseg + static_cast<int64_t>(t) * a.n_e;
+    for (int i = 0; i < EPL; ++i) dst[full ? e0 + i : min(e0 + i, a.n_e - 1)] = g[i];
   };
-  // step 0 from R_min (the boundary point takes slot 0's values)
-  end_step(g, prev, prev, hfirst, T(1));
-  if (MODE != 2 && n > 0) store_g(0);
-  // slot values are loaded one step ahead, so the load overlaps a step
+  // Slot values are loaded one step ahead, so the load overlaps a step.  A
+  // wait for that load must not also wait for a gamma store issued just
+  // before it: in FP32 the stores close each step, and the loop is entered
+  // as it repeats (prefetch, then two stores), so the compiler waits for the
+  // prefetch alone; in FP64, where the compiler sinks the first prefetch
+  // below step 0's store, a node's gamma is stored in the next step, right
+  // after that step's prefetch.
+  constexpr bool late_store = sizeof(T) == 4;
   node4<T> nxt = nodes[slot0 + min(1, last)];
+  // step 0 from R_min (the boundary point takes slot 0's values); a segment
+  // with no node still owns one slot, so its store is in range
+  end_step(g, prev, prev, hfirst, T(1));
+  if (late_store && MODE != 2) store_g(0);
   for (int t = 1; t < n; ++t) {
     const node4<T> cur = nxt;
     nxt = nodes[slot0 + min(t + 1, last)];
+    if (!late_store && MODE != 2) store_g(t - 1);
     mid_step(g, prev, cur, T(1));
     prev = cur;
-    if (MODE != 2) store_g(t);
+    if (late_store && MODE != 2) store_g(t);
   }
+  if (!late_store && MODE != 2 && n > 0) store_g(n - 1);
   // step n to R_max (the boundary point takes slot n-1's values)
   if (n > 0) end_step(g, prev, prev, hlast, T(1));
   if (MODE == 0 || MODE == 2) {
