@@ -317,9 +317,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
 
   // ---- gamma~: R_max -> R_min with D -> -D*
-  double rw[EPL];  // pole weights R_p of the lane's energies (0 for padding)
+  T rw[EPL];  // pole weights R_p of the lane's energies (0 for padding)
   for (int i = 0; i < EPL; ++i)
-    rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + min(e0 + i, a.n_e - 1)] : 0.0;
+    rw[i] = static_cast<T>((MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + min(e0 + i, a.n_e - 1)] : 0.0);
   cpx<T> gt[EPL];
   prev = nodes[slot0 + last];
   {
@@ -381,7 +381,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // the wave, since all groups start their march together)
   auto node_sums = [&](int64_t node, const node4<T>& nv, const cpx<T>* gn, int k) {
     if (MODE == 0) {
-      double sfx = 0.0, sfy = 0.0, sg = 0.0, s1 = 0.0, s2 = 0.0;
+      // the lane's few poles are summed in the sweep precision, the lanes'
+      // partial sums in FP64
+      T pfx = T(0), pfy = T(0), pg = T(0), p1 = T(0), p2 = T(0);
       for (int i = 0; i < EPL; ++i) {
         const cpx<T> gg = gn[i];
         const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
@@ -393,13 +395,15 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
         const T ax = fmaT(sxs, ix, -(sys * iy));  // Re((gamma + gamma~) I)
         const T by = fmaT(dxs, iy, dys * ix);     // Im((gamma - gamma~) I)
-        const double r = rw[i];
-        sfx += r * static_cast<double>(ax);
-        sfy += r * static_cast<double>(by);
-        sg += r * static_cast<double>(iy);
-        s1 += r * static_cast<double>(dys);
-        s2 += r * static_cast<double>(sxs);
+        const T r = rw[i];
+        pfx = fmaT(r, ax, pfx);
+        pfy = fmaT(r, by, pfy);
+        pg = fmaT(r, iy, pg);
+        p1 = fmaT(r, dys, p1);
+        p2 = fmaT(r, sxs, p2);
       }
+      const double sfx = static_cast<double>(pfx), sfy = static_cast<double>(pfy), sg = static_cast<double>(pg);
+      const double s1 = static_cast<double>(p1), s2 = static_cast<double>(p2);
       // Im(D* gamma - D gamma~) summed over the lane's poles
       const double si = static_cast<double>(nv.dx) * s1 - static_cast<double>(nv.dy) * s2;
       // S_f = -2 i pi t~ (sfx + i sfy), S_g = 2 pi t~ sg, S_I = 2 pi t~ si
