@@ -353,7 +353,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "d-wave [110] square 40 xi0, 400x400, 64 angles, 64 poles, t=0.1, "
                                "1 flux quantum, kappa=20, 1 vortex (Picard iterations)",
-                   "name": WORKLOAD, "precision": "fp32 sweep / fp64 sums",
+                   "name": WORKLOAD, "precision": "fp32 sweep and per-lane pole sums / fp64 cross-lane sums",
                    "steps_per_iteration": steps_iter, "segments": info["n_segments"],
                    "nodes": info["n_nodes"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",

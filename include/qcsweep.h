@@ -59,9 +59,10 @@ typedef enum {
 } qc_status;
 
 typedef enum { QC_FP64 = 0, QC_MIXED = 1 } qc_precision;
-/* QC_MIXED: interpolated node values, the Riccati marches and the Green's
- * functions in complex FP32; energy sums, angle sums, gap denominator, free
- * energy, A-solve and residuals in FP64.  The interface is FP64 either way. */
+/* QC_MIXED: interpolated node values, the Riccati marches, the Green's
+ * functions and each lane's sum over its few poles (2 or 3) in complex FP32;
+ * the energy sums across lanes, angle sums, gap denominator, free energy,
+ * A-solve and residuals in FP64.  The interface is FP64 either way. */
 
 typedef enum {
   QC_SHAPE_DISC = 0,             /* cx, cy, radius */
