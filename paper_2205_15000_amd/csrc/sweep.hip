@@ -403,9 +403,8 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         p2 = fmaT(r, sxs, p2);
       }
       const double sfx = static_cast<double>(pfx), sfy = static_cast<double>(pfy), sg = static_cast<double>(pg);
-      const double s1 = static_cast<double>(p1), s2 = static_cast<double>(p2);
       // Im(D* gamma - D gamma~) summed over the lane's poles
-      const double si = static_cast<double>(nv.dx) * s1 - static_cast<double>(nv.dy) * s2;
+      const double si = static_cast<double>(fmaT(nv.dx, p1, -(nv.dy * p2)));
       // S_f = -2 i pi t~ (sfx + i sfy), S_g = 2 pi t~ sg, S_I = 2 pi t~ si
       if (a.G >= 8) {
         // the lane's four partials go to LDS; every second node the group
