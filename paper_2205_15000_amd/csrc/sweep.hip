@@ -389,16 +389,14 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
         const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
         const T dxr = T(1) + xx;
-        const T ri = drcp(fmaT(dxr, dxr, xy * xy));
-        const T ix = dxr * ri, iy = -xy * ri;  // I = 1/(1+X)
+        // I = 1/(1+X) = (dxr - i xy) u / R with u = R / |1+X|^2 (R the pole weight)
+        const T r = rw[i];
+        const T u = r * drcp(fmaT(dxr, dxr, xy * xy));
         const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
         const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
-        const T ax = fmaT(sxs, ix, -(sys * iy));  // Re((gamma + gamma~) I)
-        const T by = fmaT(dxs, iy, dys * ix);     // Im((gamma - gamma~) I)
-        const T r = rw[i];
-        pfx = fmaT(r, ax, pfx);
-        pfy = fmaT(r, by, pfy);
-        pg = fmaT(r, iy, pg);
+        pfx = fmaT(u, fmaT(sxs, dxr, sys * xy), pfx);     // R Re((gamma + gamma~) I)
+        pfy = fmaT(u, fmaT(dys, dxr, -(dxs * xy)), pfy);  // R Im((gamma - gamma~) I)
+        pg = fmaT(-u, xy, pg);                            // R Im I
         p1 = fmaT(r, dys, p1);
         p2 = fmaT(r, sxs, p2);
       }
