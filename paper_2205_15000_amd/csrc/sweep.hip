@@ -465,15 +465,22 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // a step (gamma comes back from HBM: it was written a whole march ago)
   // (FP32 only: in FP64 the registers would cost a wave per SIMD)
   constexpr bool gpre = MODE != 2 && sizeof(T) == 4;
+  // (the prefetched row, max(t - 2, 0) at step t, is walked down with a
+  // pointer rather than formed from t, which costs 64-bit multiplies)
   nxt = nodes[slot0 + max(n - 2, 0)];
   cpx<T> gnx[EPL];
-  if (gpre) load_g(gnx, max(n - 2, 0));
+  const cpx<T>* grow = gseg + static_cast<int64_t>(max(n - 2, 0)) * a.n_e;
+  auto load_row = [&](cpx<T>* gv, const cpx<T>* row) {
+    for (int i = 0; i < EPL; ++i) gv[i] = row[full ? e0 + i : min(e0 + i, a.n_e - 1)];
+  };
+  if (gpre) load_row(gnx, grow);
   for (int t = n - 1; t >= 1; --t) {
     const node4<T> cur = nxt;
     nxt = nodes[slot0 + max(t - 2, 0)];
     if (gpre) {
       for (int i = 0; i < EPL; ++i) gn[i] = gnx[i];
-      load_g(gnx, max(t - 2, 0));
+      if (t >= 2) grow -= a.n_e;
+      load_row(gnx, grow);
     } else if (MODE != 2) {
       load_g(gn, t - 1);
     }
