@@ -4,7 +4,8 @@ LDOS post-process.
 Oracle (test infrastructure only).  Follows Alg. 1 (Sec. III.A), Eqs.
 gapeq_fixpoint and current_density (Sec. II), the Eilenberger free-energy
 form (Sec. II), App. D (A-solve), App. E (Picard on the concatenated x) and
-the LDOS definition of Sec. II with the burn-in of App. B.
+the LDOS definition of Sec. II with the burn-in of App. B; App. E also
+gives Polyak's heavy-ball accelerator.
 """
 import math
 import numpy as np
@@ -296,13 +297,26 @@ def rel_norm(new, old, p=2):
     return num / den
 
 
-def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2):
-    """Picard self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on
-    grain cells, kappa^2 A_ind on all cells): x <- x + alpha (g(x) - x),
-    with A from the current of the same iteration (App. D).  During the
-    first `burnin` iterations Delta and A stay fixed and only the boundary
-    values update (App. B).  Returns the final fields and the per-iteration
-    history of (eps_Delta, eps_j, eps_A, eps_Omega, Omega)."""
+def polyak_step(x, v, gx, alpha, beta):
+    """Polyak's heavy-ball update of App. E: the velocity v relaxes with
+    drag beta toward alpha times the difference d = g(x) - x, and x moves
+    by the new velocity.  Returns (x_next, v_next)."""
+    v_next = (1.0 - beta) * v + alpha * (gx - x)
+    return x + v_next, v_next
+
+
+def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator="picard", beta=0.5):
+    """Self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on grain
+    cells, kappa^2 A_ind on all cells), with A from the current of the same
+    iteration (App. D).  accelerator "picard": x <- x + alpha (g(x) - x);
+    "polyak": the heavy-ball step (polyak_step) with step size alpha and
+    drag beta, the velocity starting at zero.  The kappa^2 scale of A drops
+    out of both updates, which are linear in x.  During the first `burnin`
+    iterations Delta and A stay fixed and only the boundary values update
+    (App. B).  Returns the final fields and the per-iteration history of
+    (eps_Delta, eps_j, eps_A, eps_Omega, Omega)."""
+    if accelerator not in ("picard", "polyak"):
+        raise ValueError("unknown accelerator %r" % (accelerator,))
     ny, nx = grain.grid.ny, grain.grid.nx
     delta = np.array(delta, dtype=np.complex128).reshape(grain.ncomp, ny, nx)
     A = np.array(A_ind, dtype=np.float64).reshape(2, ny, nx)
@@ -311,6 +325,8 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2):
     hist = []
     j_old = None
     om_old = None
+    v_d = np.zeros_like(delta)
+    v_a = np.zeros_like(A)
     for it in range(n_iter):
         out = grain.iterate(delta, A, bc)
         bc = out["bc"]
@@ -322,9 +338,13 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2):
             continue
         ax, ay = fields.solve_A(j[0], j[1], m, grain.grid.h, grain.kappa)
         A_new = np.stack([ax, ay])
-        d_new = delta + alpha * (out["delta_new"] - delta)
+        if accelerator == "polyak":
+            d_new, v_d = polyak_step(delta, v_d, out["delta_new"], alpha, beta)
+            A_next, v_a = polyak_step(A, v_a, A_new, alpha, beta)
+        else:
+            d_new = delta + alpha * (out["delta_new"] - delta)
+            A_next = A + alpha * (A_new - A)
         d_new[:, ~m] = 0.0
-        A_next = A + alpha * (A_new - A)
         e_d = rel_norm(d_new[:, m], delta[:, m], norm_p)
         e_a = rel_norm(A_next, A, norm_p)
         e_j = rel_norm(j, j_old, norm_p) if j_old is not None else math.inf
