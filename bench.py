@@ -13,6 +13,8 @@ the mixed FP32-sweep / FP64-sum path; the FP64 path is timed beside it.
 
 Other measurements of the same library (one JSON line each; not the
 headline):
+    --mode accel [--iters N]      Picard against Polyak's heavy ball: iterations
+                                  to a 1e-6 global error on the benchmark workload
     --mode converge [--iters N]   mixed and FP64 Picard runs from the same
                                   start; difference of the final states
     --mode ldos [--prior N --bc-iters K]
@@ -64,7 +66,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--mode", choices=["iteration", "converge", "ldos", "batch", "adjoint", "lanes", "valu"],
+    ap.add_argument("--mode", choices=["iteration", "converge", "accel", "ldos", "batch", "adjoint", "lanes", "valu"],
                     default="iteration")
     ap.add_argument("--workload", default="d_disc_200")
     ap.add_argument("--iters", type=int, default=None)
@@ -145,6 +147,33 @@ def mode_converge(qs, torch, wl, iters):
             "A_max_abs_diff": float(np.max(np.abs(out["mixed"][1] - out["fp64"][1]))),
             "A_max": float(np.max(np.abs(out["fp64"][1]))),
             "residual_history_max_rel_diff": float(hist)}
+
+
+def mode_accel(qs, torch, wl, iters, tol):
+    """Picard (step 1) against Polyak's heavy ball (step 2, drag 0.5: the
+    defaults App. E lists) on the benchmark workload, mixed, from the same
+    start: iterations and time until every global error is below tol."""
+    sp = wl.spec(WORKLOAD)
+    d0 = wl.initial_delta(WORKLOAD, sp)
+    a0 = wl.initial_A(WORKLOAD, sp)
+    runs = {}
+    for kind, alpha in (("picard", 1.0), ("polyak", 2.0)):
+        print("bench: accel %s, up to %d iterations" % (kind, iters), file=sys.stderr, flush=True)
+        g = qs.Grain(sp, "mixed")
+        g.set_accelerator(kind, 0.5)
+        dd = torch.as_tensor(d0).cuda()
+        ad = torch.as_tensor(a0).cuda()
+        t0 = time.perf_counter()
+        try:
+            it, res, conv = g.scf(dd, ad, iters, tol=tol, alpha=alpha)
+            torch.cuda.synchronize()
+            runs[kind] = {"step": alpha, "iters": it, "converged": bool(conv), "s": time.perf_counter() - t0,
+                          "res_last": res[it - 1, :4].tolist()}
+        except qs.QcError as e:
+            runs[kind] = {"step": alpha, "diverged": str(e)}
+        g.close()
+    return {"metric": "iterations to a global error below tol, Picard vs Polyak (mixed)", "workload": WORKLOAD,
+            "tol": tol, "max_iters": iters, "drag": 0.5, "runs": runs}
 
 
 def mode_ldos(qs, torch, wl, n_prior, bc_iters):
@@ -313,6 +342,8 @@ def main():
     if args.mode != "iteration":
         if args.mode == "converge":
             res = mode_converge(qs, torch, wl, args.iters or 3000)
+        elif args.mode == "accel":
+            res = mode_accel(qs, torch, wl, args.iters or 3000, 1e-6)
         elif args.mode == "ldos":
             res = mode_ldos(qs, torch, wl, args.prior, args.bc_iters)
         elif args.mode == "adjoint":

@@ -237,6 +237,18 @@ qc_status qc_scf_run(qc_grain* grain, double* delta_io, double* A_io, int max_it
                      int min_iter, int burnin, double tol, int norm_p, double alpha,
                      int* iters_done, double* residuals_out, void* stream);
 
+/* Accelerator of qc_scf_run (App. E) on the concatenated x = (Re Delta,
+ * Im Delta, kappa^2 A):
+ *   kind 0: Picard, x <- x + alpha d with d = g(x) - x (the default);
+ *   kind 1: Polyak's heavy ball, v <- (1 - beta) v + alpha d, x <- x + v,
+ *           with drag beta in (0, 1] and v = 0 at the start of every run.
+ * alpha is qc_scf_run's argument.  Both updates are linear in x, so the
+ * kappa^2 scale of A drops out.  eps_Delta and eps_A are then the norms of
+ * the step taken (alpha d, or v) relative to the old x.  Polyak keeps two
+ * device arrays of the sizes of Delta and A, allocated at its first run.
+ * Errors: QC_ERR_INVALID for an unknown kind or a drag outside (0, 1]. */
+qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
+
 /* Local density of states N(R, e)/N_F = < -Im g^R / pi > (Sec. II) at the
  * real energies e + i*broadening, Delta and A frozen: bc_iters sweeps update
  * only the boundary values (burn-in, App. B), then one sweep produces the

@@ -98,6 +98,7 @@ _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ct
 _sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
 _sig("qc_green_average", ctypes.c_int, [_P, _P, _P, _P, _P])
 _sig("qc_grain_set_adjoint_checkpoint", ctypes.c_int, [_P, ctypes.c_int])
+_sig("qc_grain_set_accelerator", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)])
 _sig("qc_batch_destroy", None, [_P])
@@ -403,7 +404,9 @@ class Grain:
         return A, Bt
 
     def scf(self, delta, A, max_iter, min_iter=0, burnin=0, tol=0.0, norm_p=2, alpha=1.0, stream=None):
-        """Picard SCF in place on (delta, A); returns (iters, residuals[iters,5], converged)."""
+        """SCF in place on (delta, A) with the grain's accelerator (Picard
+        unless set_accelerator chose Polyak); returns (iters,
+        residuals[iters,5], converged)."""
         torch = _torch()
         dp = _dptr(delta, torch.complex128, (self.ncomp, self.ny, self.nx), "delta")
         ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
@@ -460,6 +463,12 @@ class Grain:
     def set_state(self, buf, stream=None):
         _check(lib.qc_set_state(self._g, ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(buf.numel()),
                                 _stream(stream)))
+
+    def set_accelerator(self, kind, beta=0.5):
+        """SCF accelerator of scf(): "picard" or "polyak" (heavy ball with
+        drag beta; the step size is scf's alpha)."""
+        k = {"picard": 0, "polyak": 1}[kind]
+        _check(lib.qc_grain_set_accelerator(self._g, k, float(beta)))
 
     def set_adjoint_checkpoint(self, every):
         """Reverse mode with checkpoints every `every` slots (default 32;

@@ -320,6 +320,12 @@ struct qc_grain {
   double* jcur = nullptr;
   double* jold = nullptr;
   double* anew = nullptr;
+  // SCF accelerator (App. E): 0 Picard, 1 Polyak with drag beta; the
+  // Polyak velocities of Delta and A
+  int accel = 0;
+  double beta = 0.5;
+  double* vel_d = nullptr;
+  double* vel_a = nullptr;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -341,7 +347,7 @@ void free_grain(qc_grain* g) {
                   g->tap_s_w, g->tap_e_seg, g->tap_e_w, g->grain_cells, g->rb_idx, g->rb_w, g->rb4, g->mask,
                   g->eps, g->rpd, g->den, g->logt, g->nodes, g->cells, g->order, g->gbuf, g->node_out, g->bc[0][0],
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
-                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->gtbuf, g->lgt, g->gS, g->gV,
+                  g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->vel_d, g->vel_a, g->gtbuf, g->lgt, g->gS, g->gV,
                   g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw,
                   g->ckbase, g->ckg, g->ckgt, g->ckscr};
   for (void* p : ptrs)
@@ -922,7 +928,7 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
 // Picard step xold += alpha (xnew - xold) in the same pass
 void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* idx, int64_t n, int nrep,
                   int64_t field_stride, int stride, int p, int reg, hipStream_t st, bool update = false,
-                  double alpha = 1.0) {
+                  double alpha = 1.0, double* vel = nullptr) {
   qc::DiffNormArgs a;
   a.xnew = xnew;
   a.xold = xold;
@@ -935,6 +941,8 @@ void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* 
   a.part = region(g, reg);
   a.update = update ? xold : nullptr;
   a.alpha = alpha;
+  a.vel = vel;
+  a.beta = g->beta;
   qc::launch_diff_norm(a, kParts, st);
 }
 
@@ -997,6 +1005,17 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
     ensure_sweep_buffers(g);
     qc::launch_fill(g->jcur, 2 * g->ncell, 0.0, st);
     qc::launch_fill(g->jold, 2 * g->ncell, 0.0, st);
+    // Polyak: velocities start at zero in every run
+    const bool polyak = g->accel == 1;
+    if (polyak) {
+      if (!g->vel_d) g->vel_d = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
+      if (!g->vel_a) g->vel_a = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
+      qc::launch_fill(g->vel_d, 2 * g->ncomp * g->ncell, 0.0, st);
+      qc::launch_fill(g->vel_a, 2 * g->ncell, 0.0, st);
+    }
+    // the norms are of the step taken: alpha (g(x) - x) for Picard, the
+    // velocity for Polyak
+    const double nscale = polyak ? 1.0 : alpha;
     double om_old = 0.0;
     bool have_old = false;
     int it = 0;
@@ -1016,16 +1035,17 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       do_solve_A(g, g->jcur, g->anew, nullptr, st);
       // residuals of Delta and A with their Picard steps fused in
       enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st, true,
-                   alpha);
+                   alpha, polyak ? g->vel_d : nullptr);
       if (have_old) enqueue_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ, st);
-      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, true, alpha);
+      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, true, alpha,
+                   polyak ? g->vel_a : nullptr);
       std::swap(g->jold, g->jcur);
       fetch_parts(g, st);
       const double om = omega_from_parts(g);
       double res[5];
-      res[0] = alpha * rel_from_parts(g, kRDiffD, norm_p);
+      res[0] = nscale * rel_from_parts(g, kRDiffD, norm_p);
       res[1] = have_old ? rel_from_parts(g, kRDiffJ, norm_p) : INFINITY;
-      res[2] = alpha * rel_from_parts(g, kRDiffA, norm_p);
+      res[2] = nscale * rel_from_parts(g, kRDiffA, norm_p);
       res[3] = (have_old && om_old != 0.0) ? std::fabs(om - om_old) / std::fabs(om_old) : INFINITY;
       res[4] = om;
       if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
@@ -1477,6 +1497,15 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     hcheck(hipGetLastError(), "adjoint launch");
     return QC_OK;
   });
+}
+
+qc_status qc_grain_set_accelerator(qc_grain* g, int kind, double beta) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (kind != 0 && kind != 1) return fail(QC_ERR_INVALID, "accelerator must be 0 (Picard) or 1 (Polyak)");
+  if (kind == 1 && !(beta > 0.0 && beta <= 1.0)) return fail(QC_ERR_INVALID, "Polyak drag must be in (0, 1]");
+  g->accel = kind;
+  g->beta = kind == 1 ? beta : 0.5;
+  return QC_OK;
 }
 
 qc_status qc_grain_set_adjoint_checkpoint(qc_grain* g, int every) {

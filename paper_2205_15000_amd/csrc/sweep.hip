@@ -797,10 +797,18 @@ __global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
     const int64_t e = r * a.field_stride + (a.idx ? a.idx[i] : i);
     double dn = 0.0, dd = 0.0;
     for (int c = 0; c < a.stride; ++c) {
-      const double vn = a.xnew[e * a.stride + c], vo = a.xold[e * a.stride + c];
-      dn += (vn - vo) * (vn - vo);
+      const int64_t k = e * a.stride + c;
+      const double vn = a.xnew[k], vo = a.xold[k];
+      double step = vn - vo;
+      if (a.vel) {  // the heavy-ball step
+        step = (1.0 - a.beta) * a.vel[k] + a.alpha * (vn - vo);
+        a.vel[k] = step;
+        a.update[k] = vo + step;
+      } else if (a.update) {
+        a.update[k] = vo + a.alpha * (vn - vo);  // the Picard step
+      }
+      dn += step * step;
       dd += vo * vo;
-      if (a.update) a.update[e * a.stride + c] = vo + a.alpha * (vn - vo);  // the Picard step
     }
     if (a.p == 2) {
       acc0 += dn;

@@ -129,6 +129,10 @@ struct DiffNormArgs {
   double* part;
   double* update;  // nullptr, or xold itself: then xold += alpha (xnew - xold) in the same pass
   double alpha;
+  // Polyak (App. E) when vel is set: vel <- (1 - beta) vel + alpha (xnew - xold),
+  // xold += vel, and the norm is taken of the step vel instead of xnew - xold
+  double* vel;
+  double beta;
 };
 
 // ---- reverse mode (adjoint.hip)

@@ -190,6 +190,42 @@ def test_scf_with_A_solve_matches_oracle():
     g.close()
 
 
+def test_scf_polyak_matches_oracle():
+    """Polyak's heavy ball (App. E) with the A-solve: 8 iterations after a
+    burn-in, then the same grain run again (the velocity restarts at zero)
+    and switched back to Picard."""
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: 8 Polyak iterations with A, fp64" % name)
+    g = qs.Grain(sp, "fp64")
+    g.set_accelerator("polyak", beta=0.4)
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    m = og.mask
+    for rerun in range(2):
+        g.reset_bc()
+        dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+        it, res, conv = g.scf(dd, ad, 8, alpha=1.5, burnin=1)
+        dref, aref, hist, _ = oscf.scf(og, d0, a0, 8, alpha=1.5, burnin=1, accelerator="polyak", beta=0.4)
+        assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
+        assert _close(ad.cpu().numpy(), aref, FP64_TOL)
+        h = np.array(hist)
+        fin = np.isfinite(h)
+        assert np.max(np.abs(res[fin] - h[fin]) / np.maximum(np.abs(h[fin]), 1e-12)) < 1e-8
+    # and back to Picard
+    g.set_accelerator("picard")
+    g.reset_bc()
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    g.scf(dd, ad, 3, alpha=0.7)
+    dref, aref, _, _ = oscf.scf(og, d0, a0, 3, alpha=0.7)
+    assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
+    with pytest.raises(qs.QcError):
+        g.set_accelerator("polyak", beta=1.5)
+    g.close()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 2e-4)])
 def test_ldos_matches_oracle(precision, tol):
     qs = _qs()
