@@ -305,17 +305,39 @@ def polyak_step(x, v, gx, alpha, beta):
     return x + v_next, v_next
 
 
+BB_STEP_MIN, BB_STEP_MAX = 1e-3, 1e2  # App. E's default bounds of the BB step
+
+
+def bb_step_size(alpha, d, d_prev, i, amin=BB_STEP_MIN, amax=BB_STEP_MAX):
+    """Barzilai-Borwein step size of App. E for accelerated iteration i
+    (counted from 0): alpha_{i+1} = alpha_i s_i with s_i = |d_{i-1}|^2 /
+    |d_{i-1}.(d_i - d_{i-1})| for odd i and |d_{i-1}.(d_i - d_{i-1})| /
+    |d_i - d_{i-1}|^2 for even i, clamped to [amin, amax].  A zero
+    denominator keeps alpha_i.  d_prev is None for the first iteration,
+    which keeps the initial step."""
+    if d_prev is None:
+        return alpha
+    diff = d - d_prev
+    pd = abs(float(np.dot(d_prev, diff)))
+    num, den = (float(np.dot(d_prev, d_prev)), pd) if i % 2 == 1 else (pd, float(np.dot(diff, diff)))
+    if den == 0.0:
+        return alpha
+    return min(max(alpha * num / den, amin), amax)
+
+
 def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator="picard", beta=0.5):
     """Self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on grain
     cells, kappa^2 A_ind on all cells), with A from the current of the same
     iteration (App. D).  accelerator "picard": x <- x + alpha (g(x) - x);
     "polyak": the heavy-ball step (polyak_step) with step size alpha and
     drag beta, the velocity starting at zero.  The kappa^2 scale of A drops
-    out of both updates, which are linear in x.  During the first `burnin`
+    out of both updates, which are linear in x.  "bb": x <- x + alpha_i d
+    with the Barzilai-Borwein step (bb_step_size) from the dot products of
+    the concatenated d, where kappa^2 does enter; alpha is the first step.  During the first `burnin`
     iterations Delta and A stay fixed and only the boundary values update
     (App. B).  Returns the final fields and the per-iteration history of
     (eps_Delta, eps_j, eps_A, eps_Omega, Omega)."""
-    if accelerator not in ("picard", "polyak"):
+    if accelerator not in ("picard", "polyak", "bb"):
         raise ValueError("unknown accelerator %r" % (accelerator,))
     ny, nx = grain.grid.ny, grain.grid.nx
     delta = np.array(delta, dtype=np.complex128).reshape(grain.ncomp, ny, nx)
@@ -327,6 +349,8 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
     om_old = None
     v_d = np.zeros_like(delta)
     v_a = np.zeros_like(A)
+    a_bb, d_prev, i_bb = alpha, None, 0
+    ksc = grain.kappa ** 2 if grain.kappa > 0.0 else 1.0
     for it in range(n_iter):
         out = grain.iterate(delta, A, bc)
         bc = out["bc"]
@@ -338,7 +362,15 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
             continue
         ax, ay = fields.solve_A(j[0], j[1], m, grain.grid.h, grain.kappa)
         A_new = np.stack([ax, ay])
-        if accelerator == "polyak":
+        if accelerator == "bb":
+            dD = out["delta_new"] - delta
+            dA = A_new - A
+            dvec = np.concatenate([dD[:, m].real.ravel(), dD[:, m].imag.ravel(), ksc * dA.ravel()])
+            a_bb = bb_step_size(a_bb, dvec, d_prev, i_bb)
+            d_prev, i_bb = dvec, i_bb + 1
+            d_new = delta + a_bb * dD
+            A_next = A + a_bb * dA
+        elif accelerator == "polyak":
             d_new, v_d = polyak_step(delta, v_d, out["delta_new"], alpha, beta)
             A_next, v_a = polyak_step(A, v_a, A_new, alpha, beta)
         else:
