@@ -13,7 +13,7 @@ the mixed FP32-sweep / FP64-sum path; the FP64 path is timed beside it.
 
 Other measurements of the same library (one JSON line each; not the
 headline):
-    --mode accel [--iters N]      Picard against Polyak's heavy ball: iterations
+    --mode accel [--iters N]      Picard against Polyak's heavy ball and BB: iterations
                                   to a 1e-6 global error on the benchmark workload
     --mode converge [--iters N]   mixed and FP64 Picard runs from the same
                                   start; difference of the final states
@@ -150,14 +150,15 @@ def mode_converge(qs, torch, wl, iters):
 
 
 def mode_accel(qs, torch, wl, iters, tol):
-    """Picard (step 1) against Polyak's heavy ball (step 2, drag 0.5: the
-    defaults App. E lists) on the benchmark workload, mixed, from the same
-    start: iterations and time until every global error is below tol."""
+    """Picard (step 1) against Polyak's heavy ball (step 2, drag 0.5) and
+    Barzilai-Borwein (first step 1), the defaults App. E lists, on the
+    benchmark workload, mixed, from the same start: iterations and time
+    until every global error is below tol."""
     sp = wl.spec(WORKLOAD)
     d0 = wl.initial_delta(WORKLOAD, sp)
     a0 = wl.initial_A(WORKLOAD, sp)
     runs = {}
-    for kind, alpha in (("picard", 1.0), ("polyak", 2.0)):
+    for kind, alpha in (("picard", 1.0), ("polyak", 2.0), ("bb", 1.0)):
         print("bench: accel %s, up to %d iterations" % (kind, iters), file=sys.stderr, flush=True)
         g = qs.Grain(sp, "mixed")
         g.set_accelerator(kind, 0.5)
@@ -172,7 +173,7 @@ def mode_accel(qs, torch, wl, iters, tol):
         except qs.QcError as e:
             runs[kind] = {"step": alpha, "diverged": str(e)}
         g.close()
-    return {"metric": "iterations to a global error below tol, Picard vs Polyak (mixed)", "workload": WORKLOAD,
+    return {"metric": "iterations to a global error below tol, Picard vs Polyak vs BB (mixed)", "workload": WORKLOAD,
             "tol": tol, "max_iters": iters, "drag": 0.5, "runs": runs}
 
 

@@ -238,15 +238,22 @@ qc_status qc_scf_run(qc_grain* grain, double* delta_io, double* A_io, int max_it
                      int* iters_done, double* residuals_out, void* stream);
 
 /* Accelerator of qc_scf_run (App. E) on the concatenated x = (Re Delta,
- * Im Delta, kappa^2 A):
+ * Im Delta on grain cells, kappa^2 A; kappa^2 read as 1 when kappa <= 0):
  *   kind 0: Picard, x <- x + alpha d with d = g(x) - x (the default);
  *   kind 1: Polyak's heavy ball, v <- (1 - beta) v + alpha d, x <- x + v,
- *           with drag beta in (0, 1] and v = 0 at the start of every run.
- * alpha is qc_scf_run's argument.  Both updates are linear in x, so the
- * kappa^2 scale of A drops out.  eps_Delta and eps_A are then the norms of
- * the step taken (alpha d, or v) relative to the old x.  Polyak keeps two
- * device arrays of the sizes of Delta and A, allocated at its first run.
- * Errors: QC_ERR_INVALID for an unknown kind or a drag outside (0, 1]. */
+ *           with drag beta in (0, 1] and v = 0 at the start of every run;
+ *   kind 2: Barzilai-Borwein, x <- x + a_i d_i with a_0 = alpha and, for
+ *           accelerated iteration i >= 1 of the run, a_i = a_{i-1} s_i:
+ *           s_i = |d_{i-1}|^2 / |d_{i-1}.(d_i - d_{i-1})| for odd i,
+ *           |d_{i-1}.(d_i - d_{i-1})| / |d_i - d_{i-1}|^2 for even i,
+ *           a_i clamped to [1e-3, 1e2]; a zero denominator keeps a_{i-1}.
+ *           beta is ignored.
+ * alpha is qc_scf_run's argument.  Picard and Polyak are linear in x, so the
+ * kappa^2 scale of A drops out of them; it enters BB's dot products.
+ * eps_Delta and eps_A are then the norms of the step taken (alpha d, v or
+ * a_i d) relative to the old x.  Polyak and BB keep two device arrays of
+ * the sizes of Delta and A, allocated at their first run.
+ * Errors: QC_ERR_INVALID for an unknown kind or a Polyak drag outside (0, 1]. */
 qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
 
 /* Local density of states N(R, e)/N_F = < -Im g^R / pi > (Sec. II) at the

@@ -465,9 +465,10 @@ class Grain:
                                 _stream(stream)))
 
     def set_accelerator(self, kind, beta=0.5):
-        """SCF accelerator of scf(): "picard" or "polyak" (heavy ball with
-        drag beta; the step size is scf's alpha)."""
-        k = {"picard": 0, "polyak": 1}[kind]
+        """SCF accelerator of scf(): "picard", "polyak" (heavy ball with
+        drag beta; the step size is scf's alpha) or "bb" (Barzilai-Borwein
+        step sizes, scf's alpha the first)."""
+        k = {"picard": 0, "polyak": 1, "bb": 2}[kind]
         _check(lib.qc_grain_set_accelerator(self._g, k, float(beta)))
 
     def set_adjoint_checkpoint(self, every):

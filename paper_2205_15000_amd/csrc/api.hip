@@ -320,8 +320,9 @@ struct qc_grain {
   double* jcur = nullptr;
   double* jold = nullptr;
   double* anew = nullptr;
-  // SCF accelerator (App. E): 0 Picard, 1 Polyak with drag beta; the
-  // Polyak velocities of Delta and A
+  // SCF accelerator (App. E): 0 Picard, 1 Polyak with drag beta, 2
+  // Barzilai-Borwein; the Polyak velocities (BB: previous differences) of
+  // Delta and A
   int accel = 0;
   double beta = 0.5;
   double* vel_d = nullptr;
@@ -336,8 +337,14 @@ struct qc_grain {
 };
 
 static constexpr int kParts = 256;
+// bounds of the Barzilai-Borwein step (App. E's defaults)
+static constexpr double kBBStepMin = 1e-3, kBBStepMax = 1e2;
 // regions of the block-partial buffer (kParts doubles each, diffs 2 kParts)
-enum { kROmega = 0, kRB2 = 1, kRJx = 2, kRJy = 3, kRDiffD = 4, kRDiffJ = 6, kRDiffA = 8, kRegions = 10 };
+// (BB dot products 3 kParts each)
+enum {
+  kROmega = 0, kRB2 = 1, kRJx = 2, kRJy = 3, kRDiffD = 4, kRDiffJ = 6, kRDiffA = 8, kRBBD = 10, kRBBA = 13,
+  kRegions = 16
+};
 
 namespace {
 
@@ -1005,17 +1012,21 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
     ensure_sweep_buffers(g);
     qc::launch_fill(g->jcur, 2 * g->ncell, 0.0, st);
     qc::launch_fill(g->jold, 2 * g->ncell, 0.0, st);
-    // Polyak: velocities start at zero in every run
-    const bool polyak = g->accel == 1;
-    if (polyak) {
+    // Polyak: velocities start at zero in every run; BB keeps the previous
+    // iteration's difference in the same arrays
+    const bool polyak = g->accel == 1, bb = g->accel == 2;
+    if (polyak || bb) {
       if (!g->vel_d) g->vel_d = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
       if (!g->vel_a) g->vel_a = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
       qc::launch_fill(g->vel_d, 2 * g->ncomp * g->ncell, 0.0, st);
       qc::launch_fill(g->vel_a, 2 * g->ncell, 0.0, st);
     }
-    // the norms are of the step taken: alpha (g(x) - x) for Picard, the
-    // velocity for Polyak
-    const double nscale = polyak ? 1.0 : alpha;
+    // the norms are of the step taken: alpha (g(x) - x) for Picard and BB,
+    // the velocity for Polyak
+    double nscale = polyak ? 1.0 : alpha;
+    double a_bb = alpha;  // BB step, alpha for the first iteration
+    int i_bb = 0;
+    const double ksc = g->kappa > 0.0 ? g->kappa * g->kappa : 1.0;  // x holds kappa^2 A
     double om_old = 0.0;
     bool have_old = false;
     int it = 0;
@@ -1034,13 +1045,40 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       }
       do_solve_A(g, g->jcur, g->anew, nullptr, st);
       // residuals of Delta and A with their Picard steps fused in
-      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st, true,
+      // (BB: norms and dot products first; the step follows once its size is known)
+      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st, !bb,
                    alpha, polyak ? g->vel_d : nullptr);
       if (have_old) enqueue_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ, st);
-      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, true, alpha,
+      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, !bb, alpha,
                    polyak ? g->vel_a : nullptr);
+      if (bb) {
+        qc::launch_bb_dots(g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, g->vel_d,
+                           region(g, kRBBD), kParts, st);
+        qc::launch_bb_dots(g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, ksc, g->vel_a, region(g, kRBBA), kParts,
+                           st);
+      }
       std::swap(g->jold, g->jcur);
       fetch_parts(g, st);
+      if (bb) {
+        if (i_bb > 0) {
+          double pp = 0.0, pd = 0.0, dd = 0.0;
+          for (int reg : {kRBBD, kRBBA}) {
+            const double* q = g->part_host + static_cast<int64_t>(reg) * kParts;
+            for (int b = 0; b < kParts; ++b) {
+              pp += q[3 * b];
+              pd += q[3 * b + 1];
+              dd += q[3 * b + 2];
+            }
+          }
+          pd = std::fabs(pd);
+          const double num = (i_bb % 2 == 1) ? pp : pd, den = (i_bb % 2 == 1) ? pd : dd;
+          if (den != 0.0) a_bb = std::min(std::max(a_bb * num / den, kBBStepMin), kBBStepMax);
+        }
+        ++i_bb;
+        nscale = a_bb;
+        qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, a_bb, st);
+        qc::launch_picard(A_io, g->anew, nullptr, 2 * g->ncell, 1, 0, 1, a_bb, st);
+      }
       const double om = omega_from_parts(g);
       double res[5];
       res[0] = nscale * rel_from_parts(g, kRDiffD, norm_p);
@@ -1501,7 +1539,7 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
 
 qc_status qc_grain_set_accelerator(qc_grain* g, int kind, double beta) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
-  if (kind != 0 && kind != 1) return fail(QC_ERR_INVALID, "accelerator must be 0 (Picard) or 1 (Polyak)");
+  if (kind < 0 || kind > 2) return fail(QC_ERR_INVALID, "accelerator must be 0 (Picard), 1 (Polyak) or 2 (BB)");
   if (kind == 1 && !(beta > 0.0 && beta <= 1.0)) return fail(QC_ERR_INVALID, "Polyak drag must be in (0, 1]");
   g->accel = kind;
   g->beta = kind == 1 ? beta : 0.5;

@@ -857,6 +857,45 @@ __global__ void __launch_bounds__(256) picard_kernel(double* __restrict__ x, con
   }
 }
 
+// Barzilai-Borwein dot products (App. E) over one field of the concatenated
+// x: with d = scale (xnew - xold) and dp the previous iteration's d, block
+// partials of dp.dp, dp.(d - dp) and (d - dp).(d - dp); dp <- d.
+__global__ void __launch_bounds__(256) bb_dots_kernel(const double* __restrict__ xnew,
+                                                      const double* __restrict__ xold,
+                                                      const int32_t* __restrict__ idx, int64_t n, int nrep,
+                                                      int64_t field_stride, int stride, double scale,
+                                                      double* __restrict__ dprev, double* __restrict__ part) {
+  __shared__ double sm[3][256];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const int64_t total = n * nrep;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t / n, i = t - r * n;
+    const int64_t e = r * field_stride + (idx ? idx[i] : i);
+    for (int c = 0; c < stride; ++c) {
+      const int64_t k = e * stride + c;
+      const double d = scale * (xnew[k] - xold[k]);
+      const double pv = dprev[k];
+      const double q = d - pv;
+      a0 += pv * pv;
+      a1 += pv * q;
+      a2 += q * q;
+      dprev[k] = d;
+    }
+  }
+  sm[0][threadIdx.x] = a0;
+  sm[1][threadIdx.x] = a1;
+  sm[2][threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) part[3 * blockIdx.x + c] = sm[c][0];
+}
+
 // --------------------------------------------------------------------------
 // A-solve (App. D): zero-padded FFT correlation with the cell-averaged
 // Green's function of the 2D Laplacian
@@ -1104,6 +1143,12 @@ void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, 
 }
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(diff_norm_kernel, dim3(nparts), dim3(256), 0, st, a);
+}
+void launch_bb_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
+                    int64_t field_stride, int stride, double scale, double* dprev, double* part, int nparts,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(bb_dots_kernel, dim3(nparts), dim3(256), 0, st, xnew, xold, idx, n, nrep, field_stride, stride,
+                     scale, dprev, part);
 }
 void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, int nrep, int64_t field_stride,
                    int stride, double alpha, hipStream_t st) {

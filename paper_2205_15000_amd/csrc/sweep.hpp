@@ -245,6 +245,10 @@ void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream
 void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,
                       hipStream_t st);
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st);
+// partials [nparts][3] of dp.dp, dp.(d - dp), (d - dp).(d - dp), d = scale (xnew - xold); dprev <- d
+void launch_bb_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
+                    int64_t field_stride, int stride, double scale, double* dprev, double* part, int nparts,
+                    hipStream_t st);
 void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, int nrep, int64_t field_stride,
                    int stride, double alpha, hipStream_t st);
 void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st);

@@ -226,6 +226,33 @@ def test_scf_polyak_matches_oracle():
     g.close()
 
 
+def test_scf_barzilai_borwein_matches_oracle():
+    """Barzilai-Borwein steps (App. E) with the A-solve and kappa^2 in the
+    dot products: 10 iterations after a burn-in, FP64, against the oracle;
+    run twice on the same grain (the step restarts at alpha)."""
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: 10 BB iterations with A, fp64" % name)
+    g = qs.Grain(sp, "fp64")
+    g.set_accelerator("bb")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    m = og.mask
+    for rerun in range(2):
+        g.reset_bc()
+        dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+        it, res, conv = g.scf(dd, ad, 10, alpha=0.8, burnin=1)
+        dref, aref, hist, _ = oscf.scf(og, d0, a0, 10, alpha=0.8, burnin=1, accelerator="bb")
+        assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
+        assert _close(ad.cpu().numpy(), aref, FP64_TOL)
+        h = np.array(hist)
+        fin = np.isfinite(h)
+        assert np.max(np.abs(res[fin] - h[fin]) / np.maximum(np.abs(h[fin]), 1e-12)) < 1e-8
+    g.close()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 2e-4)])
 def test_ldos_matches_oracle(precision, tol):
     qs = _qs()
