@@ -13,8 +13,9 @@ the mixed FP32-sweep / FP64-sum path; the FP64 path is timed beside it.
 
 Other measurements of the same library (one JSON line each; not the
 headline):
-    --mode accel [--iters N]      Picard against Polyak's heavy ball and BB: iterations
-                                  to a 1e-6 global error on the benchmark workload
+    --mode accel [--iters N --tol T --accel-workload NAME]
+                                  Picard against Polyak's heavy ball and BB: iterations
+                                  to a global error below tol (default 1e-6, benchmark workload)
     --mode converge [--iters N]   mixed and FP64 Picard runs from the same
                                   start; difference of the final states
     --mode ldos [--prior N --bc-iters K]
@@ -73,6 +74,8 @@ def parse():
     ap.add_argument("--prior", type=int, default=200)
     ap.add_argument("--bc-iters", type=int, default=20)
     ap.add_argument("--grains", type=int, default=64)
+    ap.add_argument("--accel-workload", default=WORKLOAD)
+    ap.add_argument("--tol", type=float, default=1e-6)
     return ap.parse_args()
 
 
@@ -149,14 +152,14 @@ def mode_converge(qs, torch, wl, iters):
             "residual_history_max_rel_diff": float(hist)}
 
 
-def mode_accel(qs, torch, wl, iters, tol):
+def mode_accel(qs, torch, wl, iters, tol, name=WORKLOAD):
     """Picard (step 1) against Polyak's heavy ball (step 2, drag 0.5) and
     Barzilai-Borwein (first step 1), the defaults App. E lists, on the
     benchmark workload, mixed, from the same start: iterations and time
     until every global error is below tol."""
-    sp = wl.spec(WORKLOAD)
-    d0 = wl.initial_delta(WORKLOAD, sp)
-    a0 = wl.initial_A(WORKLOAD, sp)
+    sp = wl.spec(name)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
     runs = {}
     for kind, alpha in (("picard", 1.0), ("polyak", 2.0), ("bb", 1.0)):
         print("bench: accel %s, up to %d iterations" % (kind, iters), file=sys.stderr, flush=True)
@@ -173,7 +176,7 @@ def mode_accel(qs, torch, wl, iters, tol):
         except qs.QcError as e:
             runs[kind] = {"step": alpha, "diverged": str(e)}
         g.close()
-    return {"metric": "iterations to a global error below tol, Picard vs Polyak vs BB (mixed)", "workload": WORKLOAD,
+    return {"metric": "iterations to a global error below tol, Picard vs Polyak vs BB (mixed)", "workload": name,
             "tol": tol, "max_iters": iters, "drag": 0.5, "runs": runs}
 
 
@@ -344,7 +347,7 @@ def main():
         if args.mode == "converge":
             res = mode_converge(qs, torch, wl, args.iters or 3000)
         elif args.mode == "accel":
-            res = mode_accel(qs, torch, wl, args.iters or 3000, 1e-6)
+            res = mode_accel(qs, torch, wl, args.iters or 3000, args.tol, args.accel_workload)
         elif args.mode == "ldos":
             res = mode_ldos(qs, torch, wl, args.prior, args.bc_iters)
         elif args.mode == "adjoint":
