@@ -325,6 +325,48 @@ def bb_step_size(alpha, d, d_prev, i, amin=BB_STEP_MIN, amax=BB_STEP_MAX):
     return min(max(alpha * num / den, amin), amax)
 
 
+# App. E's CongAcc defaults: first step, step factor k, minimum similarity,
+# step bounds
+CONG_STEP, CONG_K, CONG_SMIN, CONG_STEP_MIN, CONG_STEP_MAX = 0.5, 1.234, 0.7, 1e-3, 1e2
+
+
+def similarity_weight(mm, md, dd, smin, n_bisect=60):
+    """The weight w* in [0, 1] at which the cosine similarity of
+    w m + (1 - w) d with d equals smin (App. E), by bisection, from the dot
+    products m.m, m.d and d.d.  At w = 0 the similarity is 1; the caller
+    applies it only when the similarity at w = 1 is below smin."""
+    def sim(w):
+        uu = w * w * mm + 2.0 * w * (1.0 - w) * md + (1.0 - w) * (1.0 - w) * dd
+        return (w * md + (1.0 - w) * dd) / math.sqrt(uu * dd) if uu > 0.0 else 1.0
+    lo, hi = 0.0, 1.0
+    for _ in range(n_bisect):
+        mid = 0.5 * (lo + hi)
+        if sim(mid) >= smin:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def congacc_component(m, d, alpha, w, first, k=CONG_K, smin=CONG_SMIN, amin=CONG_STEP_MIN, amax=CONG_STEP_MAX):
+    """CongAcc (App. E) for one component c of x (the real or imaginary part
+    of one order-parameter component, or one component of A): the cosine
+    similarity s of the moving average m with the difference d scales the
+    step, alpha <- alpha k^s (clamped); the weight w is kept while s >= smin
+    and otherwise replaced by similarity_weight; m <- w m + (1 - w) d.  The
+    first iteration takes w = 0 (so m = d) and keeps alpha; a similarity
+    with a zero vector is read as 0.  Returns (m_next, alpha_next, w_next);
+    the step is x <- x + alpha_next m_next."""
+    if first:
+        return d.copy(), alpha, 0.0
+    mm, md, dd = float(np.dot(m, m)), float(np.dot(m, d)), float(np.dot(d, d))
+    s = md / math.sqrt(mm * dd) if mm > 0.0 and dd > 0.0 else 0.0
+    alpha = min(max(alpha * k ** s, amin), amax)
+    if s < smin and mm > 0.0 and dd > 0.0:
+        w = similarity_weight(mm, md, dd, smin)
+    return w * m + (1.0 - w) * d, alpha, w
+
+
 def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator="picard", beta=0.5):
     """Self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on grain
     cells, kappa^2 A_ind on all cells), with A from the current of the same
@@ -333,11 +375,13 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
     drag beta, the velocity starting at zero.  The kappa^2 scale of A drops
     out of both updates, which are linear in x.  "bb": x <- x + alpha_i d
     with the Barzilai-Borwein step (bb_step_size) from the dot products of
-    the concatenated d, where kappa^2 does enter; alpha is the first step.  During the first `burnin`
+    the concatenated d, where kappa^2 does enter; alpha is the first step.
+    "congacc": per component of x (congacc_component), alpha the first step
+    of every component; kappa^2 drops out again.  During the first `burnin`
     iterations Delta and A stay fixed and only the boundary values update
     (App. B).  Returns the final fields and the per-iteration history of
     (eps_Delta, eps_j, eps_A, eps_Omega, Omega)."""
-    if accelerator not in ("picard", "polyak", "bb"):
+    if accelerator not in ("picard", "polyak", "bb", "congacc"):
         raise ValueError("unknown accelerator %r" % (accelerator,))
     ny, nx = grain.grid.ny, grain.grid.nx
     delta = np.array(delta, dtype=np.complex128).reshape(grain.ncomp, ny, nx)
@@ -350,6 +394,9 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
     v_d = np.zeros_like(delta)
     v_a = np.zeros_like(A)
     a_bb, d_prev, i_bb = alpha, None, 0
+    ncomp_x = 2 * grain.ncomp + 2
+    cg = [None] * ncomp_x, [alpha] * ncomp_x, [0.0] * ncomp_x  # m, alpha, w per component
+    cg_first = True
     ksc = grain.kappa ** 2 if grain.kappa > 0.0 else 1.0
     for it in range(n_iter):
         out = grain.iterate(delta, A, bc)
@@ -362,7 +409,26 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
             continue
         ax, ay = fields.solve_A(j[0], j[1], m, grain.grid.h, grain.kappa)
         A_new = np.stack([ax, ay])
-        if accelerator == "bb":
+        if accelerator == "congacc":
+            dD = out["delta_new"] - delta
+            dA = A_new - A
+            parts = []
+            for g_ in range(grain.ncomp):
+                parts += [dD[g_][m].real.copy(), dD[g_][m].imag.copy()]
+            parts += [dA[0].ravel().copy(), dA[1].ravel().copy()]
+            d_new = delta.copy()
+            A_next = A.copy()
+            for c, dc in enumerate(parts):
+                mc, ac, wc = congacc_component(cg[0][c], dc, cg[1][c], cg[2][c], cg_first)
+                cg[0][c], cg[1][c], cg[2][c] = mc, ac, wc
+                step = ac * mc
+                if c < 2 * grain.ncomp:
+                    g_, im = divmod(c, 2)
+                    d_new[g_][m] += 1j * step if im else step
+                else:
+                    A_next[c - 2 * grain.ncomp] += step.reshape(ny, nx)
+            cg_first = False
+        elif accelerator == "bb":
             dD = out["delta_new"] - delta
             dA = A_new - A
             dvec = np.concatenate([dD[:, m].real.ravel(), dD[:, m].imag.ravel(), ksc * dA.ravel()])

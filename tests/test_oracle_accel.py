@@ -106,3 +106,53 @@ def test_bb_on_the_bcs_fixed_point_stays_put():
     delta = np.where(gr.mask, dbulk, 0)[None].astype(complex)
     d1, a1, _, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 3, accelerator="bb", alpha=1.0)
     assert np.max(np.abs(d1[0][gr.mask] - dbulk)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_similarity_weight_solves_its_quadratic(seed):
+    # S_C(w m + (1 - w) d, d) = smin squared is a quadratic in w:
+    # (w md + (1-w) dd)^2 = smin^2 dd (w^2 mm + 2 w (1-w) md + (1-w)^2 dd);
+    # its root in [0, 1] with a positive left side is the weight
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(7)
+    m = -d + 0.6 * rng.standard_normal(7)  # pointing away from d
+    mm, md, dd = m @ m, m @ d, d @ d
+    smin = scf.CONG_SMIN
+    a, b = md - dd, dd  # numerator = a w + b
+    q2 = a * a - smin ** 2 * dd * (mm - 2 * md + dd)
+    q1 = 2 * a * b - smin ** 2 * dd * (2 * md - 2 * dd)
+    q0 = b * b - smin ** 2 * dd * dd
+    roots = [r.real for r in np.roots([q2, q1, q0]) if abs(r.imag) < 1e-12 and 0 <= r.real <= 1
+             and a * r.real + b > 0]
+    assert len(roots) == 1
+    w = scf.similarity_weight(mm, md, dd, smin)
+    assert abs(w - roots[0]) < 1e-12
+    u = w * m + (1 - w) * d
+    assert abs(u @ d / np.sqrt((u @ u) * dd) - smin) < 1e-12
+
+
+def test_congacc_component_scales_the_step_by_the_similarity():
+    d = np.array([1.0, -2.0, 0.5])
+    m0, a0, w0 = scf.congacc_component(None, d, 0.5, 0.3, True)
+    assert np.array_equal(m0, d) and a0 == 0.5 and w0 == 0.0
+    # aligned: s = 1, alpha grows by k, the weight is kept
+    m1, a1, w1 = scf.congacc_component(2.0 * d, d, 0.5, 0.25, False)
+    assert abs(a1 - 0.5 * scf.CONG_K) < 1e-15 and w1 == 0.25
+    assert np.allclose(m1, 0.25 * 2.0 * d + 0.75 * d, rtol=1e-15)
+    # pointing away: alpha shrinks by k^s (s < 0), and the weight makes the
+    # new average exactly smin-similar to d
+    e = np.array([2.0, 1.0, 0.0])  # orthogonal to d
+    m = -d + 0.5 * e
+    s = m @ d / np.sqrt((m @ m) * (d @ d))
+    m2, a2, w2 = scf.congacc_component(m, d, 0.5, 0.25, False)
+    assert s < 0 and abs(a2 - 0.5 * scf.CONG_K ** s) < 1e-15 and 0.0 < w2 < 1.0
+    assert abs(m2 @ d / np.sqrt((m2 @ m2) * (d @ d)) - scf.CONG_SMIN) < 1e-12
+
+
+def test_congacc_on_the_bcs_fixed_point_stays_put():
+    from oracle import bulk
+    gr = _cfg1_like()
+    dbulk = bulk.bulk_gap(0.5, 16)
+    delta = np.where(gr.mask, dbulk, 0)[None].astype(complex)
+    d1, a1, _, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 3, accelerator="congacc", alpha=0.5)
+    assert np.max(np.abs(d1[0][gr.mask] - dbulk)) < 1e-12
