@@ -153,15 +153,15 @@ def mode_converge(qs, torch, wl, iters):
 
 
 def mode_accel(qs, torch, wl, iters, tol, name=WORKLOAD):
-    """Picard (step 1) against Polyak's heavy ball (step 2, drag 0.5) and
-    Barzilai-Borwein (first step 1), the defaults App. E lists, on the
-    benchmark workload, mixed, from the same start: iterations and time
-    until every global error is below tol."""
+    """Picard (step 1) against Polyak's heavy ball (step 2, drag 0.5),
+    Barzilai-Borwein (first step 1) and CongAcc (first step 0.5), the
+    defaults App. E lists, on the benchmark workload, mixed, from the same
+    start: iterations and time until every global error is below tol."""
     sp = wl.spec(name)
     d0 = wl.initial_delta(name, sp)
     a0 = wl.initial_A(name, sp)
     runs = {}
-    for kind, alpha in (("picard", 1.0), ("polyak", 2.0), ("bb", 1.0)):
+    for kind, alpha in (("picard", 1.0), ("polyak", 2.0), ("bb", 1.0), ("congacc", 0.5)):
         print("bench: accel %s, up to %d iterations" % (kind, iters), file=sys.stderr, flush=True)
         g = qs.Grain(sp, "mixed")
         g.set_accelerator(kind, 0.5)
@@ -176,7 +176,7 @@ def mode_accel(qs, torch, wl, iters, tol, name=WORKLOAD):
         except qs.QcError as e:
             runs[kind] = {"step": alpha, "diverged": str(e)}
         g.close()
-    return {"metric": "iterations to a global error below tol, Picard vs Polyak vs BB (mixed)", "workload": name,
+    return {"metric": "iterations to a global error below tol, Picard vs Polyak vs BB vs CongAcc (mixed)", "workload": name,
             "tol": tol, "max_iters": iters, "drag": 0.5, "runs": runs}
 
 

@@ -247,12 +247,21 @@ qc_status qc_scf_run(qc_grain* grain, double* delta_io, double* A_io, int max_it
  *           s_i = |d_{i-1}|^2 / |d_{i-1}.(d_i - d_{i-1})| for odd i,
  *           |d_{i-1}.(d_i - d_{i-1})| / |d_i - d_{i-1}|^2 for even i,
  *           a_i clamped to [1e-3, 1e2]; a zero denominator keeps a_{i-1}.
+ *           beta is ignored;
+ *   kind 3: CongAcc, per component c of x (Re and Im of each Delta
+ *           component, A_x, A_y): s = cosine similarity of the moving
+ *           average m_c with d_c, a_c <- a_c 1.234^s clamped to [1e-3, 1e2],
+ *           the weight w_c kept while s >= 0.7 and otherwise set by
+ *           bisection so that w m + (1 - w) d has similarity 0.7 with d,
+ *           m_c <- w_c m_c + (1 - w_c) d_c, x_c <- x_c + a_c m_c.  The first
+ *           iteration takes w = 0 and a_c = alpha; a similarity with a zero
+ *           vector counts as 0.  Needs norm_p = 2 (QC_ERR_INVALID otherwise).
  *           beta is ignored.
  * alpha is qc_scf_run's argument.  Picard and Polyak are linear in x, so the
  * kappa^2 scale of A drops out of them; it enters BB's dot products.
  * eps_Delta and eps_A are then the norms of the step taken (alpha d, v or
- * a_i d) relative to the old x.  Polyak and BB keep two device arrays of
- * the sizes of Delta and A, allocated at their first run.
+ * a_i d, a_c m_c) relative to the old x.  Polyak, BB and CongAcc keep two
+ * device arrays of the sizes of Delta and A, allocated at their first run.
  * Errors: QC_ERR_INVALID for an unknown kind or a Polyak drag outside (0, 1]. */
 qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
 

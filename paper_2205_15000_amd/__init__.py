@@ -467,8 +467,9 @@ class Grain:
     def set_accelerator(self, kind, beta=0.5):
         """SCF accelerator of scf(): "picard", "polyak" (heavy ball with
         drag beta; the step size is scf's alpha) or "bb" (Barzilai-Borwein
-        step sizes, scf's alpha the first)."""
-        k = {"picard": 0, "polyak": 1, "bb": 2}[kind]
+        step sizes, scf's alpha the first) or "congacc" (per-component steps,
+        scf's alpha the first; 2-norm residuals)."""
+        k = {"picard": 0, "polyak": 1, "bb": 2, "congacc": 3}[kind]
         _check(lib.qc_grain_set_accelerator(self._g, k, float(beta)))
 
     def set_adjoint_checkpoint(self, every):

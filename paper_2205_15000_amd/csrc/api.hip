@@ -327,6 +327,9 @@ struct qc_grain {
   double beta = 0.5;
   double* vel_d = nullptr;
   double* vel_a = nullptr;
+  // CongAcc: per-component dot-product partials [component][kParts][3]
+  double* cpart = nullptr;
+  double* cpart_host = nullptr;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -339,6 +342,26 @@ struct qc_grain {
 static constexpr int kParts = 256;
 // bounds of the Barzilai-Borwein step (App. E's defaults)
 static constexpr double kBBStepMin = 1e-3, kBBStepMax = 1e2;
+// CongAcc (App. E's defaults): step factor, minimum similarity, step bounds
+static constexpr double kCongK = 1.234, kCongSmin = 0.7, kCongStepMin = 1e-3, kCongStepMax = 1e2;
+
+// The weight w* in [0, 1] at which w m + (1 - w) d has cosine similarity
+// smin with d, by bisection from m.m, m.d and d.d (similarity 1 at w = 0).
+static double congacc_weight(double mm, double md, double dd, double smin) {
+  auto sim = [&](double w) {
+    const double uu = w * w * mm + 2.0 * w * (1.0 - w) * md + (1.0 - w) * (1.0 - w) * dd;
+    return uu > 0.0 ? (w * md + (1.0 - w) * dd) / std::sqrt(uu * dd) : 1.0;
+  };
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sim(mid) >= smin)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
 // regions of the block-partial buffer (kParts doubles each, diffs 2 kParts)
 // (BB dot products 3 kParts each)
 enum {
@@ -360,6 +383,8 @@ void free_grain(qc_grain* g) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
+  if (g->cpart) (void)hipFree(g->cpart);
+  if (g->cpart_host) (void)hipHostFree(g->cpart_host);
   for (auto& e : g->ev) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -954,6 +979,17 @@ void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* 
 }
 
 // ||new - old||_p / ||old||_p from fetched partials (0/0 = 0, x/0 = inf)
+// sqrt(step2) / ||old||_2 with ||old|| from the diff partials of region reg
+double cong_rel(const qc_grain* g, int reg, double step2) {
+  const double* q = g->part_host + static_cast<int64_t>(reg) * kParts;
+  double den = 0.0;
+  for (int i = 0; i < kParts; ++i) den += q[2 * i + 1];
+  const double num = std::sqrt(step2);
+  den = std::sqrt(den);
+  if (den == 0.0) return num == 0.0 ? 0.0 : INFINITY;
+  return num / den;
+}
+
 double rel_from_parts(const qc_grain* g, int reg, int p) {
   const double* q = g->part_host + static_cast<int64_t>(reg) * kParts;
   double num = 0.0, den = 0.0;
@@ -1014,8 +1050,9 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
     qc::launch_fill(g->jold, 2 * g->ncell, 0.0, st);
     // Polyak: velocities start at zero in every run; BB keeps the previous
     // iteration's difference in the same arrays
-    const bool polyak = g->accel == 1, bb = g->accel == 2;
-    if (polyak || bb) {
+    const bool polyak = g->accel == 1, bb = g->accel == 2, cong = g->accel == 3;
+    if (cong && norm_p != 2) throw std::invalid_argument("CongAcc residuals are 2-norms: norm_p must be 2");
+    if (polyak || bb || cong) {
       if (!g->vel_d) g->vel_d = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
       if (!g->vel_a) g->vel_a = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
       qc::launch_fill(g->vel_d, 2 * g->ncomp * g->ncell, 0.0, st);
@@ -1026,6 +1063,15 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
     double nscale = polyak ? 1.0 : alpha;
     double a_bb = alpha;  // BB step, alpha for the first iteration
     int i_bb = 0;
+    // CongAcc: components 2 G + (0 re, 1 im) of Delta, then A_x, A_y
+    const int ncx = 2 * g->ncomp + 2;
+    std::vector<double> cg_a(ncx, alpha), cg_w(ncx, 0.0);
+    bool cg_first = true;
+    if (cong && !g->cpart) {
+      g->cpart = static_cast<double*>(dalloc(sizeof(double) * 3 * kParts * ncx));
+      hcheck(hipHostMalloc(reinterpret_cast<void**>(&g->cpart_host), sizeof(double) * 3 * kParts * ncx),
+             "hipHostMalloc");
+    }
     const double ksc = g->kappa > 0.0 ? g->kappa * g->kappa : 1.0;  // x holds kappa^2 A
     double om_old = 0.0;
     bool have_old = false;
@@ -1046,11 +1092,24 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       do_solve_A(g, g->jcur, g->anew, nullptr, st);
       // residuals of Delta and A with their Picard steps fused in
       // (BB: norms and dot products first; the step follows once its size is known)
-      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st, !bb,
-                   alpha, polyak ? g->vel_d : nullptr);
+      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st,
+                   !bb && !cong, alpha, polyak ? g->vel_d : nullptr);
       if (have_old) enqueue_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ, st);
-      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, !bb, alpha,
+      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, !bb && !cong, alpha,
                    polyak ? g->vel_a : nullptr);
+      if (cong && !cg_first) {
+        for (int c = 0; c < ncx; ++c) {
+          double* pc = g->cpart + static_cast<int64_t>(c) * 3 * kParts;
+          if (c < 2 * g->ncomp)
+            qc::launch_congacc_dots(g->dnew, delta_io, g->grain_cells, g->ncg, static_cast<int64_t>(c / 2) * g->ncell,
+                                    2, c % 2, g->vel_d, pc, kParts, st);
+          else
+            qc::launch_congacc_dots(g->anew, A_io, nullptr, g->ncell,
+                                    static_cast<int64_t>(c - 2 * g->ncomp) * g->ncell, 1, 0, g->vel_a, pc, kParts, st);
+        }
+        hcheck(hipMemcpyAsync(g->cpart_host, g->cpart, sizeof(double) * 3 * kParts * ncx, hipMemcpyDeviceToHost, st),
+               "D2H");
+      }
       if (bb) {
         qc::launch_bb_dots(g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, g->vel_d,
                            region(g, kRBBD), kParts, st);
@@ -1079,11 +1138,46 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
         qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, a_bb, st);
         qc::launch_picard(A_io, g->anew, nullptr, 2 * g->ncell, 1, 0, 1, a_bb, st);
       }
+      // CongAcc: per-component step sizes and weights, then the step; the
+      // 2-norms of the step per field follow from the same dot products
+      double cg_step2[2] = {0.0, 0.0};
+      if (cong) {
+        for (int c = 0; c < ncx; ++c) {
+          const int f = c < 2 * g->ncomp ? 0 : 1;
+          if (cg_first) continue;
+          double mm = 0.0, md = 0.0, dd = 0.0;
+          const double* q = g->cpart_host + static_cast<int64_t>(c) * 3 * kParts;
+          for (int b = 0; b < kParts; ++b) {
+            mm += q[3 * b];
+            md += q[3 * b + 1];
+            dd += q[3 * b + 2];
+          }
+          const double sc = (mm > 0.0 && dd > 0.0) ? md / std::sqrt(mm * dd) : 0.0;
+          cg_a[c] = std::min(std::max(cg_a[c] * std::pow(kCongK, sc), kCongStepMin), kCongStepMax);
+          if (sc < kCongSmin && mm > 0.0 && dd > 0.0) cg_w[c] = congacc_weight(mm, md, dd, kCongSmin);
+          const double w = cg_w[c];
+          cg_step2[f] += cg_a[c] * cg_a[c] * (w * w * mm + 2.0 * w * (1.0 - w) * md + (1.0 - w) * (1.0 - w) * dd);
+        }
+        qc::CongCoef cd{}, ca{};
+        for (int c = 0; c < 2 * g->ncomp; ++c) {
+          cd.a[c] = cg_a[c];
+          cd.w[c] = cg_first ? 0.0 : cg_w[c];
+        }
+        for (int c = 0; c < 2; ++c) {
+          ca.a[c] = cg_a[2 * g->ncomp + c];
+          ca.w[c] = cg_first ? 0.0 : cg_w[2 * g->ncomp + c];
+        }
+        qc::launch_congacc_update(delta_io, g->dnew, g->vel_d, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, cd, st);
+        qc::launch_congacc_update(A_io, g->anew, g->vel_a, nullptr, g->ncell, 2, g->ncell, 1, ca, st);
+      }
       const double om = omega_from_parts(g);
       double res[5];
       res[0] = nscale * rel_from_parts(g, kRDiffD, norm_p);
+      if (cong && !cg_first) res[0] = cong_rel(g, kRDiffD, cg_step2[0]);
       res[1] = have_old ? rel_from_parts(g, kRDiffJ, norm_p) : INFINITY;
       res[2] = nscale * rel_from_parts(g, kRDiffA, norm_p);
+      if (cong && !cg_first) res[2] = cong_rel(g, kRDiffA, cg_step2[1]);
+      if (cong) cg_first = false;
       res[3] = (have_old && om_old != 0.0) ? std::fabs(om - om_old) / std::fabs(om_old) : INFINITY;
       res[4] = om;
       if (residuals_out) std::memcpy(residuals_out + 5 * it, res, sizeof(res));
@@ -1539,7 +1633,8 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
 
 qc_status qc_grain_set_accelerator(qc_grain* g, int kind, double beta) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
-  if (kind < 0 || kind > 2) return fail(QC_ERR_INVALID, "accelerator must be 0 (Picard), 1 (Polyak) or 2 (BB)");
+  if (kind < 0 || kind > 3)
+    return fail(QC_ERR_INVALID, "accelerator must be 0 (Picard), 1 (Polyak), 2 (BB) or 3 (CongAcc)");
   if (kind == 1 && !(beta > 0.0 && beta <= 1.0)) return fail(QC_ERR_INVALID, "Polyak drag must be in (0, 1]");
   g->accel = kind;
   g->beta = kind == 1 ? beta : 0.5;

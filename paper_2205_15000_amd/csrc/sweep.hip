@@ -896,6 +896,56 @@ __global__ void __launch_bounds__(256) bb_dots_kernel(const double* __restrict__
     for (int c = 0; c < 3; ++c) part[3 * blockIdx.x + c] = sm[c][0];
 }
 
+// CongAcc (App. E): dot products m.m, m.d, d.d of one component of x, with
+// d = xnew - xold and m the component's moving average.
+__global__ void __launch_bounds__(256) congacc_dots_kernel(const double* __restrict__ xnew,
+                                                           const double* __restrict__ xold,
+                                                           const int32_t* __restrict__ idx, int64_t n, int64_t base,
+                                                           int stride, int c, const double* __restrict__ m,
+                                                           double* __restrict__ part) {
+  __shared__ double sm[3][256];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t k = (base + (idx ? idx[i] : i)) * stride + c;
+    const double d = xnew[k] - xold[k], mv = m[k];
+    a0 += mv * mv;
+    a1 += mv * d;
+    a2 += d * d;
+  }
+  sm[0][threadIdx.x] = a0;
+  sm[1][threadIdx.x] = a1;
+  sm[2][threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int j = 0; j < 3; ++j) sm[j][threadIdx.x] += sm[j][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 3; ++j) part[3 * blockIdx.x + j] = sm[j][0];
+}
+
+// CongAcc step: m <- w m + (1 - w) d, x += a m, with d = gx - x and the
+// coefficients of component r * stride + c.
+__global__ void __launch_bounds__(256) congacc_update_kernel(double* __restrict__ x, const double* __restrict__ gx,
+                                                             double* __restrict__ m, const int32_t* __restrict__ idx,
+                                                             int64_t n, int nrep, int64_t field_stride, int stride,
+                                                             CongCoef cf) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrep) return;
+  const int64_t r = t / n, i = t - r * n;
+  const int64_t e = r * field_stride + (idx ? idx[i] : i);
+  for (int c = 0; c < stride; ++c) {
+    const int comp = static_cast<int>(r) * stride + c;
+    const int64_t k = e * stride + c;
+    const double w = cf.w[comp];
+    const double mn = w * m[k] + (1.0 - w) * (gx[k] - x[k]);
+    m[k] = mn;
+    x[k] += cf.a[comp] * mn;
+  }
+}
+
 // --------------------------------------------------------------------------
 // A-solve (App. D): zero-padded FFT correlation with the cell-averaged
 // Green's function of the 2D Laplacian
@@ -1143,6 +1193,17 @@ void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, 
 }
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(diff_norm_kernel, dim3(nparts), dim3(256), 0, st, a);
+}
+void launch_congacc_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int64_t base,
+                         int stride, int c, const double* m, double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(congacc_dots_kernel, dim3(nparts), dim3(256), 0, st, xnew, xold, idx, n, base, stride, c, m,
+                     part);
+}
+void launch_congacc_update(double* x, const double* gx, double* m, const int32_t* idx, int64_t n, int nrep,
+                           int64_t field_stride, int stride, const CongCoef& cf, hipStream_t st) {
+  if (n * nrep > 0)
+    hipLaunchKernelGGL(congacc_update_kernel, dim3(nblk(n * nrep)), dim3(256), 0, st, x, gx, m, idx, n, nrep,
+                       field_stride, stride, cf);
 }
 void launch_bb_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
                     int64_t field_stride, int stride, double scale, double* dprev, double* part, int nparts,

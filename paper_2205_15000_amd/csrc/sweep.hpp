@@ -245,6 +245,18 @@ void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream
 void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,
                       hipStream_t st);
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st);
+// CongAcc (App. E): per-component step sizes and weights of one field
+constexpr int kCongMaxComp = 8;
+struct CongCoef {
+  double a[kCongMaxComp], w[kCongMaxComp];
+};
+// partials [nparts][3] of m.m, m.d, d.d over component c of the elements
+// (base + idx[i] or base + i) * stride + c, d = xnew - xold
+void launch_congacc_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int64_t base,
+                         int stride, int c, const double* m, double* part, int nparts, hipStream_t st);
+// m <- w m + (1 - w) d, x += a m with the coefficients of component r * stride + c
+void launch_congacc_update(double* x, const double* gx, double* m, const int32_t* idx, int64_t n, int nrep,
+                           int64_t field_stride, int stride, const CongCoef& cf, hipStream_t st);
 // partials [nparts][3] of dp.dp, dp.(d - dp), (d - dp).(d - dp), d = scale (xnew - xold); dprev <- d
 void launch_bb_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int nrep,
                     int64_t field_stride, int stride, double scale, double* dprev, double* part, int nparts,

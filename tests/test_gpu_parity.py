@@ -253,6 +253,37 @@ def test_scf_barzilai_borwein_matches_oracle():
     g.close()
 
 
+def test_scf_congacc_matches_oracle():
+    """CongAcc (App. E) per component, with the A-solve, FP64, against the
+    oracle: 10 iterations after a burn-in on one grain, 5 on a two-component
+    grain.  On the latter the moving average of each A component turns
+    exactly opposite to its difference at the sixth iteration; no weight then
+    reaches the minimum similarity, the bisection lands where the average
+    vanishes, and later similarities of rounding-level vectors decide the
+    steps differently on the two sides."""
+    qs = _qs()
+    for name, n_it in (("small_d110_field", 10), ("small_holed_mixed", 5)):
+        sp = wl.spec(name)
+        _note("case %s: %d CongAcc iterations, fp64" % (name, n_it))
+        g = qs.Grain(sp, "fp64")
+        g.set_accelerator("congacc")
+        og = oracle_grain(sp)
+        d0 = wl.initial_delta(name, sp)
+        a0 = wl.initial_A(name, sp)
+        m = og.mask
+        dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+        it, res, conv = g.scf(dd, ad, n_it, alpha=0.5, burnin=1)
+        dref, aref, hist, _ = oscf.scf(og, d0, a0, n_it, alpha=0.5, burnin=1, accelerator="congacc")
+        assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
+        assert _close(ad.cpu().numpy(), aref, FP64_TOL)
+        h = np.array(hist)
+        fin = np.isfinite(h)
+        assert np.max(np.abs(res[fin] - h[fin]) / np.maximum(np.abs(h[fin]), 1e-12)) < 1e-8
+        with pytest.raises(qs.QcError):
+            g.scf(dd, ad, 2, norm_p=1)
+        g.close()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 2e-4)])
 def test_ldos_matches_oracle(precision, tol):
     qs = _qs()
