@@ -328,6 +328,8 @@ def bb_step_size(alpha, d, d_prev, i, amin=BB_STEP_MIN, amax=BB_STEP_MAX):
 # App. E's CongAcc defaults: first step, step factor k, minimum similarity,
 # step bounds
 CONG_STEP, CONG_K, CONG_SMIN, CONG_STEP_MIN, CONG_STEP_MAX = 0.5, 1.234, 0.7, 1e-3, 1e2
+# Similarities at or below -1 + CONG_ANTI count as anti-parallel m and d.
+CONG_ANTI = 1e-9
 
 
 def similarity_weight(mm, md, dd, smin, n_bisect=60):
@@ -348,26 +350,42 @@ def similarity_weight(mm, md, dd, smin, n_bisect=60):
     return 0.5 * (lo + hi)
 
 
-def congacc_component(m, d, alpha, w, first, k=CONG_K, smin=CONG_SMIN, amin=CONG_STEP_MIN, amax=CONG_STEP_MAX):
+def congacc_component(m, d, alpha, w, first, k=CONG_K, smin=CONG_SMIN, amin=CONG_STEP_MIN, amax=CONG_STEP_MAX,
+                      stats=None):
     """CongAcc (App. E) for one component c of x (the real or imaginary part
     of one order-parameter component, or one component of A): the cosine
     similarity s of the moving average m with the difference d scales the
     step, alpha <- alpha k^s (clamped); the weight w is kept while s >= smin
     and otherwise replaced by similarity_weight; m <- w m + (1 - w) d.  The
     first iteration takes w = 0 (so m = d) and keeps alpha; a similarity
-    with a zero vector is read as 0.  Returns (m_next, alpha_next, w_next);
-    the step is x <- x + alpha_next m_next."""
+    with a zero vector is read as 0.
+    When m and d are anti-parallel (s <= -1 + CONG_ANTI) the blend
+    w m + (1 - w) d is a multiple of d that changes sign at one weight: its
+    similarity with d jumps from 1 to -1 there, so the equation for w* has
+    no root, and a bisection would stop where the blend vanishes.  That
+    case takes w = 0: the average restarts from d (and alpha has just
+    shrunk by k^-1).
+    stats (a dict, optional) counts the weights set by bisection ("bisect")
+    and by the anti-parallel rule ("anti").  Returns (m_next, alpha_next,
+    w_next); the step is x <- x + alpha_next m_next."""
     if first:
         return d.copy(), alpha, 0.0
     mm, md, dd = float(np.dot(m, m)), float(np.dot(m, d)), float(np.dot(d, d))
     s = md / math.sqrt(mm * dd) if mm > 0.0 and dd > 0.0 else 0.0
     alpha = min(max(alpha * k ** s, amin), amax)
     if s < smin and mm > 0.0 and dd > 0.0:
-        w = similarity_weight(mm, md, dd, smin)
+        if s <= -1.0 + CONG_ANTI:
+            w = 0.0
+            key = "anti"
+        else:
+            w = similarity_weight(mm, md, dd, smin)
+            key = "bisect"
+        if stats is not None:
+            stats[key] = stats.get(key, 0) + 1
     return w * m + (1.0 - w) * d, alpha, w
 
 
-def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator="picard", beta=0.5):
+def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator="picard", beta=0.5, stats=None):
     """Self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on grain
     cells, kappa^2 A_ind on all cells), with A from the current of the same
     iteration (App. D).  accelerator "picard": x <- x + alpha (g(x) - x);
@@ -379,13 +397,23 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
     "congacc": per component of x (congacc_component), alpha the first step
     of every component; kappa^2 drops out again.  During the first `burnin`
     iterations Delta and A stay fixed and only the boundary values update
-    (App. B).  Returns the final fields and the per-iteration history of
-    (eps_Delta, eps_j, eps_A, eps_Omega, Omega)."""
+    (App. B).
+    Convergence is checked before the accelerator moves x (Alg. 1): eps_Delta
+    and eps_A are Eq. global_error of g(x) against x, i.e. ||d|| / ||x|| per
+    field; eps_j and eps_Omega compare with the previous iteration.
+    kappa <= 0 (no screening) has no induced vector potential: A_ind is set
+    to zero before the first sweep and stays zero (eps_A = 0).
+    stats: optional dict passed to congacc_component; it also collects the
+    components whose weight was bisected ("bisect_components").  Returns the final
+    fields, the per-iteration history of (eps_Delta, eps_j, eps_A,
+    eps_Omega, Omega) and the boundary values of the last sweep."""
     if accelerator not in ("picard", "polyak", "bb", "congacc"):
         raise ValueError("unknown accelerator %r" % (accelerator,))
     ny, nx = grain.grid.ny, grain.grid.nx
     delta = np.array(delta, dtype=np.complex128).reshape(grain.ncomp, ny, nx)
     A = np.array(A_ind, dtype=np.float64).reshape(2, ny, nx)
+    if grain.kappa <= 0.0:
+        A[:] = 0.0
     m = grain.mask
     bc = None
     hist = []
@@ -419,7 +447,10 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
             d_new = delta.copy()
             A_next = A.copy()
             for c, dc in enumerate(parts):
-                mc, ac, wc = congacc_component(cg[0][c], dc, cg[1][c], cg[2][c], cg_first)
+                nb = stats.get("bisect", 0) if stats is not None else 0
+                mc, ac, wc = congacc_component(cg[0][c], dc, cg[1][c], cg[2][c], cg_first, stats=stats)
+                if stats is not None and stats.get("bisect", 0) > nb:
+                    stats.setdefault("bisect_components", set()).add(c)
                 cg[0][c], cg[1][c], cg[2][c] = mc, ac, wc
                 step = ac * mc
                 if c < 2 * grain.ncomp:
@@ -443,8 +474,8 @@ def scf(grain, delta, A_ind, n_iter, alpha=1.0, burnin=0, norm_p=2, accelerator=
             d_new = delta + alpha * (out["delta_new"] - delta)
             A_next = A + alpha * (A_new - A)
         d_new[:, ~m] = 0.0
-        e_d = rel_norm(d_new[:, m], delta[:, m], norm_p)
-        e_a = rel_norm(A_next, A, norm_p)
+        e_d = rel_norm(out["delta_new"][:, m], delta[:, m], norm_p)
+        e_a = rel_norm(A_new, A, norm_p)
         e_j = rel_norm(j, j_old, norm_p) if j_old is not None else math.inf
         e_o = abs(om - om_old) / abs(om_old) if (om_old is not None and om_old != 0.0) else math.inf
         hist.append((e_d, e_j, e_a, e_o, om))

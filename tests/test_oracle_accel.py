@@ -156,3 +156,79 @@ def test_congacc_on_the_bcs_fixed_point_stays_put():
     delta = np.where(gr.mask, dbulk, 0)[None].astype(complex)
     d1, a1, _, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 3, accelerator="congacc", alpha=0.5)
     assert np.max(np.abs(d1[0][gr.mask] - dbulk)) < 1e-12
+
+
+def test_congacc_anti_parallel_average_restarts_from_d():
+    """m exactly opposite to d: the blend w m + (1 - w) d is (1 - w(1 + c)) d
+    for m = -c d, so its similarity with d is +1 below w = 1/(1 + c) and -1
+    above, and no weight gives s_min.  A bisection on the similarity stops
+    where the blend vanishes (its norm falls to rounding level, which froze
+    the component in the earlier rule); the rule takes w = 0 instead, so the
+    average restarts from d and the step shrinks by k^-1."""
+    d = np.array([0.3, -1.1, 0.7, 2.0])
+    m = -0.4 * d
+    mm, md, dd = m @ m, m @ d, d @ d
+    w_bis = scf.similarity_weight(mm, md, dd, scf.CONG_SMIN)
+    blend = w_bis * m + (1 - w_bis) * d
+    assert np.linalg.norm(blend) < 1e-6 * np.linalg.norm(d)   # the collapse the rule avoids
+    st = {}
+    m1, a1, w1 = scf.congacc_component(m, d, 0.8, 0.35, False, stats=st)
+    assert w1 == 0.0 and np.array_equal(m1, d)
+    assert abs(a1 - 0.8 / scf.CONG_K) < 1e-15
+    assert st == {"anti": 1}
+    # nearly but not exactly opposite: the equation has its root again and
+    # the bisection sets the weight
+    e = np.array([1.0, 0.5, 0.2, -0.1])
+    e -= (e @ d) / dd * d
+    mb = -0.4 * d + 1e-3 * e
+    st = {}
+    m2, a2, w2 = scf.congacc_component(mb, d, 0.8, 0.35, False, stats=st)
+    assert st == {"bisect": 1} and 0.0 < w2 < 1.0
+    assert abs(m2 @ d / np.sqrt((m2 @ m2) * dd) - scf.CONG_SMIN) < 1e-9
+
+
+def test_congacc_collinear_component_converges_to_its_fixed_point():
+    """A component whose map is g(x) = 0 (every d, m and x are multiples of
+    one vector): with alpha growing by k per iteration the steps overshoot,
+    m turns exactly opposite to d, and the earlier bisection rule froze x at
+    a nonzero value with a step of rounding size.  With the anti-parallel
+    rule x keeps shrinking toward the fixed point 0."""
+    x0 = np.array([0.2, -0.5, 0.1])
+    x = x0.copy()
+    m, a, w, first = None, 0.5, 0.0, True
+    st = {}
+    for _ in range(40):
+        d = -x
+        m, a, w = scf.congacc_component(m, d, a, w, first, stats=st)
+        first = False
+        x = x + a * m
+    assert st.get("anti", 0) >= 1
+    assert np.linalg.norm(x) < 1e-6 * np.linalg.norm(x0)
+
+
+def test_scf_residual_is_checked_before_the_step():
+    """Alg. 1 checks Eq. global_error after the A-solve and before the
+    accelerator: eps_Delta = ||g(x) - x|| / ||x||, whatever step is then
+    taken.  A Picard run with alpha = 0.3 reports the same first eps_Delta
+    as one with alpha = 1 (both start from the same x)."""
+    gr = _cfg1_like()
+    rng = np.random.default_rng(3)
+    delta = np.where(gr.mask, 0.25 * (1 + 0.05 * rng.uniform(-1, 1, gr.mask.shape)), 0)[None].astype(complex)
+    _, _, h1, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 1, alpha=1.0)
+    _, _, h3, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 1, alpha=0.3)
+    out = gr.iterate(delta, np.zeros((2, 32, 32)))
+    m = gr.mask
+    ref = np.linalg.norm(out["delta_new"][:, m] - delta[:, m]) / np.linalg.norm(delta[:, m])
+    assert abs(h1[0][0] - ref) < 1e-14 and abs(h3[0][0] - ref) < 1e-14
+
+
+def test_scf_without_screening_holds_A_at_zero():
+    """kappa <= 0: no induced vector potential; a nonzero A given to the
+    SCF is dropped before the first sweep."""
+    gr = _cfg1_like()
+    delta = np.where(gr.mask, 0.25, 0)[None].astype(complex)
+    A0 = 0.01 * np.ones((2, 32, 32))
+    d1, a1, h, _ = scf.scf(gr, delta, A0, 2, accelerator="congacc", alpha=0.5)
+    d2, _, _, _ = scf.scf(gr, delta, np.zeros((2, 32, 32)), 2, accelerator="congacc", alpha=0.5)
+    assert np.array_equal(a1, np.zeros((2, 32, 32))) and all(r[2] == 0.0 for r in h)
+    assert np.array_equal(d1, d2)

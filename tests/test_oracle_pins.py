@@ -1,0 +1,267 @@
+"""Further pins of the oracle: the external gauges, the LDOS post-process,
+the gauge covariance of the whole map with an induced vector potential, the
+continuity equation, the sampled-cell evaluation, and closed-form segment
+end points of the trajectory tables."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geometry as geo, sweep, scf, bulk, fields
+
+
+# --------------------------------------------------- external field (App. F)
+@pytest.mark.parametrize("gauge", ["symmetric", "landau"])
+def test_uniform_gauges_have_the_flux_density_of_the_unit_table(gauge):
+    """alpha flux quanta through the area A give B = alpha Phi0 / A; with
+    B0 = Phi0 / (pi xi0^2) that is pi alpha / A.  Both linear gauges have
+    this curl everywhere (central differences are exact on linear fields),
+    and the line integral around a circle is B times its area."""
+    area, alpha, cx, cy = 37.5, 1.7, 0.3, -0.2
+    h = 0.25
+    x = cx + (np.arange(40) - 19.5) * h
+    X, Y = np.meshgrid(x, x)
+    ax, ay = fields.external_A(gauge, alpha, area, cx, cy, X, Y)
+    b = fields.curl(ax, ay, h)
+    assert np.max(np.abs(b[1:-1, 1:-1] - math.pi * alpha / area)) < 1e-12
+    th = np.linspace(0, 2 * math.pi, 4001)[:-1]
+    R = 2.0
+    px, py = cx + R * np.cos(th), cy + R * np.sin(th)
+    qx, qy = fields.external_A(gauge, alpha, area, cx, cy, px, py)
+    circ = np.sum(qx * (-np.sin(th)) + qy * np.cos(th)) * R * (2 * math.pi / len(th))
+    assert abs(circ - math.pi * alpha / area * math.pi * R * R) < 1e-12
+
+
+def test_solenoid_gauge_is_curl_free_and_encloses_alpha_quanta():
+    """The solenoid field alpha/(2r) phi-hat: zero curl off the centre, and
+    a line integral of pi alpha (alpha flux quanta in units of A0 xi0 =
+    Phi0/pi) around any loop that encloses the centre, zero otherwise."""
+    alpha = 0.8
+    errs = []
+    for h in (0.1, 0.05):
+        n = int(round(2.0 / h)) + 1
+        x = 3.0 + (np.arange(n) - (n - 1) / 2) * h      # a patch away from the centre
+        X, Y = np.meshgrid(x, x - 2.0)
+        ax, ay = fields.external_A("solenoid", alpha, 10.0, 0.0, 0.0, X, Y)
+        b = fields.curl(ax, ay, h)
+        errs.append(np.max(np.abs(b[1:-1, 1:-1])))
+    # the central differences of a curl-free field: O(h^2) remainder only
+    assert errs[1] < 1e-3 * alpha and 3.5 < errs[0] / errs[1] < 4.5, errs
+    th = np.linspace(0, 2 * math.pi, 2001)[:-1]
+    for (ox, oy, R, inside) in ((0.4, -0.3, 1.5, True), (3.0, 1.0, 1.0, False)):
+        px, py = ox + R * np.cos(th), oy + R * np.sin(th)
+        qx, qy = fields.external_A("solenoid", alpha, 10.0, 0.0, 0.0, px, py)
+        circ = np.sum(qx * (-np.sin(th)) + qy * np.cos(th)) * R * (2 * math.pi / len(th))
+        assert abs(circ - (math.pi * alpha if inside else 0.0)) < 1e-9
+
+
+# ----------------------------------------------------- LDOS (Sec. II, App. B)
+def _bcs_dos(e, broad, d):
+    z = e + 1j * broad
+    s = np.sqrt(z * z - d * d + 0j)
+    s = np.where(s.imag < 0, -s, s)              # retarded branch, Im s > 0
+    return (z / s).real
+
+
+@pytest.mark.parametrize("bc_iters", [0, 2])
+def test_ldos_of_a_uniform_s_wave_grain_is_the_bcs_density_of_states(bc_iters):
+    """A uniform s-wave gap with no field: the bulk root is left unchanged
+    by every step and by specular reflection, so every grain cell carries the
+    bulk density of states N/N_F = Re[z / sqrt(z^2 - |Delta|^2)] with
+    z = e + i delta, for any number of burn-in sweeps."""
+    gr = scf.Grain(22, 22, 0.6, [geo.Disc(0.1, -0.2, 6.0)], 12, 4, 0.5)
+    d0 = 0.26 * np.exp(0.7j)
+    delta = np.where(gr.mask, d0, 0)[None]
+    e = np.array([-0.5, -0.2, 0.0, 0.1, 0.25, 0.27, 0.4])
+    broad = 0.02
+    out = gr.ldos(delta, np.zeros((2, 22, 22)), e, broad, bc_iters)
+    ref = _bcs_dos(e, broad, abs(d0))
+    assert np.max(np.abs(out[:, gr.mask] - ref[:, None])) < 1e-12
+    assert np.all(out[:, ~gr.mask] == 0.0)
+
+
+def test_ldos_zero_energy_peak_on_a_110_edge_needs_the_burn_in():
+    """d-wave with [110] edges: every reflection changes the sign of the gap,
+    and the converged boundary values give N(0)/N_F = sqrt(|D_phi|^2 +
+    delta^2)/delta on each trajectory at the wall.  A wall cell sits within a
+    cell of the wall, so its angle average approaches <sqrt(|D_phi|^2 +
+    delta^2)>/delta (bounded above by it); without burn-in the starts are
+    bulk roots and the cell shows the gapped bulk value instead."""
+    t, npol, nth = 0.1, 4, 16
+    gr = scf.Grain(40, 40, 0.3, [geo.regular_polygon(0, 0, 4, 11.7)], nth, npol, t,
+                   components=(("dx2y2", 1.0),), crystal_rotation=0.125)
+    d0 = 0.25
+    delta = np.where(gr.mask, d0, 0)[None].astype(complex)
+    broad = 0.08
+    X, Y = gr.grid.centres()
+    # grain cells next to the middle of the bottom edge
+    row = np.nonzero(gr.mask.any(axis=1))[0][0]
+    cols = np.nonzero(gr.mask[row] & (np.abs(X[row]) < 1.5))[0]
+    zes = np.sum(gr.wk * np.sqrt((d0 * np.abs(gr.eta[0])) ** 2 + broad ** 2)) / broad
+    bulk_v = np.sum(gr.wk * broad / np.sqrt((d0 * np.abs(gr.eta[0])) ** 2 + broad ** 2))
+    n0 = gr.ldos(delta, np.zeros((2, 40, 40)), [0.0], broad, 0)[0, row, cols]
+    n8 = gr.ldos(delta, np.zeros((2, 40, 40)), [0.0], broad, 8)[0, row, cols]
+    assert np.all(n8 > 0.6 * zes) and np.all(n8 < 1.02 * zes), (n8, zes)
+    assert np.all(n0 < 0.5 * n8), (n0, n8, bulk_v)
+
+
+# ----------------------------------- gauge covariance with A_ind (Sec. V.A)
+def _gauge_case(h, shift):
+    """Disc grain with a smooth complex gap, a smooth induced A and an
+    external solenoid field; shift = 0 or 1 applies the gauge
+    transformation Delta -> Delta e^{i L}, A_ind -> A_ind + (q/2) grad L."""
+    R = 5.2
+    n = int(round(2 * (R + 0.8) / h))
+    gr = scf.Grain(n, n, h, [geo.Disc(0.0, 0.0, R)], 16, 4, 0.5, components=(("s", 1.0),),
+                   kappa=3.0, flux_quanta=0.3, gauge="solenoid")
+    X, Y = gr.grid.centres()
+    delta = (0.24 + 0.03 * np.cos(0.5 * X) + 0.02j * np.sin(0.4 * Y)) * np.exp(0.15j * X)
+    A = np.stack([0.03 * np.sin(0.3 * Y + 0.2), 0.02 * np.cos(0.25 * X)])
+    lam = 0.35 * X - 0.2 * Y + 0.3 * np.sin(0.4 * X + 0.3 * Y)
+    glx = 0.35 + 0.12 * np.cos(0.4 * X + 0.3 * Y)
+    gly = -0.2 + 0.09 * np.cos(0.4 * X + 0.3 * Y)
+    if shift:
+        delta = delta * np.exp(1j * lam)
+        A = A + 0.5 * gr.q * np.stack([glx, gly])
+    delta = np.where(gr.mask, delta, 0)[None]
+    return gr, delta, A, lam
+
+
+def _frozen_iterations(gr, delta, A, n):
+    bc = None
+    for _ in range(n):
+        o = gr.iterate(delta, A, bc)
+        bc = o["bc"]
+    return o
+
+
+def test_gauge_transformation_with_induced_field_is_covariant_to_second_order():
+    """(Delta e^{iL}, A_ind + (q/2) grad L) gives Delta_new e^{iL} with the
+    same j and free-energy density: exact for the continuum equations,
+    O(h^2) for the discrete map (bilinear interpolation of the phase, and
+    the boundary taps between lines), after the boundary values have
+    forgotten the bulk-root starts (frozen fields, several sweeps).  This
+    exercises the clamped bilinear A_ind stencil and the q v.A term of z: a
+    wrong sign or factor there breaks the covariance at O(1)."""
+    errs = []
+    for h in (0.5, 0.25):
+        res = []
+        for shift in (0, 1):
+            gr, d, A, lam = _gauge_case(h, shift)
+            res.append(_frozen_iterations(gr, d, A, 4))
+        o0, o1 = res
+        m = gr.mask
+        X, Y = gr.grid.centres()
+        inner = m & (np.hypot(X, Y) < 3.5)
+        dn0 = o0["delta_new"][0] * np.exp(1j * lam)
+        e_d = np.max(np.abs(o1["delta_new"][0] - dn0)[inner]) / np.max(np.abs(dn0[m]))
+        e_j = np.max(np.abs(o1["j"] - o0["j"])[:, inner]) / np.max(np.abs(o0["j"][:, m]))
+        errs.append((e_d, e_j))
+    (d1, j1), (d2, j2) = errs
+    # h = 0.5 / 0.25 / 0.125 give 1.5e-2 / 4.1e-3 / 1.3e-3 (Delta_new) and
+    # 1.6e-2 / 5.3e-3 / 2.0e-3 (j)
+    assert d2 < 6e-3 and j2 < 8e-3, errs
+    assert d1 / d2 > 3.0 and j1 / j2 > 2.5, errs
+
+
+def test_wrong_charge_in_the_gauge_shift_is_not_covariant():
+    """Control for the test above: the opposite shift of A breaks it."""
+    h = 0.5
+    gr, d0_, A0, lam = _gauge_case(h, 0)
+    _, d1_, A1, _ = _gauge_case(h, 1)
+    A_bad = 2 * A0 - A1                          # A_ind - (q/2) grad L
+    o0 = _frozen_iterations(gr, d0_, A0, 4)
+    o1 = _frozen_iterations(gr, d1_, A_bad, 4)
+    m = gr.mask
+    X, Y = gr.grid.centres()
+    inner = m & (np.hypot(X, Y) < 3.5)
+    e_j = np.max(np.abs(o1["j"] - o0["j"])[:, inner]) / np.max(np.abs(o0["j"][:, m]))
+    assert e_j > 0.2
+
+
+# ------------------------------------------- continuity equation (Sec. II)
+def test_current_divergence_equals_the_gap_equation_source():
+    """Along a trajectory the Riccati equations give v.grad g = i(D f~ - D* f)
+    (z drops out), so for any Delta and A the current of Eq. current_density
+    and the gap-equation numerator of Eq. gapeq_fixpoint obey
+      div j = 4 q sum_G den_G Im(conj(Delta_G) Delta_G,new)
+    at every point, per angle and pole; it vanishes at self-consistency
+    (current conservation).  The discrete map satisfies it to O(h^2): the
+    residual falls about fourfold when h halves."""
+    res = []
+    for h in (0.4, 0.2):
+        R = 5.0
+        n = int(round(2 * (R + 0.6) / h))
+        gr = scf.Grain(n, n, h, [geo.Disc(0.0, 0.0, R)], 16, 4, 0.5, components=(("s", 1.0),),
+                       kappa=2.0, flux_quanta=0.0)
+        X, Y = gr.grid.centres()
+        delta = np.where(gr.mask, (0.22 + 0.04 * np.cos(0.6 * X) * np.sin(0.5 * Y)) * np.exp(0.25j * X + 0.1j * Y),
+                         0)[None]
+        A = np.stack([0.04 * np.sin(0.3 * Y), 0.03 * np.cos(0.35 * X)])
+        o = _frozen_iterations(gr, delta, A, 3)
+        jx, jy = o["j"]
+        div = np.zeros_like(jx)
+        div[1:-1, 1:-1] = (jx[1:-1, 2:] - jx[1:-1, :-2] + jy[2:, 1:-1] - jy[:-2, 1:-1]) / (2 * h)
+        src = 4 * gr.q * gr.gap_denominator()[0] * np.imag(np.conj(delta[0]) * o["delta_new"][0])
+        inner = gr.mask & (np.hypot(X, Y) < 3.0)
+        scale = np.max(np.abs(src[inner]))
+        res.append((np.max(np.abs(div - src)[inner]) / scale, scale))
+    (r1, s1), (r2, s2) = res
+    assert s1 > 1e-3
+    assert r2 < 2e-2 and r1 / r2 > 3.0, res
+
+
+# --------------------------------------------- sampled cells (full sizes)
+def test_iterate_cells_equals_the_full_map_at_its_cells():
+    """iterate_cells sweeps only the segments feeding the sampled cells; from
+    bulk starts it must give the full map's values there."""
+    gr = scf.Grain(26, 24, 0.5, [geo.Disc(0.2, 0.1, 5.8), geo.regular_polygon(1.0, -0.5, 4, 2.5, 0.1, add=False)],
+                   12, 5, 0.4, components=(("s", 1.0), ("dxy", 0.7)), kappa=2.0, flux_quanta=0.6)
+    rng = np.random.default_rng(8)
+    X, Y = gr.grid.centres()
+    delta = np.stack([0.22 * np.exp(-1j * np.arctan2(Y - 0.4, X + 0.3)), 0.05 * np.exp(0.3j * X)])
+    delta = np.where(gr.mask[None], delta + 0.01 * rng.standard_normal(delta.shape), 0)
+    A = np.stack([0.03 * np.sin(0.4 * Y), 0.02 * np.cos(0.3 * X)])
+    full = gr.iterate(delta, A)
+    cells = np.sort(rng.choice(np.flatnonzero(gr.mask), 30, replace=False))
+    dn, j = gr.iterate_cells(delta, A, cells)
+    scale = np.max(np.abs(full["delta_new"]))
+    assert np.max(np.abs(dn - full["delta_new"].reshape(2, -1)[:, cells])) < 1e-13 * scale
+    assert np.max(np.abs(j - full["j"].reshape(2, -1)[:, cells])) < 1e-13 * np.max(np.abs(full["j"]))
+
+
+# ----------------------------------- trajectory end points (Sec. III.A)
+@pytest.mark.parametrize("phi", [0.0, 0.37, 1.2, 2.9])
+def test_disc_segment_ends_are_the_chord_ends(phi):
+    """A line at distance u from the centre of a disc of radius R meets it
+    at s = s_c +- sqrt(R^2 - u^2) (s_c the foot of the centre on the line)."""
+    grid = geo.Grid(30, 30, 0.5)
+    cx, cy, R = 0.4, -0.3, 6.1
+    tab = geo.AngleTable(grid, [geo.Disc(cx, cy, R)], phi)
+    ex, ey = math.cos(phi), math.sin(phi)
+    for s in range(tab.nseg):
+        px, py = tab.point(tab.seg_line[s], 0.0)
+        # offset of the line from the disc centre, and the foot's parameter
+        dx, dy = cx - px, cy - py
+        sc = dx * ex + dy * ey
+        u2 = dx * dx + dy * dy - sc * sc
+        half = math.sqrt(R * R - u2)
+        assert abs(tab.smin[s] - (sc - half)) < 1e-10 and abs(tab.smax[s] - (sc + half)) < 1e-10
+
+
+@pytest.mark.parametrize("phi", [0.21, 0.9, 2.2])
+def test_square_segment_ends_are_the_edge_crossings(phi):
+    """An axis-aligned square [-a, a]^2 crossed by the line p + s e: the
+    inside interval is the intersection of the slabs |p_x + s e_x| <= a and
+    |p_y + s e_y| <= a."""
+    grid = geo.Grid(28, 28, 0.5)
+    a = 5.3
+    tab = geo.AngleTable(grid, [geo.regular_polygon(0.0, 0.0, 4, 2 * a)], phi)
+    ex, ey = math.cos(phi), math.sin(phi)
+    for s in range(tab.nseg):
+        px, py = tab.point(tab.seg_line[s], 0.0)
+        lo, hi = -math.inf, math.inf
+        for p, e in ((px, ex), (py, ey)):
+            t1, t2 = (-a - p) / e, (a - p) / e
+            lo, hi = max(lo, min(t1, t2)), min(hi, max(t1, t2))
+        assert abs(tab.smin[s] - lo) < 1e-10 and abs(tab.smax[s] - hi) < 1e-10
