@@ -245,6 +245,71 @@ class Grain:
         den = self.gap_denominator()
         return num / den[:, None], np.stack([jx, jy])
 
+    # -- Luttinger-Ward free energy (Sec. II) ------------------------------
+    def condensation_base(self, delta):
+        """The terms of the free-energy density (Eq. qcLWFE) before the
+        propagator term: sum_G |Delta_G|^2 ln(t/t_c,G) + pi T sum_n
+        <|Delta(p)|^2>/|e_n|, the latter as 2 pi sum_p R_p/z_p times the
+        quadrature mean of |sum_G eta_G(phi_k) Delta_G|^2.  [ny, nx], zero
+        off the grain."""
+        ny, nx = self.grid.ny, self.grid.nx
+        delta = np.asarray(delta, dtype=np.complex128).reshape(self.ncomp, ny, nx)
+        m = self.mask
+        dcell = delta[:, m]
+        d2avg = np.zeros(dcell.shape[1])
+        for k in range(self.n_theta):
+            dk = np.tensordot(self.eta[:, k], dcell, axes=(0, 0))
+            d2avg += self.wk[k] * (dk * np.conj(dk)).real
+        out = np.zeros((ny, nx))
+        out[m] = (np.sum((dcell * np.conj(dcell)).real * np.log(self.t / self.tc)[:, None], axis=0)
+                  + 2.0 * math.pi * np.sum(self.rp / self.zp) * d2avg)
+        return out
+
+    def free_energy_lw(self, delta, A_ind, n_lambda, bc_iters):
+        """Luttinger-Ward form of the free energy (Eqs. qcLWFE and
+        qcLWFE_I): the propagator term is
+          I(R) = int_0^1 dlambda T sum_n <Delta*(p,R) f_lambda + Delta(p,R) f~_lambda>,
+        with f_lambda, f~_lambda the propagators of the Eilenberger equation
+        solved with the scaled gap lambda Delta (A unscaled).  With f(-e) =
+        f~(e)* the sum over both signs of e_n is twice the real part of the
+        positive poles', and <Delta*(p) t~ sum_p R_p (f + conj f~)> =
+        sum_G conj(Delta_G) Num_G, with Num_G the gap numerator of
+        Eq. gapeq_fixpoint; so per lambda
+          I_lambda(R) = 2 sum_G den_G Re[conj(Delta_G(R)) Delta_new,G[lambda Delta](R)].
+        Readings: Delta and the propagators meet at the reference cell
+        (after the rotate-back, as in the gap update); the lambda integral
+        is Gauss-Legendre with n_lambda nodes on [0, 1]; for each lambda the
+        boundary values start from the bulk roots of lambda Delta and take
+        bc_iters burn-in sweeps (App. B) before the sweep that is used.
+        Returns (omega_density [ny, nx], omega_total) with the magnetic term
+        h^2 sum (kappa^2/2)|B_ind|^2 as in the Eilenberger form."""
+        ny, nx = self.grid.ny, self.grid.nx
+        delta = np.asarray(delta, dtype=np.complex128).reshape(self.ncomp, ny, nx)
+        A_ind = np.asarray(A_ind, dtype=np.float64).reshape(2, ny, nx)
+        m = self.mask
+        den = self.gap_denominator()
+        x, w = np.polynomial.legendre.leggauss(int(n_lambda))
+        lam = 0.5 * (x + 1.0)
+        wl = 0.5 * w
+        integral = np.zeros((ny, nx))
+        for lv, wv in zip(lam, wl):
+            dl = lv * delta
+            bc = None
+            for _ in range(int(bc_iters)):
+                bc = self.iterate(dl, A_ind, bc)["bc"]
+            dn = self.iterate(dl, A_ind, bc)["delta_new"]
+            term = np.zeros((ny, nx))
+            for c in range(self.ncomp):
+                term += 2.0 * den[c] * (np.conj(delta[c]) * dn[c]).real
+            integral += wv * term
+        om = self.condensation_base(delta) - np.where(m, integral, 0.0)
+        h = self.grid.h
+        total = h * h * om.sum()
+        if self.kappa > 0.0:
+            b = fields.curl(A_ind[0], A_ind[1], h)
+            total += h * h * np.sum(0.5 * self.kappa ** 2 * b * b)
+        return om, total
+
     # -- LDOS ---------------------------------------------------------------
     def ldos(self, delta, A_ind, energies, broadening, bc_iters):
         """Angle-averaged local density of states N(R, e)/N_F =

@@ -265,3 +265,62 @@ def test_square_segment_ends_are_the_edge_crossings(phi):
             t1, t2 = (-a - p) / e, (a - p) / e
             lo, hi = max(lo, min(t1, t2)), min(hi, max(t1, t2))
         assert abs(tab.smin[s] - lo) < 1e-10 and abs(tab.smax[s] - hi) < 1e-10
+
+
+# ------------------------------- Luttinger-Ward free energy (Sec. II)
+@pytest.mark.parametrize("bc_iters", [0, 1])
+def test_luttinger_ward_form_of_a_uniform_s_wave_state_is_the_bulk_free_energy(bc_iters):
+    """In a uniform s-wave state f_lambda = pi lambda Delta/sqrt(e^2 +
+    lambda^2 |Delta|^2), so int_0^1 dlambda (Delta* f_lambda + Delta
+    f~_lambda) = 2 pi (Omega_n - |e_n|) and Eq. qcLWFE becomes
+    |D|^2 ln t + pi T sum_n |D|^4 / (|e_n| (Omega_n + |e_n|)^2) (Eq. FEbulk):
+    -0.020601374 at t = 0.5 with 16 poles at the BCS gap.  The integrand is
+    analytic in lambda, so 12 Gauss-Legendre nodes reach rounding level; 4
+    do not."""
+    gr = scf.Grain(32, 32, 0.625, [geo.Disc(0, 0, 10)], 32, 16, 0.5)
+    db = bulk.bulk_gap(0.5, 16)
+    delta = np.where(gr.mask, db * np.exp(0.3j), 0)[None]
+    ref = bulk.bulk_free_energy(db, 0.5, 16)
+    assert abs(ref + 0.020601374) < 1e-9
+    om, tot = gr.free_energy_lw(delta, np.zeros((2, 32, 32)), 12, bc_iters)
+    assert np.max(np.abs(om[gr.mask] - ref)) < 1e-14
+    assert np.all(om[~gr.mask] == 0.0)
+    assert abs(tot - gr.area * ref) < 1e-12 * abs(gr.area * ref)
+    om4, _ = gr.free_energy_lw(delta, np.zeros((2, 32, 32)), 4, bc_iters)
+    assert np.max(np.abs(om4[gr.mask] - ref)) > 1e-8
+
+
+def test_luttinger_ward_equals_the_eilenberger_form_in_a_uniform_d_wave_square():
+    """d_{x2-y2} in an axis-aligned square keeps its bulk state exactly (no
+    pair breaking at [100] edges), so both forms of the free energy give the
+    angle-resolved bulk value (Eq. FEbulk with |Delta(p)|^2 = |eta|^2 D^2);
+    near the gap nodes the lambda integrand is less smooth and needs 24
+    nodes."""
+    t, npol, nth = 0.2, 16, 16
+    gr = scf.Grain(30, 30, 0.5, [geo.regular_polygon(0, 0, 4, 12.0)], nth, npol, t, components=(("dx2y2", 1.0),))
+    e2 = np.abs(gr.eta[0]) ** 2
+    db = bulk.bulk_gap(t, npol, e2, gr.wk)
+    delta = np.where(gr.mask, db, 0)[None].astype(complex)
+    A = np.zeros((2, 30, 30))
+    ref = bulk.bulk_free_energy(db, t, npol, e2, gr.wk)
+    eil = gr.iterate(delta, A)["omega_density"]
+    om, _ = gr.free_energy_lw(delta, A, 24, 1)
+    assert np.max(np.abs(eil[gr.mask] - ref)) < 1e-14
+    assert np.max(np.abs(om[gr.mask] - ref)) < 1e-14
+
+
+def test_luttinger_ward_propagator_term_is_linear_in_the_lambda_integrand():
+    """The lambda integral of Eq. qcLWFE_I at one node reduces to the gap
+    numerator of the scaled sweep: with a single Gauss-Legendre node
+    (lambda = 1/2, weight 1) the propagator term is 2 den Re(conj(Delta)
+    Delta_new[Delta/2]) at every cell, for any state (here a vortex with a
+    field)."""
+    gr = scf.Grain(24, 24, 0.5, [geo.Disc(0, 0, 5.4)], 12, 5, 0.4, kappa=2.0, flux_quanta=0.7)
+    X, Y = gr.grid.centres()
+    delta = np.where(gr.mask, 0.22 * np.exp(-1j * np.arctan2(Y - 0.3, X + 0.4)), 0)[None]
+    A = np.stack([0.03 * np.sin(0.4 * Y), 0.02 * np.cos(0.3 * X)])
+    om, tot = gr.free_energy_lw(delta, A, 1, 0)
+    dn = gr.iterate(0.5 * delta, A)["delta_new"]
+    term = 2 * gr.gap_denominator()[0] * np.real(np.conj(delta[0]) * dn[0])
+    base = gr.condensation_base(delta)
+    assert np.max(np.abs(om - (base - np.where(gr.mask, term, 0)))) < 1e-15
