@@ -45,18 +45,24 @@ sys.path.insert(0, HERE)
 
 METRIC = "Riccati trajectory-steps/s, FP32-mixed vs FP64 at 1e-4*Delta0 error; %roofline"
 WORKLOAD = "d110_square_400"
-# algorithmic flops (complex ops expanded into real ones; sqrt, reciprocal
-# count one each): per implicit-midpoint step (App. C) and per node and pole
-# for the Green's functions and the three pole sums
-FLOPS_PER_STEP = 71
-FLOPS_PER_NODE_POLE = 82
-PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, FP64 and unpacked FP32
-PEAK_FP32_PACKED_TFLOPS = 157.3
+# Algorithmic work per trajectory step: the method's nominal count, about 59
+# flops for the implicit-midpoint update (App. C, two square roots and two
+# divisions included) plus the Green's functions and pole sums of a node
+# (about 75 flops per node and pole, i.e. about 37 per step): 96 flops.
+FLOPS_PER_STEP = 96
+# A recount of the final formulas (complex ops expanded, sqrt and reciprocal
+# one flop each): 71 per step plus 82 per (node, pole); reported beside.
+RECOUNT_PER_STEP = 71
+RECOUNT_PER_NODE_POLE = 82
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6      # MI355X published FP64 vector peak
+# unpacked FP32 issues at the FP64 rate: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+UNPACKED_FP32_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep launch (mixed) from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs scaled by a plain-copy calibration (profiles/sweep_kernel_d110_square_400.md);
 # None whenever the kernel changed after the counters were taken.
-SWEEP_TRAFFIC_BYTES = 11.51e9
+SWEEP_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -80,6 +86,9 @@ def parse():
 
 
 def timed_scf(qs, torch, sp, precision, d0, a0, steps, warmup):
+    """warmup + steps Picard iterations from (d0, a0); only the last steps
+    are timed.  Also returns the final state and, from one more sweep
+    outside the timed region, its current and free energy."""
     g = qs.Grain(sp, precision)
     dd = torch.as_tensor(d0).cuda()
     ad = torch.as_tensor(a0).cuda()
@@ -95,30 +104,99 @@ def timed_scf(qs, torch, sp, precision, d0, a0, steps, warmup):
     g.profile(False)
     info = dict(g.info)
     info["energies_per_lane"], info["lanes_per_segment"] = g.lanes()
+    _, j, om = g.sweep(dd, ad)
+    final = {"delta": dd.cpu().numpy(), "A": ad.cpu().numpy(), "j": j.cpu().numpy(), "omega": om}
     g.close()
-    return dt, it, sweep_ms, launches, info, res
+    return dt, it, sweep_ms, launches, info, res, final
 
 
-def cpu_baseline(sp, d0, a0, n_angles):
-    """The oracle as it stands, timed on a bounded sample: the complete
-    sweep (node values, start values, both marches, pole sums) of the first
-    n_angles Fermi-surface angles of the same workload."""
+def error_vs_fp64(mixed, fp64, mask, delta0):
+    """Mixed against FP64 after the same iterations from the same start:
+    the largest |Delta| difference on grain cells in units of Delta0 and the
+    relative differences of j, A and the free energy."""
+    dm, df = mixed["delta"][:, mask], fp64["delta"][:, mask]
+
+    def rel(a, b):
+        n = np.linalg.norm(b.ravel())
+        return float(np.linalg.norm((a - b).ravel()) / n) if n > 0 else float(np.linalg.norm(a.ravel()))
+    return {"delta_max_abs_over_delta0": float(np.max(np.abs(dm - df)) / delta0),
+            "j_rel_l2": rel(mixed["j"], fp64["j"]), "A_rel_l2": rel(mixed["A"], fp64["A"]),
+            "omega_rel": float(abs(mixed["omega"] - fp64["omega"]) / abs(fp64["omega"])),
+            "tolerance_delta_over_delta0": 1e-4}
+
+
+_CPU = {}
+
+
+def _oracle_angles(ks):
+    """The oracle's complete sweep (node values, start values, both marches,
+    pole sums) of the angles ks; returns the trajectory steps done."""
     from oracle import sweep as osw
-    sys.path.insert(0, os.path.join(HERE, "tests"))
-    from helpers import oracle_grain
-    og = oracle_grain(sp)
+    og, d0, a0 = _CPU["og"], _CPU["d0"], _CPU["a0"]
     eps = 1j * og.zp * og.tt
     steps = 0
-    t0 = time.perf_counter()
-    for k in range(n_angles):
+    for k in ks:
         data = og.data(k)
         dn, an = og.node_values(k, data, d0, a0)
         g0, gt0 = og.start_values(k, data, dn, an, eps, None)
         gn, gtn, _, _ = osw.march(data, dn, an, eps, og.q, g0, gt0)
         osw.node_sums(gn, gtn, dn, og.rp, og.tt)
         steps += 2 * og.n_poles * int(np.sum(og.tables[k].nnodes + 1))
-    dt = time.perf_counter() - t0
-    return steps / dt, dt, steps
+    return steps
+
+
+def cpu_baseline(sp, d0, a0, n_angles, workers):
+    """The oracle as it stands on the host cores, before any GPU use: the
+    first iteration's sweep of n_angles angles on one core, then of every
+    angle with the angles split over `workers` forked processes."""
+    sys.path.insert(0, os.path.join(HERE, "tests"))
+    from helpers import oracle_grain
+    _CPU.update(og=oracle_grain(sp), d0=d0, a0=a0)
+    t0 = time.perf_counter()
+    st1 = _oracle_angles(range(n_angles))
+    dt1 = time.perf_counter() - t0
+    out = {"one_core": (st1 / dt1, dt1, st1)}
+    if workers > 1:
+        import multiprocessing as mp
+        nth = sp["n_theta"]
+        chunks = [list(range(w, nth, workers)) for w in range(workers)]
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(workers) as pool:
+            stw = sum(pool.map(_oracle_angles, chunks))
+        dtw = time.perf_counter() - t0
+        out["all_cores"] = (stw / dtw, dtw, stw)
+    return out
+
+
+def host_cores():
+    """Cores this process may run on, capped at the 16 a one-GPU share holds."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _load_workloads():
+    """workloads.py by path: importing the package would load the library,
+    and the CPU baseline runs before anything touches the GPU."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_qc_workloads", os.path.join(HERE, "paper_2205_15000_amd", "workloads.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
 
 
 def mode_converge(qs, torch, wl, iters):
@@ -337,8 +415,22 @@ def mode_valu(qs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path, so --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
+
+    cpu = None
+    if args.mode == "iteration" and not args.no_cpu_baseline:
+        # on the host cores, before anything touches the GPU (the pool forks)
+        wl0 = _load_workloads()
+        sp0 = wl0.spec(WORKLOAD)
+        workers = host_cores()
+        print("bench: oracle CPU baseline (%d angles on one core, all angles on %d processes)"
+              % (args.cpu_angles, workers), file=sys.stderr, flush=True)
+        cpu = cpu_baseline(sp0, wl0.initial_delta(WORKLOAD, sp0), wl0.initial_A(WORKLOAD, sp0),
+                           args.cpu_angles, workers)
+        cpu["workers"] = workers
+
     import torch
     import paper_2205_15000_amd as qs
     from paper_2205_15000_amd import workloads as wl
@@ -366,11 +458,13 @@ def main():
     a0 = wl.initial_A(WORKLOAD, sp)
     print("bench: %s mixed, %d warmup + %d timed iterations" % (WORKLOAD, args.warmup, args.steps),
           file=sys.stderr, flush=True)
-    dt, it, sweep_ms, launches, info, res = timed_scf(qs, torch, sp, "mixed", d0, a0, args.steps, args.warmup)
+    dt, it, sweep_ms, launches, info, res, fin_m = timed_scf(qs, torch, sp, "mixed", d0, a0, args.steps,
+                                                             args.warmup)
     steps_iter = info["steps_per_sweep"]
     value = steps_iter * it / dt
     ms_step = 1e3 * dt / it
-    flops_launch = FLOPS_PER_STEP * steps_iter + FLOPS_PER_NODE_POLE * info["n_nodes"] * sp["n_poles"]
+    flops_launch = FLOPS_PER_STEP * steps_iter
+    recount = RECOUNT_PER_STEP * steps_iter + RECOUNT_PER_NODE_POLE * info["n_nodes"] * sp["n_poles"]
     avg_ms = sweep_ms / max(launches, 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     out = {
@@ -388,15 +482,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "d-wave [110] square 40 xi0, 400x400, 64 angles, 64 poles, t=0.1, "
                                "1 flux quantum, kappa=20, 1 vortex (Picard iterations)",
-                   "name": WORKLOAD, "precision": "fp32 sweep and per-lane pole sums / fp64 cross-lane sums",
+                   "name": WORKLOAD, "precision": "fp32 sweeps / fp64 pole, angle and cell sums",
                    "steps_per_iteration": steps_iter, "segments": info["n_segments"],
                    "nodes": info["n_nodes"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": SWEEP_TRAFFIC_BYTES,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": SWEEP_TRAFFIC_BYTES,
                      "kernel": "sweep_kernel<float,%d,0>" % info["energies_per_lane"],
+                     "flops_per_step": FLOPS_PER_STEP, "flops_per_launch": flops_launch,
                      "lanes_per_segment": info["lanes_per_segment"], "avg_launch_ms": avg_ms,
-                     "flops_per_launch": flops_launch,
-                     "peak_fp32_packed_published": PEAK_FP32_PACKED_TFLOPS},
+                     "unpacked_fp32_ceiling": UNPACKED_FP32_TFLOPS,
+                     "frac_of_unpacked_fp32": achieved / UNPACKED_FP32_TFLOPS,
+                     "recount_flops_per_launch": recount,
+                     "recount_tflops": recount / (avg_ms * 1e-3) / 1e12},
         "sweep_only_steps_per_s": steps_iter / (avg_ms * 1e-3),
     }
     # the ceiling the device sustains under a full VALU load (same run, same
@@ -406,20 +503,30 @@ def main():
     out["roofline"]["frac_of_sustained"] = achieved / (2 * fma / 1e12)
     if not args.skip_fp64:
         print("bench: %s fp64" % WORKLOAD, file=sys.stderr, flush=True)
-        dt64, it64, sms64, l64, _, _ = timed_scf(qs, torch, sp, "fp64", d0, a0, args.steps, args.warmup)
+        dt64, it64, sms64, l64, _, _, fin_d = timed_scf(qs, torch, sp, "fp64", d0, a0, args.steps, args.warmup)
         v64 = steps_iter * it64 / dt64
         avg64 = sms64 / max(l64, 1)
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * dt64 / it64, "sweep_avg_launch_ms": avg64,
                        "sweep_only_steps_per_s": steps_iter / (avg64 * 1e-3),
-                       "roofline_frac": flops_launch / (avg64 * 1e-3) / 1e12 / PEAK_VALU_TFLOPS}
+                       "roofline_achieved": flops_launch / (avg64 * 1e-3) / 1e12, "roofline_peak": PEAK_FP64_TFLOPS,
+                       "roofline_frac": flops_launch / (avg64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
         out["mixed_over_fp64"] = value / v64
-    if not args.no_cpu_baseline:
-        print("bench: oracle CPU baseline (%d angles)" % args.cpu_angles, file=sys.stderr, flush=True)
-        v, t, st = cpu_baseline(sp, d0, a0, args.cpu_angles)
-        out["cpu_baseline"] = {"value": v, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": "oracle sweep (interpolation, both marches, pole sums) of %d of the "
-                                         "64 angles of the same workload, first iteration: %d steps in %.1f s"
-                                         % (args.cpu_angles, st, t)}
+        mask = qs.Plan(dict(sp, n_theta=4)).mask()
+        out["error_vs_fp64"] = error_vs_fp64(fin_m, fin_d, mask, wl.DELTA0)
+        out["error_vs_fp64"]["iterations"] = args.warmup + args.steps
+    if cpu is not None:
+        v1, t1, s1 = cpu["one_core"]
+        cb = {"value": v1, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
+              "sample": "oracle sweep (interpolation, both marches, pole sums) of %d of the 64 angles of the "
+                        "same workload, first iteration, one core: %d steps in %.1f s" % (args.cpu_angles, s1, t1),
+              "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        if "all_cores" in cpu:
+            vw, tw, sw = cpu["all_cores"]
+            cb.update(value=vw, cores=cpu["workers"], one_core_value=v1,
+                      sample="oracle sweep of all 64 angles of the same workload, first iteration, angles split "
+                             "over %d processes: %d steps in %.1f s (one core, %d angles: %.3g steps/s)"
+                             % (cpu["workers"], sw, tw, args.cpu_angles, v1))
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

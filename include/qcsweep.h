@@ -220,13 +220,39 @@ qc_status qc_sweep(qc_grain* grain, const double* delta, const double* A_ind,
  * With kappa <= 0 both outputs are zero. */
 qc_status qc_solve_A(qc_grain* grain, const double* j, double* A_out, double* B_out, void* stream);
 
+/* Luttinger-Ward form of the free energy (Sec. II, Eqs. qcLWFE and
+ * qcLWFE_I), the check on the Eilenberger form that qc_sweep returns: per
+ * grain cell
+ *   omega = sum_G |Delta_G|^2 ln(t/t_c,G) + 2 pi sum_p (R_p/z_p) <|Delta(p)|^2>
+ *           - int_0^1 dlambda 2 sum_G den_G Re[conj(Delta_G) Delta_new,G[lambda Delta]],
+ * where Delta_new[lambda Delta] is the gap update (Eq. gapeq_fixpoint) of one
+ * sweep with the scaled gap lambda Delta (A unscaled) and den_G its
+ * denominator: with f(-e) = f~(e)*, T sum_n <Delta* f + Delta f~> over both
+ * signs of the energies equals that expression.  The lambda integral is
+ * the n_lambda-point Gauss-Legendre rule on [0, 1]; for every lambda the
+ * boundary values start from bulk roots and take bc_iters burn-in sweeps
+ * (App. B) before the sweep that is used.  The total adds
+ * h^2 sum (kappa^2/2) |B_ind|^2 as the Eilenberger form does.  Costs
+ * n_lambda (bc_iters + 1) sweeps.  The grain's boundary store is restored
+ * before the call returns.
+ *   delta          device complex [ncomp][ny][nx]
+ *   A_ind          device double [2][ny][nx]
+ *   omega_density  device double [ny][nx] (zero off the grain), may be NULL
+ *   omega_total    host double
+ * Errors: QC_ERR_INVALID unless 1 <= n_lambda <= 64 and bc_iters >= 0. */
+qc_status qc_free_energy_lw(qc_grain* grain, const double* delta, const double* A_ind, int n_lambda,
+                            int bc_iters, double* omega_density, double* omega_total, void* stream);
+
 /* Picard self-consistency (App. E) on x = (Re Delta_G, Im Delta_G on grain
  * cells, kappa^2 A_ind): x <- x + alpha (g(x) - x), A from the current of
  * the same iteration.  The first `burnin` iterations keep Delta and A fixed
  * and only update boundary values (App. B).  Stops when every global error
  * (Eq. global_error with norm_p in {1, 2, 0 = infinity}) of Delta, j, A and
  * the free energy is below tol, after at least min_iter iterations, or at
- * max_iter.
+ * max_iter.  The errors of Delta and A are those of d = g(x) - x relative to
+ * x, taken after the A-solve and before the accelerator moves x (Alg. 1);
+ * those of j and the free energy compare with the previous iteration.
+ * With kappa <= 0 (no screening) A_io is set to zero and stays zero.
  *   delta_io   device complex [ncomp][ny][nx], in: start, out: final
  *   A_io       device double [2][ny][nx], in: start, out: final
  *   iters_done host int
@@ -255,15 +281,22 @@ qc_status qc_scf_run(qc_grain* grain, double* delta_io, double* A_io, int max_it
  *           bisection so that w m + (1 - w) d has similarity 0.7 with d,
  *           m_c <- w_c m_c + (1 - w_c) d_c, x_c <- x_c + a_c m_c.  The first
  *           iteration takes w = 0 and a_c = alpha; a similarity with a zero
- *           vector counts as 0.  Needs norm_p = 2 (QC_ERR_INVALID otherwise).
- *           beta is ignored.
+ *           vector counts as 0.  Anti-parallel m_c and d_c (s <= -1 + 1e-9)
+ *           leave no weight with similarity 0.7 (the blend is a multiple of
+ *           d_c that flips sign where it vanishes): then w_c = 0, so the
+ *           average restarts from d_c.  Needs norm_p = 2 (QC_ERR_INVALID
+ *           otherwise).  beta is ignored.
  * alpha is qc_scf_run's argument.  Picard and Polyak are linear in x, so the
  * kappa^2 scale of A drops out of them; it enters BB's dot products.
- * eps_Delta and eps_A are then the norms of the step taken (alpha d, v or
- * a_i d, a_c m_c) relative to the old x.  Polyak, BB and CongAcc keep two
+ * Polyak, BB and CongAcc keep two
  * device arrays of the sizes of Delta and A, allocated at their first run.
  * Errors: QC_ERR_INVALID for an unknown kind or a Polyak drag outside (0, 1]. */
 qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
+
+/* Counts, over the grain's lifetime, of the CongAcc weights that were set by
+ * bisection and by the anti-parallel rule (see qc_grain_set_accelerator).
+ * Either pointer may be NULL.  Errors: QC_ERR_INVALID for a NULL grain. */
+qc_status qc_grain_get_accel_stats(const qc_grain* grain, int64_t* bisected, int64_t* anti_parallel);
 
 /* Local density of states N(R, e)/N_F = < -Im g^R / pi > (Sec. II) at the
  * real energies e + i*broadening, Delta and A frozen: bc_iters sweeps update
@@ -321,7 +354,8 @@ void qc_batch_destroy(qc_batch* batch);
 qc_status qc_batch_get_info(const qc_batch* batch, int64_t* steps_per_iteration, int* energies_per_lane,
                             int* n_tiles);
 /* set / read grain i's fields: device complex [ncomp][ny][nx] and device
- * double [2][ny][nx] of that grain (copies; off-grain Delta set to zero). */
+ * double [2][ny][nx] of that grain (copies; off-grain Delta set to zero;
+ * a grain with kappa <= 0 stores A = 0, as qc_scf_run holds it). */
 qc_status qc_batch_set_fields(qc_batch* batch, int i, const double* delta, const double* A_ind, void* stream);
 qc_status qc_batch_get_fields(const qc_batch* batch, int i, double* delta_out, double* A_out, void* stream);
 /* n_iter Picard iterations of every grain (stream NULL: the batch's own

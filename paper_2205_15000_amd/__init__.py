@@ -97,8 +97,10 @@ _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes
 _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
 _sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
 _sig("qc_green_average", ctypes.c_int, [_P, _P, _P, _P, _P])
+_sig("qc_free_energy_lw", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _D, _P])
 _sig("qc_grain_set_adjoint_checkpoint", ctypes.c_int, [_P, ctypes.c_int])
 _sig("qc_grain_set_accelerator", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double])
+_sig("qc_grain_get_accel_stats", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)])
 _sig("qc_batch_destroy", None, [_P])
@@ -452,6 +454,20 @@ class Grain:
         _check(lib.qc_green_average(self._g, dp, ap, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
+    def free_energy_lw(self, delta, A, n_lambda, bc_iters, density=False, stream=None):
+        """Luttinger-Ward free energy: returns omega_total (and the density
+        [ny, nx] when density is set)."""
+        torch = _torch()
+        shp_d = (self.ncomp, self.ny, self.nx)
+        dp = _dptr(delta, torch.complex128, shp_d, "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        od = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self._dev()) if density else None
+        tot = ctypes.c_double(0.0)
+        _check(lib.qc_free_energy_lw(self._g, dp, ap, int(n_lambda), int(bc_iters),
+                                     ctypes.c_void_p(od.data_ptr()) if od is not None else None,
+                                     ctypes.byref(tot), _stream(stream)))
+        return (tot.value, od) if density else tot.value
+
     def get_state(self, stream=None):
         torch = _torch()
         n = ctypes.c_size_t(0)
@@ -471,6 +487,14 @@ class Grain:
         scf's alpha the first; 2-norm residuals)."""
         k = {"picard": 0, "polyak": 1, "bb": 2, "congacc": 3}[kind]
         _check(lib.qc_grain_set_accelerator(self._g, k, float(beta)))
+
+    def accel_stats(self):
+        """(bisected, anti_parallel): CongAcc weights set by bisection and by
+        the anti-parallel rule over the grain's lifetime."""
+        b = ctypes.c_int64(0)
+        a = ctypes.c_int64(0)
+        _check(lib.qc_grain_get_accel_stats(self._g, ctypes.byref(b), ctypes.byref(a)))
+        return b.value, a.value
 
     def set_adjoint_checkpoint(self, every):
         """Reverse mode with checkpoints every `every` slots (default 32;

@@ -330,6 +330,13 @@ struct qc_grain {
   // CongAcc: per-component dot-product partials [component][kParts][3]
   double* cpart = nullptr;
   double* cpart_host = nullptr;
+  // CongAcc weights set by bisection and by the anti-parallel rule
+  int64_t cong_bisect = 0, cong_anti = 0;
+  // Luttinger-Ward free energy: per-cell lambda integral, lambda Delta, and
+  // the boundary store kept aside while the lambda sweeps run
+  double* lw_acc = nullptr;
+  double* lw_dl = nullptr;
+  void* lw_save = nullptr;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -344,6 +351,11 @@ static constexpr int kParts = 256;
 static constexpr double kBBStepMin = 1e-3, kBBStepMax = 1e2;
 // CongAcc (App. E's defaults): step factor, minimum similarity, step bounds
 static constexpr double kCongK = 1.234, kCongSmin = 0.7, kCongStepMin = 1e-3, kCongStepMax = 1e2;
+// a similarity at or below -1 + kCongAnti reads as anti-parallel m and d:
+// the blend w m + (1 - w) d is then a multiple of d whose similarity with d
+// jumps from 1 to -1 where it vanishes, so no weight reaches smin; the
+// average restarts from d (w = 0)
+static constexpr double kCongAnti = 1e-9;
 
 // The weight w* in [0, 1] at which w m + (1 - w) d has cosine similarity
 // smin with d, by bisection from m.m, m.d and d.d (similarity 1 at w = 0).
@@ -379,7 +391,7 @@ void free_grain(qc_grain* g) {
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->vel_d, g->vel_a, g->gtbuf, g->lgt, g->gS, g->gV,
                   g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw,
-                  g->ckbase, g->ckg, g->ckgt, g->ckscr};
+                  g->ckbase, g->ckg, g->ckgt, g->ckscr, g->lw_acc, g->lw_dl, g->lw_save};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
@@ -979,17 +991,6 @@ void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* 
 }
 
 // ||new - old||_p / ||old||_p from fetched partials (0/0 = 0, x/0 = inf)
-// sqrt(step2) / ||old||_2 with ||old|| from the diff partials of region reg
-double cong_rel(const qc_grain* g, int reg, double step2) {
-  const double* q = g->part_host + static_cast<int64_t>(reg) * kParts;
-  double den = 0.0;
-  for (int i = 0; i < kParts; ++i) den += q[2 * i + 1];
-  const double num = std::sqrt(step2);
-  den = std::sqrt(den);
-  if (den == 0.0) return num == 0.0 ? 0.0 : INFINITY;
-  return num / den;
-}
-
 double rel_from_parts(const qc_grain* g, int reg, int p) {
   const double* q = g->part_host + static_cast<int64_t>(reg) * kParts;
   double num = 0.0, den = 0.0;
@@ -1024,6 +1025,98 @@ qc_status qc_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out,
   });
 }
 
+// Nodes and weights of the n-point Gauss-Legendre rule on [0, 1]: the roots
+// of P_n by Newton's method from Chebyshev-like starts, weights
+// 2 / ((1 - x^2) P_n'(x)^2) on [-1, 1], halved for [0, 1].
+static void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double r = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = r;  // P_0, P_1
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * r * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double pn = n == 1 ? r : p1, pm = n == 1 ? 1.0 : p0;  // P_n, P_{n-1}
+      dp = n * (r * pn - pm) / (r * r - 1.0);
+      const double dr = pn / dp;
+      r -= dr;
+      if (std::fabs(dr) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = r;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * r * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double pn = n == 1 ? r : p1, pm = n == 1 ? 1.0 : p0;
+      dp = n * (r * pn - pm) / (r * r - 1.0);
+    }
+    x[i] = 0.5 * (1.0 - r);
+    w[i] = 1.0 / ((1.0 - r * r) * dp * dp);
+  }
+}
+
+qc_status qc_free_energy_lw(qc_grain* g, const double* delta, const double* A_ind, int n_lambda, int bc_iters,
+                            double* omega_density, double* omega_total, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !omega_total) return fail(QC_ERR_INVALID, "delta, A_ind and omega_total are required");
+  if (n_lambda < 1 || n_lambda > 64 || bc_iters < 0) return fail(QC_ERR_INVALID, "need 1 <= n_lambda <= 64, bc_iters >= 0");
+  return guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    ensure_sweep_buffers(g);
+    const size_t half = 2 * g->real_bytes() * g->nseg * g->n_poles;
+    if (!g->lw_acc) g->lw_acc = static_cast<double*>(dalloc(sizeof(double) * std::max<int64_t>(g->ncg, 1)));
+    if (!g->lw_dl) g->lw_dl = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncomp * g->ncell));
+    if (!g->lw_save) g->lw_save = dalloc(2 * half);
+    // the grain's boundary store is kept aside and restored at the end
+    const int saved_valid = g->bc_valid, saved_cur = g->bc_cur;
+    if (saved_valid) {
+      hcheck(hipMemcpyAsync(g->lw_save, g->bc[g->bc_cur][0], half, hipMemcpyDeviceToDevice, st), "copy");
+      hcheck(hipMemcpyAsync(static_cast<char*>(g->lw_save) + half, g->bc[g->bc_cur][1], half, hipMemcpyDeviceToDevice,
+                            st),
+             "copy");
+    }
+    std::vector<double> lam, wl;
+    gauss_legendre01(n_lambda, lam, wl);
+    for (int l = 0; l < n_lambda; ++l) {
+      qc::launch_scale(delta, lam[l], 2 * g->ncomp * g->ncell, g->lw_dl, st);
+      g->bc_valid = 0;  // each coupling starts from bulk roots of lambda Delta
+      for (int it = 0; it <= bc_iters; ++it)
+        do_sweep(g, g->lw_dl, A_ind, g->dnew, g->jcur, nullptr, nullptr, st, false);
+      qc::launch_lw_accumulate(delta, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, g->den, wl[l], l == 0,
+                               g->lw_acc, st);
+    }
+    if (omega_density) qc::launch_fill(omega_density, g->ncell, 0.0, st);
+    qc::launch_lw_finish(delta, g->grain_cells, g->ncg, g->ncomp, g->ncell, g->n_theta, g->eta, g->wk, g->logt,
+                         g->twopi_rz, g->lw_acc, g->omega_cell, omega_density, st);
+    qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, region(g, kROmega), kParts, st);
+    if (g->kappa > 0.0) {
+      qc::launch_curl(A_ind, g->bbuf, g->nx, g->ny, g->h, st);
+      qc::launch_block_sum(g->bbuf, nullptr, g->ncell, 1, region(g, kRB2), kParts, st);
+    }
+    fetch_parts(g, st);
+    *omega_total = omega_from_parts(g);
+    // restore the store the caller's next sweep expects
+    g->bc_cur = saved_cur;
+    g->bc_valid = saved_valid;
+    if (saved_valid) {
+      hcheck(hipMemcpyAsync(g->bc[g->bc_cur][0], g->lw_save, half, hipMemcpyDeviceToDevice, st), "copy");
+      hcheck(hipMemcpyAsync(g->bc[g->bc_cur][1], static_cast<char*>(g->lw_save) + half, half, hipMemcpyDeviceToDevice,
+                            st),
+             "copy");
+    }
+    hcheck(hipStreamSynchronize(st), "sync");
+    return QC_OK;
+  });
+}
+
 qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, int min_iter, int burnin,
                      double tol, int norm_p, double alpha, int* iters_done, double* residuals_out, void* stream) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
@@ -1043,6 +1136,8 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       qc::launch_fill(delta_io, 2 * g->ncomp * g->ncell, 0.0, st);
       qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, st);
     }
+    // no screening (kappa <= 0): no induced vector potential, A stays zero
+    if (g->kappa <= 0.0) qc::launch_fill(A_io, 2 * g->ncell, 0.0, st);
     // the sweeps write grain cells only: off-grain j stays zero in both
     // current buffers, and off-grain Delta_new is never read here
     ensure_sweep_buffers(g);
@@ -1058,9 +1153,8 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       qc::launch_fill(g->vel_d, 2 * g->ncomp * g->ncell, 0.0, st);
       qc::launch_fill(g->vel_a, 2 * g->ncell, 0.0, st);
     }
-    // the norms are of the step taken: alpha (g(x) - x) for Picard and BB,
-    // the velocity for Polyak
-    double nscale = polyak ? 1.0 : alpha;
+    // the global errors are of d = g(x) - x, taken before the accelerator
+    // moves x (Alg. 1)
     double a_bb = alpha;  // BB step, alpha for the first iteration
     int i_bb = 0;
     // CongAcc: components 2 G + (0 re, 1 im) of Delta, then A_x, A_y
@@ -1134,16 +1228,12 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
           if (den != 0.0) a_bb = std::min(std::max(a_bb * num / den, kBBStepMin), kBBStepMax);
         }
         ++i_bb;
-        nscale = a_bb;
         qc::launch_picard(delta_io, g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, a_bb, st);
         qc::launch_picard(A_io, g->anew, nullptr, 2 * g->ncell, 1, 0, 1, a_bb, st);
       }
-      // CongAcc: per-component step sizes and weights, then the step; the
-      // 2-norms of the step per field follow from the same dot products
-      double cg_step2[2] = {0.0, 0.0};
+      // CongAcc: per-component step sizes and weights, then the step
       if (cong) {
         for (int c = 0; c < ncx; ++c) {
-          const int f = c < 2 * g->ncomp ? 0 : 1;
           if (cg_first) continue;
           double mm = 0.0, md = 0.0, dd = 0.0;
           const double* q = g->cpart_host + static_cast<int64_t>(c) * 3 * kParts;
@@ -1154,9 +1244,15 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
           }
           const double sc = (mm > 0.0 && dd > 0.0) ? md / std::sqrt(mm * dd) : 0.0;
           cg_a[c] = std::min(std::max(cg_a[c] * std::pow(kCongK, sc), kCongStepMin), kCongStepMax);
-          if (sc < kCongSmin && mm > 0.0 && dd > 0.0) cg_w[c] = congacc_weight(mm, md, dd, kCongSmin);
-          const double w = cg_w[c];
-          cg_step2[f] += cg_a[c] * cg_a[c] * (w * w * mm + 2.0 * w * (1.0 - w) * md + (1.0 - w) * (1.0 - w) * dd);
+          if (sc < kCongSmin && mm > 0.0 && dd > 0.0) {
+            if (sc <= -1.0 + kCongAnti) {
+              cg_w[c] = 0.0;
+              ++g->cong_anti;
+            } else {
+              cg_w[c] = congacc_weight(mm, md, dd, kCongSmin);
+              ++g->cong_bisect;
+            }
+          }
         }
         qc::CongCoef cd{}, ca{};
         for (int c = 0; c < 2 * g->ncomp; ++c) {
@@ -1172,11 +1268,9 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       }
       const double om = omega_from_parts(g);
       double res[5];
-      res[0] = nscale * rel_from_parts(g, kRDiffD, norm_p);
-      if (cong && !cg_first) res[0] = cong_rel(g, kRDiffD, cg_step2[0]);
+      res[0] = rel_from_parts(g, kRDiffD, norm_p);
       res[1] = have_old ? rel_from_parts(g, kRDiffJ, norm_p) : INFINITY;
-      res[2] = nscale * rel_from_parts(g, kRDiffA, norm_p);
-      if (cong && !cg_first) res[2] = cong_rel(g, kRDiffA, cg_step2[1]);
+      res[2] = rel_from_parts(g, kRDiffA, norm_p);
       if (cong) cg_first = false;
       res[3] = (have_old && om_old != 0.0) ? std::fabs(om - om_old) / std::fabs(om_old) : INFINITY;
       res[4] = om;
@@ -1641,6 +1735,13 @@ qc_status qc_grain_set_accelerator(qc_grain* g, int kind, double beta) {
   return QC_OK;
 }
 
+qc_status qc_grain_get_accel_stats(const qc_grain* g, int64_t* bisected, int64_t* anti_parallel) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (bisected) *bisected = g->cong_bisect;
+  if (anti_parallel) *anti_parallel = g->cong_anti;
+  return QC_OK;
+}
+
 qc_status qc_grain_set_adjoint_checkpoint(qc_grain* g, int every) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
   if (every < 0 || every > 4096) return fail(QC_ERR_INVALID, "checkpoint interval must be in [0, 4096]");
@@ -1944,7 +2045,12 @@ qc_status qc_batch_set_fields(qc_batch* b, int i, const double* delta, const dou
     qc::launch_fill(b->delta[i], 2 * g->ncomp * g->ncell, 0.0, S(stream));
     qc::launch_picard(b->delta[i], g->dnew, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, 1.0, S(stream));
     qc::launch_fill(g->dnew, 2 * g->ncomp * g->ncell, 0.0, S(stream));
-    hcheck(hipMemcpyAsync(b->A[i], A_ind, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, S(stream)), "copy");
+    // no screening (kappa <= 0): no induced vector potential, A stays zero
+    if (g->kappa <= 0.0)
+      qc::launch_fill(b->A[i], 2 * g->ncell, 0.0, S(stream));
+    else
+      hcheck(hipMemcpyAsync(b->A[i], A_ind, sizeof(double) * 2 * g->ncell, hipMemcpyDeviceToDevice, S(stream)),
+             "copy");
     return QC_OK;
   });
 }

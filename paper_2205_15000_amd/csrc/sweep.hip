@@ -381,28 +381,51 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // the wave, since all groups start their march together)
   auto node_sums = [&](int64_t node, const node4<T>& nv, const cpx<T>* gn, int k) {
     if (MODE == 0) {
-      // the lane's few poles are summed in the sweep precision, the lanes'
-      // partial sums in FP64
-      T pfx = T(0), pfy = T(0), pg = T(0), p1 = T(0), p2 = T(0);
-      for (int i = 0; i < EPL; ++i) {
-        const cpx<T> gg = gn[i];
-        const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
-        const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
-        const T dxr = T(1) + xx;
-        // I = 1/(1+X) = (dxr - i xy) u / R with u = R / |1+X|^2 (R the pole weight)
-        const T r = rw[i];
-        const T u = r * drcp(fmaT(dxr, dxr, xy * xy));
-        const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
-        const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
-        pfx = fmaT(u, fmaT(sxs, dxr, sys * xy), pfx);     // R Re((gamma + gamma~) I)
-        pfy = fmaT(u, fmaT(dys, dxr, -(dxs * xy)), pfy);  // R Im((gamma - gamma~) I)
-        pg = fmaT(-u, xy, pg);                            // R Im I
-        p1 = fmaT(r, dys, p1);
-        p2 = fmaT(r, sxs, p2);
+      double sfx, sfy, sg, si;
+      if constexpr (sizeof(T) == 4) {
+        // mixed precision: each pole's terms are formed from the FP32
+        // marches and summed over poles in FP64
+        sfx = sfy = sg = si = 0.0;
+        for (int i = 0; i < EPL; ++i) {
+          const cpx<T> gg = gn[i];
+          const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
+          const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
+          const T dxr = T(1) + xx;
+          // I = 1/(1+X) = (dxr - i xy) u / R with u = R / |1+X|^2 (R the pole weight)
+          const T r = rw[i];
+          const T u = r * drcp(fmaT(dxr, dxr, xy * xy));
+          const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
+          const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
+          sfx += static_cast<double>(u * fmaT(sxs, dxr, sys * xy));     // R Re((gamma + gamma~) I)
+          sfy += static_cast<double>(u * fmaT(dys, dxr, -(dxs * xy)));  // R Im((gamma - gamma~) I)
+          sg -= static_cast<double>(u * xy);                            // R Im I
+          // R Im(D* gamma - D gamma~)
+          si += static_cast<double>(r * fmaT(nv.dx, dys, -(nv.dy * sxs)));
+        }
+      } else {
+        T pfx = T(0), pfy = T(0), pg = T(0), p1 = T(0), p2 = T(0);
+        for (int i = 0; i < EPL; ++i) {
+          const cpx<T> gg = gn[i];
+          const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
+          const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
+          const T dxr = T(1) + xx;
+          // I = 1/(1+X) = (dxr - i xy) u / R with u = R / |1+X|^2 (R the pole weight)
+          const T r = rw[i];
+          const T u = r * drcp(fmaT(dxr, dxr, xy * xy));
+          const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
+          const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
+          pfx = fmaT(u, fmaT(sxs, dxr, sys * xy), pfx);     // R Re((gamma + gamma~) I)
+          pfy = fmaT(u, fmaT(dys, dxr, -(dxs * xy)), pfy);  // R Im((gamma - gamma~) I)
+          pg = fmaT(-u, xy, pg);                            // R Im I
+          p1 = fmaT(r, dys, p1);
+          p2 = fmaT(r, sxs, p2);
+        }
+        sfx = pfx;
+        sfy = pfy;
+        sg = pg;
+        // Im(D* gamma - D gamma~) summed over the lane's poles
+        si = fmaT(nv.dx, p1, -(nv.dy * p2));
       }
-      const double sfx = static_cast<double>(pfx), sfy = static_cast<double>(pfy), sg = static_cast<double>(pg);
-      // Im(D* gamma - D gamma~) summed over the lane's poles
-      const double si = static_cast<double>(fmaT(nv.dx, p1, -(nv.dy * p2)));
       // S_f = -2 i pi t~ (sfx + i sfy), S_g = 2 pi t~ sg, S_I = 2 pi t~ si
       if (a.G >= 8) {
         // the lane's four partials go to LDS; every second node the group
@@ -787,6 +810,66 @@ __global__ void __launch_bounds__(256) block_sum_kernel(const double* __restrict
 // doubles each (stride 2: complex modulus).  p = 1, 2, or 0 (max).
 // Elements may be gathered through idx (grain cells) when idx != nullptr,
 // for `nrep` consecutive fields of `field_stride` elements.
+// Luttinger-Ward free energy (Sec. II): the propagator term at one
+// coupling lambda, 2 sum_G den_G Re(conj(Delta_G) Delta_new_G[lambda Delta])
+// with den_G the gap-equation denominator, weighted into acc per grain cell
+__global__ void __launch_bounds__(256) lw_accumulate_kernel(const double* __restrict__ delta,
+                                                            const double* __restrict__ dnew,
+                                                            const int32_t* __restrict__ grain_cells, int64_t ncg,
+                                                            int ncomp, int64_t ncell, const double* __restrict__ den,
+                                                            double w, int first, double* __restrict__ acc) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncg) return;
+  const int64_t cell = grain_cells[c];
+  double v = 0.0;
+  for (int g = 0; g < ncomp; ++g) {
+    const int64_t o = 2 * (static_cast<int64_t>(g) * ncell + cell);
+    v += den[g] * (delta[o] * dnew[o] + delta[o + 1] * dnew[o + 1]);
+  }
+  v *= 2.0 * w;
+  acc[c] = first ? v : acc[c] + v;
+}
+
+// The terms of the free-energy density before the propagator term,
+// sum_G |Delta_G|^2 ln(t / t_c,G) + 2 pi sum_p (R_p / z_p) <|Delta(p)|^2>,
+// minus the lambda integral of the propagator term
+__global__ void __launch_bounds__(256) lw_finish_kernel(const double* __restrict__ delta,
+                                                        const int32_t* __restrict__ grain_cells, int64_t ncg,
+                                                        int ncomp, int64_t ncell, int n_theta,
+                                                        const double* __restrict__ eta, const double* __restrict__ wk,
+                                                        const double* __restrict__ logt, double twopi_rz,
+                                                        const double* __restrict__ acc,
+                                                        double* __restrict__ omega_cell, double* __restrict__ omega) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncg) return;
+  const int64_t cell = grain_cells[c];
+  double dx[4], dy[4], base = 0.0;
+  for (int g = 0; g < ncomp; ++g) {
+    dx[g] = delta[2 * (static_cast<int64_t>(g) * ncell + cell)];
+    dy[g] = delta[2 * (static_cast<int64_t>(g) * ncell + cell) + 1];
+    base += (dx[g] * dx[g] + dy[g] * dy[g]) * logt[g];
+  }
+  double d2 = 0.0;
+  for (int k = 0; k < n_theta; ++k) {
+    double px = 0.0, py = 0.0;
+    for (int g = 0; g < ncomp; ++g) {
+      const double ex = eta[2 * (g * n_theta + k)], ey = eta[2 * (g * n_theta + k) + 1];
+      px += ex * dx[g] - ey * dy[g];
+      py += ex * dy[g] + ey * dx[g];
+    }
+    d2 += wk[k] * (px * px + py * py);
+  }
+  const double om = base + twopi_rz * d2 - acc[c];
+  omega_cell[c] = om;
+  if (omega) omega[cell] = om;
+}
+
+__global__ void __launch_bounds__(256) scale_kernel(const double* __restrict__ x, double s, int64_t n,
+                                                    double* __restrict__ y) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = s * x[i];
+}
+
 __global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
   __shared__ double s0[256], s1[256];
   double acc0 = 0.0, acc1 = 0.0;
@@ -799,15 +882,16 @@ __global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
     for (int c = 0; c < a.stride; ++c) {
       const int64_t k = e * a.stride + c;
       const double vn = a.xnew[k], vo = a.xold[k];
-      double step = vn - vo;
+      const double d = vn - vo;
       if (a.vel) {  // the heavy-ball step
-        step = (1.0 - a.beta) * a.vel[k] + a.alpha * (vn - vo);
+        const double step = (1.0 - a.beta) * a.vel[k] + a.alpha * d;
         a.vel[k] = step;
         a.update[k] = vo + step;
       } else if (a.update) {
-        a.update[k] = vo + a.alpha * (vn - vo);  // the Picard step
+        a.update[k] = vo + a.alpha * d;  // the Picard step
       }
-      dn += step * step;
+      // the global error is of g(x) - x, before any step (Alg. 1)
+      dn += d * d;
       dd += vo * vo;
     }
     if (a.p == 2) {
@@ -1216,6 +1300,23 @@ void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, i
   if (n * nrep > 0)
     hipLaunchKernelGGL(picard_kernel, dim3(nblk(n * nrep)), dim3(256), 0, st, x, gx, idx, n, nrep, field_stride,
                        stride, alpha);
+}
+void launch_lw_accumulate(const double* delta, const double* delta_new, const int32_t* grain_cells, int64_t ncg,
+                          int ncomp, int64_t ncell, const double* den, double w, int first, double* acc,
+                          hipStream_t st) {
+  if (ncg > 0)
+    hipLaunchKernelGGL(lw_accumulate_kernel, dim3(nblk(ncg)), dim3(256), 0, st, delta, delta_new, grain_cells, ncg,
+                       ncomp, ncell, den, w, first, acc);
+}
+void launch_lw_finish(const double* delta, const int32_t* grain_cells, int64_t ncg, int ncomp, int64_t ncell,
+                      int n_theta, const double* eta, const double* wk, const double* logt, double twopi_rz,
+                      const double* acc, double* omega_cell, double* omega, hipStream_t st) {
+  if (ncg > 0)
+    hipLaunchKernelGGL(lw_finish_kernel, dim3(nblk(ncg)), dim3(256), 0, st, delta, grain_cells, ncg, ncomp, ncell,
+                       n_theta, eta, wk, logt, twopi_rz, acc, omega_cell, omega);
+}
+void launch_scale(const double* x, double s, int64_t n, double* y, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(scale_kernel, dim3(nblk(n)), dim3(256), 0, st, x, s, n, y);
 }
 void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st) {
   hipLaunchKernelGGL(means_kernel, dim3(1), dim3(256), 0, st, part, nparts, inv_n, mean);

@@ -264,6 +264,17 @@ void launch_bb_dots(const double* xnew, const double* xold, const int32_t* idx, 
 void launch_picard(double* x, const double* gx, const int32_t* idx, int64_t n, int nrep, int64_t field_stride,
                    int stride, double alpha, hipStream_t st);
 void launch_means(const double* part, int nparts, double inv_n, double* mean, hipStream_t st);
+// Luttinger-Ward free energy: per grain cell c, acc[c] (+)= w * 2 sum_G
+// den_G Re(conj(delta_G) delta_new_G) (first: = instead of +=)
+void launch_lw_accumulate(const double* delta, const double* delta_new, const int32_t* grain_cells, int64_t ncg,
+                          int ncomp, int64_t ncell, const double* den, double w, int first, double* acc,
+                          hipStream_t st);
+// omega(c) = sum_G |delta_G|^2 logt_G + twopi_rz sum_k w_k |sum_G eta_G(k) delta_G|^2 - acc[c] on grain
+// cells: written to omega_cell[c] (grain-cell order) and, when given, omega[cell]
+void launch_lw_finish(const double* delta, const int32_t* grain_cells, int64_t ncg, int ncomp, int64_t ncell,
+                      int n_theta, const double* eta, const double* wk, const double* logt, double twopi_rz,
+                      const double* acc, double* omega_cell, double* omega, hipStream_t st);
+void launch_scale(const double* x, double s, int64_t n, double* y, hipStream_t st);
 void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, const double* mean,
                         double2* w, hipStream_t st);
 void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, const double2* pre, hipStream_t st);

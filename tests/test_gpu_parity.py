@@ -255,16 +255,16 @@ def test_scf_barzilai_borwein_matches_oracle():
 
 def test_scf_congacc_matches_oracle():
     """CongAcc (App. E) per component, with the A-solve, FP64, against the
-    oracle: 10 iterations after a burn-in on one grain, 5 on a two-component
-    grain.  On the latter the moving average of each A component turns
-    exactly opposite to its difference at the sixth iteration; no weight then
-    reaches the minimum similarity, the bisection lands where the average
-    vanishes, and later similarities of rounding-level vectors decide the
-    steps differently on the two sides."""
+    oracle: 10 iterations after a burn-in on a one-component grain with a
+    field, 12 on a two-component grain without screening (A held at zero)
+    with a first step large enough that the similarity of every Delta
+    component falls below the minimum at least once, so the weights of the
+    second component are set by bisection too.  The number of bisected
+    weights equals the oracle's."""
     qs = _qs()
-    for name, n_it in (("small_d110_field", 10), ("small_holed_mixed", 5)):
+    for name, n_it, alpha in (("small_d110_field", 10, 0.5), ("small_holed_mixed", 12, 1.0)):
         sp = wl.spec(name)
-        _note("case %s: %d CongAcc iterations, fp64" % (name, n_it))
+        _note("case %s: %d CongAcc iterations, alpha %g, fp64" % (name, n_it, alpha))
         g = qs.Grain(sp, "fp64")
         g.set_accelerator("congacc")
         og = oracle_grain(sp)
@@ -272,13 +272,18 @@ def test_scf_congacc_matches_oracle():
         a0 = wl.initial_A(name, sp)
         m = og.mask
         dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
-        it, res, conv = g.scf(dd, ad, n_it, alpha=0.5, burnin=1)
-        dref, aref, hist, _ = oscf.scf(og, d0, a0, n_it, alpha=0.5, burnin=1, accelerator="congacc")
+        it, res, conv = g.scf(dd, ad, n_it, alpha=alpha, burnin=1)
+        st = {}
+        dref, aref, hist, _ = oscf.scf(og, d0, a0, n_it, alpha=alpha, burnin=1, accelerator="congacc", stats=st)
         assert _close(dd.cpu().numpy()[:, m], dref[:, m], FP64_TOL)
         assert _close(ad.cpu().numpy(), aref, FP64_TOL)
         h = np.array(hist)
         fin = np.isfinite(h)
         assert np.max(np.abs(res[fin] - h[fin]) / np.maximum(np.abs(h[fin]), 1e-12)) < 1e-8
+        bis, anti = g.accel_stats()
+        assert st.get("bisect", 0) >= 1 and bis == st.get("bisect", 0) and anti == st.get("anti", 0)
+        if g.ncomp == 2:
+            assert {2, 3} <= st["bisect_components"]
         with pytest.raises(qs.QcError):
             g.scf(dd, ad, 2, norm_p=1)
         g.close()
@@ -373,6 +378,45 @@ def test_full_size_d110_square_400_sampled_cells(precision):
     g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_d110_square_400_three_maps_match_oracle(precision):
+    """The 400x400 [110] square with a vortex, field and kappa = 20 in the
+    benchmark's launch configuration: three iteration maps chained as
+    Picard with step 1 and the A-solve between them, so the second and third
+    maps start from the specular boundary taps of the previous one, against
+    the oracle's values stored by tests/golden/make_d110_square_400.py at
+    every cell of the four [110] edges (corners included) and 200 interior
+    cells: Delta_new, j and Omega_total of each map.  FP64 within 1e-10
+    (normwise and elementwise against the largest value); the mixed path
+    within 2e-5 Delta0 on Delta and 1e-4 of the largest |j| on j."""
+    import os
+    qs = _qs()
+    name = "d110_square_400"
+    sp = wl.spec(name)
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + "_iter3.npz"))
+    cells = gold["cells"]
+    _note("case %s %s: three chained maps vs the oracle at %d cells" % (name, precision, len(cells)))
+    g = qs.Grain(sp, precision)
+    d = _dev(wl.initial_delta(name, sp), torch.complex128)
+    a = _dev(wl.initial_A(name, sp), torch.float64)
+    for i in range(len(gold["omega_total"])):
+        dn, j, om = g.sweep(d, a)
+        dg = dn.cpu().numpy().reshape(1, -1)[:, cells]
+        jg = j.cpu().numpy().reshape(2, -1)[:, cells]
+        dref, jref, oref = gold["delta_new"][i], gold["j"][i], gold["omega_total"][i]
+        if precision == "fp64":
+            assert _close(dg, dref, FP64_TOL), (i, rel_err(dg, dref))
+            assert _close(jg, jref, FP64_TOL), (i, rel_err(jg, jref))
+            assert abs(om - oref) <= FP64_TOL * abs(oref), (i, om, oref)
+        else:
+            assert np.max(np.abs(dg - dref)) <= 2e-5 * wl.DELTA0, (i, np.max(np.abs(dg - dref)) / wl.DELTA0)
+            assert np.max(np.abs(jg - jref)) <= 1e-4 * np.max(np.abs(jref)), (i, np.max(np.abs(jg - jref)))
+            assert abs(om - oref) <= 1e-5 * abs(oref), (i, om, oref)
+        a, _ = g.solve_A(j, B=False)
+        d = dn
+    g.close()
+
+
 @pytest.mark.parametrize("name,precision", [("small_d110_field", "fp64"), ("small_mask_blob", "fp64"),
                                             ("small_holed_mixed", "fp64"), ("small_d110_field", "mixed")])
 def test_green_average_matches_oracle(name, precision):
@@ -456,3 +500,35 @@ def test_degenerate_inputs_match_oracle(case):
         assert abs(om - ref["omega_total"]) <= FP64_TOL * abs(ref["omega_total"])
     g.close()
 
+
+
+@pytest.mark.parametrize("name,precision", [("small_d110_field", "fp64"), ("small_holed_mixed", "fp64"),
+                                            ("small_polygon_landau", "fp64"), ("small_d110_field", "mixed")])
+def test_luttinger_ward_free_energy_matches_oracle(name, precision):
+    """The Luttinger-Ward free energy (Sec. II, Eqs. qcLWFE and qcLWFE_I):
+    4 Gauss-Legendre couplings with 2 burn-in sweeps each, density and total
+    against the oracle (FP64 1e-10; mixed 1e-4 of the largest density).  The
+    call leaves the grain's boundary store as it found it."""
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s %s: Luttinger-Ward free energy" % (name, precision))
+    g = qs.Grain(sp, precision)
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    g.sweep(dd, ad)
+    st = g.get_state().clone()
+    tot, dens = g.free_energy_lw(dd, ad, 4, 2, density=True)
+    ref_d, ref_t = og.free_energy_lw(d0, a0, 4, 2)
+    got = dens.cpu().numpy()
+    if precision == "fp64":
+        assert _close(got, ref_d, FP64_TOL), rel_err(got, ref_d)
+        assert abs(tot - ref_t) <= FP64_TOL * abs(ref_t)
+    else:
+        assert np.max(np.abs(got - ref_d)) <= 1e-4 * np.max(np.abs(ref_d))
+        assert abs(tot - ref_t) <= 1e-4 * abs(ref_t)
+    assert torch.equal(g.get_state(), st)
+    with pytest.raises(qs.QcError):
+        g.free_energy_lw(dd, ad, 0, 2)
+    g.close()
