@@ -102,6 +102,83 @@ def solve_A(jx, jy, mask, h, kappa, method="auto"):
     return s * ax, s * ay
 
 
+def green_matrix(n, h):
+    """The N x N matrix G_{m,n}, 0 <= m, n < N, of App. D (symmetric)."""
+    m = np.arange(n)
+    return green_kernel(m[:, None], m[None, :], h)
+
+
+def truncation_rank(lams, eps):
+    """N* of App. D: with the eigenvalues sorted by decreasing magnitude,
+    the smallest integer with sqrt(1 - sum_{n<N*} lam_n^2 / sum_n lam_n^2)
+    < eps (eps > 0).  The left side is evaluated as
+    sqrt(sum_{n>=N*} lam_n^2 / sum_n lam_n^2), equal in exact arithmetic,
+    so that tolerances below 1e-8 are not lost to the cancellation in
+    1 - (kept / total)."""
+    l2 = np.sort(np.abs(np.asarray(lams, dtype=np.float64)))[::-1] ** 2
+    tot = float(np.sum(l2))
+    # tail[k] = sum_{n >= k} lam_n^2, summed from the smallest
+    tail = np.concatenate([np.cumsum(l2[::-1])[::-1], [0.0]])
+    for k in range(len(l2) + 1):
+        if math.sqrt(tail[k] / tot) < eps:
+            return k
+    return len(l2)
+
+
+def green_eigen(n, h, eps):
+    """Eigen-decomposition of G (App. D), G = V Lambda V^T, truncated to the
+    N* eigenpairs of largest |lambda| (truncation_rank).  Returns (lam[N*],
+    V[N, N*]) with the eigenvectors as columns."""
+    lam, vec = np.linalg.eigh(green_matrix(n, h))
+    order = np.argsort(-np.abs(lam), kind="stable")
+    lam, vec = lam[order], vec[:, order]
+    k = truncation_rank(lam, eps)
+    return lam[:k], vec[:, :k]
+
+
+def solve_A_eigen(jx, jy, mask, h, kappa, eps):
+    """Induced vector potential with the separable, eigen-truncated kernel of
+    App. D on an N x N grid: with G_{a,b} = sum_k lam_k V_a^(k) V_b^(k),
+      A[r,c] = -kappa^-2 sum_{k<N*} lam_k sum_{r',c'} V^(k)_{|r'-r|} V^(k)_{|c'-c|} j'[r',c'],
+    i.e. A = -kappa^-2 sum_k lam_k T_k J' T_k with the symmetric Toeplitz
+    matrices T_k[a,b] = V^(k)_{|a-b|}; j' is the current minus its grain
+    mean on grain cells, zero elsewhere (as in solve_A).  eps = 0: no
+    decomposition, the full kernel (solve_A).  Returns (A_x, A_y, N*)."""
+    ny, nx = jx.shape
+    if ny != nx:
+        raise ValueError("the eigen-truncated kernel needs a square grid")
+    if kappa <= 0.0:
+        return np.zeros((ny, nx)), np.zeros((ny, nx)), 0
+    if eps <= 0.0:
+        ax, ay = solve_A(jx, jy, mask, h, kappa)
+        return ax, ay, nx
+    msk = mask.astype(bool)
+    jpx = np.where(msk, jx - jx[msk].mean(), 0.0)
+    jpy = np.where(msk, jy - jy[msk].mean(), 0.0)
+    lam, V = green_eigen(nx, h, eps)
+    idx = np.abs(np.arange(nx)[:, None] - np.arange(nx)[None, :])
+    ax = np.zeros((ny, nx))
+    ay = np.zeros((ny, nx))
+    for k in range(len(lam)):
+        T = V[idx, k]
+        ax += lam[k] * (T @ jpx @ T)
+        ay += lam[k] * (T @ jpy @ T)
+    s = -1.0 / (kappa * kappa)
+    return s * ax, s * ay, len(lam)
+
+
+def magnetic_moment(jx, jy, mask, X, Y, cx, cy):
+    """Magnetic moment of the in-plane current (Sec. V.A,
+    Eq. magnetic_moment_def), m = (N_l d / 2) int R x j dR, along z, in the
+    unit m0 = j0 xi0 V with V = N_l d A (A the grain area h^2 x grain
+    cells): m_z / m0 = (1 / (2 A)) h^2 sum over grain cells of
+    ((x - cx) j_y - (y - cy) j_x) at the cell centres X, Y, about the
+    origin (cx, cy) (reading: the grid centre).  The h^2 cancels."""
+    msk = np.asarray(mask, dtype=bool)
+    tq = (X - cx) * jy - (Y - cy) * jx
+    return float(np.sum(tq[msk])) / (2.0 * float(np.count_nonzero(msk)))
+
+
 def curl(ax, ay, h):
     """B = d_x A_y - d_y A_x with central differences inside and one-sided
     differences at the array edge (reading)."""

@@ -324,3 +324,104 @@ def test_luttinger_ward_propagator_term_is_linear_in_the_lambda_integrand():
     term = 2 * gr.gap_denominator()[0] * np.real(np.conj(delta[0]) * dn[0])
     base = gr.condensation_base(delta)
     assert np.max(np.abs(om - (base - np.where(gr.mask, term, 0)))) < 1e-15
+
+
+# ---- eigen-truncated A-solve and magnetic moment (App. D, Sec. V.A) ----
+
+def test_truncation_rank_is_the_smallest_count_meeting_the_tolerance():
+    """N* of App. D on a hand-made spectrum: lam^2 = 16, 4, 1, 1/4 (total
+    21.25); the tail norms sqrt(sum_{n>=k} lam^2 / total) are 1, 0.497,
+    0.2425, 0.1085, 0 for k = 0..4, in whatever order and sign the
+    eigenvalues come."""
+    lam = [0.5, -2.0, 4.0, 1.0]
+    assert fields.truncation_rank(lam, 1.1) == 0
+    assert fields.truncation_rank(lam, 0.5) == 1
+    assert fields.truncation_rank(lam, 0.3) == 2
+    assert fields.truncation_rank(lam, 0.11) == 3
+    assert fields.truncation_rank(lam, 0.1) == 4
+    assert fields.truncation_rank(lam, 1e-12) == 4
+
+
+def _random_current(n, seed):
+    rng = np.random.default_rng(seed)
+    X, Y = np.meshgrid(np.arange(n) - n / 2 + 0.5, np.arange(n) - n / 2 + 0.5)
+    mask = X ** 2 + Y ** 2 < (0.45 * n) ** 2
+    return rng.standard_normal((n, n)), rng.standard_normal((n, n)), mask
+
+
+def test_eigen_A_with_every_mode_is_the_direct_sum():
+    """With every eigenpair kept, sum_k lam_k T_k J T_k is the full
+    correlation with G (App. D): the eigen path equals the direct double
+    sum on a 24 x 24 grid to rounding, for both components."""
+    jx, jy, mask = _random_current(24, 5)
+    ax, ay = fields.solve_A(jx, jy, mask, 0.4, 2.5, method="direct")
+    ex, ey, nstar = fields.solve_A_eigen(jx, jy, mask, 0.4, 2.5, 1e-300)
+    assert nstar == 24
+    assert np.max(np.abs(ex - ax)) <= 1e-11 * np.max(np.abs(ax))
+    assert np.max(np.abs(ey - ay)) <= 1e-11 * np.max(np.abs(ay))
+
+
+def test_eigen_A_truncation_error_is_bounded_by_the_tolerance():
+    """Keeping N* modes changes the kernel by dK with ||dK||_F <= eps ||G||_F
+    (the criterion of App. D), so each A element moves by at most
+    2 kappa^-2 ||dK||_F ||j'||_2 (Cauchy-Schwarz; every offset appears at
+    most four times).  Checked at eps = 1e-3 on a 32 x 32 grid, where the
+    truncation keeps only a few modes."""
+    n, h, kappa, eps = 32, 0.5, 1.5, 1e-3
+    jx, jy, mask = _random_current(n, 6)
+    ax, ay = fields.solve_A(jx, jy, mask, h, kappa, method="direct")
+    ex, ey, nstar = fields.solve_A_eigen(jx, jy, mask, h, kappa, eps)
+    assert 1 <= nstar < n // 2
+    G = fields.green_matrix(n, h)
+    lam, V = fields.green_eigen(n, h, eps)
+    dK = np.linalg.norm(G - (V * lam) @ V.T)
+    assert dK < eps * np.linalg.norm(G)
+    for a, e, j in ((ax, ex, jx), (ay, ey, jy)):
+        jp = np.where(mask, j - j[mask].mean(), 0.0)
+        bound = 2.0 / kappa ** 2 * dK * np.linalg.norm(jp)
+        assert 0.0 < np.max(np.abs(e - a)) <= bound
+
+
+def test_magnetic_moment_of_a_rigidly_rotating_disc():
+    """j = w z x R on a disc of radius R (Sec. V.A, Eq. magnetic_moment_def):
+    m_z / m0 = (1 / 2A) int r^2 w dR = w R^2 / 4 in the continuum; the cell
+    sum converges to it as h -> 0."""
+    errs = []
+    for h in (0.4, 0.2, 0.1):
+        n = int(round(24.0 / h))
+        g = geo.Grid(n, n, h)
+        X, Y = g.centres()
+        mask = g.mask([geo.Disc(0.0, 0.0, 10.0)])
+        w = 0.3
+        m = fields.magnetic_moment(-w * Y, w * X, mask, X, Y, g.cx, g.cy)
+        errs.append(abs(m - w * 100.0 / 4.0) / (w * 100.0 / 4.0))
+    assert errs[-1] < 1e-2 and errs[-1] < errs[0]
+
+
+def test_magnetic_moment_of_an_annulus_with_azimuthal_current():
+    """Uniform azimuthal current j0 on R< <= r <= R>: m_z / m0 =
+    j0 2 pi (R>^3 - R<^3) / 3 / (2 pi (R>^2 - R<^2))."""
+    h, n, r1, r2, j0 = 0.1, 240, 4.0, 11.0, 0.7
+    g = geo.Grid(n, n, h)
+    X, Y = g.centres()
+    mask = g.mask([geo.Disc(0.0, 0.0, r2), geo.Disc(0.0, 0.0, r1, False)])
+    r = np.hypot(X, Y)
+    jx, jy = -j0 * Y / r, j0 * X / r
+    m = fields.magnetic_moment(jx, jy, mask, X, Y, g.cx, g.cy)
+    ref = j0 * (r2 ** 3 - r1 ** 3) / (3.0 * (r2 ** 2 - r1 ** 2))
+    assert abs(m - ref) < 5e-3 * ref
+
+
+def test_magnetic_moment_is_origin_independent_without_net_current():
+    """sum over cells of (R - O) x j does not depend on O when sum j = 0."""
+    n, h = 30, 0.5
+    g = geo.Grid(n, n, h)
+    X, Y = g.centres()
+    mask = g.mask([geo.Disc(0.0, 0.0, 6.5)])
+    rng = np.random.default_rng(8)
+    jx, jy = rng.standard_normal((2, n, n))
+    jx = np.where(mask, jx - jx[mask].mean(), 0.0)
+    jy = np.where(mask, jy - jy[mask].mean(), 0.0)
+    m0 = fields.magnetic_moment(jx, jy, mask, X, Y, g.cx, g.cy)
+    m1 = fields.magnetic_moment(jx, jy, mask, X, Y, g.cx + 3.7, g.cy - 1.2)
+    assert abs(m1 - m0) < 1e-12 * max(abs(m0), 1.0)
