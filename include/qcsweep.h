@@ -109,13 +109,21 @@ typedef struct {
  *   n_poles            positive Ozaki poles of the energy sums (Sec. III.A)
  *   t                  T/Tc, 0 < t
  *   ncomp, tc_rel      order-parameter components and their T_c,G / Tc
- *   eta                complex [ncomp][n_theta] basis values eta_G(phi_k)
- *                      (App. F table, crystal rotation applied by caller)
+ *   eta                complex [ncomp][n_theta] basis values eta_G(phi_k),
+ *                      or NULL: then basis[ncomp] (qc_basis) names each
+ *                      component's App. F function and the library
+ *                      tabulates eta_G(phi_k) = f_G(phi_k - 2 pi
+ *                      crystal_rotation) (rotation in full turns, App. B)
  *   kappa              penetration depth / xi0; <= 0 means infinite (A_ind=0)
  *   flux_quanta, gauge external field (App. B, App. F)
  *   charge_sign        +1 or -1 (sign of the carrier charge; -1 electrons)
  *   precision          qc_precision
  */
+/* Basis functions of App. F (circular Fermi surface), phi measured from the
+ * crystal a-axis: s = 1, d_{x2-y2} = sqrt2 cos 2 phi, d_xy = sqrt2 sin 2 phi,
+ * g_{xy(x2-y2)} = sqrt2 sin 4 phi. */
+typedef enum { QC_BASIS_S = 0, QC_BASIS_DX2Y2 = 1, QC_BASIS_DXY = 2, QC_BASIS_G = 3 } qc_basis;
+
 typedef struct {
   int nx, ny;
   double h;
@@ -133,6 +141,8 @@ typedef struct {
   int gauge;
   int charge_sign;
   int precision;
+  const int* basis;
+  double crystal_rotation;
 } qc_grain_desc;
 
 typedef struct qc_plan qc_plan;    /* host-side trajectory tables */
@@ -179,6 +189,17 @@ qc_status qc_plan_get_segments(const qc_plan* plan, double* out);
 qc_status qc_plan_get_taps(const qc_plan* plan, int at_start, int32_t* seg_out, double* w_out);
 /* z_out, r_out: host double [n_poles] Ozaki poles and residues. */
 qc_status qc_plan_get_poles(const qc_plan* plan, double* z_out, double* r_out);
+/* basis values eta_G(phi_k) the plan uses: host complex [ncomp][n_theta] */
+qc_status qc_plan_get_eta(const qc_plan* plan, double* eta_out);
+/* grain cells of a device grain: host uint8 [ny][nx], 1 inside */
+qc_status qc_grain_get_mask(const qc_grain* grain, uint8_t* mask_out);
+/* Angle pairs of the plan (see qc_grain_set_pairing): whether the tables of
+ * phi_k and phi_k + pi mirror each other, the trajectory steps a paired
+ * Matsubara sweep marches, and (optional, host int32 [n_segments]) the
+ * mirror segment on phi_k - pi of every segment of an angle phi_k >= pi
+ * (-1 for the others and when unavailable). */
+qc_status qc_plan_get_pairing(const qc_plan* plan, int* available, int64_t* swept_steps_per_sweep,
+                              int32_t* seg_mirror_out);
 
 /* ---- device grain -------------------------------------------------------- */
 /* Builds the plan and uploads it to `device`.  The boundary-value store
@@ -219,6 +240,34 @@ qc_status qc_sweep(qc_grain* grain, const double* delta, const double* A_ind,
  *   B_out  device double [ny][nx], may be NULL
  * With kappa <= 0 both outputs are zero. */
 qc_status qc_solve_A(qc_grain* grain, const double* j, double* A_out, double* B_out, void* stream);
+
+/* A-solve with the separable, eigen-truncated kernel of App. D on a square
+ * grid: G_{m,n} = sum_k lambda_k V_m^(k) V_n^(k) (eigen-decomposition of
+ * the N x N matrix G, done once on the host by Householder reduction and
+ * implicit QR), kept to the N* modes of largest |lambda| with N* the
+ * smallest count whose dropped remainder has
+ * sqrt(sum_dropped lambda^2 / sum_all lambda^2) < eps (the App. D
+ * criterion, summed over the dropped modes).  Then every A-solve of the
+ * grain (qc_solve_A, qc_scf_run, batches) computes
+ *   A = -kappa^-2 sum_k lambda_k T_k J' T_k,  T_k[a][b] = V^(k)_{|a-b|},
+ * as two FP64 matrix-core contractions per component (J' the current minus
+ * its grain mean on grain cells).  eps = 0 restores the exact zero-padded
+ * FFT correlation (the default).  Device memory: 2 (N* + 1) N^2 doubles.
+ * Errors: QC_ERR_INVALID for eps < 0 or, with eps > 0, nx != ny. */
+qc_status qc_grain_set_A_solver(qc_grain* grain, double eps);
+/* the tolerance set and the modes kept (0 for the FFT solve); either
+ * pointer may be NULL. */
+qc_status qc_grain_get_A_solver(const qc_grain* grain, double* eps, int* n_modes);
+
+/* Magnetic moment of the in-plane current (Sec. V.A,
+ * Eq. magnetic_moment_def) along z, per unit thickness, in units of
+ * m0 = j0 xi0 V (V = thickness x grain area):
+ *   m_z / m0 = (1 / 2A) h^2 sum over grain cells of (x - c_x) j_y - (y - c_y) j_x,
+ * about the grid centre (c_x, c_y), A = h^2 x (grain cells).
+ *   j     device double [2][ny][nx]
+ *   m_out host double
+ * Synchronises the stream. */
+qc_status qc_magnetic_moment(qc_grain* grain, const double* j, double* m_out, void* stream);
 
 /* Luttinger-Ward form of the free energy (Sec. II, Eqs. qcLWFE and
  * qcLWFE_I), the check on the Eilenberger form that qc_sweep returns: per
@@ -293,6 +342,30 @@ qc_status qc_scf_run(qc_grain* grain, double* delta_io, double* A_io, int max_it
  * Errors: QC_ERR_INVALID for an unknown kind or a Polyak drag outside (0, 1]. */
 qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
 
+/* Angle pairs.  For an order parameter even in the momentum direction
+ * (singlet pairing: every basis function of App. F), gamma~ along a
+ * trajectory is the complex conjugate of gamma along the reversed one
+ * (Sec. II.A: gamma~(p, e_n) = gamma(-p, e_n)*), and the rotated lattice of
+ * angle phi_k + pi is that of phi_k with both axes reversed (Sec. III.A).
+ * So the Matsubara sweeps of qc_sweep, qc_scf_run, qc_free_energy_lw and the
+ * batch march the angles phi_k < pi only: the node sums of phi_k + pi are
+ * those of the mirror node (S_f and S_I equal, S_g of opposite sign) and
+ * its end values the conjugates of the mirror segment's (stored, so the
+ * boundary store stays complete for every reader).  The result is the
+ * same map up to rounding, at half the marches.  Available when n_theta is
+ * even, the quadrature weights and basis values of phi_k and phi_k + pi
+ * agree, and the planner's tables of the two angles mirror each other
+ * exactly (same segments, node counts, slot positions within 1e-9 h and
+ * fallback cells); enabled by default when available.  LDOS, the Green's
+ * function average and the reverse mode always march every angle.  Set it
+ * before qc_batch_create for grains of a batch.
+ * Errors: QC_ERR_INVALID when enabling on a grain where it is unavailable. */
+qc_status qc_grain_set_pairing(qc_grain* grain, int enable);
+/* available / enabled flags and the trajectory steps one Matsubara sweep
+ * marches (steps_per_sweep of qc_plan_info counts every angle); any output
+ * pointer may be NULL. */
+qc_status qc_grain_get_pairing(const qc_grain* grain, int* available, int* enabled, int64_t* swept_steps_per_sweep);
+
 /* Counts, over the grain's lifetime, of the CongAcc weights that were set by
  * bisection and by the anti-parallel rule (see qc_grain_set_accelerator).
  * Either pointer may be NULL.  Errors: QC_ERR_INVALID for a NULL grain. */
@@ -308,6 +381,25 @@ qc_status qc_grain_get_accel_stats(const qc_grain* grain, int64_t* bisected, int
 qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,
                   const double* energies, int n_e, double broadening, int bc_iters,
                   double* ldos_out, void* stream);
+
+/* The LDOS as qc_ldos, with the boundary iteration run to convergence (the
+ * post-process of Sec. IV and App. B: burn-in until the LDOS settles):
+ * every iteration is a full output sweep whose start values are the
+ * previous sweep's end values (bulk roots at the first), and a block of
+ * energies stops after the sweep whose LDOS changed by less than tol in
+ * the relative 2-norm over all cells and the block's energies, or at
+ * max_iter.  Energies are processed in blocks of energies_per_block (0:
+ * the largest power of two up to 64 that fits half of the free device
+ * memory); blocks converge independently (the boundary condition couples
+ * angles, not energies).  The block that took the most sweeps gives
+ * iters_out; with one block the result equals qc_ldos with
+ * bc_iters = iters_out - 1.
+ *   ldos_out device double [n_e][ny][nx]; iters_out host int, may be NULL
+ * Errors: as qc_ldos, and QC_ERR_INVALID for max_iter < 1 or tol < 0. */
+qc_status qc_ldos_converge(qc_grain* grain, const double* delta, const double* A_ind,
+                           const double* energies, int n_e, double broadening, double tol,
+                           int max_iter, int energies_per_block, int* iters_out,
+                           double* ldos_out, void* stream);
 
 /* Reverse mode of the most recent qc_sweep on this grain (the map with the
  * boundary store it read held fixed; start values that are bulk roots of

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Grain", "Plan", "QcError", "lib", "basis_table", "spec_desc", "PRECISIONS", "sweep_autograd"]
+__all__ = ["Grain", "Plan", "QcError", "lib", "spec_desc", "PRECISIONS", "sweep_autograd"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqcsweep.so")
@@ -25,6 +25,7 @@ QC_OK, QC_NOT_CONVERGED = 0, 1
 PRECISIONS = {"fp64": 0, "mixed": 1}
 _SHAPES = {"disc": 0, "regular_polygon": 1, "polygon": 2, "mask": 3}
 _GAUGES = {"symmetric": 0, "landau": 1, "solenoid": 2}
+_BASIS = {"s": 0, "dx2y2": 1, "dxy": 2, "g": 3}
 
 
 class QcError(RuntimeError):
@@ -49,7 +50,8 @@ class _Desc(ctypes.Structure):
                 ("ncomp", ctypes.c_int), ("tc_rel", ctypes.POINTER(ctypes.c_double)),
                 ("eta", ctypes.POINTER(ctypes.c_double)), ("kappa", ctypes.c_double),
                 ("flux_quanta", ctypes.c_double), ("gauge", ctypes.c_int),
-                ("charge_sign", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("charge_sign", ctypes.c_int), ("precision", ctypes.c_int),
+                ("basis", ctypes.POINTER(ctypes.c_int)), ("crystal_rotation", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -85,21 +87,32 @@ _sig("qc_plan_get_mask", ctypes.c_int, [_P, _P])
 _sig("qc_plan_get_segments", ctypes.c_int, [_P, _P])
 _sig("qc_plan_get_taps", ctypes.c_int, [_P, ctypes.c_int, _P, _P])
 _sig("qc_plan_get_poles", ctypes.c_int, [_P, _P, _P])
+_sig("qc_plan_get_eta", ctypes.c_int, [_P, _P])
+_sig("qc_plan_get_pairing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64), _P])
 _sig("qc_grain_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_Desc), ctypes.POINTER(_P)])
 _sig("qc_grain_destroy", None, [_P])
 _sig("qc_grain_get_info", ctypes.c_int, [_P, ctypes.POINTER(_Info)])
+_sig("qc_grain_get_mask", ctypes.c_int, [_P, _P])
 _sig("qc_grain_reset_bc", ctypes.c_int, [_P])
 _sig("qc_grain_get_lanes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)])
 _sig("qc_sweep", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P])
 _sig("qc_solve_A", ctypes.c_int, [_P, _P, _P, _P, _P])
+_sig("qc_grain_set_A_solver", ctypes.c_int, [_P, ctypes.c_double])
+_sig("qc_grain_get_A_solver", ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int)])
+_sig("qc_magnetic_moment", ctypes.c_int, [_P, _P, _D, _P])
 _sig("qc_scf_run", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int), _P, _P])
 _sig("qc_ldos", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P])
+_sig("qc_ldos_converge", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int), _P, _P])
 _sig("qc_sweep_adjoint", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P])
 _sig("qc_green_average", ctypes.c_int, [_P, _P, _P, _P, _P])
 _sig("qc_free_energy_lw", ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _D, _P])
 _sig("qc_grain_set_adjoint_checkpoint", ctypes.c_int, [_P, ctypes.c_int])
 _sig("qc_grain_set_accelerator", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double])
+_sig("qc_grain_set_pairing", ctypes.c_int, [_P, ctypes.c_int])
+_sig("qc_grain_get_pairing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int64)])
 _sig("qc_grain_get_accel_stats", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)])
 _sig("qc_get_state", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P])
 _sig("qc_batch_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P)])
@@ -135,27 +148,6 @@ def valu_rate(op, device=0):
     v = ctypes.c_double()
     _check(lib.qc_valu_rate(int(device), ["fma", "rsq", "sqrt", "rcp"].index(op), ctypes.byref(v)))
     return v.value
-
-
-def basis_table(components, n_theta, crystal_rotation=0.0):
-    """eta_G(phi_k) for the basis functions of App. F (circular Fermi
-    surface) at phi_k = 2 pi k / n_theta, rotated by the crystal-axes angle
-    (in full turns): s = 1, dx2y2 = sqrt2 cos 2phi, dxy = sqrt2 sin 2phi,
-    g = sqrt2 sin 4phi.  Returns complex [ncomp][n_theta]."""
-    phi = np.array([2.0 * math.pi * k / n_theta for k in range(n_theta)]) - 2.0 * math.pi * crystal_rotation
-    rows = []
-    for name, _tc in components:
-        if name == "s":
-            rows.append(np.ones(n_theta))
-        elif name == "dx2y2":
-            rows.append(math.sqrt(2.0) * np.cos(2.0 * phi))
-        elif name == "dxy":
-            rows.append(math.sqrt(2.0) * np.sin(2.0 * phi))
-        elif name == "g":
-            rows.append(math.sqrt(2.0) * np.sin(4.0 * phi))
-        else:
-            raise ValueError("unknown basis function %r" % (name,))
-    return np.array(rows, dtype=np.complex128)
 
 
 class _DescHolder:
@@ -195,12 +187,14 @@ class _DescHolder:
                 s.mask = mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         self.keep.append(shapes)
         n_theta = int(spec["n_theta"])
+        # the basis functions by name (the library tabulates them), or an
+        # explicit eta table when the spec gives one
         eta = spec.get("eta")
-        if eta is None:
-            eta = basis_table(comps, n_theta, spec.get("crystal_rotation", 0.0))
-        eta = np.ascontiguousarray(np.asarray(eta, dtype=np.complex128).reshape(len(comps), n_theta))
+        if eta is not None:
+            eta = np.ascontiguousarray(np.asarray(eta, dtype=np.complex128).reshape(len(comps), n_theta))
+        basis = np.ascontiguousarray([_BASIS[c[0]] for c in comps], dtype=np.int32)
         tc = np.ascontiguousarray([float(c[1]) for c in comps], dtype=np.float64)
-        self.keep += [eta, tc]
+        self.keep += [eta, basis, tc]
         d = _Desc()
         d.nx, d.ny, d.h, d.x0, d.y0 = nx, ny, h, x0, y0
         d.shapes = shapes
@@ -210,7 +204,9 @@ class _DescHolder:
         d.t = float(spec["t"])
         d.ncomp = len(comps)
         d.tc_rel = tc.ctypes.data_as(_D)
-        d.eta = eta.ctypes.data_as(_D)
+        d.eta = eta.ctypes.data_as(_D) if eta is not None else None
+        d.basis = basis.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.crystal_rotation = float(spec.get("crystal_rotation", 0.0))
         d.kappa = float(spec.get("kappa", 0.0))
         d.flux_quanta = float(spec.get("flux_quanta", 0.0))
         d.gauge = _GAUGES[spec.get("gauge", "symmetric")]
@@ -270,6 +266,20 @@ class Plan:
         r = np.zeros(n)
         _check(lib.qc_plan_get_poles(self._p, z.ctypes.data, r.ctypes.data))
         return z, r
+
+    def eta(self):
+        """Basis values eta_G(phi_k) of the plan, complex [ncomp, n_theta]."""
+        out = np.zeros((self._h.desc.ncomp, self._h.desc.n_theta), dtype=np.complex128)
+        _check(lib.qc_plan_get_eta(self._p, out.ctypes.data))
+        return out
+
+    def pairing(self):
+        """(available, swept steps per paired sweep, mirror segment per segment)."""
+        a = ctypes.c_int(0)
+        n = ctypes.c_int64(0)
+        mir = np.zeros(self.info["n_segments"], dtype=np.int32)
+        _check(lib.qc_plan_get_pairing(self._p, ctypes.byref(a), ctypes.byref(n), mir.ctypes.data))
+        return bool(a.value), n.value, mir
 
 
 def _torch():
@@ -373,6 +383,12 @@ class Grain:
     def _dev(self):
         return _torch().device("cuda", self.device)
 
+    def mask(self):
+        """Grain cells, bool [ny, nx]."""
+        m = np.zeros((self.ny, self.nx), dtype=np.uint8)
+        _check(lib.qc_grain_get_mask(self._g, m.ctypes.data))
+        return m.astype(bool)
+
     def reset_bc(self):
         _check(lib.qc_grain_reset_bc(self._g))
 
@@ -405,6 +421,25 @@ class Grain:
                               ctypes.c_void_p(Bt.data_ptr()) if Bt is not None else None, _stream(stream)))
         return A, Bt
 
+    def set_A_solver(self, eps):
+        """eps > 0: eigen-truncated separable A-solve (square grids); 0: FFT."""
+        _check(lib.qc_grain_set_A_solver(self._g, float(eps)))
+
+    def A_solver(self):
+        """(eps, modes kept)."""
+        e = ctypes.c_double(0.0)
+        n = ctypes.c_int(0)
+        _check(lib.qc_grain_get_A_solver(self._g, ctypes.byref(e), ctypes.byref(n)))
+        return e.value, n.value
+
+    def magnetic_moment(self, j, stream=None):
+        """m_z / m0 of the current j [2, ny, nx] about the grid centre."""
+        torch = _torch()
+        jp = _dptr(j, torch.float64, (2, self.ny, self.nx), "j")
+        m = ctypes.c_double(0.0)
+        _check(lib.qc_magnetic_moment(self._g, jp, ctypes.byref(m), _stream(stream)))
+        return m.value
+
     def scf(self, delta, A, max_iter, min_iter=0, burnin=0, tol=0.0, norm_p=2, alpha=1.0, stream=None):
         """SCF in place on (delta, A) with the grain's accelerator (Picard
         unless set_accelerator chose Polyak); returns (iters,
@@ -427,6 +462,20 @@ class Grain:
         _check(lib.qc_ldos(self._g, dp, ap, e.ctypes.data, len(e), float(broadening), int(bc_iters),
                            ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out
+
+    def ldos_converge(self, delta, A, energies, broadening, tol, max_iter, energies_per_block=0, stream=None):
+        """LDOS with the boundary iteration run until it changes by less than
+        tol; returns (ldos [E, ny, nx], sweeps of the slowest block)."""
+        torch = _torch()
+        dp = _dptr(delta, torch.complex128, (self.ncomp, self.ny, self.nx), "delta")
+        ap = _dptr(A, torch.float64, (2, self.ny, self.nx), "A")
+        e = np.ascontiguousarray(energies, dtype=np.float64)
+        out = torch.empty((len(e), self.ny, self.nx), dtype=torch.float64, device=self._dev())
+        it = ctypes.c_int(0)
+        _check(lib.qc_ldos_converge(self._g, dp, ap, e.ctypes.data, len(e), float(broadening), float(tol),
+                                    int(max_iter), int(energies_per_block), ctypes.byref(it),
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out, it.value
 
     def sweep_adjoint(self, delta, A, g_delta_new=None, g_j=None, g_omega=0.0, stream=None):
         """Reverse mode of the most recent sweep: returns (grad_delta, grad_A)
@@ -487,6 +536,19 @@ class Grain:
         scf's alpha the first; 2-norm residuals)."""
         k = {"picard": 0, "polyak": 1, "bb": 2, "congacc": 3}[kind]
         _check(lib.qc_grain_set_accelerator(self._g, k, float(beta)))
+
+    def set_pairing(self, enable):
+        """Angle pairs (phi_k, phi_k + pi) in the Matsubara sweeps: one march
+        serves both directions (on by default where the tables allow it)."""
+        _check(lib.qc_grain_set_pairing(self._g, 1 if enable else 0))
+
+    def pairing(self):
+        """(available, enabled, trajectory steps one Matsubara sweep marches)."""
+        a = ctypes.c_int(0)
+        e = ctypes.c_int(0)
+        n = ctypes.c_int64(0)
+        _check(lib.qc_grain_get_pairing(self._g, ctypes.byref(a), ctypes.byref(e), ctypes.byref(n)))
+        return bool(a.value), bool(e.value), n.value
 
     def accel_stats(self):
         """(bisected, anti_parallel): CongAcc weights set by bisection and by

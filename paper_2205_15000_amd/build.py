@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libqcsweep.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "sweep.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["plan.cpp", "sweep.hip", "adjoint.hip", "vecpot.hip", "api.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -125,11 +125,18 @@ void check_desc(const qc_grain_desc* d) {
   if (d->n_poles < 1 || d->n_poles > 512) throw std::invalid_argument("n_poles must be in [1, 512]");
   if (!(d->t > 0.0) || !std::isfinite(d->t)) throw std::invalid_argument("t must be finite and > 0");
   if (d->ncomp < 1 || d->ncomp > 4) throw std::invalid_argument("ncomp must be in [1, 4]");
-  if (!d->tc_rel || !d->eta) throw std::invalid_argument("tc_rel and eta are required");
+  if (!d->tc_rel) throw std::invalid_argument("tc_rel is required");
+  if (!d->eta && !d->basis) throw std::invalid_argument("either eta or basis is required");
+  if (!d->eta) {
+    if (!std::isfinite(d->crystal_rotation)) throw std::invalid_argument("crystal_rotation must be finite");
+    for (int c = 0; c < d->ncomp; ++c)
+      if (d->basis[c] < QC_BASIS_S || d->basis[c] > QC_BASIS_G) throw std::invalid_argument("unknown basis function");
+  }
   for (int g = 0; g < d->ncomp; ++g)
     if (!(d->tc_rel[g] > 0.0) || !std::isfinite(d->tc_rel[g])) throw std::invalid_argument("tc_rel must be > 0");
-  for (int64_t i = 0; i < 2LL * d->ncomp * d->n_theta; ++i)
-    if (!std::isfinite(d->eta[i])) throw std::invalid_argument("eta must be finite");
+  if (d->eta)
+    for (int64_t i = 0; i < 2LL * d->ncomp * d->n_theta; ++i)
+      if (!std::isfinite(d->eta[i])) throw std::invalid_argument("eta must be finite");
   if (!std::isfinite(d->kappa) || !std::isfinite(d->flux_quanta)) throw std::invalid_argument("kappa/flux must be finite");
   if (d->gauge < 0 || d->gauge > 2) throw std::invalid_argument("gauge must be 0, 1 or 2");
   if (d->charge_sign != 1 && d->charge_sign != -1) throw std::invalid_argument("charge_sign must be +1 or -1");
@@ -162,7 +169,14 @@ void fill_plan_inputs(const qc_grain_desc* d, qc::Plan& p) {
   p.ncomp = d->ncomp;
   p.tc_rel.assign(d->tc_rel, d->tc_rel + d->ncomp);
   p.eta.resize(static_cast<size_t>(d->ncomp) * d->n_theta);
-  for (size_t i = 0; i < p.eta.size(); ++i) p.eta[i] = {d->eta[2 * i], d->eta[2 * i + 1]};
+  if (d->eta) {
+    for (size_t i = 0; i < p.eta.size(); ++i) p.eta[i] = {d->eta[2 * i], d->eta[2 * i + 1]};
+  } else {
+    for (int c = 0; c < d->ncomp; ++c)
+      for (int k = 0; k < d->n_theta; ++k)
+        p.eta[static_cast<size_t>(c) * d->n_theta + k] =
+            qc::basis_eta(d->basis[c], 2.0 * kPi * k / d->n_theta - 2.0 * kPi * d->crystal_rotation);
+  }
   p.kappa = d->kappa;
   p.flux = d->flux_quanta;
   p.gauge = d->gauge;
@@ -332,6 +346,22 @@ struct qc_grain {
   double* cpart_host = nullptr;
   // CongAcc weights set by bisection and by the anti-parallel rule
   int64_t cong_bisect = 0, cong_anti = 0;
+  // angle pairs (k, k + n_theta/2): the sweep of the Matsubara iteration
+  // runs the lower angles only (see build_pairs); pair_ok when the tables
+  // allow it, pairing when it is in use
+  bool pair_ok = false, pairing = false;
+  int64_t nseg_pair = 0, nslot_pair = 0, npairs = 0;
+  int32_t* order_pair = nullptr;
+  int4* rb4_pair = nullptr;
+  int2* mirror_pairs = nullptr;
+  // eigen-truncated A-solve (App. D): tolerance, kept modes, eigenvalues and
+  // eigenvectors [a_nmodes][nx], masked current and per-mode products
+  double a_eps = 0.0;
+  int a_nmodes = 0;
+  double* a_lam = nullptr;
+  double* a_vk = nullptr;
+  double* a_jp = nullptr;
+  double* a_y = nullptr;
   // Luttinger-Ward free energy: per-cell lambda integral, lambda Delta, and
   // the boundary store kept aside while the lambda sweeps run
   double* lw_acc = nullptr;
@@ -391,7 +421,8 @@ void free_grain(qc_grain* g) {
                   g->bc[0][1], g->bc[1][0], g->bc[1][1], g->omega_cell, g->dmean, g->part, g->bbuf, g->fw, g->fw2,
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->vel_d, g->vel_a, g->gtbuf, g->lgt, g->gS, g->gV,
                   g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw,
-                  g->ckbase, g->ckg, g->ckgt, g->ckscr, g->lw_acc, g->lw_dl, g->lw_save};
+                  g->ckbase, g->ckg, g->ckgt, g->ckscr, g->lw_acc, g->lw_dl, g->lw_save, g->order_pair, g->rb4_pair,
+                  g->mirror_pairs, g->a_lam, g->a_vk, g->a_jp, g->a_y};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
@@ -463,7 +494,8 @@ qc::BackArgs back_args(qc_grain* g, const double* delta, double* dnew, double* j
   r.ncomp = g->ncomp;
   r.n_theta = g->n_theta;
   r.grain_cells = g->grain_cells;
-  r.rb4 = g->rb4;
+  r.rb4 = g->pairing ? g->rb4_pair : g->rb4;
+  r.pair_k0 = g->pairing ? g->n_theta / 2 : g->n_theta;
   r.nx = g->nx;
   r.x0 = g->x0;
   r.y0 = g->y0;
@@ -488,10 +520,13 @@ qc::BackArgs back_args(qc_grain* g, const double* delta, double* dnew, double* j
   return r;
 }
 
-void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st) {
+// node values of every slot, or (pair) of the slots of the lower angles of
+// the angle pairs only
+void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st, bool pair = false) {
   qc::InterpArgs a;
-  a.nslot = g->nslot;
-  a.nseg = g->nseg;
+  pair = pair && g->pairing;
+  a.nslot = pair ? g->nslot_pair : g->nslot;
+  a.nseg = pair ? g->nseg_pair : g->nseg;
   a.ncell = g->ncell;
   a.ncomp = g->ncomp;
   a.n_theta = g->n_theta;
@@ -521,10 +556,14 @@ void do_interp(qc_grain* g, const double* delta, const double* A, hipStream_t st
     qc::launch_interp<double>(a, cells, g->nodes, st);
 }
 
-qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const double* eps, const double* rp) {
+// arguments of a sweep over every segment, or (pair) over the segments of
+// the lower angles of the angle pairs
+qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const double* eps, const double* rp,
+                         bool pair = false) {
   qc::SweepArgs a;
-  a.nseg = g->nseg;
-  a.order = g->order;
+  pair = pair && g->pairing;
+  a.nseg = pair ? g->nseg_pair : g->nseg;
+  a.order = pair ? g->order_pair : g->order;
   int epl;
   lane_shape(n_e, g->epl_override, g->precision == QC_MIXED, a.G, epl);
   a.log2g = ilog2(a.G);
@@ -570,6 +609,16 @@ void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc:
   }
 }
 
+// the end values of the upper angles of the pairs, from their mirrors, so
+// that the boundary store is complete for every reader
+void mirror_fill(qc_grain* g, void* bc_g, void* bc_gt, hipStream_t st) {
+  if (!g->pairing) return;
+  if (g->precision == QC_MIXED)
+    qc::launch_mirror_fill<float>(g->mirror_pairs, g->npairs, g->n_poles, bc_g, bc_gt, st);
+  else
+    qc::launch_mirror_fill<double>(g->mirror_pairs, g->npairs, g->n_poles, bc_g, bc_gt, st);
+}
+
 double omega_from_parts(const qc_grain* g) {
   double tot = g->h * g->h * region_sum(g, kROmega);
   if (g->kappa > 0.0) tot += g->h * g->h * 0.5 * g->kappa * g->kappa * region_sum(g, kRB2);
@@ -598,8 +647,8 @@ void ensure_sweep_buffers(qc_grain* g, bool spill = true) {
 void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_new, double* j, double* omega,
               double* omega_total, hipStream_t st, bool zero_out = true) {
   ensure_sweep_buffers(g);
-  do_interp(g, delta, A, st);
-  qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
+  do_interp(g, delta, A, st, true);
+  qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd, true);
   a.bc_valid = g->bc_valid;
   qc::SweepBufs b;
   b.nodes = g->nodes;
@@ -610,6 +659,7 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   b.gbuf = g->gbuf;
   b.ebuf = nullptr;
   launch_sweep_timed(g, 0, a, b, st);
+  mirror_fill(g, b.bc_g_next, b.bc_gt_next, st);
   g->last_bc_valid = g->bc_valid;
   g->bc_cur = 1 - g->bc_cur;
   g->bc_valid = 1;
@@ -753,6 +803,32 @@ qc_status qc_plan_get_poles(const qc_plan* plan, double* z_out, double* r_out) {
   return QC_OK;
 }
 
+qc_status qc_plan_get_eta(const qc_plan* plan, double* eta_out) {
+  if (!plan || !eta_out) return fail(QC_ERR_INVALID, "NULL argument");
+  const qc::Plan& p = plan->p;
+  for (size_t i = 0; i < p.eta.size(); ++i) {
+    eta_out[2 * i] = p.eta[i].real();
+    eta_out[2 * i + 1] = p.eta[i].imag();
+  }
+  return QC_OK;
+}
+
+qc_status qc_plan_get_pairing(const qc_plan* plan, int* available, int64_t* swept_steps_per_sweep,
+                              int32_t* seg_mirror_out) {
+  if (!plan) return fail(QC_ERR_INVALID, "plan is NULL");
+  const qc::Plan& p = plan->p;
+  if (available) *available = p.pair_ok ? 1 : 0;
+  if (swept_steps_per_sweep) {
+    int64_t s = 0;
+    const int64_t nsw = p.pair_ok ? p.nseg_pair : p.nseg;
+    for (int64_t k = 0; k < nsw; ++k) s += p.seg_n[k] + 1;
+    *swept_steps_per_sweep = 2 * static_cast<int64_t>(p.n_poles) * s;
+  }
+  if (seg_mirror_out)
+    for (int64_t k = 0; k < p.nseg; ++k) seg_mirror_out[k] = p.pair_ok ? p.seg_mirror[k] : -1;
+  return QC_OK;
+}
+
 qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out) {
   if (!out) return fail(QC_ERR_INVALID, "out is NULL");
   *out = nullptr;
@@ -865,6 +941,21 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
       std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return p.seg_n[x] > p.seg_n[y]; });
       g->order = static_cast<int32_t*>(upload(ord));
     }
+    if (p.pair_ok) {
+      std::vector<int32_t> ord(static_cast<size_t>(p.nseg_pair));
+      for (int64_t k = 0; k < p.nseg_pair; ++k) ord[k] = static_cast<int32_t>(k);
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return p.seg_n[x] > p.seg_n[y]; });
+      g->order_pair = static_cast<int32_t*>(upload(ord));
+      g->rb4_pair = static_cast<int4*>(upload(p.rb4_pair));
+      std::vector<int2> mp;
+      for (int64_t sg = p.nseg_pair; sg < p.nseg; ++sg) mp.push_back(make_int2(static_cast<int>(sg), p.seg_mirror[sg]));
+      g->mirror_pairs = static_cast<int2*>(upload(mp));
+      g->npairs = static_cast<int64_t>(mp.size());
+      g->nseg_pair = p.nseg_pair;
+      g->nslot_pair = p.nslot_pair;
+      g->pair_ok = true;
+      g->pairing = true;
+    }
     // gbuf, node_out and the boundary store are allocated by the first sweep
     g->omega_cell = static_cast<double*>(dalloc(sizeof(double) * g->ncg));
     g->part = static_cast<double*>(dalloc(sizeof(double) * kRegions * kParts));
@@ -916,6 +1007,15 @@ void qc_grain_destroy(qc_grain* grain) {
   free_grain(grain);
 }
 
+qc_status qc_grain_get_mask(const qc_grain* grain, uint8_t* mask_out) {
+  if (!grain || !mask_out) return fail(QC_ERR_INVALID, "NULL argument");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(grain->device), "hipSetDevice");
+    hcheck(hipMemcpy(mask_out, grain->mask, static_cast<size_t>(grain->ncell), hipMemcpyDeviceToHost), "copy");
+    return QC_OK;
+  });
+}
+
 qc_status qc_grain_get_info(const qc_grain* grain, qc_plan_info* out) {
   if (!grain || !out) return fail(QC_ERR_INVALID, "NULL argument");
   *out = grain->info;
@@ -954,6 +1054,15 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
   qc::launch_block_sum(j, g->grain_cells, g->ncg, 0, region(g, kRJx), kParts, st);
   qc::launch_block_sum(j + g->ncell, g->grain_cells, g->ncg, 0, region(g, kRJy), kParts, st);
   qc::launch_means(region(g, kRJx), kParts, 1.0 / static_cast<double>(g->ncg), g->dmean, st);
+  if (g->a_nmodes > 0) {
+    // the separable kernel kept to its largest modes: two MFMA contractions
+    qc::launch_masked_current(j, g->mask, g->ncell, g->dmean, g->a_jp, st);
+    qc::launch_eig_vecpot(g->nx, g->a_nmodes, g->a_jp, g->a_vk, g->a_lam, g->a_y, A_out,
+                          -1.0 / (g->kappa * g->kappa), st);
+    if (B_out) qc::launch_curl(A_out, B_out, g->nx, g->ny, g->h, st);
+    hcheck(hipGetLastError(), "A-solve launch");
+    return;
+  }
   qc::launch_pad_current(j, g->mask, g->nx, g->ny, g->px, g->py, g->dmean, g->fw, st);
   // the padded current is zero beyond row ny, and only rows < ny of the
   // correlation are kept; the product with the kernel's transform is taken
@@ -1113,6 +1222,79 @@ qc_status qc_free_energy_lw(qc_grain* g, const double* delta, const double* A_in
              "copy");
     }
     hcheck(hipStreamSynchronize(st), "sync");
+    return QC_OK;
+  });
+}
+
+// N* of App. D: the smallest count of the largest-|lambda| modes whose
+// dropped remainder has sqrt(sum lambda^2 (dropped) / sum lambda^2 (all))
+// below eps (summed over the dropped modes directly, not as 1 - kept/total)
+static int kept_modes(const std::vector<double>& lam_sorted, double eps) {
+  const int n = static_cast<int>(lam_sorted.size());
+  std::vector<double> tail(n + 1, 0.0);
+  for (int k = n - 1; k >= 0; --k) tail[k] = tail[k + 1] + lam_sorted[k] * lam_sorted[k];
+  for (int k = 0; k <= n; ++k)
+    if (std::sqrt(tail[k] / tail[0]) < eps) return k;
+  return n;
+}
+
+qc_status qc_grain_set_A_solver(qc_grain* g, double eps) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(QC_ERR_INVALID, "eps must be finite and >= 0");
+  if (eps > 0.0 && g->nx != g->ny) return fail(QC_ERR_INVALID, "the eigen-truncated A-solve needs a square grid");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    hcheck(hipDeviceSynchronize(), "sync");
+    for (double** p : {&g->a_lam, &g->a_vk, &g->a_jp, &g->a_y})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    g->a_nmodes = 0;
+    g->a_eps = eps;
+    if (eps == 0.0) return QC_OK;
+    const int n = g->nx;
+    std::vector<double> G(static_cast<size_t>(n) * n);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) G[static_cast<size_t>(a) * n + b] = green_mn(a, b, g->h);
+    std::vector<double> lam, vec;
+    qc::sym_eigen(n, G, lam, vec);
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return std::fabs(lam[x]) > std::fabs(lam[y]); });
+    std::vector<double> ls(n);
+    for (int i = 0; i < n; ++i) ls[i] = lam[ord[i]];
+    const int nk = std::max(kept_modes(ls, eps), 1);
+    std::vector<double> lk(nk), vk(static_cast<size_t>(nk) * n);
+    for (int k = 0; k < nk; ++k) {
+      lk[k] = ls[k];
+      for (int a = 0; a < n; ++a) vk[static_cast<size_t>(k) * n + a] = vec[static_cast<size_t>(a) * n + ord[k]];
+    }
+    g->a_lam = static_cast<double*>(upload(lk));
+    g->a_vk = static_cast<double*>(upload(vk));
+    g->a_jp = static_cast<double*>(dalloc(sizeof(double) * 2 * g->ncell));
+    g->a_y = static_cast<double*>(dalloc(sizeof(double) * 2 * static_cast<size_t>(nk) * g->ncell));
+    g->a_nmodes = nk;
+    return QC_OK;
+  });
+}
+
+qc_status qc_grain_get_A_solver(const qc_grain* g, double* eps, int* n_modes) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (eps) *eps = g->a_eps;
+  if (n_modes) *n_modes = g->a_nmodes;
+  return QC_OK;
+}
+
+qc_status qc_magnetic_moment(qc_grain* g, const double* j, double* m_out, void* stream) {
+  if (!g || !j || !m_out) return fail(QC_ERR_INVALID, "grain, j and m_out are required");
+  return guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    qc::launch_torque(j, g->grain_cells, g->ncg, g->ncell, g->nx, g->x0, g->y0, g->h, g->cx, g->cy, g->bbuf, st);
+    qc::launch_block_sum(g->bbuf, nullptr, g->ncg, 0, region(g, kRJx), kParts, st);
+    fetch_parts(g, st);
+    *m_out = region_sum(g, kRJx) / (2.0 * static_cast<double>(g->ncg));
     return QC_OK;
   });
 }
@@ -1385,6 +1567,125 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
   if (deps) (void)hipFree(deps);
   if (lg) (void)hipFree(lg);
   if (le) (void)hipFree(le);
+  return rs;
+}
+
+qc_status qc_ldos_converge(qc_grain* g, const double* delta, const double* A_ind, const double* energies, int n_e,
+                           double broadening, double tol, int max_iter, int energies_per_block, int* iters_out,
+                           double* ldos_out, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !energies || !ldos_out) return fail(QC_ERR_INVALID, "NULL argument");
+  if (n_e < 1 || max_iter < 1 || energies_per_block < 0) return fail(QC_ERR_INVALID, "bad n_e, max_iter or block");
+  if (!(broadening > 0.0) || !std::isfinite(broadening)) return fail(QC_ERR_INVALID, "broadening must be > 0");
+  if (!(tol >= 0.0)) return fail(QC_ERR_INVALID, "tol must be >= 0");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(energies[i])) return fail(QC_ERR_INVALID, "energies must be finite");
+  void* bcl[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  double* deps = nullptr;
+  double* prev = nullptr;
+  void* lg = nullptr;
+  void* le = nullptr;
+  qc_status rs = guarded([&]() -> qc_status {
+    hipStream_t st = S(stream);
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    const size_t rb = g->real_bytes();
+    std::vector<double> eps(2 * n_e);
+    for (int i = 0; i < n_e; ++i) {
+      eps[2 * i] = energies[i];
+      eps[2 * i + 1] = broadening;
+    }
+    deps = static_cast<double*>(upload(eps));
+    do_interp(g, delta, A_ind, st);
+    // energy block: the caller's, or the largest power of two up to 64 whose
+    // gamma rows fit in half of the free device memory
+    int blk = energies_per_block;
+    if (blk == 0) {
+      size_t free_b = 0, total_b = 0;
+      hcheck(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      const double budget = std::max(static_cast<double>(1 << 30), 0.5 * static_cast<double>(free_b));
+      const double per_e = static_cast<double>(g->nslot) * 3.0 * rb + 4.0 * rb * g->nseg;
+      blk = 64;
+      while (blk > 1 && blk * per_e > budget) blk >>= 1;
+    }
+    blk = std::min(blk, n_e);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) bcl[a][b] = dalloc(2 * rb * g->nseg * blk);
+    lg = dalloc(2 * rb * g->nslot * blk);
+    le = dalloc(rb * g->nslot * blk);
+    prev = static_cast<double*>(dalloc(sizeof(double) * blk * g->ncell));
+    qc::launch_fill(ldos_out, static_cast<int64_t>(n_e) * g->ncell, 0.0, st);
+    int worst = 0;
+    for (int e0 = 0; e0 < n_e; e0 += blk) {
+      const int ne = std::min(blk, n_e - e0);
+      double* out = ldos_out + static_cast<int64_t>(e0) * g->ncell;
+      int cur = 0, it = 0;
+      for (; it < max_iter; ++it) {
+        // one output sweep of the block from the previous end values (bulk
+        // roots at the first), which also stores this sweep's end values
+        qc::SweepArgs a = sweep_args(g, ne, ne, 0, deps + 2 * e0, nullptr);
+        a.bc_valid = it > 0;
+        qc::SweepBufs b;
+        b.nodes = g->nodes;
+        b.bc_g_prev = bcl[cur][0];
+        b.bc_gt_prev = bcl[cur][1];
+        b.bc_g_next = bcl[1 - cur][0];
+        b.bc_gt_next = bcl[1 - cur][1];
+        b.gbuf = lg;
+        b.ebuf = le;
+        launch_sweep_timed(g, 1, a, b, st);
+        cur = 1 - cur;
+        if (it > 0)
+          hcheck(hipMemcpyAsync(prev, out, sizeof(double) * ne * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
+        qc::LdosBackArgs la;
+        la.ncg = g->ncg;
+        la.ncell = g->ncell;
+        la.n_theta = g->n_theta;
+        la.n_e = ne;
+        la.e_off = 0;
+        la.grain_cells = g->grain_cells;
+        la.rb_idx = g->rb_idx;
+        la.rb_w = g->rb_w;
+        la.wk = g->wk;
+        la.out = out;
+        if (g->precision == QC_MIXED)
+          qc::launch_ldos_back<float>(la, le, st);
+        else
+          qc::launch_ldos_back<double>(la, le, st);
+        hcheck(hipGetLastError(), "ldos launch");
+        if (it == 0) continue;
+        // relative 2-norm change of the block's LDOS (every cell; zero off the grain)
+        qc::DiffNormArgs dn;
+        dn.xnew = out;
+        dn.xold = prev;
+        dn.idx = nullptr;
+        dn.n = static_cast<int64_t>(ne) * g->ncell;
+        dn.nrep = 1;
+        dn.field_stride = 0;
+        dn.stride = 1;
+        dn.p = 2;
+        dn.part = region(g, kRDiffD);
+        dn.update = nullptr;
+        dn.alpha = 1.0;
+        dn.vel = nullptr;
+        dn.beta = 0.0;
+        qc::launch_diff_norm(dn, kParts, st);
+        fetch_parts(g, st);
+        if (rel_from_parts(g, kRDiffD, 2) < tol) {
+          ++it;
+          break;
+        }
+      }
+      worst = std::max(worst, it);
+    }
+    hcheck(hipStreamSynchronize(st), "sync");
+    if (iters_out) *iters_out = worst;
+    return QC_OK;
+  });
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      if (bcl[a][b]) (void)hipFree(bcl[a][b]);
+  for (void* p : {static_cast<void*>(deps), static_cast<void*>(prev), lg, le})
+    if (p) (void)hipFree(p);
   return rs;
 }
 
@@ -1735,6 +2036,30 @@ qc_status qc_grain_set_accelerator(qc_grain* g, int kind, double beta) {
   return QC_OK;
 }
 
+qc_status qc_grain_set_pairing(qc_grain* g, int enable) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (enable && !g->pair_ok) return fail(QC_ERR_INVALID, "this grain's tables do not allow angle pairs");
+  g->pairing = enable != 0;
+  return QC_OK;
+}
+
+qc_status qc_grain_get_pairing(const qc_grain* g, int* available, int* enabled, int64_t* swept_steps_per_sweep) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (available) *available = g->pair_ok ? 1 : 0;
+  if (enabled) *enabled = g->pairing ? 1 : 0;
+  if (swept_steps_per_sweep) {
+    if (!g->pairing) {
+      *swept_steps_per_sweep = g->info.steps_per_sweep;
+    } else {
+      const std::vector<int32_t> n = download(g->seg_n, g->nseg_pair);
+      int64_t s = 0;
+      for (int32_t v : n) s += v + 1;
+      *swept_steps_per_sweep = 2 * static_cast<int64_t>(g->n_poles) * s;
+    }
+  }
+  return QC_OK;
+}
+
 qc_status qc_grain_get_accel_stats(const qc_grain* g, int64_t* bisected, int64_t* anti_parallel) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
   if (bisected) *bisected = g->cong_bisect;
@@ -1845,11 +2170,13 @@ void build_tiles(qc_batch* b) {
     qc_grain* g = b->grains[gi];
     int G, epl;
     lane_shape(g->n_poles, b->epl, g->precision == QC_MIXED, G, epl);
-    std::vector<int32_t> ord(g->nseg), n(g->nseg);
-    hcheck(hipMemcpy(ord.data(), g->order, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
+    const int64_t nsw = g->pairing ? g->nseg_pair : g->nseg;
+    std::vector<int32_t> ord(nsw), n(g->nseg);
+    hcheck(hipMemcpy(ord.data(), g->pairing ? g->order_pair : g->order, sizeof(int32_t) * nsw, hipMemcpyDeviceToHost),
+           "copy");
     hcheck(hipMemcpy(n.data(), g->seg_n, sizeof(int32_t) * g->nseg, hipMemcpyDeviceToHost), "copy");
     const int per = 64 / G;
-    for (int64_t w = 0; w < g->nseg; w += per)
+    for (int64_t w = 0; w < nsw; w += per)
       groups[epl].push_back({static_cast<int>(gi), static_cast<int>(w), n[ord[w]] + 1});
   }
   std::vector<int2> t;
@@ -1895,7 +2222,7 @@ void upload_args(qc_batch* b, hipStream_t st) {
     qc_grain* g = b->grains[gi];
     int G, epl;
     lane_shape(g->n_poles, b->epl, g->precision == QC_MIXED, G, epl);
-    qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
+    qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd, true);
     a.G = G;
     a.log2g = ilog2(G);
     a.bc_valid = g->bc_valid;
@@ -1921,7 +2248,7 @@ void rotate_back_grain(qc_grain* g, const double* delta, double* dnew, double* j
 // one persistent sweep over all grains, per-grain rotate-back, A-solve and
 // update.  Only kernel launches: it can be captured into a graph.
 void batch_iteration(qc_batch* b, hipStream_t st, bool upload) {
-  for (size_t gi = 0; gi < b->grains.size(); ++gi) do_interp(b->grains[gi], b->delta[gi], b->A[gi], st);
+  for (size_t gi = 0; gi < b->grains.size(); ++gi) do_interp(b->grains[gi], b->delta[gi], b->A[gi], st, true);
   if (upload) upload_args(b, st);
   for (size_t k = 0; k < b->grp_epl.size(); ++k) {
     if (b->precision == QC_MIXED)
@@ -1933,6 +2260,7 @@ void batch_iteration(qc_batch* b, hipStream_t st, bool upload) {
   }
   for (size_t gi = 0; gi < b->grains.size(); ++gi) {
     qc_grain* g = b->grains[gi];
+    mirror_fill(g, g->bc[1 - g->bc_cur][0], g->bc[1 - g->bc_cur][1], st);
     rotate_back_grain(g, b->delta[gi], g->dnew, g->jcur, st);
     // A from the current (zero for an infinite penetration depth), as in the
     // single-grain Picard loop

@@ -159,6 +159,17 @@ void external_A(const Plan& p, double x, double y, double& ax, double& ay) {
 
 }  // namespace
 
+std::complex<double> basis_eta(int kind, double phi) {
+  const double r2 = std::sqrt(2.0);
+  switch (kind) {
+    case 0: return {1.0, 0.0};
+    case 1: return {r2 * std::cos(2.0 * phi), 0.0};
+    case 2: return {r2 * std::sin(2.0 * phi), 0.0};
+    case 3: return {r2 * std::sin(4.0 * phi), 0.0};
+    default: throw std::runtime_error("unknown basis function");
+  }
+}
+
 std::vector<double> fs_weights(int n) {
   std::vector<double> pat;
   if (n % 4 == 0)
@@ -239,6 +250,111 @@ void ozaki_table(int n_poles, std::vector<double>& z, std::vector<double>& r) {
   }
 }
 
+// T = Q^T A Q by Householder reflections H = I - 2 v v^T, each zeroing one
+// column below the subdiagonal (A22 <- A22 - v w^T - w v^T with
+// w = 2 (A22 v - (v.A22 v) v)), Q accumulated as H_0 H_1 ...; then implicit
+// QR steps on the unreduced trailing block of T: a Wilkinson shift from its
+// last 2 x 2, a Givens rotation from the shifted first column, the bulge
+// chased down with rotations that zero it, every rotation applied to the
+// columns of Q.  Off-diagonals below 1e-16 (|d_i| + |d_i+1|) are dropped.
+void sym_eigen(int n, std::vector<double> a, std::vector<double>& lam, std::vector<double>& z) {
+  auto A = [&](int r, int c) -> double& { return a[static_cast<size_t>(r) * n + c]; };
+  z.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) z[static_cast<size_t>(i) * n + i] = 1.0;
+  std::vector<double> v(n), p(n), w(n);
+  // ---- Householder: zero column k below the subdiagonal
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // length of x = A[k+1:, k]
+    double nx = 0.0;
+    for (int i = 0; i < m; ++i) nx += A(k + 1 + i, k) * A(k + 1 + i, k);
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const double x0 = A(k + 1, k);
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    for (int i = 0; i < m; ++i) v[i] = A(k + 1 + i, k);
+    v[0] -= alpha;
+    double nv = 0.0;
+    for (int i = 0; i < m; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    if (nv == 0.0) continue;
+    for (int i = 0; i < m; ++i) v[i] /= nv;
+    // p = A22 v, K = v.p, w = 2 (p - K v); A22 <- A22 - v w^T - w v^T
+    double K = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      const double* row = &a[static_cast<size_t>(k + 1 + i) * n + k + 1];
+      for (int j = 0; j < m; ++j) s += row[j] * v[j];
+      p[i] = s;
+      K += v[i] * s;
+    }
+    for (int i = 0; i < m; ++i) w[i] = 2.0 * (p[i] - K * v[i]);
+    for (int i = 0; i < m; ++i) {
+      double* row = &a[static_cast<size_t>(k + 1 + i) * n + k + 1];
+      for (int j = 0; j < m; ++j) row[j] -= v[i] * w[j] + w[i] * v[j];
+    }
+    A(k + 1, k) = alpha;
+    A(k, k + 1) = alpha;
+    for (int i = 1; i < m; ++i) {
+      A(k + 1 + i, k) = 0.0;
+      A(k, k + 1 + i) = 0.0;
+    }
+    // Q <- Q H: columns k+1.. of every row: row <- row - 2 (row . v) v
+    for (int r = 0; r < n; ++r) {
+      double* row = &z[static_cast<size_t>(r) * n + k + 1];
+      double s = 0.0;
+      for (int j = 0; j < m; ++j) s += row[j] * v[j];
+      s *= 2.0;
+      for (int j = 0; j < m; ++j) row[j] -= s * v[j];
+    }
+  }
+  std::vector<double> d(n), e(std::max(n - 1, 1), 0.0);
+  for (int i = 0; i < n; ++i) d[i] = A(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
+  // ---- implicit QR on the tridiagonal matrix
+  int m = n - 1;
+  int guard = 0;
+  while (m > 0) {
+    if (guard > 100 * n) throw std::runtime_error("sym_eigen: the QR iteration did not converge");
+    // deflate negligible off-diagonals at the bottom
+    if (std::fabs(e[m - 1]) <= 1e-16 * (std::fabs(d[m - 1]) + std::fabs(d[m]))) {
+      e[m - 1] = 0.0;
+      --m;
+      continue;
+    }
+    int l = m - 1;
+    while (l > 0 && std::fabs(e[l - 1]) > 1e-16 * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
+    if (l > 0) e[l - 1] = 0.0;
+    ++guard;
+    // Wilkinson shift from the trailing 2 x 2 block
+    const double del = 0.5 * (d[m - 1] - d[m]);
+    const double b2 = e[m - 1] * e[m - 1];
+    const double mu = d[m] - b2 / (del + (del >= 0.0 ? 1.0 : -1.0) * std::sqrt(del * del + b2));
+    double pp = d[l] - mu, qq = e[l];
+    for (int k = l; k < m; ++k) {
+      const double r = std::hypot(pp, qq);
+      const double c = r > 0.0 ? pp / r : 1.0, s = r > 0.0 ? qq / r : 0.0;
+      if (k > l) e[k - 1] = r;
+      const double Aa = d[k], B = e[k], C = d[k + 1];
+      d[k] = c * c * Aa + 2.0 * c * s * B + s * s * C;
+      d[k + 1] = s * s * Aa - 2.0 * c * s * B + c * c * C;
+      e[k] = c * s * (C - Aa) + (c * c - s * s) * B;
+      if (k + 1 < m) {
+        const double D = e[k + 1];
+        qq = s * D;       // the bulge T[k][k+2]
+        e[k + 1] = c * D;
+        pp = e[k];
+      }
+      for (int r2 = 0; r2 < n; ++r2) {
+        double* row = &z[static_cast<size_t>(r2) * n];
+        const double zk = row[k], zk1 = row[k + 1];
+        row[k] = c * zk + s * zk1;
+        row[k + 1] = -s * zk + c * zk1;
+      }
+    }
+  }
+  lam = d;
+}
+
 int64_t Plan::steps_per_sweep() const {
   int64_t s = 0;
   for (int64_t k = 0; k < nseg; ++k) s += seg_n[k] + 1;
@@ -273,6 +389,114 @@ Shape mask_shape(const uint8_t* mask, int nx, int ny, double x0, double y0, doub
       }
     }
   return sh;
+}
+
+// Angle k + n_theta/2 has the lattice of angle k with both axes reversed:
+// line i, node j there is the point of line M-1-i, node M-1-j of angle k.
+// Along such a pair of lines gamma~ of one direction is the complex
+// conjugate of gamma of the other for an order parameter that is even in
+// the momentum direction (singlet pairing), so one march serves both.  The
+// tables of the two angles are built independently; pairing is enabled
+// only where they agree: same segments with the same node counts, slot
+// positions within 1e-9 h, the same fallback cells, equal weights and
+// basis values.
+static void build_pairs(Plan& p) {
+  p.pair_ok = false;
+  p.seg_mirror.assign(static_cast<size_t>(p.nseg), -1);
+  p.rb4_pair.clear();
+  p.nseg_pair = p.nseg;
+  p.nslot_pair = p.nslot;
+  const int n = p.n_theta, M = p.M;
+  if (n < 2 || n % 2 != 0) return;
+  const int n2 = n / 2;
+  for (int k = 0; k < n2; ++k) {
+    if (std::fabs(p.wk[k + n2] - p.wk[k]) > 1e-14 * p.wk[k]) return;
+  }
+  double emax = 0.0;
+  for (const auto& e : p.eta) emax = std::max(emax, std::abs(e));
+  for (int g = 0; g < p.ncomp; ++g)
+    for (int k = 0; k < n2; ++k)
+      if (std::abs(p.eta[static_cast<size_t>(g) * n + k + n2] - p.eta[static_cast<size_t>(g) * n + k]) >
+          1e-14 * emax)
+        return;
+  std::vector<int64_t> slot_mirror(static_cast<size_t>(p.nslot), -1);
+  const double tol = 1e-9 * p.h;
+  for (int k = n2; k < n; ++k) {
+    for (int i = 0; i < M; ++i) {
+      const int64_t a0 = p.line_seg0[static_cast<size_t>(k) * (M + 1) + i];
+      const int64_t a1 = p.line_seg0[static_cast<size_t>(k) * (M + 1) + i + 1];
+      const int64_t b0 = p.line_seg0[static_cast<size_t>(k - n2) * (M + 1) + (M - 1 - i)];
+      const int64_t b1 = p.line_seg0[static_cast<size_t>(k - n2) * (M + 1) + (M - 1 - i) + 1];
+      if (a1 - a0 != b1 - b0) return;
+      for (int64_t q = 0; q < a1 - a0; ++q) {
+        const int64_t sa = a0 + q, sb = b1 - 1 - q;  // segments run the other way
+        const int na = p.seg_n[sa];
+        if (p.seg_n[sb] != na) return;
+        if (na > 0 && p.seg_jfirst[sb] != M - p.seg_jfirst[sa] - na) return;
+        const int nsl = std::max(na, 1);
+        for (int t = 0; t < nsl; ++t) {
+          const int64_t la = p.seg_slot0[sa] + t, lb = p.seg_slot0[sb] + (nsl - 1 - t);
+          if (std::fabs(p.slot_px[la] - p.slot_px[lb]) > tol || std::fabs(p.slot_py[la] - p.slot_py[lb]) > tol)
+            return;
+          if (p.slot_fb[la] != p.slot_fb[lb]) return;
+          slot_mirror[la] = lb;
+        }
+        p.seg_mirror[sa] = static_cast<int32_t>(sb);
+      }
+    }
+  }
+  // The boundary taps of an upper segment must be the mirror image of its
+  // mirror's (start taps of s' against end taps of s and vice versa: the
+  // same weights on mirrored segments), so that its start values are the
+  // conjugates of its mirror's.  A line through a corner of the boundary
+  // can record a different wall tangent in the two directions; such grains
+  // keep every angle.
+  std::vector<int32_t> partner(static_cast<size_t>(p.nseg), -1);
+  for (int64_t sg = 0; sg < p.nseg; ++sg)
+    if (p.seg_mirror[sg] >= 0) {
+      partner[sg] = p.seg_mirror[sg];
+      partner[p.seg_mirror[sg]] = static_cast<int32_t>(sg);
+    }
+  for (int64_t sg = 0; sg < p.nseg; ++sg) {
+    if (p.seg_mirror[sg] < 0) continue;
+    const int64_t mg = p.seg_mirror[sg];
+    for (int side = 0; side < 2; ++side) {
+      // side 0: start taps of sg vs end taps of mg; side 1: the reverse
+      const int32_t* ta = side == 0 ? &p.tap_start_seg[sg * 4] : &p.tap_end_seg[sg * 4];
+      const double* wa = side == 0 ? &p.tap_start_w[sg * 4] : &p.tap_end_w[sg * 4];
+      const int32_t* tb = side == 0 ? &p.tap_end_seg[mg * 4] : &p.tap_start_seg[mg * 4];
+      const double* wb = side == 0 ? &p.tap_end_w[mg * 4] : &p.tap_start_w[mg * 4];
+      for (int a = 0; a < 4; ++a) {
+        if (wa[a] == 0.0) continue;
+        // the mirrored tap must appear on the other side with its weight
+        double wsum = 0.0;
+        for (int b = 0; b < 4; ++b)
+          if (wb[b] != 0.0 && tb[b] == partner[ta[a]]) wsum += wb[b];
+        double wself = 0.0;
+        for (int c = 0; c < 4; ++c)
+          if (wa[c] != 0.0 && ta[c] == ta[a]) wself += wa[c];
+        if (std::fabs(wsum - wself) > 1e-12) return;
+      }
+      double na = 0.0, nb = 0.0;
+      for (int a = 0; a < 4; ++a) {
+        na += wa[a];
+        nb += wb[a];
+      }
+      if ((na > 0.0) != (nb > 0.0)) return;
+    }
+  }
+  const int64_t nc = static_cast<int64_t>(p.grain_cells.size());
+  p.rb4_pair = p.rb4;
+  for (size_t i = static_cast<size_t>(n2) * nc * 4; i < p.rb4_pair.size(); ++i) {
+    const int32_t v = p.rb4_pair[i];
+    if (v >= 0) {
+      if (slot_mirror[v] < 0) throw std::runtime_error("angle pairs: rotate-back corner without a mirror");
+      p.rb4_pair[i] = static_cast<int32_t>(slot_mirror[v]);
+    }
+  }
+  p.nseg_pair = p.angle_seg0[n2];
+  p.nslot_pair = p.seg_slot0[p.nseg_pair];
+  p.pair_ok = true;
 }
 
 void build_plan(Plan& p) {
@@ -595,6 +819,8 @@ void build_plan(Plan& p) {
         }
     }
   }
+
+  build_pairs(p);
 }
 
 }  // namespace qc

@@ -85,6 +85,18 @@ struct Plan {
   std::vector<int32_t> tap_start_seg, tap_end_seg;
   std::vector<double> tap_start_w, tap_end_w;
 
+  // ---- angle pairs (k, k + n_theta/2): the same lattice points on reversed
+  // lines.  pair_ok when every segment of an angle k >= n_theta/2 has a
+  // mirror on angle k - n_theta/2 with the same nodes in reverse order (same
+  // slot positions and nearest-cell fallbacks), and the weights and basis
+  // values of the two angles agree.  seg_mirror[s] is that mirror for
+  // segments of the upper angles (-1 for the lower ones); rb4_pair is rb4
+  // with the slots of the upper angles replaced by their mirrors.
+  bool pair_ok = false;
+  int64_t nseg_pair = 0, nslot_pair = 0;  // segments / slots of the lower angles
+  std::vector<int32_t> seg_mirror;
+  std::vector<int32_t> rb4_pair;
+
   int64_t steps_per_sweep() const;
 };
 
@@ -95,7 +107,17 @@ void build_plan(Plan& p);
 // the 2N x 2N tridiagonal continued-fraction matrix, Jacobi rotations.
 void ozaki_table(int n_poles, std::vector<double>& z, std::vector<double>& r);
 
+// App. F basis function (qc_basis) at the angle phi from the crystal axis:
+// s = 1, d_{x2-y2} = sqrt2 cos 2 phi, d_xy = sqrt2 sin 2 phi, g = sqrt2 sin 4 phi.
+std::complex<double> basis_eta(int kind, double phi);
+
 // Normalised periodic Fermi-surface quadrature weights (Sec. III.A).
 std::vector<double> fs_weights(int n_theta);
+
+// Eigen-decomposition of a dense symmetric n x n matrix (row-major, taken
+// by value): Householder reduction to tridiagonal form, then implicit QR
+// sweeps with Wilkinson shifts.  lam[i] with eigenvector column i of
+// vec (row-major, vec[r * n + i]).
+void sym_eigen(int n, std::vector<double> a, std::vector<double>& lam, std::vector<double>& vec);
 
 }  // namespace qc

@@ -310,7 +310,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   if (!late_store && MODE != 2 && n > 0) store_g(n - 1);
   // step n to R_max (the boundary point takes slot n-1's values)
   if (n > 0) end_step(g, prev, prev, hlast, T(1));
-  if (MODE == 0 || MODE == 2) {
+  // end values for the next sweep (the LDOS output pass writes them only
+  // when iterating to convergence: bc_g_next given)
+  if (MODE == 0 || MODE == 2 || (MODE == 1 && bc_g_next)) {
     cpx<T>* dst = bc_g_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
       if (e0 + i < a.n_e) dst[i] = g[i];
@@ -515,7 +517,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   if (MODE == 0 && a.G >= 8 && (n & 1)) lds_reduce(slot0, 1);
   // step 0 to R_min (boundary point = slot 0)
   if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
-  if (MODE == 0 || MODE == 2) {
+  if (MODE == 0 || MODE == 2 || (MODE == 1 && bc_gt_next)) {
     cpx<T>* dst = bc_gt_next + seg * a.n_e_tot + a.e_off + e0;
     for (int i = 0; i < EPL; ++i)
       if (e0 + i < a.n_e) dst[i] = gt[i];
@@ -666,6 +668,7 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
       dkx += ex * dx_[g] - ey * dy_[g];
       dky += ex * dy_[g] + ey * dx_[g];
     }
+    if (k >= a.pair_k0) cg = -cg;  // S_g of the reversed direction
     jx += a.four_q * wk * epx * cg;
     jy += a.four_q * wk * epy * cg;
     icell += wk * ci;
@@ -706,6 +709,23 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   a.j[a.ncell + cell] = jy;
   if (a.omega) a.omega[cell] = om;
   a.omega_cell[c] = om;
+}
+
+// gamma~ along a line is the conjugate of gamma along the reversed line
+// (even order parameter): the end values of the upper angle of a pair follow
+// from its mirror segment's
+template <typename T>
+__global__ void __launch_bounds__(256) mirror_fill_kernel(const int2* __restrict__ pairs, int64_t npairs, int n_e,
+                                                          cpx<T>* __restrict__ bc_g, cpx<T>* __restrict__ bc_gt) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= npairs * n_e) return;
+  const int64_t q = t / n_e;
+  const int e = static_cast<int>(t - q * n_e);
+  const int2 pr = pairs[q];
+  const int64_t dst = static_cast<int64_t>(pr.x) * n_e + e, src = static_cast<int64_t>(pr.y) * n_e + e;
+  const cpx<T> g = bc_g[src], gt = bc_gt[src];
+  bc_g[dst] = mk(gt.x, -gt.y);
+  bc_gt[dst] = mk(g.x, -g.y);
 }
 
 template <typename T>
@@ -806,10 +826,6 @@ __global__ void __launch_bounds__(256) block_sum_kernel(const double* __restrict
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// Partial p-norms of (new - old) and of old over `n` elements of `stride`
-// doubles each (stride 2: complex modulus).  p = 1, 2, or 0 (max).
-// Elements may be gathered through idx (grain cells) when idx != nullptr,
-// for `nrep` consecutive fields of `field_stride` elements.
 // Luttinger-Ward free energy (Sec. II): the propagator term at one
 // coupling lambda, 2 sum_G den_G Re(conj(Delta_G) Delta_new_G[lambda Delta])
 // with den_G the gap-equation denominator, weighted into acc per grain cell
@@ -870,6 +886,10 @@ __global__ void __launch_bounds__(256) scale_kernel(const double* __restrict__ x
   if (i < n) y[i] = s * x[i];
 }
 
+// Partial p-norms of (new - old) and of old over `n` elements of `stride`
+// doubles each (stride 2: complex modulus).  p = 1, 2, or 0 (max).
+// Elements may be gathered through idx (grain cells) when idx != nullptr,
+// for `nrep` consecutive fields of `field_stride` elements.
 __global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
   __shared__ double s0[256], s1[256];
   double acc0 = 0.0, acc1 = 0.0;
@@ -1243,6 +1263,15 @@ void launch_valu_rate(int op, float* out, int nblocks, int iters, hipStream_t st
     default: hipLaunchKernelGGL(valu_rate_kernel<3>, dim3(nblocks), dim3(256), 0, st, out, iters, 0.999f); break;
   }
 }
+
+template <typename T>
+void launch_mirror_fill(const int2* pairs, int64_t npairs, int n_e, void* bc_g, void* bc_gt, hipStream_t st) {
+  if (npairs * n_e > 0)
+    hipLaunchKernelGGL(mirror_fill_kernel<T>, dim3(nblk(npairs * n_e)), dim3(256), 0, st, pairs, npairs, n_e,
+                       static_cast<cpx<T>*>(bc_g), static_cast<cpx<T>*>(bc_gt));
+}
+template void launch_mirror_fill<float>(const int2*, int64_t, int, void*, void*, hipStream_t);
+template void launch_mirror_fill<double>(const int2*, int64_t, int, void*, void*, hipStream_t);
 
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;

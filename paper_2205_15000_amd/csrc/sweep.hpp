@@ -105,6 +105,10 @@ struct BackArgs {
   double* j;
   double* omega;       // [ny][nx] or nullptr
   double* omega_cell;  // [ncg] scratch for the total
+  // angles k >= pair_k0 read the node sums of their mirror slots on angle
+  // k - n_theta/2 (rb4 already points there): S_g changes sign, S_f and
+  // S_I do not.  n_theta when angle pairs are off.
+  int pair_k0;
 };
 
 struct LdosBackArgs {
@@ -229,6 +233,11 @@ void launch_interp(const InterpArgs& a, void* cells, void* nodes, hipStream_t st
 template <typename T>
 void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
+// End values of the upper angle of each pair from its mirror segment:
+// gamma_end(s') = conj(gamma~_end(s)), gamma~_end(s') = conj(gamma_end(s))
+// for each (s', s) in pairs, n_e energies per segment (T = float or double)
+template <typename T>
+void launch_mirror_fill(const int2* pairs, int64_t npairs, int n_e, void* bc_g, void* bc_gt, hipStream_t st);
 // blocks of 256 lanes, each lane writes out[lane]: out holds nblocks * 256 floats
 void launch_valu_rate(int op, float* out, int nblocks, int iters, hipStream_t st);
 template <typename T>
@@ -275,6 +284,16 @@ void launch_lw_finish(const double* delta, const int32_t* grain_cells, int64_t n
                       int n_theta, const double* eta, const double* wk, const double* logt, double twopi_rz,
                       const double* acc, double* omega_cell, double* omega, hipStream_t st);
 void launch_scale(const double* x, double s, int64_t n, double* y, hipStream_t st);
+// eigen-truncated A-solve (vecpot.hip): jp [2][n][n] masked current, vk
+// [nmodes][n] eigenvectors, lam [nmodes]; y [2][nmodes][n][n] work;
+// aout [2][n][n] = alpha sum_k lam_k T_k jp T_k
+void launch_eig_vecpot(int n, int nmodes, const double* jp, const double* vk, const double* lam, double* y,
+                       double* aout, double alpha, hipStream_t st);
+void launch_masked_current(const double* j, const uint8_t* mask, int64_t ncell, const double* mean, double* jp,
+                           hipStream_t st);
+// per grain cell (x - cx) j_y - (y - cy) j_x, grain-cell order
+void launch_torque(const double* j, const int32_t* grain_cells, int64_t ncg, int64_t ncell, int nx, double x0,
+                   double y0, double h, double cx, double cy, double* out, hipStream_t st);
 void launch_pad_current(const double* j, const uint8_t* mask, int nx, int ny, int px, int py, const double* mean,
                         double2* w, hipStream_t st);
 void launch_fft_rows(double2* w, int rows, int logn, const double2* tw, int sign, const double2* pre, hipStream_t st);

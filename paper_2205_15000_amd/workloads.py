@@ -17,6 +17,9 @@ DELTA0 = 0.28072974178344257
 # bulk d-wave gap at t = 0.1 with 64 poles and 64 angles, in units of DELTA0
 # (root of the homogeneous gap equation; used only as a starting amplitude)
 D_BULK_T01 = 0.8577177
+# bulk s-wave gap at t = 0.5 with 16 poles, in units of DELTA0 (the same
+# root; starting amplitude of the vortex demonstration)
+S_BULK_T05 = 0.9568823
 
 
 def _disc(cx, cy, r, add=True):
@@ -70,6 +73,15 @@ SPECS = {
     "d110_square_512_ldos": dict(nx=512, ny=512, h=0.1, shapes=[_square(0, 0, 51.2)], n_theta=256, n_poles=64,
                                  t=0.1, components=[("dx2y2", 1.0)], crystal_rotation=0.125, kappa=100.0,
                                  flux_quanta=0.0, gauge="symmetric", charge_sign=-1),
+    # the paper's demonstration (Sec. IV, the App. B configuration listing):
+    # s-wave disc R = 15 xi0 at 20 points per xi0 (600 x 600, h = 0.05), 32
+    # angles, t = 0.5, 1.5 flux quanta (symmetric gauge), penetration depth
+    # 5 xi0, one vortex of winding -1 at the centre, no noise; 16 Ozaki poles
+    # (their largest energy, 53 x 2 pi Tc, lies above the listing's cutoff
+    # of 16)
+    "swave_disc_vortex": dict(nx=600, ny=600, h=0.05, shapes=[_disc(0, 0, 15.0)], n_theta=32, n_poles=16, t=0.5,
+                              components=[("s", 1.0)], kappa=5.0, flux_quanta=1.5, gauge="symmetric",
+                              charge_sign=-1),
     # ---- small parity cases (several tiles, ragged tails, every option) ----
     # d-wave [110] square with field, finite kappa and an off-centre vortex
     "small_d110_field": dict(nx=40, ny=40, h=0.5, shapes=[_square(0, 0, 18.3)], n_theta=16, n_poles=8, t=0.3,
@@ -129,6 +141,9 @@ def initial_delta(name, sp=None, seed=None):
         xv, yv = rng.uniform(-5.0, 5.0, 2)
         phase = -np.arctan2(Y - yv, X - xv)
         return (D_BULK_T01 * DELTA0 * np.exp(1j * phase))[None].astype(np.complex128)
+    if name == "swave_disc_vortex":
+        # bulk amplitude with the phase of one vortex of winding -1 at the centre
+        return (S_BULK_T05 * DELTA0 * np.exp(-1j * np.arctan2(Y, X)))[None].astype(np.complex128)
     if name == "d_disc_200":
         rng = np.random.default_rng(4 if seed is None else seed)
         u = rng.uniform(-0.05, 0.05, (ny, nx))
@@ -149,12 +164,18 @@ def initial_A(name, sp=None, seed=None):
     workloads, a small smooth seeded field for the parity cases."""
     sp = sp or spec(name)
     nx, ny = sp["nx"], sp["ny"]
-    if name in ("s_disc_32", "d110_square_400", "d_disc_200", "d110_square_512_ldos"):
+    if name in ("s_disc_32", "d110_square_400", "d_disc_200", "d110_square_512_ldos", "swave_disc_vortex"):
         return np.zeros((2, ny, nx))
     rng = np.random.default_rng(23 if seed is None else seed)
     X, Y = centres(sp)
     a, b, c, d = rng.uniform(0.1, 0.4, 4)
     return 0.02 * np.stack([np.sin(a * X + b * Y), np.cos(c * X - d * Y)])
+
+
+def vortex_ldos_energies(n=128):
+    """The demonstration's LDOS post-process (Sec. IV listing): n energies
+    from 0 to 0.5 (units of 2 pi k_B Tc), endpoints included."""
+    return np.linspace(0.0, 0.5, n)
 
 
 def ldos_energies(n=512):

@@ -532,3 +532,196 @@ def test_luttinger_ward_free_energy_matches_oracle(name, precision):
     with pytest.raises(qs.QcError):
         g.free_energy_lw(dd, ad, 0, 2)
     g.close()
+
+
+@pytest.mark.parametrize("name,precision", [("s_disc_32", "fp64"), ("small_d110_field", "fp64"),
+                                            ("small_holed_mixed", "fp64"), ("small_d110_field", "mixed")])
+def test_angle_pairs_equal_the_full_sweep(name, precision):
+    """Paired sweeps (one march per pair of opposite directions) against
+    sweeps of every angle: three chained maps (so the second and third read
+    boundary values the pairs filled in) give the same Delta_new, j and
+    Omega to rounding (1e-12 FP64, 1e-5 mixed), and the stores agree."""
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s %s: angle pairs vs every angle" % (name, precision))
+    d0 = _dev(wl.initial_delta(name, sp), torch.complex128)
+    a0 = _dev(wl.initial_A(name, sp), torch.float64)
+    out = []
+    for pair in (True, False):
+        g = qs.Grain(sp, precision)
+        avail, on, _ = g.pairing()
+        assert avail and on
+        g.set_pairing(pair)
+        _, on, swept = g.pairing()
+        assert on == pair
+        d, a = d0.clone(), a0.clone()
+        res = []
+        for _ in range(3):
+            dn, j, om = g.sweep(d, a)
+            res.append((dn.cpu().numpy(), j.cpu().numpy(), om))
+            d = dn
+        res.append(g.get_state().cpu().numpy())
+        out.append((res, swept))
+        g.close()
+    (p, swept), (f, full) = out
+    assert 2 * swept == full
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for i in range(3):
+        assert _close(p[i][0], f[i][0], tol), (i, rel_err(p[i][0], f[i][0]))
+        assert _close(p[i][1], f[i][1], tol), (i, rel_err(p[i][1], f[i][1]))
+        assert abs(p[i][2] - f[i][2]) <= tol * abs(f[i][2])
+    if precision == "fp64":
+        sp_ = p[3].view(np.float64)
+        sf_ = f[3].view(np.float64)
+        assert np.max(np.abs(sp_ - sf_)) <= 1e-12 * np.max(np.abs(sf_))
+
+
+@pytest.mark.parametrize("name", ["small_polygon_landau", "small_mask_blob"])
+def test_angle_pairs_unavailable_where_the_tables_do_not_mirror(name):
+    """An odd angle count, and a cell-mask boundary whose corners give
+    direction-dependent wall tangents: every angle is swept."""
+    qs = _qs()
+    sp = wl.spec(name)
+    g = qs.Grain(sp, "fp64")
+    assert g.pairing()[:2] == (False, False)
+    with pytest.raises(qs.QcError):
+        g.set_pairing(True)
+    g.close()
+
+
+@pytest.mark.parametrize("name,eps", [("small_d110_field", 1e-6), ("small_d110_field", 1e-3),
+                                      ("small_d110_field", 1e-300)])
+def test_eigen_truncated_A_solve_matches_oracle(name, eps):
+    """The separable, eigen-truncated A-solve (App. D) on a square grid: the
+    modes kept and A against the oracle's (numpy eigh) at 1e-10 of the
+    largest |A|, for the default tolerance, a coarse one and every mode;
+    eps = 0 restores the FFT solve."""
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s: eigen-truncated A-solve, eps %g" % (name, eps))
+    g = qs.Grain(sp, "fp64")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    _, j, _ = g.sweep(_dev(d0, torch.complex128), _dev(a0, torch.float64))
+    jj = j.cpu().numpy()
+    g.set_A_solver(eps)
+    A, B = g.solve_A(j)
+    ax, ay, nstar = fields.solve_A_eigen(jj[0], jj[1], og.mask, sp["h"], sp["kappa"], eps)
+    assert g.A_solver() == (eps, nstar)
+    ref = np.stack([ax, ay])
+    got = A.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref)), np.max(np.abs(got - ref))
+    b = fields.curl(ax, ay, sp["h"])
+    assert np.max(np.abs(B.cpu().numpy() - b)) <= 1e-10 * np.max(np.abs(b))
+    g.set_A_solver(0.0)
+    assert g.A_solver() == (0.0, 0)
+    A2, _ = g.solve_A(j)
+    ex, ey = fields.solve_A(jj[0], jj[1], og.mask, sp["h"], sp["kappa"], method="direct")
+    assert _close(A2.cpu().numpy(), np.stack([ex, ey]), FP64_TOL)
+    g.close()
+
+
+def test_eigen_A_solve_full_size_and_magnetic_moment():
+    """The 400x400 [110] square: the eigen-truncated A-solve at the paper's
+    default tolerance (1e-6) against the oracle's (1e-10) and within the
+    truncation bound of the exact solve; the magnetic moment of the current
+    (Sec. V.A) against the oracle's sum (1e-12)."""
+    qs = _qs()
+    name = "d110_square_400"
+    sp = wl.spec(name)
+    _note("case %s: eigen-truncated A-solve and magnetic moment" % name)
+    g = qs.Grain(sp, "fp64")
+    og_mask = qs.Plan(dict(sp, n_theta=4)).mask()
+    _, j, _ = g.sweep(_dev(wl.initial_delta(name, sp), torch.complex128), _dev(wl.initial_A(name, sp), torch.float64))
+    jj = j.cpu().numpy()
+    exact, _ = g.solve_A(j, B=False)
+    g.set_A_solver(1e-6)
+    A, _ = g.solve_A(j, B=False)
+    ax, ay, nstar = fields.solve_A_eigen(jj[0], jj[1], og_mask, sp["h"], sp["kappa"], 1e-6)
+    assert g.A_solver()[1] == nstar
+    ref = np.stack([ax, ay])
+    assert np.max(np.abs(A.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+    lam, V = fields.green_eigen(sp["nx"], sp["h"], 1e-6)
+    G = fields.green_matrix(sp["nx"], sp["h"])
+    dK = np.linalg.norm(G - (V * lam) @ V.T)
+    for c in range(2):
+        jp = np.where(og_mask, jj[c] - jj[c][og_mask].mean(), 0.0)
+        bound = 2.0 / sp["kappa"] ** 2 * dK * np.linalg.norm(jp)
+        assert np.max(np.abs(A.cpu().numpy()[c] - exact.cpu().numpy()[c])) <= bound
+    X, Y = wl.centres(sp)
+    m = g.magnetic_moment(j)
+    mref = fields.magnetic_moment(jj[0], jj[1], og_mask, X, Y, 0.0, 0.0)
+    assert abs(m - mref) <= 1e-12 * max(abs(mref), 1e-300) + 1e-15
+    g.close()
+
+
+def test_ldos_converge_matches_oracle():
+    """The LDOS post-process run to convergence (Sec. IV, App. B): the
+    boundary iteration stops once the LDOS changes by less than tol; with
+    one energy block the result is qc_ldos with bc_iters = sweeps - 1, and
+    matches the oracle's LDOS with that burn-in (FP64 1e-10)."""
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: LDOS to convergence" % name)
+    g = qs.Grain(sp, "fp64")
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    dd, ad = _dev(d0, torch.complex128), _dev(a0, torch.float64)
+    en = np.linspace(-0.3, 0.3, 5)
+    out, iters = g.ldos_converge(dd, ad, en, 0.02, 1e-6, 60, energies_per_block=len(en))
+    assert 2 <= iters < 60
+    same = g.ldos(dd, ad, en, 0.02, iters - 1).cpu().numpy()
+    got = out.cpu().numpy()
+    assert np.max(np.abs(got - same)) <= 1e-12 * np.max(np.abs(same))
+    ref = og.ldos(d0, a0, en, 0.02, iters - 1)
+    assert _close(got, ref, FP64_TOL), rel_err(got, ref)
+    # blocks of two energies converge on their own, each within the tolerance
+    out2, it2 = g.ldos_converge(dd, ad, en, 0.02, 1e-6, 60, energies_per_block=2)
+    assert it2 <= iters + 1
+    assert np.max(np.abs(out2.cpu().numpy() - got)) <= 1e-4 * np.max(np.abs(got))
+    g.close()
+
+
+def test_resume_from_saved_state_and_burn_in():
+    """Save and resume (App. B): Delta, A and the boundary store saved after
+    8 Picard iterations and loaded into a fresh grain continue exactly as the
+    uninterrupted run (FP64, bitwise).  Loading only Delta and A, burn-in
+    iterations update the boundary store with the fields held fixed (the
+    residuals read 0), and bring the next map closer to the resumed one
+    than a restart from bulk start values."""
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: save, resume, burn-in" % name)
+    d0 = _dev(wl.initial_delta(name, sp), torch.complex128)
+    a0 = _dev(wl.initial_A(name, sp), torch.float64)
+    g1 = qs.Grain(sp, "fp64")
+    d, a = d0.clone(), a0.clone()
+    g1.scf(d, a, 8, alpha=0.7)
+    d8, a8, st = d.clone(), a.clone(), g1.get_state().clone()
+    g1.scf(d, a, 4, alpha=0.7)
+    g2 = qs.Grain(sp, "fp64")
+    g2.set_state(st)
+    dr, ar = d8.clone(), a8.clone()
+    g2.scf(dr, ar, 4, alpha=0.7)
+    assert torch.equal(dr, d) and torch.equal(ar, a)
+    # fields only: restart from bulk starts, with and without burn-in
+    g3 = qs.Grain(sp, "fp64")
+    db, ab = d8.clone(), a8.clone()
+    it, res, _ = g3.scf(db, ab, 6, burnin=6, alpha=0.7)
+    assert torch.equal(db, d8) and torch.equal(ab, a8)
+    assert np.all(res[:, :4] == 0.0)
+    g4 = qs.Grain(sp, "fp64")
+    g4.set_state(st)
+    dn_resumed = g4.sweep(d8, a8)[0]
+    dn_burnt = g3.sweep(d8, a8)[0]
+    g5 = qs.Grain(sp, "fp64")
+    dn_cold = g5.sweep(d8, a8)[0]
+    e_burnt = float((dn_burnt - dn_resumed).abs().max())
+    e_cold = float((dn_cold - dn_resumed).abs().max())
+    assert e_burnt < e_cold, (e_burnt, e_cold)
+    for g in (g1, g2, g3, g4, g5):
+        g.close()

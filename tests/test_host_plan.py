@@ -104,3 +104,54 @@ def test_boundary_taps_match_oracle(name):
                 assert len(ref) == len(ws), (name, k, local)
                 assert np.array_equal(ss, [r[0] for r in ref])
                 assert np.max(np.abs(ws - np.array([r[1] for r in ref]))) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL + ["d_disc_200"])
+def test_angle_pairs_mirror_the_segments(name):
+    """Angle pairs (Sec. II.A: gamma~(p) = gamma(-p)* for an even order
+    parameter; Sec. III.A: the lattice of phi_k + pi is that of phi_k with
+    both axes reversed): every segment of an upper angle has a mirror on
+    angle k - n_theta/2, line M-1-i, with the same node count, the nodes in
+    reverse order (jfirst' = M - jfirst - n) and the ends swapped
+    (s_min' = -s_max), so the paired sweep marches half the steps.  An odd
+    angle count has no pairs."""
+    sp = wl.spec(name)
+    pl = qs.Plan(sp)
+    ok, swept, mir = pl.pairing()
+    n = sp["n_theta"]
+    # an odd angle count has no pairs; the cell-mask grain has lines through
+    # corners of its boundary polyline, whose wall tangent depends on the
+    # direction of the line, so its boundary taps do not mirror
+    assert ok == (n % 2 == 0 and name != "small_mask_blob")
+    if not ok:
+        assert swept == pl.info["steps_per_sweep"] and np.all(mir == -1)
+        return
+    seg = pl.segments()
+    M = pl.info["lattice_m"]
+    upper = seg[:, 0] >= n // 2
+    assert np.all(mir[~upper] == -1) and np.all(mir[upper] >= 0)
+    a, b = seg[upper], seg[mir[upper]]
+    assert np.array_equal(b[:, 0], a[:, 0] - n // 2)
+    assert np.array_equal(b[:, 1], M - 1 - a[:, 1])
+    assert np.array_equal(b[:, 5], a[:, 5])
+    has = a[:, 5] > 0
+    assert np.array_equal(b[has, 4], M - a[has, 4] - a[has, 5])
+    assert np.allclose(b[:, 2], -a[:, 3], atol=1e-9 * sp["h"]) and np.allclose(b[:, 3], -a[:, 2], atol=1e-9 * sp["h"])
+    # a bijection onto the lower angles, and half the steps
+    assert len(np.unique(mir[upper])) == int(upper.sum()) == int((~upper).sum())
+    assert 2 * swept == pl.info["steps_per_sweep"]
+
+
+@pytest.mark.parametrize("name", ["small_d110_field", "small_holed_mixed", "small_mask_blob", "d110_square_400"])
+def test_library_basis_table_matches_oracle(name):
+    """The library tabulates eta_G(phi_k) from the App. F basis names and the
+    crystal rotation itself (the binding passes names only); it equals the
+    oracle's independently written table (which is pinned to the App. F
+    polynomials), and an explicit eta table passed instead is used as is."""
+    sp = wl.spec(name)
+    og = oracle_grain(sp)
+    eta = qs.Plan(dict(sp, n_theta=sp["n_theta"])).eta()
+    assert np.max(np.abs(eta - og.eta)) <= 1e-14
+    rng = np.random.default_rng(2)
+    given = rng.standard_normal(eta.shape) + 1j * rng.standard_normal(eta.shape)
+    assert np.array_equal(qs.Plan(dict(sp, eta=given)).eta(), given)
