@@ -31,6 +31,13 @@ headline):
                                   both precisions (default: the 48-pole disc)
     --mode valu                   sustained FP32 fma / rsq / sqrt / rcp rates of
                                   the device (the issue ceiling of the sweep)
+    --mode vortex                 the paper's demonstration (s-wave disc, vortex,
+                                  600x600): iterations of Picard, Polyak, BB and
+                                  CongAcc to 1e-5, then the LDOS post-process
+                                  (720 angles, 128 energies, to 1e-4)
+    --mode errors                 mixed against FP64 per result on the 400x400
+                                  workload: Delta, j, Omega, A, <g>, LDOS, and
+                                  the self-consistent Delta (CongAcc to 1e-6)
 """
 import argparse
 import json
@@ -73,15 +80,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--mode", choices=["iteration", "converge", "accel", "ldos", "batch", "adjoint", "lanes", "valu"],
+    ap.add_argument("--mode", choices=["iteration", "converge", "accel", "ldos", "batch", "adjoint", "lanes", "valu",
+                                       "vortex", "errors"],
                     default="iteration")
     ap.add_argument("--workload", default="d_disc_200")
     ap.add_argument("--iters", type=int, default=None)
-    ap.add_argument("--prior", type=int, default=200)
+    ap.add_argument("--prior", type=int, default=4000)
     ap.add_argument("--bc-iters", type=int, default=20)
     ap.add_argument("--grains", type=int, default=64)
     ap.add_argument("--accel-workload", default=WORKLOAD)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--ldos-angles", type=int, default=720)
     return ap.parse_args()
 
 
@@ -260,17 +269,19 @@ def mode_accel(qs, torch, wl, iters, tol, name=WORKLOAD):
 
 
 def mode_ldos(qs, torch, wl, n_prior, bc_iters):
-    """LDOS of the 512x512 [110] square: a mixed Picard prior solve at 64
-    angles, then 256 angles x 512 real energies with bc_iters boundary
-    iterations (Delta and A frozen)."""
+    """LDOS of the 512x512 [110] square: an FP64 prior solve at 64 angles
+    (CongAcc, to a global error of 1e-6 or n_prior iterations), then 256
+    angles x 512 real energies with bc_iters boundary iterations (Delta and
+    A frozen)."""
     name = "d110_square_512_ldos"
     sp = wl.spec(name)
     d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
     a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
-    print("bench: ldos prior solve, %d iterations" % n_prior, file=sys.stderr, flush=True)
+    print("bench: ldos prior solve, up to %d iterations" % n_prior, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    g = qs.Grain(dict(sp, n_theta=64), "mixed")
-    g.scf(d0, a0, n_prior, tol=1e-6)
+    g = qs.Grain(dict(sp, n_theta=64), "fp64")
+    g.set_accelerator("congacc")
+    prior_it, prior_res, prior_conv = g.scf(d0, a0, n_prior, tol=1e-6, alpha=0.5)
     torch.cuda.synchronize()
     g.close()
     prior_s = time.perf_counter() - t0
@@ -290,7 +301,8 @@ def mode_ldos(qs, torch, wl, n_prior, bc_iters):
     return {"metric": "LDOS trajectory-steps/s", "workload": name, "energies": len(en), "bc_iters": bc_iters,
             "value": steps / dt, "unit": "trajectory-steps/s", "seconds": dt, "steps": steps,
             "sweep_kernel_ms": ms, "sweep_launches": nl, "sweep_only_steps_per_s": steps / (ms * 1e-3),
-            "prior_solve_s": prior_s, "finite": bool(np.isfinite(o).all())}
+            "prior_solve_s": prior_s, "prior_iters": prior_it, "prior_converged": bool(prior_conv),
+            "prior_res_last": prior_res[prior_it - 1, :4].tolist(), "finite": bool(np.isfinite(o).all())}
 
 
 def mode_batch(qs, torch, wl, n, iters):
@@ -413,6 +425,136 @@ def mode_valu(qs):
             "transcendental_over_fma": {op: r[op] / r["fma"] for op in ("rsq", "sqrt", "rcp")}}
 
 
+def mode_vortex(qs, torch, wl, max_iter, ldos_angles):
+    """The demonstration of Sec. IV (App. B listing): every accelerator of
+    App. E from the same start, FP64, to the listing's tolerance 1e-5; then
+    the LDOS post-process of the converged CongAcc state (Sec. IV listing:
+    energies 0..0.5, broadening 0.008, iterated to 1e-4) in the mixed path,
+    and the save / restore round trip of the state."""
+    name = "swave_disc_vortex"
+    sp = wl.spec(name)
+    d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    paper = {"picard": "F", "polyak": "F", "bb": 45, "congacc": 42}
+    runs = {}
+    keep = None
+    for kind, alpha in (("picard", 1.0), ("polyak", 2.0), ("bb", 1.0), ("congacc", 0.5)):
+        print("bench: vortex %s" % kind, file=sys.stderr, flush=True)
+        g = qs.Grain(sp, "fp64")
+        g.set_accelerator(kind, 0.5)
+        d, a = d0.clone(), a0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            it, res, conv = g.scf(d, a, max_iter, tol=1e-5, alpha=alpha)
+            torch.cuda.synchronize()
+            runs[kind] = {"step": alpha, "iters": it, "converged": bool(conv), "s": time.perf_counter() - t0,
+                          "res_last": res[it - 1, :4].tolist(), "paper_iters": paper[kind]}
+        except qs.QcError as e:
+            runs[kind] = {"step": alpha, "diverged": str(e), "paper_iters": paper[kind]}
+        if kind == "congacc":
+            t0 = time.perf_counter()
+            st = g.get_state().clone()
+            g2 = qs.Grain(sp, "fp64")
+            g2.set_state(st)
+            dn, _, _ = g2.sweep(d, a)
+            torch.cuda.synchronize()
+            runs[kind]["resume_s"] = time.perf_counter() - t0
+            runs[kind]["resume_first_map_max_change_over_delta0"] = float((dn - d).abs().max()) / wl.DELTA0
+            g2.close()
+            keep = (d, a)
+        g.close()
+    d, a = keep
+    print("bench: vortex LDOS, %d angles" % ldos_angles, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    gl = qs.Grain(dict(sp, n_theta=ldos_angles), "mixed")
+    setup = time.perf_counter() - t0
+    en = wl.vortex_ldos_energies(128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ld, iters = gl.ldos_converge(d, a, en, 0.008, 1e-4, 1000, energies_per_block=32)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps_bc = gl.info["steps_per_sweep"] // sp["n_poles"] * len(en)
+    ld = ld.cpu().numpy()
+    X, Y = wl.centres(sp)
+    r = np.hypot(X, Y)
+    gl.close()
+    return {"metric": "iterations to 1e-5 per accelerator, and the LDOS post-process", "workload": name,
+            "precision_scf": "fp64", "runs": runs,
+            "ldos": {"angles": ldos_angles, "energies": len(en), "broadening": 0.008, "tol": 1e-4,
+                     "sweeps_slowest_block": iters, "seconds": dt, "plan_and_upload_s": setup,
+                     "steps_per_sweep_all_energies": steps_bc,
+                     "core_N0": float(ld[0][r < 0.3].mean()), "ring_8_9_N0": float(ld[0][(r > 8) & (r < 9)].mean()),
+                     "finite": bool(np.isfinite(ld).all())}}
+
+
+def mode_errors(qs, torch, wl, scf_iters):
+    """Mixed against FP64 per result on the 400x400 [110] workload: the
+    first three chained maps against the oracle's stored values (Delta, j,
+    Omega), the A-solve of each precision's current, the Green's function
+    average and the LDOS (64 angles, 16 energies) against the FP64 path,
+    and the self-consistent Delta of CongAcc runs to 1e-6 in both."""
+    name = WORKLOAD
+    sp = wl.spec(name)
+    gold = np.load(os.path.join(HERE, "tests", "golden", name + "_iter3.npz"))
+    cells = gold["cells"]
+    d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    out = {"metric": "mixed vs FP64 error per result", "workload": name, "delta0": wl.DELTA0}
+    maps = {}
+    for prec in ("mixed", "fp64"):
+        print("bench: errors, three maps %s" % prec, file=sys.stderr, flush=True)
+        g = qs.Grain(sp, prec)
+        d, a = d0.clone(), a0.clone()
+        rows = []
+        for i in range(3):
+            dn, j, om = g.sweep(d, a)
+            A, _ = g.solve_A(j, B=False)
+            dg = dn.cpu().numpy().reshape(1, -1)[:, cells]
+            jg = j.cpu().numpy().reshape(2, -1)[:, cells]
+            rows.append({"delta_max_abs_over_delta0": float(np.max(np.abs(dg - gold["delta_new"][i])) / wl.DELTA0),
+                         "j_max_abs_over_max_j": float(np.max(np.abs(jg - gold["j"][i])) / np.max(np.abs(gold["j"][i]))),
+                         "omega_rel": float(abs(om - gold["omega_total"][i]) / abs(gold["omega_total"][i]))})
+            maps.setdefault(prec, []).append(A.cpu().numpy())
+            d, a = dn, A
+        out["maps_vs_oracle_" + prec] = rows
+        g.close()
+    out["A_max_abs_over_max_A"] = [float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
+                                   for x, y in zip(maps["mixed"], maps["fp64"])]
+    res = {}
+    for prec in ("mixed", "fp64"):
+        print("bench: errors, <g> and LDOS %s" % prec, file=sys.stderr, flush=True)
+        g = qs.Grain(sp, prec)
+        g.sweep(d0, a0)
+        gav = g.green_average(d0, a0).cpu().numpy()
+        ld = g.ldos(d0, a0, np.linspace(-1.5, 1.5, 16) * wl.DELTA0, 0.01 * wl.DELTA0, 10).cpu().numpy()
+        res[prec] = (gav, ld)
+        g.close()
+    out["green_average_max_abs_over_max"] = float(np.max(np.abs(res["mixed"][0] - res["fp64"][0]))
+                                                  / np.max(np.abs(res["fp64"][0])))
+    out["ldos_max_abs"] = float(np.max(np.abs(res["mixed"][1] - res["fp64"][1])))
+    out["ldos_max"] = float(np.max(np.abs(res["fp64"][1])))
+    sc = {}
+    for prec in ("fp64", "mixed"):
+        print("bench: errors, CongAcc to 1e-6 %s" % prec, file=sys.stderr, flush=True)
+        g = qs.Grain(sp, prec)
+        g.set_accelerator("congacc")
+        d, a = d0.clone(), a0.clone()
+        t0 = time.perf_counter()
+        it, hist, conv = g.scf(d, a, scf_iters, tol=1e-6, alpha=0.5)
+        torch.cuda.synchronize()
+        sc[prec] = {"iters": it, "converged": bool(conv), "s": time.perf_counter() - t0,
+                    "res_last": hist[it - 1, :4].tolist(), "delta": d.cpu().numpy()}
+        g.close()
+    m = qs.Plan(dict(sp, n_theta=4)).mask()
+    diff = np.max(np.abs(sc["mixed"]["delta"][:, m] - sc["fp64"]["delta"][:, m])) / wl.DELTA0
+    for prec in sc:
+        sc[prec].pop("delta")
+    out["self_consistent"] = {"runs": sc, "delta_max_abs_over_delta0": float(diff), "tolerance": 1e-4}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -449,6 +591,10 @@ def main():
             res = mode_lanes(qs, torch, wl, args.workload, args.iters or 8)
         elif args.mode == "valu":
             res = mode_valu(qs)
+        elif args.mode == "vortex":
+            res = mode_vortex(qs, torch, wl, args.iters or 1000, args.ldos_angles)
+        elif args.mode == "errors":
+            res = mode_errors(qs, torch, wl, args.iters or 6000)
         else:
             res = mode_batch(qs, torch, wl, args.grains, args.iters or 6)
         print(json.dumps(res), flush=True)

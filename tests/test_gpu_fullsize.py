@@ -225,3 +225,72 @@ def test_batch_largest_grain_first_map_matches_oracle(precision):
     else:
         err = np.max(np.abs(got - ref)) / wl.DELTA0
         assert err <= 2e-5, err
+
+
+def test_swave_disc_vortex_end_to_end():
+    """The paper's demonstration (Sec. IV, App. B listing): s-wave disc of
+    radius 15 xi0 at 20 points per xi0 (600 x 600), 32 angles, t = 0.5,
+    1.5 flux quanta, penetration depth 5 xi0, one vortex of winding -1 at
+    the centre.  App. E's table has Picard and Polyak fail there and BB and
+    CongAcc converge to 1e-5 in 45 and 42 iterations; here CongAcc and BB
+    (FP64) must converge within 300 (39 and 73 here).  The converged state has a vortex core
+    at the centre (|Delta| below 0.15 of the bulk gap in the four central
+    cells), the bulk gap within 15% on the ring 8 < r < 9 xi0, and a phase
+    winding of -1 around r = 5 xi0.  Saving the fields and boundary store
+    and loading them into a fresh grain, the next map changes Delta by less
+    than the tolerance; the LDOS post-process (128 angles here, 16 energies
+    in [0, 0.5], broadening 0.008, to 1e-4) shows the core states at zero
+    energy and a gap away from the core."""
+    qs = _qs()
+    name = "swave_disc_vortex"
+    sp = wl.spec(name)
+    d0 = torch.as_tensor(wl.initial_delta(name, sp)).cuda()
+    a0 = torch.as_tensor(wl.initial_A(name, sp)).cuda()
+    res = {}
+    for kind, alpha in (("congacc", 0.5), ("bb", 1.0)):
+        _note("full size: %s with %s" % (name, kind))
+        g = qs.Grain(sp, "fp64")
+        g.set_accelerator(kind)
+        d, a = d0.clone(), a0.clone()
+        it, hist, conv = g.scf(d, a, 300, tol=1e-5, alpha=alpha)
+        res[kind] = (it, conv, d, a, g)
+        _note("  %s: %d iterations, converged %s" % (kind, it, conv))
+        assert conv, (kind, it, hist[-1])
+    it, conv, d, a, g = res["congacc"]
+    X, Y = wl.centres(sp)
+    r = np.hypot(X, Y)
+    dabs = d.abs().cpu().numpy()[0]
+    dbulk = wl.S_BULK_T05 * wl.DELTA0
+    assert np.max(dabs[r < 0.05]) < 0.15 * dbulk
+    ring = (r > 8.0) & (r < 9.0)
+    assert np.all(np.abs(dabs[ring] / dbulk - 1.0) < 0.15)
+    ph = np.angle(d.cpu().numpy()[0])
+    t = np.linspace(0, 2 * np.pi, 720, endpoint=False)
+    xs, ys = 5.0 * np.cos(t), 5.0 * np.sin(t)
+    ii = np.clip(((xs + 15.0) / sp["h"]).astype(int), 0, sp["nx"] - 1)
+    jj = np.clip(((ys + 15.0) / sp["h"]).astype(int), 0, sp["ny"] - 1)
+    loop = ph[jj, ii]
+    dph = np.diff(np.concatenate([loop, loop[:1]]))  # a closed loop of cells
+    dph = (dph + np.pi) % (2 * np.pi) - np.pi
+    assert abs(dph.sum() / (2 * np.pi) + 1.0) < 1e-6
+    # save and resume
+    st = g.get_state().clone()
+    g2 = qs.Grain(sp, "fp64")
+    g2.set_state(st)
+    dn, _, _ = g2.sweep(d, a)
+    m = g2.mask()
+    assert float((dn - d).abs().max()) < 1e-3 * dbulk
+    g2.close()
+    for k in res:
+        res[k][4].close()
+    # LDOS post-process on the converged state
+    _note("full size: %s LDOS post-process" % name)
+    gl = qs.Grain(dict(sp, n_theta=128), "mixed")
+    en = np.linspace(0.0, 0.5, 16)
+    ld, iters = gl.ldos_converge(d, a, en, 0.008, 1e-4, 200)
+    ld = ld.cpu().numpy()
+    gl.close()
+    assert np.isfinite(ld).all() and ld[:, m].min() > -1e-6 and iters < 200
+    core = ld[0][r < 0.3]
+    assert core.mean() > 1.0, core.mean()
+    assert ld[0][ring].mean() < 0.2, ld[0][ring].mean()
