@@ -231,6 +231,26 @@ qc_status qc_sweep(qc_grain* grain, const double* delta, const double* A_ind,
                    double* delta_new, double* j, double* omega_density,
                    double* omega_total, void* stream);
 
+/* qc_sweep without allocation, for callers that cannot allocate device
+ * memory (code under stream or graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same map, arguments and results as
+ * qc_sweep; the per-call work arrays (slot values, the gamma spill between
+ * the two marches, per-node sums, packed interpolation cells) live in one
+ * 64 MiB array that the library holds on each device it runs on until the
+ * process ends, instead of grain-owned allocations.  Calls on one device
+ * share that array, so calls that overlap on one GPU race; nothing in it
+ * needs clearing between calls (every element a call reads it wrote
+ * first).  Needs a grain whose boundary store exists (any earlier qc_sweep
+ * or qc_set_state creates it).  Errors: QC_ERR_INVALID when the grain needs
+ * more scratch than the array holds (qc_sweep_static_bytes tells) or has no
+ * boundary store yet. */
+qc_status qc_sweep_static(qc_grain* grain, const double* delta, const double* A_ind,
+                          double* delta_new, double* j, double* omega_density,
+                          double* omega_total, void* stream);
+/* scratch bytes qc_sweep_static needs for this grain and the size of the
+ * per-device array; either pointer may be NULL. */
+qc_status qc_sweep_static_bytes(const qc_grain* grain, size_t* needed, size_t* available);
+
 /* Induced vector potential from a current (App. D): the grain mean of j is
  * subtracted on grain cells, then A = -kappa^-2 sum G_{|dm|,|dn|} j' over the
  * whole array (zero-padded FFT correlation), B = curl A with central

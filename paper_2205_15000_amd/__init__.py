@@ -96,6 +96,8 @@ _sig("qc_grain_get_mask", ctypes.c_int, [_P, _P])
 _sig("qc_grain_reset_bc", ctypes.c_int, [_P])
 _sig("qc_grain_get_lanes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)])
 _sig("qc_sweep", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P])
+_sig("qc_sweep_static", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P])
+_sig("qc_sweep_static_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)])
 _sig("qc_solve_A", ctypes.c_int, [_P, _P, _P, _P, _P])
 _sig("qc_grain_set_A_solver", ctypes.c_int, [_P, ctypes.c_double])
 _sig("qc_grain_get_A_solver", ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int)])

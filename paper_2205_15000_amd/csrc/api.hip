@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1037,6 +1038,106 @@ qc_status qc_sweep(qc_grain* g, const double* delta, const double* A_ind, double
     do_sweep(g, delta, A_ind, delta_new, j, omega_density, omega_total, S(stream));
     return QC_OK;
   });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free sweep: the per-call work arrays of qc_sweep (slot values,
+// the gamma spill, per-node sums, packed interpolation cells) live in one
+// file-scope device array instead of grain-owned allocations.  Each device
+// holds its own copy of the array until the process ends; its address on a
+// device comes from hipGetSymbolAddress with that device current.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;  // 64 MiB per device
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (device current)
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) throw std::invalid_argument("device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    hcheck(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw HipError("hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// bytes of scratch one sweep of this grain needs: slot values, gamma spill,
+// per-node sums, packed cells (one component)
+size_t static_sweep_bytes(const qc_grain* g) {
+  const size_t rb = g->real_bytes();
+  size_t b = align256(4 * rb * g->nslot) + align256(2 * rb * g->nslot * g->n_poles) +
+             align256(4 * sizeof(double) * g->nslot);
+  if (g->ncomp == 1) b += align256(4 * rb * g->ncell);
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+qc_status qc_sweep_static(qc_grain* g, const double* delta, const double* A_ind, double* delta_new, double* j,
+                          double* omega_density, double* omega_total, void* stream) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!delta || !A_ind || !delta_new || !j) return fail(QC_ERR_INVALID, "delta, A_ind, delta_new and j are required");
+  const size_t need = static_sweep_bytes(g);
+  if (need > kScratchBytes)
+    return fail(QC_ERR_INVALID, "qc_sweep_static: this grain needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
+                                    " the library holds per device (use qc_sweep)");
+  if (!g->bc[0][0] || !g->bc[1][0])
+    return fail(QC_ERR_INVALID, "qc_sweep_static: the grain has no boundary store yet (run qc_sweep or "
+                                "qc_set_state once first)");
+  return guarded([&]() -> qc_status {
+    hcheck(hipSetDevice(g->device), "hipSetDevice");
+    unsigned char* base = static_cast<unsigned char*>(scratch_ptr(g->device));
+    const size_t rb = g->real_bytes();
+    // the grain's own work arrays are set aside for the call
+    void* own_nodes = g->nodes;
+    void* own_gbuf = g->gbuf;
+    double* own_out = g->node_out;
+    void* own_cells = g->cells;
+    size_t off = 0;
+    g->nodes = base + off;
+    off += align256(4 * rb * g->nslot);
+    g->gbuf = base + off;
+    off += align256(2 * rb * g->nslot * g->n_poles);
+    g->node_out = reinterpret_cast<double*>(base + off);
+    off += align256(4 * sizeof(double) * g->nslot);
+    if (g->ncomp == 1) g->cells = base + off;
+    qc_status st = QC_OK;
+    try {
+      do_sweep(g, delta, A_ind, delta_new, j, omega_density, omega_total, S(stream));
+    } catch (...) {
+      g->nodes = own_nodes;
+      g->gbuf = own_gbuf;
+      g->node_out = own_out;
+      g->cells = own_cells;
+      throw;
+    }
+    g->nodes = own_nodes;
+    g->gbuf = own_gbuf;
+    g->node_out = own_out;
+    g->cells = own_cells;
+    return st;
+  });
+}
+
+qc_status qc_sweep_static_bytes(const qc_grain* g, size_t* needed, size_t* available) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (needed) *needed = static_sweep_bytes(g);
+  if (available) *available = kScratchBytes;
+  return QC_OK;
 }
 
 }  // extern "C"
