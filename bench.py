@@ -37,7 +37,8 @@ headline):
                                   (720 angles, 128 energies, to 1e-4)
     --mode errors                 mixed against FP64 per result on the 400x400
                                   workload: Delta, j, Omega, A, <g>, LDOS, and
-                                  the self-consistent Delta (CongAcc to 1e-6)
+                                  the self-consistent Delta (CongAcc to 1e-8,
+                                  up to one global phase)
 """
 import argparse
 import json
@@ -494,7 +495,9 @@ def mode_errors(qs, torch, wl, scf_iters):
     first three chained maps against the oracle's stored values (Delta, j,
     Omega), the A-solve of each precision's current, the Green's function
     average and the LDOS (64 angles, 16 energies) against the FP64 path,
-    and the self-consistent Delta of CongAcc runs to 1e-6 in both."""
+    and the self-consistent Delta: FP64 CongAcc to 1e-8, then the mixed path
+    from that state to 1e-8, compared up to one global phase (a common phase
+    factor leaves the gap equation and the current unchanged)."""
     name = WORKLOAD
     sp = wl.spec(name)
     gold = np.load(os.path.join(HERE, "tests", "golden", name + "_iter3.npz"))
@@ -535,23 +538,33 @@ def mode_errors(qs, torch, wl, scf_iters):
                                                   / np.max(np.abs(res["fp64"][0])))
     out["ldos_max_abs"] = float(np.max(np.abs(res["mixed"][1] - res["fp64"][1])))
     out["ldos_max"] = float(np.max(np.abs(res["fp64"][1])))
+    # the self-consistent state: FP64 with CongAcc to 1e-8 from the start,
+    # then the mixed path from that state to 1e-8 (its own fixed point next
+    # to the FP64 one); independent runs from the start can settle in
+    # different states (vortex positions are not unique)
     sc = {}
+    d, a = d0.clone(), a0.clone()
     for prec in ("fp64", "mixed"):
-        print("bench: errors, CongAcc to 1e-6 %s" % prec, file=sys.stderr, flush=True)
+        print("bench: errors, CongAcc to 1e-8 %s" % prec, file=sys.stderr, flush=True)
         g = qs.Grain(sp, prec)
         g.set_accelerator("congacc")
-        d, a = d0.clone(), a0.clone()
         t0 = time.perf_counter()
-        it, hist, conv = g.scf(d, a, scf_iters, tol=1e-6, alpha=0.5)
+        it, hist, conv = g.scf(d, a, scf_iters, tol=1e-8, alpha=0.5)
         torch.cuda.synchronize()
         sc[prec] = {"iters": it, "converged": bool(conv), "s": time.perf_counter() - t0,
-                    "res_last": hist[it - 1, :4].tolist(), "delta": d.cpu().numpy()}
+                    "res_last": hist[it - 1, :4].tolist(), "delta": d.cpu().numpy().copy()}
         g.close()
     m = qs.Plan(dict(sp, n_theta=4)).mask()
-    diff = np.max(np.abs(sc["mixed"]["delta"][:, m] - sc["fp64"]["delta"][:, m])) / wl.DELTA0
+    x, y = sc["fp64"]["delta"][:, m], sc["mixed"]["delta"][:, m]
+    chi = float(np.angle(np.vdot(x, y)))
+    raw = np.max(np.abs(y - x)) / wl.DELTA0
+    diff = np.max(np.abs(y * np.exp(-1j * chi) - x)) / wl.DELTA0
     for prec in sc:
         sc[prec].pop("delta")
-    out["self_consistent"] = {"runs": sc, "delta_max_abs_over_delta0": float(diff), "tolerance": 1e-4}
+    out["self_consistent"] = {"runs": sc, "mixed_started_from": "the FP64 self-consistent state",
+                              "global_phase_rad": chi,
+                              "delta_max_abs_over_delta0_raw": float(raw),
+                              "delta_max_abs_over_delta0": float(diff), "tolerance": 1e-4}
     return out
 
 
@@ -594,7 +607,7 @@ def main():
         elif args.mode == "vortex":
             res = mode_vortex(qs, torch, wl, args.iters or 1000, args.ldos_angles)
         elif args.mode == "errors":
-            res = mode_errors(qs, torch, wl, args.iters or 6000)
+            res = mode_errors(qs, torch, wl, args.iters or 9000)
         else:
             res = mode_batch(qs, torch, wl, args.grains, args.iters or 6)
         print(json.dumps(res), flush=True)

@@ -355,6 +355,11 @@ struct qc_grain {
   int32_t* order_pair = nullptr;
   int4* rb4_pair = nullptr;
   int2* mirror_pairs = nullptr;
+  // transposed rotate-back of the paired reverse mode: the entries of the
+  // upper angles moved onto their mirror slots
+  int64_t* btp_ptr = nullptr;
+  int32_t* btp_c = nullptr;
+  double* btp_w = nullptr;
   // eigen-truncated A-solve (App. D): tolerance, kept modes, eigenvalues and
   // eigenvectors [a_nmodes][nx], masked current and per-mode products
   double a_eps = 0.0;
@@ -423,7 +428,7 @@ void free_grain(qc_grain* g) {
                   g->ghat, g->twx, g->twy, g->dnew, g->jcur, g->jold, g->anew, g->vel_d, g->vel_a, g->gtbuf, g->lgt, g->gS, g->gV,
                   g->bt_ptr, g->bt_c, g->bt_w, g->it_dptr, g->it_ds, g->it_dw, g->it_aptr, g->it_as, g->it_aw,
                   g->ckbase, g->ckg, g->ckgt, g->ckscr, g->lw_acc, g->lw_dl, g->lw_save, g->order_pair, g->rb4_pair,
-                  g->mirror_pairs, g->a_lam, g->a_vk, g->a_jp, g->a_y};
+                  g->mirror_pairs, g->a_lam, g->a_vk, g->a_jp, g->a_y, g->btp_ptr, g->btp_c, g->btp_w};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (g->part_host) (void)hipHostFree(g->part_host);
@@ -1981,6 +1986,49 @@ void ensure_adjoint_tables(qc_grain* g) {
   g->it_aw = static_cast<double*>(upload(a.w));
 }
 
+// The transposed rotate-back for the paired reverse mode.  A corner of an
+// upper angle k' = k + n_theta/2 reads the node sums of its mirror slot on
+// angle k (S_f, S_I equal, S_g of opposite sign); its gradient terms, formed
+// with the mirror slot's angle (w, eta equal; v_k' = -v_k cancels the S_g
+// sign), are those of a corner of angle k, so the entry moves onto the
+// mirror slot with its weight.
+void ensure_adjoint_pair_tables(qc_grain* g) {
+  if (g->btp_ptr || !g->pair_ok) return;
+  const int64_t nc = g->ncg;
+  const int n2 = g->n_theta / 2;
+  const size_t n = static_cast<size_t>(g->n_theta) * 4 * nc;
+  const std::vector<int32_t> idx = download(g->rb_idx, n);
+  const std::vector<double> w = download(g->rb_w, n);
+  const std::vector<int4> r4 = download(g->rb4, static_cast<size_t>(g->n_theta) * nc);
+  const std::vector<int4> r4p = download(g->rb4_pair, static_cast<size_t>(g->n_theta) * nc);
+  std::vector<int32_t> mirror(static_cast<size_t>(g->nslot), -1);
+  for (size_t e = static_cast<size_t>(n2) * nc; e < r4.size(); ++e) {
+    const int32_t a[4] = {r4[e].x, r4[e].y, r4[e].z, r4[e].w};
+    const int32_t b[4] = {r4p[e].x, r4p[e].y, r4p[e].z, r4p[e].w};
+    for (int q = 0; q < 4; ++q)
+      if (a[q] >= 0) mirror[a[q]] = b[q];
+  }
+  std::vector<int64_t> row;
+  std::vector<int32_t> col;
+  std::vector<double> ww;
+  for (size_t o = 0; o < n; ++o) {
+    if (w[o] == 0.0) continue;
+    const int k = static_cast<int>(o / (4 * static_cast<size_t>(nc)));
+    int32_t sl = idx[o];
+    if (k >= n2) {
+      sl = mirror[sl];
+      if (sl < 0) throw std::runtime_error("paired reverse mode: a corner without a mirror slot");
+    }
+    row.push_back(sl);
+    col.push_back(static_cast<int32_t>(o % nc));
+    ww.push_back(w[o]);
+  }
+  const Csr c = to_csr(g->nslot, row, col, ww);
+  g->btp_ptr = static_cast<int64_t*>(upload(c.ptr));
+  g->btp_c = static_cast<int32_t*>(upload(c.col));
+  g->btp_w = static_cast<double*>(upload(c.w));
+}
+
 }  // namespace
 
 extern "C" {
@@ -2028,7 +2076,11 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     if (!g->gS) g->gS = static_cast<double*>(dalloc(sizeof(double) * 4 * g->nslot));
     if (!g->gV) g->gV = static_cast<double*>(dalloc(sizeof(double) * 3 * g->nslot));
     ensure_adjoint_tables(g);
-    do_interp(g, delta, A_ind, st);
+    // with angle pairs the reverse mode marches the lower angles only, as
+    // the forward sweep does
+    const bool pair = g->pairing;
+    if (pair) ensure_adjoint_pair_tables(g);
+    do_interp(g, delta, A_ind, st, pair);
     // gradients of the per-node sums
     qc::BackAdjArgs ba;
     ba.ncg = g->ncg;
@@ -2049,14 +2101,14 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
     ba.gdn = g_delta_new;
     ba.gj = g_j;
     ba.gS = g->gS;
-    ba.nslot = g->nslot;
+    ba.nslot = pair ? g->nslot_pair : g->nslot;
     ba.slot_angle = g->slot_angle;
-    ba.bt_ptr = g->bt_ptr;
-    ba.bt_c = g->bt_c;
-    ba.bt_w = g->bt_w;
+    ba.bt_ptr = pair ? g->btp_ptr : g->bt_ptr;
+    ba.bt_c = pair ? g->btp_c : g->bt_c;
+    ba.bt_w = pair ? g->btp_w : g->bt_w;
     qc::launch_back_adjoint(ba, st);
     // reverse sweep with the store the latest sweep read
-    qc::AdjArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd);
+    qc::AdjArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd, pair);
     a.bc_valid = g->last_bc_valid;
     qc::AdjBufs b;
     b.nodes = g->nodes;
@@ -2073,10 +2125,12 @@ qc_status qc_sweep_adjoint(qc_grain* g, const double* delta, const double* A_ind
       b.ckg = g->ckg;
       b.ckgt = g->ckgt;
       b.scr = g->ckscr;
-      b.nthr = g->nseg * G;
+      b.nthr = a.nseg * G;
     }
     qc::launch_adjoint(epl, a, b, st);
     hcheck(hipGetLastError(), "adjoint launch");
+    // the upper angles' slots take no part in the paired map
+    if (pair) qc::launch_fill(g->gV + 3 * g->nslot_pair, 3 * (g->nslot - g->nslot_pair), 0.0, st);
     // back to the reference grid (the gather writes every cell)
     qc::InterpAdjArgs ia;
     ia.nslot = g->nslot;

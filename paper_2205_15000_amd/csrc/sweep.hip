@@ -319,9 +319,12 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   }
 
   // ---- gamma~: R_max -> R_min with D -> -D*
-  T rw[EPL];  // pole weights R_p of the lane's energies (0 for padding)
+  // pole weights R_p of the lane's energies (0 for padding), kept in FP64:
+  // the gap denominator holds them exactly, and rounding them to FP32 in
+  // the node sums would bias every gap update the same way
+  double rw[EPL];
   for (int i = 0; i < EPL; ++i)
-    rw[i] = static_cast<T>((MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + min(e0 + i, a.n_e - 1)] : 0.0);
+    rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + min(e0 + i, a.n_e - 1)] : 0.0;
   cpx<T> gt[EPL];
   prev = nodes[slot0 + last];
   {
@@ -386,23 +389,31 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
       double sfx, sfy, sg, si;
       if constexpr (sizeof(T) == 4) {
         // mixed precision: each pole's terms are formed from the FP32
-        // marches and summed over poles in FP64
-        sfx = sfy = sg = si = 0.0;
+        // marches, weighted by R_p and summed over poles in FP64
         for (int i = 0; i < EPL; ++i) {
           const cpx<T> gg = gn[i];
           const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
           const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
           const T dxr = T(1) + xx;
-          // I = 1/(1+X) = (dxr - i xy) u / R with u = R / |1+X|^2 (R the pole weight)
-          const T r = rw[i];
-          const T u = r * drcp(fmaT(dxr, dxr, xy * xy));
+          // I = 1/(1+X) = (dxr - i xy) u with u = 1 / |1+X|^2
+          const T u = drcp(fmaT(dxr, dxr, xy * xy));
           const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
           const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
-          sfx += static_cast<double>(u * fmaT(sxs, dxr, sys * xy));     // R Re((gamma + gamma~) I)
-          sfy += static_cast<double>(u * fmaT(dys, dxr, -(dxs * xy)));  // R Im((gamma - gamma~) I)
-          sg -= static_cast<double>(u * xy);                            // R Im I
-          // R Im(D* gamma - D gamma~)
-          si += static_cast<double>(r * fmaT(nv.dx, dys, -(nv.dy * sxs)));
+          const double tfx = static_cast<double>(u * fmaT(sxs, dxr, sys * xy));     // Re((gamma + gamma~) I)
+          const double tfy = static_cast<double>(u * fmaT(dys, dxr, -(dxs * xy)));  // Im((gamma - gamma~) I)
+          const double tg = static_cast<double>(u * xy);                            // -Im I
+          const double ti = static_cast<double>(fmaT(nv.dx, dys, -(nv.dy * sxs)));  // Im(D* gamma - D gamma~)
+          if (i == 0) {
+            sfx = rw[0] * tfx;
+            sfy = rw[0] * tfy;
+            sg = -rw[0] * tg;
+            si = rw[0] * ti;
+          } else {
+            sfx = __builtin_fma(rw[i], tfx, sfx);
+            sfy = __builtin_fma(rw[i], tfy, sfy);
+            sg = __builtin_fma(-rw[i], tg, sg);
+            si = __builtin_fma(rw[i], ti, si);
+          }
         }
       } else {
         T pfx = T(0), pfy = T(0), pg = T(0), p1 = T(0), p2 = T(0);
@@ -412,7 +423,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
           const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
           const T dxr = T(1) + xx;
           // I = 1/(1+X) = (dxr - i xy) u / R with u = R / |1+X|^2 (R the pole weight)
-          const T r = rw[i];
+          const T r = static_cast<T>(rw[i]);
           const T u = r * drcp(fmaT(dxr, dxr, xy * xy));
           const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
           const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;

@@ -182,3 +182,27 @@ def test_checkpointed_adjoint_equals_stored_adjoint(name):
             assert np.max(np.abs(ga - ra)) <= 1e-12 * np.max(np.abs(ra)), (frozen, ck)
     g.close()
 
+
+
+@pytest.mark.parametrize("name,ck", [("small_d110_field", 32), ("small_holed_mixed", 0), ("s_disc_32", 3)])
+def test_paired_adjoint_equals_the_adjoint_of_every_angle(name, ck):
+    """With angle pairs the reverse mode marches the lower angles only (the
+    corners of the upper angles feed their mirror slots); the gradients
+    equal those of the reverse mode over every angle to rounding (frozen
+    store from a first sweep, checkpointed and stored modes)."""
+    qs, sp, g, d0, a0, c1, c2, c3 = _setup(name)
+    _note("case %s checkpoint %d: paired vs every-angle adjoint" % (name, ck))
+    assert g.pairing()[1]
+    dd, ad = torch.as_tensor(d0).cuda(), torch.as_tensor(a0).cuda()
+    c1d, c2d = torch.as_tensor(c1).cuda(), torch.as_tensor(c2).cuda()
+    g.set_adjoint_checkpoint(ck)
+    out = []
+    for pair in (True, False):
+        g.set_pairing(pair)
+        g.reset_bc()
+        g.sweep(dd, ad)
+        g.sweep(dd, ad)
+        out.append([x.cpu().numpy() for x in g.sweep_adjoint(dd, ad, c1d, c2d, c3)])
+    for x, y in zip(out[0], out[1]):
+        assert np.max(np.abs(x - y)) <= 1e-12 * np.max(np.abs(y)), np.max(np.abs(x - y))
+    g.close()
