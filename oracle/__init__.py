@@ -17,5 +17,6 @@ Modules
   fields    external gauges, 2D Laplacian Green's function, A-solve
   scf       one iteration map, Picard SCF loop, LDOS
   bulk      closed forms of the homogeneous state (pins)
+  annulus   London-Maxwell closed forms of a screened annulus (pins)
 """
-from . import tables, geometry, sweep, fields, scf, bulk  # noqa: F401
+from . import tables, geometry, sweep, fields, scf, bulk, annulus  # noqa: F401

@@ -425,3 +425,67 @@ def test_magnetic_moment_is_origin_independent_without_net_current():
     m0 = fields.magnetic_moment(jx, jy, mask, X, Y, g.cx, g.cy)
     m1 = fields.magnetic_moment(jx, jy, mask, X, Y, g.cx + 3.7, g.cy - 1.2)
     assert abs(m1 - m0) < 1e-12 * max(abs(m0), 1.0)
+
+
+# ------------------------------------- screened annulus (Sec. V.A closed forms)
+from oracle import annulus  # noqa: E402
+
+_RING = (25.0, 10.0)
+
+
+@pytest.mark.parametrize("lam,alpha,n", [(2.0, 0.5, 0), (5.0, 0.0, -1), (20.0, 1.3, -2), (7.0, -0.8, 1)])
+def test_annulus_field_solves_the_london_maxwell_equation(lam, alpha, n):
+    """A(R) of the annulus solves -(A'' + A'/R - A/R^2) = -(A + n Phi0 /
+    (2 pi R)) / lam^2 (central differences, step 1e-3); A is continuous at
+    R<, where the hole's uniform field takes over; B = (1/R) d(R A)/dR equals
+    the applied alpha Phi0 / A at R>, and the flux through the hole plus the
+    flux through the annulus equals the line integral 2 pi R> A(R>)."""
+    Ro, Ri = _RING
+    f = lambda R: annulus.field(R, Ro, Ri, lam, alpha, n)[0]  # noqa: E731
+    e = 1e-3
+    for R in np.linspace(Ri + 0.5, Ro - 0.5, 9):
+        lap = (f(R + e) - 2 * f(R) + f(R - e)) / e ** 2 + (f(R + e) - f(R - e)) / (2 * e * R) - f(R) / R ** 2
+        rhs = (f(R) + n * math.pi / (2 * math.pi * R)) / lam ** 2
+        assert abs(lap - rhs) < 1e-5 * max(abs(rhs), 1e-3), (R, lap, rhs)
+    a_in = annulus.field(Ri - 1e-12, Ro, Ri, lam, alpha, n)[0]
+    assert abs(f(Ri) - a_in) < 1e-9 * max(abs(a_in), 1e-3)
+    b_out = ((Ro + e) * f(Ro + e) - (Ro - e) * f(Ro - e)) / (2 * e * Ro)
+    area = math.pi * (Ro ** 2 - Ri ** 2)
+    assert abs(b_out - alpha * math.pi / area) < 1e-6 + 1e-6 * abs(alpha)
+    assert abs(annulus.field(Ro, Ro, Ri, lam, alpha, n)[1] - alpha * math.pi / area) < 1e-9
+    from scipy.integrate import quad
+    flux = annulus.field(1.0, Ro, Ri, lam, alpha, n)[1] * math.pi * Ri ** 2
+    flux += quad(lambda R: 2 * math.pi * R * annulus.field(R, Ro, Ri, lam, alpha, n)[1], Ri, Ro, limit=200)[0]
+    assert abs(flux - 2 * math.pi * Ro * f(Ro)) < 1e-8 * max(abs(flux), 1.0)
+
+
+@pytest.mark.parametrize("lam0,Y", [(2.0, 1.0), (5.0, 0.99886), (20.0, 0.83), (100.0, 1.0)])
+def test_annulus_moment_equals_the_moment_of_its_current(lam0, Y):
+    """d_alpha alpha + d_n n equals (pi / A) int R^2 j(R) dR over the
+    annulus, with j the linear-response current of the closed-form field
+    (Sec. V.A, Eq. magnetic_moment_def in polar coordinates), for several
+    (alpha, n); it is linear in both."""
+    from scipy.integrate import quad
+    Ro, Ri = _RING
+    area = math.pi * (Ro ** 2 - Ri ** 2)
+    for alpha, n in ((0.5, 0), (0.0, -1), (1.3, -2), (-0.4, 3)):
+        m, da, dn = annulus.moment(Ro, Ri, lam0, Y, alpha, n)
+        ref = math.pi / area * quad(lambda R: R * R * annulus.current(R, Ro, Ri, lam0, Y, alpha, n),
+                                    Ri, Ro, limit=200)[0]
+        assert abs(m - ref) < 1e-9 * max(abs(ref), 1e-6), (alpha, n, m, ref)
+        assert abs(m - (da * alpha + dn * n)) < 1e-15 + 1e-12 * abs(m)
+    # diamagnetic: a positive field gives a negative moment without winding
+    assert annulus.moment(Ro, Ri, lam0, Y, 1.0, 0)[0] < 0
+
+
+def test_annulus_moment_without_screening():
+    """lam0 -> infinity: the field is the applied one, A = B R / 2, and
+    m/m0 = -(pi Y / A) (B (R>^4 - R<^4) / 8 + n (R>^2 - R<^2) / 4) with
+    B = alpha pi / A; the closed form tends to it as 1/lam0^2."""
+    Ro, Ri = _RING
+    area = math.pi * (Ro ** 2 - Ri ** 2)
+    Y, alpha, n = 0.9, 0.7, -1
+    B = alpha * math.pi / area
+    ref = -(math.pi * Y / area) * (B * (Ro ** 4 - Ri ** 4) / 8 + n * (Ro ** 2 - Ri ** 2) / 4)
+    errs = [abs(annulus.moment(Ro, Ri, lam0, Y, alpha, n)[0] / ref - 1) for lam0 in (300.0, 3000.0)]
+    assert errs[1] < 1e-4 and errs[1] < 0.03 * errs[0], errs
