@@ -70,7 +70,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep launch (mixed) from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs scaled by a plain-copy calibration (profiles/sweep_kernel_d110_square_400.md);
 # None whenever the kernel changed after the counters were taken.
-SWEEP_TRAFFIC_BYTES = 5.759e9
+SWEEP_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -115,6 +115,7 @@ def timed_scf(qs, torch, sp, precision, d0, a0, steps, warmup):
     info = dict(g.info)
     info["energies_per_lane"], info["lanes_per_segment"] = g.lanes()
     info["pairing"], info["swept_steps_per_sweep"] = g.pairing()[1:]
+    info["wide_segments"] = g.split()[1]
     _, j, om = g.sweep(dd, ad)
     final = {"delta": dd.cpu().numpy(), "A": ad.cpu().numpy(), "j": j.cpu().numpy(), "omega": om}
     g.close()
@@ -410,6 +411,21 @@ def mode_lanes(qs, torch, wl, name, iters):
             e, G = g.lanes()
             rows.append({"precision": prec, "requested": epl, "energies_per_lane": e, "lanes_per_segment": G,
                          "sweep_ms": ms / max(n, 1)})
+        # the split launch shape at the automatic lane shape (0: off)
+        g.set_lanes(0)
+        for frac in (0.0, 0.6, 0.7, 0.75, 0.8, 0.85, 0.9):
+            g.set_split(frac)
+            g.reset_bc()
+            g.sweep(d0, a0)
+            g.sweep(d0, a0)
+            torch.cuda.synchronize()
+            g.profile(True)
+            for _ in range(iters):
+                g.sweep(d0, a0, total=False)
+            torch.cuda.synchronize()
+            ms, n = g.profile_read()
+            g.profile(False)
+            rows.append({"precision": prec, "split": frac, "wide_segments": g.split()[1], "sweep_ms": ms / max(n, 1)})
         g.close()
     return {"metric": "sweep time per lane shape", "workload": name, "n_poles": sp["n_poles"], "rows": rows}
 
@@ -650,7 +666,7 @@ def main():
                    "name": WORKLOAD, "precision": "fp32 sweeps / fp64 pole, angle and cell sums",
                    "steps_per_iteration": steps_iter, "marched_steps_per_iteration": swept,
                    "angle_pairs": bool(info["pairing"]), "segments": info["n_segments"],
-                   "nodes": info["n_nodes"]},
+                   "nodes": info["n_nodes"], "wide_segments": info["wide_segments"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": SWEEP_TRAFFIC_BYTES,
                      "kernel": "sweep_kernel<float,%d,0>" % info["energies_per_lane"],

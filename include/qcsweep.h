@@ -522,6 +522,20 @@ qc_status qc_grain_set_lanes(qc_grain* grain, int energies_per_lane);
  * <= 64).  Both outputs are host ints written on success. */
 qc_status qc_grain_get_lanes(const qc_grain* grain, int* energies_per_lane, int* lanes_per_segment);
 
+/* Split launch shape of the SCF sweep (Matsubara poles).  Segments are
+ * launched longest first.  When a launch fills the device's wave slots less
+ * than twice, its longest segments set its length; with an even number of
+ * energies per lane and twice the lanes still within 64, the segments longer
+ * than frac x the longest then march with twice the lanes and half the
+ * energies per lane (rounded up to whole waves).  frac in [0, 1]; 0 turns
+ * the split off; the default is 0.9.  Results are identical up to the order
+ * of the FP64 pole sums.  Errors: QC_ERR_INVALID for frac outside [0, 1]. */
+qc_status qc_grain_set_split(qc_grain* grain, double frac);
+/* The fraction set and the number of segments the next SCF sweep launches
+ * with the wide shape (0 when the split does not apply); either pointer may
+ * be NULL. */
+qc_status qc_grain_get_split(qc_grain* grain, double* frac, int64_t* n_wide);
+
 /* Kernel timing with HIP events on the launch stream (for roofline
  * reports).  Enable, run, then read the summed milliseconds and launch
  * count of the Riccati sweep kernel; reading resets the counters. */

@@ -129,6 +129,8 @@ _sig("qc_batch_autotune", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes
 _sig("qc_set_state", ctypes.c_int, [_P, _P, ctypes.c_size_t, _P])
 _sig("qc_profile_enable", ctypes.c_int, [_P, ctypes.c_int])
 _sig("qc_grain_set_lanes", ctypes.c_int, [_P, ctypes.c_int])
+_sig("qc_grain_set_split", ctypes.c_int, [_P, ctypes.c_double])
+_sig("qc_grain_get_split", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)])
 _sig("qc_profile_read", ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)])
 
 
@@ -575,6 +577,19 @@ class Grain:
         G = ctypes.c_int(0)
         _check(lib.qc_grain_get_lanes(self._g, ctypes.byref(e), ctypes.byref(G)))
         return e.value, G.value
+
+    def set_split(self, frac):
+        """Split launch shape of the SCF sweep: segments longer than frac x
+        the longest march with twice the lanes when the launch is short
+        (0 turns it off; default 0.9)."""
+        _check(lib.qc_grain_set_split(self._g, float(frac)))
+
+    def split(self):
+        """(fraction, segments the next SCF sweep launches with the wide shape)."""
+        f = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib.qc_grain_get_split(self._g, ctypes.byref(f), ctypes.byref(n)))
+        return f.value, n.value
 
     def profile(self, enable=True):
         _check(lib.qc_profile_enable(self._g, 1 if enable else 0))

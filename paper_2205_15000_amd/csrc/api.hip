@@ -289,6 +289,12 @@ struct qc_grain {
   void* cells = nullptr;   // packed Delta / A_ind per cell (single component)
   int32_t* order = nullptr;
   int epl_override = 0;
+  // segment node counts in launch order (every segment; lower angles of the
+  // pairs), the split fraction of the Matsubara sweep's launch shape and the
+  // device's wave slots per (precision, energies per lane), found on first use
+  std::vector<int32_t> len_order, len_order_pair;
+  double split_frac = 0.9;
+  int64_t wave_slots[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
   void* gbuf = nullptr;
   double* node_out = nullptr;
   void* bc[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -592,7 +598,30 @@ qc::SweepArgs sweep_args(qc_grain* g, int n_e, int n_e_tot, int e_off, const dou
   a.rp = rp;
   a.node_out = g->node_out;
   a.maxn = g->maxn;
+  a.nlong = 0;
   return a;
+}
+
+// Segments of a Matsubara sweep that take the wide lane shape (2G lanes,
+// EPL/2 energies per lane; see SweepArgs::nlong): only when the launch
+// fills the device's wave slots less than twice, so that its longest
+// segments set its length, and then those longer than split_frac x the
+// longest, rounded up to whole waves
+int64_t split_count(qc_grain* g, const qc::SweepArgs& a, int epl) {
+  if (!(g->split_frac > 0.0) || epl % 2 != 0 || 2 * a.G > 64 || a.nseg == 0) return 0;
+  const std::vector<int32_t>& len = a.order == g->order_pair && g->order_pair ? g->len_order_pair : g->len_order;
+  if (static_cast<int64_t>(len.size()) != a.nseg) return 0;
+  int64_t& slots = g->wave_slots[epl];
+  if (slots < 0)
+    slots = g->precision == QC_MIXED ? qc::sweep_wave_slots<float>(epl) : qc::sweep_wave_slots<double>(epl);
+  const int64_t waves = (a.nseg * a.G + 63) / 64;
+  if (slots <= 0 || waves >= 2 * slots) return 0;
+  const double cut = g->split_frac * len[0];
+  int64_t k = 0;
+  while (k < a.nseg && len[k] > cut) ++k;
+  const int64_t per = 64 / (2 * a.G);
+  k = (k + per - 1) / per * per;
+  return std::min(k, a.nseg);
 }
 
 void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc::SweepBufs& b, hipStream_t st) {
@@ -656,6 +685,11 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   do_interp(g, delta, A, st, true);
   qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd, true);
   a.bc_valid = g->bc_valid;
+  {
+    int G, epl;
+    lane_shape(a.n_e, g->epl_override, g->precision == QC_MIXED, G, epl);
+    a.nlong = split_count(g, a, epl);
+  }
   qc::SweepBufs b;
   b.nodes = g->nodes;
   b.bc_g_prev = g->bc[g->bc_cur][0];
@@ -946,12 +980,16 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
       for (int64_t k = 0; k < g->nseg; ++k) ord[k] = static_cast<int32_t>(k);
       std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return p.seg_n[x] > p.seg_n[y]; });
       g->order = static_cast<int32_t*>(upload(ord));
+      g->len_order.resize(ord.size());
+      for (size_t k = 0; k < ord.size(); ++k) g->len_order[k] = p.seg_n[ord[k]];
     }
     if (p.pair_ok) {
       std::vector<int32_t> ord(static_cast<size_t>(p.nseg_pair));
       for (int64_t k = 0; k < p.nseg_pair; ++k) ord[k] = static_cast<int32_t>(k);
       std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return p.seg_n[x] > p.seg_n[y]; });
       g->order_pair = static_cast<int32_t*>(upload(ord));
+      g->len_order_pair.resize(ord.size());
+      for (size_t k = 0; k < ord.size(); ++k) g->len_order_pair[k] = p.seg_n[ord[k]];
       g->rb4_pair = static_cast<int4*>(upload(p.rb4_pair));
       std::vector<int2> mp;
       for (int64_t sg = p.nseg_pair; sg < p.nseg; ++sg) mp.push_back(make_int2(static_cast<int>(sg), p.seg_mirror[sg]));
@@ -2236,6 +2274,28 @@ qc_status qc_grain_set_lanes(qc_grain* g, int energies_per_lane) {
     return fail(QC_ERR_INVALID, "energies_per_lane must be 0 (auto), 1, 2, 3, 4 or 8");
   g->epl_override = energies_per_lane;
   return QC_OK;
+}
+
+qc_status qc_grain_set_split(qc_grain* g, double frac) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  if (!(frac >= 0.0 && frac <= 1.0)) return fail(QC_ERR_INVALID, "frac must be in [0, 1]");
+  g->split_frac = frac;
+  return QC_OK;
+}
+
+qc_status qc_grain_get_split(qc_grain* g, double* frac, int64_t* n_wide) {
+  if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
+  return guarded([&]() -> qc_status {
+    if (frac) *frac = g->split_frac;
+    if (n_wide) {
+      hcheck(hipSetDevice(g->device), "hipSetDevice");
+      qc::SweepArgs a = sweep_args(g, g->n_poles, g->n_poles, 0, g->eps, g->rpd, true);
+      int G, epl;
+      lane_shape(a.n_e, g->epl_override, g->precision == QC_MIXED, G, epl);
+      *n_wide = split_count(g, a, epl);
+    }
+    return QC_OK;
+  });
 }
 
 qc_status qc_grain_get_lanes(const qc_grain* g, int* energies_per_lane, int* lanes_per_segment) {

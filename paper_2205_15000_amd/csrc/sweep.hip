@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<
 // formed from 1/(1+X) alone (identities at node_sums below).
 // --------------------------------------------------------------------------
 template <typename T, int EPL, int MODE>
-__device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, int lane,
+__device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, int lane, int G, int lg,
                                               const node4<T>* __restrict__ nodes,
                                               const cpx<T>* __restrict__ bc_g_prev,
                                               const cpx<T>* __restrict__ bc_gt_prev,
@@ -367,7 +367,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   auto lds_reduce = [&](int64_t node0, int cnt) {
     const int l64 = threadIdx.x & 63;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    const int lp = a.log2g - 3;  // log2 P
+    const int lp = lg - 3;  // log2 P
     const int o = lane >> lp, r = lane & ((1 << lp) - 1);
     const double2* src = reinterpret_cast<const double2*>(lsum + o * 64 + (l64 - lane));
     double v = 0.0;
@@ -440,7 +440,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         si = fmaT(nv.dx, p1, -(nv.dy * p2));
       }
       // S_f = -2 i pi t~ (sfx + i sfy), S_g = 2 pi t~ sg, S_I = 2 pi t~ si
-      if (a.G >= 8) {
+      if (G >= 8) {
         // the lane's four partials go to LDS; every second node the group
         // sums the pair (this node and the one before it, node + 1)
         const int b = k & 1;
@@ -450,13 +450,13 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         w[128] = sg;
         w[192] = si;
         if (b) lds_reduce(node + 1, 2);
-      } else if (a.G >= 4) {
+      } else if (G >= 4) {
         // lane q of the group (q < 4) ends with component q of the node's sums
-        const double v = group_sum4_scatter(sfy, -sfx, sg, si, a.G, lane);
+        const double v = group_sum4_scatter(sfy, -sfx, sg, si, G, lane);
         if (lane < 4) a.node_out[node * 4 + scatter_index(lane)] = a.twopi_tt * v;
       } else {
-        const double ox = group_sum(sfy, a.G), oy = group_sum(sfx, a.G);
-        const double oz = group_sum(sg, a.G), ow = group_sum(si, a.G);
+        const double ox = group_sum(sfy, G), oy = group_sum(sfx, G);
+        const double oz = group_sum(sg, G), ow = group_sum(si, G);
         if (lane == 0) {
           double4 o;
           o.x = a.twopi_tt * ox;
@@ -525,7 +525,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
     if (MODE != 2) node_sums(slot0 + t - 1, cur, gn, n - t);
   }
   // with an odd node count, node 0 is left alone in slot 0
-  if (MODE == 0 && a.G >= 8 && (n & 1)) lds_reduce(slot0, 1);
+  if (MODE == 0 && G >= 8 && (n & 1)) lds_reduce(slot0, 1);
   // step 0 to R_min (boundary point = slot 0)
   if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
   if (MODE == 0 || MODE == 2 || (MODE == 1 && bc_gt_next)) {
@@ -554,16 +554,33 @@ sweep_kernel(SweepArgs a, const node4<T>* __restrict__ nodes,
                                                     cpx<T>* __restrict__ bc_gt_next,
                                                     cpx<T>* __restrict__ gbuf, T* __restrict__ ebuf) {
   const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t wseg = gtid >> a.log2g;
-  const int lane = static_cast<int>(gtid & (a.G - 1));
-  if (wseg >= a.nseg) return;  // whole lane groups leave together (G | 64)
   double* lsum = nullptr;
   if constexpr (MODE == 0) {
     __shared__ double red[4 * 512];  // two nodes x four sums x 64 lanes per wave
     lsum = red + (threadIdx.x >> 6) * 512;
   }
-  sweep_segment<T, EPL, MODE>(a, wseg, lane, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, a.n_e,
-                              ebuf, lsum);
+  // The launch order is longest first.  In a launch that fills the device's
+  // wave slots about once, the longest segments set its length; the first
+  // nlong of them march with twice the lanes and half the energies per lane,
+  // so they finish in about half the time.  The split falls on a wave
+  // boundary (nlong * 2G is a multiple of 64), so each wave takes one shape.
+  int64_t r = gtid, first = 0;
+  if constexpr (MODE == 0 && EPL % 2 == 0) {
+    first = a.nlong;
+    const int64_t nl = a.nlong << (a.log2g + 1);
+    if (r < nl) {
+      sweep_segment<T, EPL / 2, MODE>(a, r >> (a.log2g + 1), static_cast<int>(r & (2 * a.G - 1)), 2 * a.G,
+                                      a.log2g + 1, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next, gbuf, a.n_e,
+                                      ebuf, lsum);
+      return;
+    }
+    r -= nl;
+  }
+  const int64_t wseg = first + (r >> a.log2g);
+  const int lane = static_cast<int>(r & (a.G - 1));
+  if (wseg >= a.nseg) return;  // whole lane groups leave together (G | 64)
+  sweep_segment<T, EPL, MODE>(a, wseg, lane, a.G, a.log2g, nodes, bc_g_prev, bc_gt_prev, bc_g_next, bc_gt_next,
+                              gbuf, a.n_e, ebuf, lsum);
 }
 
 // Batched grains: one persistent launch.  Every wave pulls tiles (a grain
@@ -593,7 +610,7 @@ batch_sweep_kernel(const BatchGrainDev* __restrict__ grains,
     const BatchGrainDev& gd = grains[tile.x];
     const int64_t wseg = static_cast<int64_t>(tile.y) + (l64 >> gd.a.log2g);
     if (wseg < gd.a.nseg)
-      sweep_segment<T, EPL, 0>(gd.a, wseg, l64 & (gd.a.G - 1), static_cast<const node4<T>*>(gd.b.nodes),
+      sweep_segment<T, EPL, 0>(gd.a, wseg, l64 & (gd.a.G - 1), gd.a.G, gd.a.log2g, static_cast<const node4<T>*>(gd.b.nodes),
                                static_cast<const cpx<T>*>(gd.b.bc_g_prev), static_cast<const cpx<T>*>(gd.b.bc_gt_prev),
                                static_cast<cpx<T>*>(gd.b.bc_g_next), static_cast<cpx<T>*>(gd.b.bc_gt_next),
                                wspill + static_cast<int64_t>(l64 >> gd.a.log2g) * gd.a.maxn * gd.a.n_e, 0, nullptr,
@@ -1210,7 +1227,8 @@ template void launch_interp<float>(const InterpArgs&, void*, void*, hipStream_t)
 
 template <typename T, int EPL, int MODE>
 static void launch_sweep_t(const SweepArgs& a, const SweepBufs& b, hipStream_t st) {
-  const int64_t threads = a.nseg * a.G;
+  const bool split = MODE == 0 && EPL % 2 == 0 && a.nlong > 0;
+  const int64_t threads = split ? a.nlong * 2 * a.G + (a.nseg - a.nlong) * a.G : a.nseg * a.G;
   hipLaunchKernelGGL((sweep_kernel<T, EPL, MODE>), dim3(nblk(threads)), dim3(256), 0, st, a,
                      static_cast<const node4<T>*>(b.nodes),
                      static_cast<const cpx<T>*>(b.bc_g_prev), static_cast<const cpx<T>*>(b.bc_gt_prev),
@@ -1243,6 +1261,28 @@ void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hip
 }
 template void launch_sweep<double>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
 template void launch_sweep<float>(int, int, const SweepArgs&, const SweepBufs&, hipStream_t);
+
+template <typename T, int EPL>
+static int64_t wave_slots_t() {
+  int dev = 0, blocks = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sweep_kernel<T, EPL, 0>, 256, 0) != hipSuccess) return 0;
+  return static_cast<int64_t>(blocks) * 4 * cus;
+}
+
+template <typename T>
+int64_t sweep_wave_slots(int epl) {
+  switch (epl) {
+    case 1: return wave_slots_t<T, 1>();
+    case 2: return wave_slots_t<T, 2>();
+    case 3: return wave_slots_t<T, 3>();
+    case 4: return wave_slots_t<T, 4>();
+    default: return wave_slots_t<T, 8>();
+  }
+}
+template int64_t sweep_wave_slots<double>(int);
+template int64_t sweep_wave_slots<float>(int);
 
 template <typename T>
 void launch_batch_sweep(int epl, const BatchGrainDev* grains, const int2* tiles, int ntiles, int* counter, int nblocks,

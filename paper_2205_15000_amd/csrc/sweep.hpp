@@ -63,6 +63,10 @@ struct SweepArgs {
   const double* rp;       // pole weights [n_e_tot]
   double* node_out;       // mode 0: [nslot][4] = S_f (re, im), S_g, S_I per node
   int maxn;               // most nodes of any segment (batched spill layout)
+  // Matsubara sweeps (mode 0) with an even EPL and 2G <= 64: the first nlong
+  // segments of the launch order take 2G lanes and EPL/2 energies per lane,
+  // the rest G lanes and EPL; nlong * 2G is a multiple of 64 (0: one shape)
+  int64_t nlong;
 };
 
 struct SweepBufs {
@@ -232,6 +236,10 @@ template <typename T>
 void launch_interp(const InterpArgs& a, void* cells, void* nodes, hipStream_t st);
 template <typename T>
 void launch_sweep(int mode, int epl, const SweepArgs& a, const SweepBufs& b, hipStream_t st);
+// wave slots of the whole device for the Matsubara sweep kernel of this
+// precision and lane shape (resident waves per CU x CUs)
+template <typename T>
+int64_t sweep_wave_slots(int epl);
 void launch_rotate_back(const BackArgs& a, hipStream_t st);
 // End values of the upper angle of each pair from its mirror segment:
 // gamma_end(s') = conj(gamma~_end(s)), gamma~_end(s') = conj(gamma_end(s))

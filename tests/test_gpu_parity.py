@@ -576,6 +576,53 @@ def test_angle_pairs_equal_the_full_sweep(name, precision):
         assert np.max(np.abs(sp_ - sf_)) <= 1e-12 * np.max(np.abs(sf_))
 
 
+@pytest.mark.parametrize("name,precision,epl", [("s_disc_32", "fp64", 0), ("small_d110_field", "fp64", 0),
+                                                ("small_polygon_landau", "fp64", 2), ("small_d110_field", "mixed", 0),
+                                                ("d110_square_400", "fp64", 0), ("d110_square_400", "mixed", 0)])
+def test_split_launch_shape_equals_one_shape(name, precision, epl):
+    """The SCF sweep with its longest segments on twice the lanes (half the
+    energies per lane) against the same sweep in one lane shape: three
+    chained maps give the same Delta_new, j and Omega up to the order of the
+    pole sums (1e-13 FP64; mixed 1e-6, where the FP32 terms may round
+    differently in the two instantiations), and the split is in use.  The
+    5-pole polygon at 2 energies per lane pads 3 lanes of its wide shape;
+    at its automatic 3 per lane the split does not apply."""
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s %s: split launch shape vs one shape" % (name, precision))
+    d0 = _dev(wl.initial_delta(name, sp), torch.complex128)
+    a0 = _dev(wl.initial_A(name, sp), torch.float64)
+    if name == "small_polygon_landau":
+        g = qs.Grain(sp, precision)
+        assert g.lanes()[0] % 2 == 1 and g.split()[1] == 0
+        g.close()
+    out = []
+    for frac in (0.8, 0.0):
+        g = qs.Grain(sp, precision)
+        g.set_lanes(epl)
+        g.set_split(frac)
+        f, n_wide = g.split()
+        assert f == frac
+        if frac > 0:
+            assert n_wide > 0, n_wide
+        else:
+            assert n_wide == 0
+        d, a = d0.clone(), a0.clone()
+        res = []
+        for _ in range(3):
+            dn, j, om = g.sweep(d, a)
+            res.append((dn.cpu().numpy(), j.cpu().numpy(), om))
+            d = dn
+        out.append(res)
+        g.close()
+    p, f = out
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    for i in range(3):
+        assert _close(p[i][0], f[i][0], tol), (i, rel_err(p[i][0], f[i][0]))
+        assert _close(p[i][1], f[i][1], tol), (i, rel_err(p[i][1], f[i][1]))
+        assert abs(p[i][2] - f[i][2]) <= tol * abs(f[i][2])
+
+
 @pytest.mark.parametrize("name", ["small_polygon_landau", "small_mask_blob"])
 def test_angle_pairs_unavailable_where_the_tables_do_not_mirror(name):
     """An odd angle count, and a cell-mask boundary whose corners give
