@@ -20,6 +20,9 @@ D_BULK_T01 = 0.8577177
 # bulk s-wave gap at t = 0.5 with 16 poles, in units of DELTA0 (the same
 # root; starting amplitude of the vortex demonstration)
 S_BULK_T05 = 0.9568823
+# bulk s-wave gap at t = 0.2 with 24 poles, in units of DELTA0 (starting
+# amplitude of the screened annulus)
+S_BULK_T02 = 0.9998739
 
 
 def _disc(cx, cy, r, add=True):
@@ -170,6 +173,23 @@ def initial_A(name, sp=None, seed=None):
     X, Y = centres(sp)
     a, b, c, d = rng.uniform(0.1, 0.4, 4)
     return 0.02 * np.stack([np.sin(a * X + b * Y), np.cos(c * X - d * Y)])
+
+
+def annulus_spec(kappa, flux_quanta, h=0.125, n_theta=64, n_poles=24):
+    """The s-wave annulus of Sec. V.A: outer radius 25 xi0, inner radius
+    10 xi0, centred in a square grid with 1 xi0 of margin (416 x 416 cells at
+    h = 0.125), t = 0.2, symmetric gauge with flux_quanta through the annulus,
+    penetration depth kappa xi0."""
+    n = int(round(2 * 26.0 / h))
+    return dict(nx=n, ny=n, h=h, shapes=[_disc(0, 0, 25.0), _disc(0, 0, 10.0, add=False)], n_theta=n_theta,
+                n_poles=n_poles, t=0.2, components=[("s", 1.0)], kappa=kappa, flux_quanta=flux_quanta,
+                gauge="symmetric", charge_sign=-1, name="swave_annulus")
+
+
+def annulus_initial_delta(sp, winding):
+    """Bulk amplitude with the phase winding 2 pi winding around the hole."""
+    X, Y = centres(sp)
+    return (S_BULK_T02 * DELTA0 * np.exp(1j * winding * np.arctan2(Y, X)))[None].astype(np.complex128)
 
 
 def vortex_ldos_energies(n=128):
