@@ -513,9 +513,9 @@ qc_status qc_grain_set_adjoint_checkpoint(qc_grain* grain, int every);
  * 4 or 8; 0 = automatic: the fewest padded energy slots weighted by each
  * variant's measured cost).  The lanes of one trajectory segment share the
  * per-node energy sums, so fewer energies per lane means more lanes per
- * segment (a power of two up to 64; a forced value that would need more is
- * replaced by the automatic choice).  Results are identical up to rounding
- * order. */
+ * segment (a power of two up to 64; a forced value that would need more, or
+ * that exceeds the number of energies of a launch, is replaced by the
+ * automatic choice).  Results are identical up to rounding order. */
 qc_status qc_grain_set_lanes(qc_grain* grain, int energies_per_lane);
 /* The lane shape the next SCF sweep of this grain will use: energies per
  * lane (1, 2, 3, 4 or 8) and lanes per trajectory segment (a power of two

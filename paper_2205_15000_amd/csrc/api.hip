@@ -87,8 +87,8 @@ int lanes_for(int n_e, int epl) {
   return G;
 }
 
-// Energies per lane: a forced value (1, 2, 3, 4, 8) if it fits 64 lanes,
-// else the shape with the least cost G * epl * f(epl), i.e. energy slots
+// Energies per lane: a forced value (1, 2, 3, 4, 8) if it fits 64 lanes and
+// does not exceed the energies, else the shape with the least cost G * epl * f(epl), i.e. energy slots
 // (padding included) weighted by the measured relative cost per slot of
 // each variant on gfx950 (64- and 48-pole grains).  Two per lane for 64
 // poles, three for 48, four for 256-energy blocks (both precisions).
@@ -97,14 +97,15 @@ void lane_shape(int n_e, int force, bool fp32, int& G, int& epl) {
   static const double kCost32[5] = {1.13, 1.0, 1.28, 1.15, 1.55};
   static const double kCost64[5] = {1.07, 1.0, 1.20, 1.12, 1.24};
   const double* kCost = fp32 ? kCost32 : kCost64;
-  if ((force == 1 || force == 2 || force == 3 || force == 4 || force == 8) && lanes_for(n_e, force) <= 64) {
+  if ((force == 1 || force == 2 || force == 3 || force == 4 || force == 8) && force <= n_e &&
+      lanes_for(n_e, force) <= 64) {
     epl = force;
   } else {
     double best = INFINITY;
-    epl = 8;
+    epl = 1;
     for (int i = 0; i < 5; ++i) {
       const int Gi = lanes_for(n_e, kEpl[i]);
-      if (Gi > 64) continue;
+      if (Gi > 64 || kEpl[i] > std::max(n_e, 1)) continue;
       const double c = kCost[i] * Gi * kEpl[i];
       if (c < best) {
         best = c;
@@ -627,6 +628,8 @@ int64_t split_count(qc_grain* g, const qc::SweepArgs& a, int epl) {
 void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc::SweepBufs& b, hipStream_t st) {
   int G, epl;
   lane_shape(a.n_e, g->epl_override, g->precision == QC_MIXED, G, epl);
+  // every lane marches epl existing energies (the kernel's lane layout)
+  if (epl > a.n_e || G * epl < a.n_e) throw std::logic_error("sweep lane shape does not fit the energies");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g->prof) {
     hcheck(hipEventCreate(&e0), "event");

@@ -217,18 +217,27 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   const T hfull = static_cast<T>(a.h);
   const T q = static_cast<T>(a.q);
   const int e0 = lane * EPL;
+  // The lane marches the energies es .. es + EPL - 1.  Its own start at e0;
+  // a lane at the end of the range (e0 + EPL > n_e) starts early enough that
+  // all EPL exist (the host never launches EPL > n_e).  The energies below
+  // e0 belong to the lane before it, whose values it reproduces exactly
+  // (same constants, same start): its loads and stores then cover EPL
+  // consecutive entries, and its duplicates carry no weight and write no
+  // end values.
+  const int es = min(e0, a.n_e - EPL);
+  bool own[EPL];
+  for (int i = 0; i < EPL; ++i) own[i] = es + i >= e0;
 
   T ex[EPL], ey[EPL];
   // interior steps (length h): kx = -h Im z - 1 and kx + 4 per energy
   T kxi[EPL], kx4i[EPL];
   for (int i = 0; i < EPL; ++i) {
-    const int e = e0 + i < a.n_e ? e0 + i : a.n_e - 1;
+    const int e = es + i;
     ex[i] = static_cast<T>(a.eps[2 * (a.e_off + e)]);
     ey[i] = static_cast<T>(a.eps[2 * (a.e_off + e) + 1]);
     kxi[i] = fmaT(-hfull, ey[i], T(-1));
     kx4i[i] = fmaT(-hfull, ey[i], T(3));
   }
-  const bool full = e0 + EPL <= a.n_e;
   const T hq4 = T(0.25) * hfull, hqa = T(0.5) * q * hfull;
 
   // Step with the half-step values (mean of two slots; sd = -1 applies
@@ -266,7 +275,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         const T w = static_cast<T>(a.tap_start_w[tb + c]);
         const cpx<T>* src = bc_g_prev + static_cast<int64_t>(a.tap_start_seg[tb + c]) * a.n_e_tot + a.e_off;
         for (int i = 0; i < EPL; ++i) {
-          const cpx<T> v = src[e0 + i < a.n_e ? e0 + i : a.n_e - 1];
+          const cpx<T> v = src[es + i];
           g[i] = mk(g[i].x + w * v.x, g[i].y + w * v.y);
         }
       }
@@ -276,15 +285,16 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
     }
   }
   // gamma spill of this segment, node t at gseg[t * n_e]: the grain's array
-  // (gmul = n_e) or a wave's own scratch (gmul = 0)
+  // (gmul = n_e) or a wave's own scratch (gmul = 0); this lane's entries
+  // start at gseg + es
   cpx<T>* const gseg = gbase + slot0 * gmul;
-  // Every lane stores every element: a padded energy repeats the last pole's
-  // march (same constants, same start) and writes the same value to that
-  // pole's entry.  With no conditional stores the compiler knows how many
+  cpx<T>* const glane = gseg + es;
+  // Every lane stores all its EPL entries (a duplicate writes the value its
+  // owner writes).  With no conditional stores the compiler knows how many
   // stores were issued after a prefetch and waits for the prefetch alone.
   auto store_g = [&](int t) {
-    cpx<T>* dst = gseg + static_cast<int64_t>(t) * a.n_e;
-    for (int i = 0; i < EPL; ++i) dst[full ? e0 + i : min(e0 + i, a.n_e - 1)] = g[i];
+    cpx<T>* dst = glane + static_cast<int64_t>(t) * a.n_e;
+    for (int i = 0; i < EPL; ++i) dst[i] = g[i];
   };
   // Slot values are loaded one step ahead, so the load overlaps a step.  A
   // wait for that load must not also wait for a gamma store issued just
@@ -299,6 +309,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // with no node still owns one slot, so its store is in range
   end_step(g, prev, prev, hfirst, T(1));
   if (late_store && MODE != 2) store_g(0);
+  // (FP32: two steps per loop turn, so the look-ahead registers rotate by
+  // renaming instead of moves; in FP64 that would cost a wave per SIMD)
+  constexpr int kUnrollG = sizeof(T) == 4 ? 2 : 1;
+#pragma unroll kUnrollG
   for (int t = 1; t < n; ++t) {
     const node4<T> cur = nxt;
     nxt = nodes[slot0 + min(t + 1, last)];
@@ -313,9 +327,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // end values for the next sweep (the LDOS output pass writes them only
   // when iterating to convergence: bc_g_next given)
   if (MODE == 0 || MODE == 2 || (MODE == 1 && bc_g_next)) {
-    cpx<T>* dst = bc_g_next + seg * a.n_e_tot + a.e_off + e0;
+    cpx<T>* dst = bc_g_next + seg * a.n_e_tot + a.e_off + es;
     for (int i = 0; i < EPL; ++i)
-      if (e0 + i < a.n_e) dst[i] = g[i];
+      if (own[i]) dst[i] = g[i];
   }
 
   // ---- gamma~: R_max -> R_min with D -> -D*
@@ -324,7 +338,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // the node sums would bias every gap update the same way
   double rw[EPL];
   for (int i = 0; i < EPL; ++i)
-    rw[i] = (MODE == 0 && e0 + i < a.n_e) ? a.rp[a.e_off + min(e0 + i, a.n_e - 1)] : 0.0;
+    rw[i] = (MODE == 0 && own[i]) ? a.rp[a.e_off + es + i] : 0.0;
   cpx<T> gt[EPL];
   prev = nodes[slot0 + last];
   {
@@ -336,7 +350,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         const T w = static_cast<T>(a.tap_end_w[tb + c]);
         const cpx<T>* src = bc_gt_prev + static_cast<int64_t>(a.tap_end_seg[tb + c]) * a.n_e_tot + a.e_off;
         for (int i = 0; i < EPL; ++i) {
-          const cpx<T> v = src[e0 + i < a.n_e ? e0 + i : a.n_e - 1];
+          const cpx<T> v = src[es + i];
           gt[i] = mk(gt[i].x + w * v.x, gt[i].y + w * v.y);
         }
       }
@@ -351,11 +365,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   //   Re g = pi Im((1-X)/(1+X)) = 2 pi Im I,
   //   (D* f + D f~) / (pi + i g) = i (D gamma~ - D* gamma)  since pi + i g = 2 pi I,
   // so the Eilenberger free-energy term needs no division.
-  // gamma of a node for this lane's energies (padded energies read the
-  // node's last pole, in range; their weight is zero)
+  // gamma of a node for this lane's energies
   auto load_g = [&](cpx<T>* gv, int t) {
-    const cpx<T>* src = gseg + static_cast<int64_t>(t) * a.n_e;
-    for (int i = 0; i < EPL; ++i) gv[i] = src[full ? e0 + i : min(e0 + i, a.n_e - 1)];
+    const cpx<T>* src = glane + static_cast<int64_t>(t) * a.n_e;
+    for (int i = 0; i < EPL; ++i) gv[i] = src[i];
   };
   // Node sums through LDS (MODE 0, G >= 8).  The wave's buffer holds two
   // nodes x four components x 64 lanes; slot b of component c of lane l is
@@ -467,9 +480,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         }
       }
     } else if (MODE == 1) {  // N/N_F = -Im g / pi = Re((1-X)/(1+X)) = 2 Re I - 1 per energy
-      T* dst = ebuf + node * a.n_e + e0;
+      T* dst = ebuf + node * a.n_e + es;
       for (int i = 0; i < EPL; ++i) {
-        if (e0 + i >= a.n_e) continue;
+        if (!own[i]) continue;
         const cpx<T> gg = gn[i];
         const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
         const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
@@ -478,9 +491,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
         dst[i] = fmaT(T(2) * dxr, ri, T(-1));
       }
     } else {  // MODE 3: (1-X)/(1+X) = 2 I - 1 per energy, complex (g = -i pi times it)
-      T* dst = ebuf + 2 * (node * a.n_e + e0);
+      T* dst = ebuf + 2 * (node * a.n_e + es);
       for (int i = 0; i < EPL; ++i) {
-        if (e0 + i >= a.n_e) continue;
+        if (!own[i]) continue;
         const cpx<T> gg = gn[i];
         const T xx = fmaT(gg.x, gt[i].x, -(gg.y * gt[i].y));
         const T xy = fmaT(gg.x, gt[i].y, gg.y * gt[i].x);
@@ -505,9 +518,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // pointer rather than formed from t, which costs 64-bit multiplies)
   nxt = nodes[slot0 + max(n - 2, 0)];
   cpx<T> gnx[EPL];
-  const cpx<T>* grow = gseg + static_cast<int64_t>(max(n - 2, 0)) * a.n_e;
+  const cpx<T>* grow = glane + static_cast<int64_t>(max(n - 2, 0)) * a.n_e;
   auto load_row = [&](cpx<T>* gv, const cpx<T>* row) {
-    for (int i = 0; i < EPL; ++i) gv[i] = row[full ? e0 + i : min(e0 + i, a.n_e - 1)];
+    for (int i = 0; i < EPL; ++i) gv[i] = row[i];
   };
   if (gpre) load_row(gnx, grow);
   for (int t = n - 1; t >= 1; --t) {
@@ -529,9 +542,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // step 0 to R_min (boundary point = slot 0)
   if (n > 0) end_step(gt, prev, prev, hfirst, T(-1));
   if (MODE == 0 || MODE == 2 || (MODE == 1 && bc_gt_next)) {
-    cpx<T>* dst = bc_gt_next + seg * a.n_e_tot + a.e_off + e0;
+    cpx<T>* dst = bc_gt_next + seg * a.n_e_tot + a.e_off + es;
     for (int i = 0; i < EPL; ++i)
-      if (e0 + i < a.n_e) dst[i] = gt[i];
+      if (own[i]) dst[i] = gt[i];
   }
 }
 
