@@ -70,7 +70,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep launch (mixed) from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs scaled by a plain-copy calibration (profiles/sweep_kernel_d110_square_400.md);
 # None whenever the kernel changed after the counters were taken.
-SWEEP_TRAFFIC_BYTES = None
+SWEEP_TRAFFIC_BYTES = 5.740e9
 
 
 def parse():

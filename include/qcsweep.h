@@ -194,10 +194,13 @@ qc_status qc_plan_get_eta(const qc_plan* plan, double* eta_out);
 /* grain cells of a device grain: host uint8 [ny][nx], 1 inside */
 qc_status qc_grain_get_mask(const qc_grain* grain, uint8_t* mask_out);
 /* Angle pairs of the plan (see qc_grain_set_pairing): whether the tables of
- * phi_k and phi_k + pi mirror each other, the trajectory steps a paired
- * Matsubara sweep marches, and (optional, host int32 [n_segments]) the
- * mirror segment on phi_k - pi of every segment of an angle phi_k >= pi
- * (-1 for the others and when unavailable). */
+ * phi_k and phi_k + pi mirror each other (*available: 0 no; 1 yes; 3 yes,
+ * and every grain cell also has the same four rotate-back corners on both
+ * angles, so the paired rotate-back gathers the node sums once per pair),
+ * the trajectory steps a paired Matsubara sweep marches, and (optional,
+ * host int32 [n_segments]) the mirror segment on phi_k - pi of every
+ * segment of an angle phi_k >= pi (-1 for the others and when
+ * unavailable). */
 qc_status qc_plan_get_pairing(const qc_plan* plan, int* available, int64_t* swept_steps_per_sweep,
                               int32_t* seg_mirror_out);
 

@@ -285,6 +285,13 @@ class Plan:
         _check(lib.qc_plan_get_pairing(self._p, ctypes.byref(a), ctypes.byref(n), mir.ctypes.data))
         return bool(a.value), n.value, mir
 
+    def rotate_fold(self):
+        """Whether every grain cell has the same rotate-back corners on both
+        angles of each pair (the paired rotate-back then gathers once)."""
+        a = ctypes.c_int(0)
+        _check(lib.qc_plan_get_pairing(self._p, ctypes.byref(a), None, None))
+        return bool(a.value & 2)
+
 
 def _torch():
     import torch

@@ -357,7 +357,7 @@ struct qc_grain {
   // angle pairs (k, k + n_theta/2): the sweep of the Matsubara iteration
   // runs the lower angles only (see build_pairs); pair_ok when the tables
   // allow it, pairing when it is in use
-  bool pair_ok = false, pairing = false;
+  bool pair_ok = false, pairing = false, rb_fold = false;
   int64_t nseg_pair = 0, nslot_pair = 0, npairs = 0;
   int32_t* order_pair = nullptr;
   int4* rb4_pair = nullptr;
@@ -509,6 +509,7 @@ qc::BackArgs back_args(qc_grain* g, const double* delta, double* dnew, double* j
   r.grain_cells = g->grain_cells;
   r.rb4 = g->pairing ? g->rb4_pair : g->rb4;
   r.pair_k0 = g->pairing ? g->n_theta / 2 : g->n_theta;
+  r.pair_fold = g->pairing && g->rb_fold ? 1 : 0;
   r.nx = g->nx;
   r.x0 = g->x0;
   r.y0 = g->y0;
@@ -860,7 +861,7 @@ qc_status qc_plan_get_pairing(const qc_plan* plan, int* available, int64_t* swep
                               int32_t* seg_mirror_out) {
   if (!plan) return fail(QC_ERR_INVALID, "plan is NULL");
   const qc::Plan& p = plan->p;
-  if (available) *available = p.pair_ok ? 1 : 0;
+  if (available) *available = p.pair_ok ? (p.rb_fold ? 3 : 1) : 0;
   if (swept_steps_per_sweep) {
     int64_t s = 0;
     const int64_t nsw = p.pair_ok ? p.nseg_pair : p.nseg;
@@ -1002,6 +1003,7 @@ qc_status qc_grain_create(int device, const qc_grain_desc* desc, qc_grain** out)
       g->nslot_pair = p.nslot_pair;
       g->pair_ok = true;
       g->pairing = true;
+      g->rb_fold = p.rb_fold;
     }
     // gbuf, node_out and the boundary store are allocated by the first sweep
     g->omega_cell = static_cast<double*>(dalloc(sizeof(double) * g->ncg));

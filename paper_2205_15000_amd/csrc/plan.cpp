@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <limits>
 #include <stdexcept>
@@ -497,6 +498,36 @@ static void build_pairs(Plan& p) {
   p.nseg_pair = p.angle_seg0[n2];
   p.nslot_pair = p.seg_slot0[p.nseg_pair];
   p.pair_ok = true;
+  // The lattice of angle k + n/2 is that of angle k turned by pi about the
+  // grid centre, so a cell's bilinear corners are the same points with the
+  // same weights.  Check that the tables agree, to rounding, on every corner
+  // of weight above 1e-12 (a cell centre on a lattice line picks its
+  // zero-weight corner on opposite sides in the two directions, or gives it
+  // a weight of the size of the rounding of cos and sin) and on the
+  // nearest-node fallback, whose tie-break could differ.
+  p.rb_fold = true;
+  for (int k = 0; k < n2 && p.rb_fold; ++k)
+    for (int64_t c = 0; c < nc && p.rb_fold; ++c) {
+      std::array<std::pair<int32_t, double>, 4> lo, up;
+      int nlo = 0, nup = 0;
+      for (int q = 0; q < 4; ++q) {
+        const double wl = p.rb_w[(static_cast<size_t>(k) * 4 + q) * nc + c];
+        const double wh = p.rb_w[(static_cast<size_t>(k + n2) * 4 + q) * nc + c];
+        if (wl > 1e-12) lo[nlo++] = {p.rb4_pair[(static_cast<size_t>(k) * nc + c) * 4 + q], wl};
+        if (wh > 1e-12) up[nup++] = {p.rb4_pair[(static_cast<size_t>(k + n2) * nc + c) * 4 + q], wh};
+      }
+      if (nlo != nup) {
+        p.rb_fold = false;
+        break;
+      }
+      std::sort(lo.begin(), lo.begin() + nlo);
+      std::sort(up.begin(), up.begin() + nup);
+      for (int q = 0; q < nlo; ++q)
+        if (lo[q].first != up[q].first || std::fabs(lo[q].second - up[q].second) > 1e-12) {
+          p.rb_fold = false;
+          break;
+        }
+    }
 }
 
 void build_plan(Plan& p) {

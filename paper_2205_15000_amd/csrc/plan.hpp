@@ -96,6 +96,10 @@ struct Plan {
   int64_t nseg_pair = 0, nslot_pair = 0;  // segments / slots of the lower angles
   std::vector<int32_t> seg_mirror;
   std::vector<int32_t> rb4_pair;
+  // rb_fold: for every grain cell, the corners of each upper angle are the
+  // corners of its lower angle (the same lattice points, in reverse order),
+  // so the rotate-back may gather once per pair
+  bool rb_fold = false;
 
   int64_t steps_per_sweep() const;
 };

@@ -666,7 +666,27 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   const double ry = rn_cell_offset(a.y0, static_cast<double>(cell / a.nx), a.h, a.cy);
   const double4* nsum = reinterpret_cast<const double4*>(a.node_out);
   double jx = 0.0, jy = 0.0, icell = 0.0, d2avg = 0.0;
-  for (int k = live ? wv : a.n_theta; k < a.n_theta; k += kBackWaves) {
+  // angle kk's share of the sums from the node sums gathered at its corners
+  // (sgn: the sign of S_g, -1 for the reversed direction of a pair)
+  auto add_angle = [&](int kk, double cfx, double cfy, double cg, double ci) {
+    const double wk = a.wk[kk];
+    double dkx = 0.0, dky = 0.0;
+    for (int g = 0; g < a.ncomp; ++g) {
+      const double ex = a.eta[2 * (g * a.n_theta + kk)], ey = a.eta[2 * (g * a.n_theta + kk) + 1];
+      const double px = wk * ex, py = -wk * ey;  // wk conj(eta)
+      nx_[g] += px * cfx - py * cfy;
+      ny_[g] += px * cfy + py * cfx;
+      dkx += ex * dx_[g] - ey * dy_[g];
+      dky += ex * dy_[g] + ey * dx_[g];
+    }
+    jx += a.four_q * wk * a.cosk[kk] * cg;
+    jy += a.four_q * wk * a.sink[kk] * cg;
+    icell += wk * ci;
+    d2avg += wk * (dkx * dkx + dky * dky);
+  };
+  // with pair_fold each gather of a lower angle serves its upper angle too
+  const int kend = a.pair_fold ? a.pair_k0 : a.n_theta;
+  for (int k = live ? wv : kend; k < kend; k += kBackWaves) {
     const int4 ix = a.rb4[static_cast<int64_t>(k) * a.ncg + c];
     const double epx = a.cosk[k], epy = a.sink[k];
     // lattice coordinates (line u, node v) of the cell centre
@@ -699,21 +719,9 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
       cg += vv.z * wq;
       ci += vv.w * wq;
     }
-    const double wk = a.wk[k];
-    double dkx = 0.0, dky = 0.0;
-    for (int g = 0; g < a.ncomp; ++g) {
-      const double ex = a.eta[2 * (g * a.n_theta + k)], ey = a.eta[2 * (g * a.n_theta + k) + 1];
-      const double px = wk * ex, py = -wk * ey;  // wk conj(eta)
-      nx_[g] += px * cfx - py * cfy;
-      ny_[g] += px * cfy + py * cfx;
-      dkx += ex * dx_[g] - ey * dy_[g];
-      dky += ex * dy_[g] + ey * dx_[g];
-    }
-    if (k >= a.pair_k0) cg = -cg;  // S_g of the reversed direction
-    jx += a.four_q * wk * epx * cg;
-    jy += a.four_q * wk * epy * cg;
-    icell += wk * ci;
-    d2avg += wk * (dkx * dkx + dky * dky);
+    // S_g of the reversed direction changes sign; S_f and S_I do not
+    add_angle(k, cfx, cfy, k >= a.pair_k0 ? -cg : cg, ci);
+    if (a.pair_fold) add_angle(k + a.pair_k0, cfx, cfy, -cg, ci);
   }
   if (wv > 0) {
     double* p = &part[wv - 1][0][lane];

@@ -113,6 +113,9 @@ struct BackArgs {
   // k - n_theta/2 (rb4 already points there): S_g changes sign, S_f and
   // S_I do not.  n_theta when angle pairs are off.
   int pair_k0;
+  // pair_fold: angle k + pair_k0 has the corners of angle k (the same
+  // lattice points), so each gather of a lower angle serves both
+  int pair_fold;
 };
 
 struct LdosBackArgs {

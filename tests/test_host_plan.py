@@ -140,6 +140,10 @@ def test_angle_pairs_mirror_the_segments(name):
     # a bijection onto the lower angles, and half the steps
     assert len(np.unique(mir[upper])) == int(upper.sum()) == int((~upper).sum())
     assert 2 * swept == pl.info["steps_per_sweep"]
+    # the lattice of phi_k + pi is the same point set, so every grain cell
+    # has the same rotate-back corners on both angles of a pair (to the
+    # rounding of cos and sin): the paired rotate-back gathers once per pair
+    assert pl.rotate_fold()
 
 
 @pytest.mark.parametrize("name", ["small_d110_field", "small_holed_mixed", "small_mask_blob", "d110_square_400"])
