@@ -18,5 +18,6 @@ Modules
   scf       one iteration map, Picard SCF loop, LDOS
   bulk      closed forms of the homogeneous state (pins)
   annulus   London-Maxwell closed forms of a screened annulus (pins)
+  disc      superflow free energy of an unscreened disc (pins)
 """
-from . import tables, geometry, sweep, fields, scf, bulk, annulus  # noqa: F401
+from . import tables, geometry, sweep, fields, scf, bulk, annulus, disc  # noqa: F401

@@ -186,8 +186,20 @@ def annulus_spec(kappa, flux_quanta, h=0.125, n_theta=64, n_poles=24):
                 gauge="symmetric", charge_sign=-1, name="swave_annulus")
 
 
+def disc_spec(flux_quanta, R=25.0, h=0.125, n_theta=64, n_poles=24):
+    """The unscreened s-wave disc of Sec. V.B (radius 25 xi0, t = 0.2,
+    infinite penetration depth), centred in a square grid with 1 xi0 of
+    margin (416 x 416 cells at h = 0.125), symmetric gauge with flux_quanta
+    through the disc."""
+    n = int(round(2 * (R + 1.0) / h))
+    return dict(nx=n, ny=n, h=h, shapes=[_disc(0, 0, R)], n_theta=n_theta, n_poles=n_poles, t=0.2,
+                components=[("s", 1.0)], kappa=0.0, flux_quanta=flux_quanta, gauge="symmetric",
+                charge_sign=-1, name="swave_disc_unscreened")
+
+
 def annulus_initial_delta(sp, winding):
-    """Bulk amplitude with the phase winding 2 pi winding around the hole."""
+    """Bulk amplitude at t = 0.2 with the phase winding 2 pi winding around
+    the grid centre (the hole of the annulus, the vortex of the disc)."""
     X, Y = centres(sp)
     return (S_BULK_T02 * DELTA0 * np.exp(1j * winding * np.arctan2(Y, X)))[None].astype(np.complex128)
 

@@ -380,3 +380,56 @@ def test_screened_annulus_moment_matches_london_maxwell(kappa, alpha, n, tol):
     _note("  m/m0 %.6g, closed form %.6g, relative %.3g" % (m, pred, m / pred - 1))
     g.close()
     assert abs(m / pred - 1) < tol, (m, pred)
+
+
+def test_unscreened_disc_free_energy_and_first_critical_field():
+    """Sec. V.B: the s-wave disc R = 25 xi0 at t = 0.2 without screening
+    (416 x 416, 64 angles, 24 poles), solved self-consistently in FP64 (BB to
+    1e-10).  Without a vortex, (Omega(alpha) - Omega(0)) / A = dw alpha^2
+    (Eq. 0vor) with dw = Y / (16 R^2) (Eq. lFKinfty): within 1e-3 at alpha
+    = 1 and 2 (measured 1e-4; alpha = 3 is solved too, for the vortex).  With one vortex of winding -1 at the centre
+    (Eq. 1vor) the difference to the vortex-free state is
+    dw (eps_core - 4 alpha): its slope in alpha is -4 dw within 1e-2
+    (measured 1e-3; eps_core, which the London theory leaves open, drops
+    out), and the two states cross at alpha = eps_core / 4, the first
+    critical field, which the paper reads off its Fig. 15 as about 3.8
+    (within 0.1).  The closed form's alpha refers to the exact area; the
+    grid's flux and free energy to its cell area."""
+    from oracle import bulk, disc
+    qs = _qs()
+    t, npol, R = 0.2, 24, 25.0
+    y = bulk.yoshida(bulk.bulk_gap(t, npol), t, npol)
+    om = {}
+    for n, alpha in ((0, 0.0), (0, 1.0), (0, 2.0), (0, 3.0), (-1, 1.0), (-1, 2.0), (-1, 3.0)):
+        sp = wl.disc_spec(alpha)
+        _note("full size: unscreened disc, winding %d, alpha %g" % (n, alpha))
+        d = torch.as_tensor(wl.annulus_initial_delta(sp, n)).cuda()
+        a = torch.zeros((2, sp["ny"], sp["nx"]), dtype=torch.float64).cuda()
+        g = qs.Grain(sp, "fp64")
+        g.set_accelerator("bb")
+        it, res, conv = g.scf(d, a, 3000, tol=1e-10, alpha=0.5)
+        assert conv, (n, alpha, res[-1])
+        _, _, o = g.sweep(d, a)
+        mask = g.mask()
+        area = sp["h"] ** 2 * mask.sum()
+        if n == -1:
+            # the vortex stayed at the centre: |Delta| is smallest within a cell of it
+            amp = np.where(mask, np.abs(d[0].cpu().numpy()), np.inf)
+            X, Y = wl.centres(sp)
+            k = np.argmin(amp)
+            assert np.hypot(X.flat[k], Y.flat[k]) < sp["h"], (X.flat[k], Y.flat[k])
+        om[(n, alpha)] = o / area
+        g.close()
+    scale = np.pi * R * R / area  # flux through the exact area per flux through the cell area
+    dw = disc.kinetic_coefficient(R, y)
+    for alpha in (1.0, 2.0):
+        got = om[(0, alpha)] - om[(0, 0.0)]
+        ref = disc.free_energy_shift(R, y, alpha * scale, 0)
+        _note("  n = 0, alpha %g: %.6g against %.6g" % (alpha, got, ref))
+        assert abs(got / ref - 1) < 1e-3, (alpha, got, ref)
+    al = np.array([1.0, 2.0, 3.0]) * scale
+    diff = [om[(-1, a_)] - om[(0, a_)] for a_ in (1.0, 2.0, 3.0)]
+    slope, icpt = np.polyfit(al, diff, 1)
+    _note("  slope %.6g against -4 dw %.6g; crossing at alpha %.3f" % (slope, -4 * dw, -icpt / slope))
+    assert abs(slope / (-4 * dw) - 1) < 1e-2, (slope, -4 * dw)
+    assert abs(-icpt / slope - 3.8) < 0.1, -icpt / slope

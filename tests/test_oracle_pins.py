@@ -489,3 +489,26 @@ def test_annulus_moment_without_screening():
     ref = -(math.pi * Y / area) * (B * (Ro ** 4 - Ri ** 4) / 8 + n * (Ro ** 2 - Ri ** 2) / 4)
     errs = [abs(annulus.moment(Ro, Ri, lam0, Y, alpha, n)[0] / ref - 1) for lam0 in (300.0, 3000.0)]
     assert errs[1] < 1e-4 and errs[1] < 0.03 * errs[0], errs
+
+
+# ------------------------------------ unscreened disc (Sec. V.B closed forms)
+from oracle import disc as odisc  # noqa: E402
+
+
+@pytest.mark.parametrize("R,Y", [(25.0, 0.998859), (15.0, 0.83), (8.0, 1.0)])
+def test_disc_free_energy_is_the_kinetic_energy_of_its_superflow(R, Y):
+    """Eq. lFEkin with rho_s = 2 N_F Y v_F v_F^T and p_s = (hbar / 2) q phi-hat
+    gives, averaged over the Fermi circle (<(v.e)^2> = v_F^2 / 2) and with
+    hbar v_F = 2 pi k_B T_c xi0, the density Y q^2 / 8 in units of
+    N_F (2 pi k_B T_c)^2, q = n / r + alpha r / R^2 in 1/xi0.  Its disc
+    average reproduces dw alpha^2 for n = 0 and, for n = -1, the terms of
+    Eq. 1vor that depend on alpha (the r^-2 term is the core's)."""
+    from scipy.integrate import quad
+    area = math.pi * R * R
+    for alpha in (0.5, 1.0, 2.7):
+        for n in (0, -1):
+            dens = lambda r: Y / 8.0 * ((alpha * r / R ** 2) ** 2 + 2 * n * alpha / R ** 2)  # noqa: E731
+            avg = quad(lambda r: dens(r) * 2 * math.pi * r, 0.0, R)[0] / area
+            ref = odisc.free_energy_shift(R, Y, alpha, n) - odisc.free_energy_shift(R, Y, 0.0, n)
+            assert abs(avg - ref) < 1e-12 * abs(ref), (alpha, n, avg, ref)
+    assert odisc.kinetic_coefficient(R, Y) == pytest.approx(Y / (16 * R * R), rel=1e-15)
