@@ -1161,17 +1161,48 @@ __global__ void __launch_bounds__(256) fft_rows_kernel(double2* __restrict__ w, 
     buf[r] = v;
   }
   __syncthreads();
-  for (int s = 1; s <= logn; ++s) {
-    const int half = 1 << (s - 1);
+  // twiddle exp(-+2 pi i pos / 2^s) of stage s
+  auto twiddle = [&](int pos, int s) {
+    double2 tf = tw[pos << (logn - s)];
+    if (sign > 0) tf.y = -tf.y;
+    return tf;
+  };
+  auto butterfly = [](double2& u, double2& v, double2 tf) {
+    const double2 vt = make_double2(v.x * tf.x - v.y * tf.y, v.x * tf.y + v.y * tf.x);
+    v = make_double2(u.x - vt.x, u.y - vt.y);
+    u = make_double2(u.x + vt.x, u.y + vt.y);
+  };
+  // two radix-2 stages per pass, the four elements a thread combines held in
+  // registers: stage s pairs (i, i + h) and (i + 2h, i + 3h), stage s + 1
+  // pairs (i, i + 2h) and (i + h, i + 3h), h = 2^(s-1)
+  int s = 1;
+  for (; s + 1 <= logn; s += 2) {
+    const int h = 1 << (s - 1);
+    for (int b = threadIdx.x; b < n / 4; b += blockDim.x) {
+      const int grp = b / h, pos = b - grp * h;
+      const int i0 = grp * 4 * h + pos;
+      double2 x0 = buf[i0], x1 = buf[i0 + h], x2 = buf[i0 + 2 * h], x3 = buf[i0 + 3 * h];
+      const double2 t1 = twiddle(pos, s);
+      butterfly(x0, x1, t1);
+      butterfly(x2, x3, t1);
+      butterfly(x0, x2, twiddle(pos, s + 1));
+      butterfly(x1, x3, twiddle(pos + h, s + 1));
+      buf[i0] = x0;
+      buf[i0 + h] = x1;
+      buf[i0 + 2 * h] = x2;
+      buf[i0 + 3 * h] = x3;
+    }
+    __syncthreads();
+  }
+  if (s == logn) {  // odd logn: one radix-2 stage left
+    const int h = 1 << (s - 1);
     for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
-      const int grp = b / half, pos = b - grp * half;
-      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-      double2 tf = tw[pos << (logn - s)];  // exp(-2 pi i pos / 2^s)
-      if (sign > 0) tf.y = -tf.y;
-      const double2 u = buf[i0], v = buf[i1];
-      const double2 vt = make_double2(v.x * tf.x - v.y * tf.y, v.x * tf.y + v.y * tf.x);
-      buf[i0] = make_double2(u.x + vt.x, u.y + vt.y);
-      buf[i1] = make_double2(u.x - vt.x, u.y - vt.y);
+      const int grp = b / h, pos = b - grp * h;
+      const int i0 = grp * 2 * h + pos;
+      double2 u = buf[i0], v = buf[i0 + h];
+      butterfly(u, v, twiddle(pos, s));
+      buf[i0] = u;
+      buf[i0 + h] = v;
     }
     __syncthreads();
   }
