@@ -72,3 +72,27 @@ def moment(Ro, Ri, lam0, Y, alpha, n):
     d_alpha = pre * (A + Ah) / (M * A) * (iv(2, Ri / lam) * kv(2, Ro / lam) - iv(2, Ro / lam) * kv(2, Ri / lam))
     d_n = pre * (2.0 * math.pi * lam * lam / (M * Ah) - 1.0)
     return d_alpha * alpha + d_n * n, d_alpha, d_n
+
+
+def free_energy_shift(Ro, Ri, lam0, Y, alpha, n, kappa):
+    """Omega(alpha, n) - Omega_bulk of the screened annulus in linear response
+    (Sec. V.A, Eqs. FEsuperflow, lFEkin, lFEmag) with the London fields of
+    Eqs. Aring, Bring, in units of N_F (2 pi k_B T_c)^2 xi0^2:
+      kinetic  int over the annulus of (Y / 2) (A + n Phi0 / (2 pi R))^2
+               (the density Y q^2 / 8 of Eq. lFEkin with q = 2 (A + n / (2R)),
+               q the phase gradient plus the vector potential in 1/xi0),
+      magnetic int of (kappa^2 / 2) (B - B_ext)^2 over the annulus and the
+               hole (outside the annulus B = B_ext; kappa^2 / 2 is 1 / (8 pi)
+               in these units).
+    Returns (total, kinetic, magnetic)."""
+    from scipy.integrate import quad
+    lam = lam0 / math.sqrt(Y)
+    A = math.pi * (Ro * Ro - Ri * Ri)
+    Ah = math.pi * Ri * Ri
+    b_ext = alpha * PHI0 / A
+    kin = quad(lambda R: 0.5 * Y * (field(R, Ro, Ri, lam, alpha, n)[0] + n * PHI0 / (2 * math.pi * R)) ** 2
+               * 2 * math.pi * R, Ri, Ro, limit=200)[0]
+    mag = quad(lambda R: 0.5 * kappa * kappa * (field(R, Ro, Ri, lam, alpha, n)[1] - b_ext) ** 2 * 2 * math.pi * R,
+               Ri, Ro, limit=200)[0]
+    mag += 0.5 * kappa * kappa * (field(0.5 * Ri, Ro, Ri, lam, alpha, n)[1] - b_ext) ** 2 * Ah
+    return kin + mag, kin, mag

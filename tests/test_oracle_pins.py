@@ -512,3 +512,45 @@ def test_disc_free_energy_is_the_kinetic_energy_of_its_superflow(R, Y):
             ref = odisc.free_energy_shift(R, Y, alpha, n) - odisc.free_energy_shift(R, Y, 0.0, n)
             assert abs(avg - ref) < 1e-12 * abs(ref), (alpha, n, avg, ref)
     assert odisc.kinetic_coefficient(R, Y) == pytest.approx(Y / (16 * R * R), rel=1e-15)
+
+
+@pytest.mark.parametrize("kappa,alpha,n", [(5.0, 0.3, 0), (5.0, 0.0, -1), (20.0, 1.3, -2), (3.0, -0.6, 1)])
+def test_annulus_free_energy_is_stationary_at_the_london_field(kappa, alpha, n):
+    """The London field minimises kinetic + magnetic energy (its Euler-Lagrange
+    equation is Eq. LMeqRing with 1 / lambda^2 = Y / kappa^2): adding
+    eps dA (dA smooth, zero at R> and inside the hole's edge region, so the
+    applied flux stays) changes the functional by O(eps^2) only, while the
+    same variation of a field off the solution changes it at first order.
+    A wrong relative factor between the two terms (kappa^2 against 1/8pi, or
+    Y/2) moves the minimiser off the London field and fails this.  The
+    functional here is integrated on its own grid; free_energy_shift must
+    agree with it at the London field."""
+    Ro, Ri, Y = 25.0, 10.0, 0.9
+    lam = kappa / math.sqrt(Y)
+    area = math.pi * (Ro ** 2 - Ri ** 2)
+    b_ext = alpha * math.pi / area
+    r = np.linspace(Ri, Ro, 20001)
+    dr = r[1] - r[0]
+    A0 = np.array([annulus.field(x, Ro, Ri, lam, alpha, n)[0] for x in r])
+    bh = annulus.field(0.5 * Ri, Ro, Ri, lam, alpha, n)[1]
+    dA = np.sin(np.pi * (r - Ri) / (Ro - Ri)) ** 2  # zero with its slope at both ends
+
+    def functional(Af):
+        B = np.gradient(r * Af, dr) / r
+        kin = 0.5 * Y * (Af + n / (2 * r)) ** 2
+        mag = 0.5 * kappa ** 2 * (B - b_ext) ** 2
+        f = (kin + mag) * 2 * np.pi * r
+        return np.sum(0.5 * (f[1:] + f[:-1])) * dr + 0.5 * kappa ** 2 * (bh - b_ext) ** 2 * math.pi * Ri ** 2
+
+    eps = 1e-3 * max(np.max(np.abs(A0)), 1e-3)
+    f0 = functional(A0)
+    tot, kin, mag = annulus.free_energy_shift(Ro, Ri, kappa, Y, alpha, n, kappa)
+    assert abs(f0 - tot) < 1e-6 * abs(tot), (f0, tot)
+    d1 = (functional(A0 + eps * dA) - functional(A0 - eps * dA)) / (2 * eps)
+    d2 = (functional(A0 + eps * dA) - 2 * f0 + functional(A0 - eps * dA)) / eps ** 2
+    assert d2 > 0
+    assert abs(d1) < 1e-6 * d2 * max(np.max(np.abs(A0)), 1.0), (d1, d2)
+    # a field off the solution (the applied one alone) is not stationary
+    Aoff = A0 + 0.05 * np.max(np.abs(A0) + 1e-3) * dA
+    d1off = (functional(Aoff + eps * dA) - functional(Aoff - eps * dA)) / (2 * eps)
+    assert abs(d1off) > 1e-3 * d2 * 0.05 * np.max(np.abs(A0) + 1e-3)
