@@ -600,6 +600,9 @@ def test_split_launch_shape_equals_one_shape(name, precision, epl):
     for frac in (0.8, 0.0):
         g = qs.Grain(sp, precision)
         g.set_lanes(epl)
+        for bad in (-0.1, 1.5, float("nan")):
+            with pytest.raises(qs.QcError):
+                g.set_split(bad)
         g.set_split(frac)
         f, n_wide = g.split()
         assert f == frac

@@ -47,6 +47,8 @@ def test_no_device_and_invalid_arguments_fail_before_launch():
     assert "grain" in str(e.value)
     assert qs.lib.qc_sweep(None, None, None, None, None, None, None, None) == -1
     assert qs.lib.qc_grain_set_accelerator(None, 1, 0.5) == -1
+    assert qs.lib.qc_grain_set_split(None, 0.9) == -1
+    assert qs.lib.qc_grain_get_split(None, None, None) == -1
 
 
 @pytest.mark.parametrize("n", [1, 5, 16, 64, 128])
