@@ -379,9 +379,12 @@ qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
  * even, the quadrature weights and basis values of phi_k and phi_k + pi
  * agree, and the planner's tables of the two angles mirror each other
  * exactly (same segments, node counts, slot positions within 1e-9 h and
- * fallback cells); enabled by default when available.  LDOS, the Green's
- * function average and the reverse mode always march every angle.  Set it
- * before qc_batch_create for grains of a batch.
+ * fallback cells); enabled by default when available.  The reverse mode
+ * marches the lower angles as the sweep does; qc_ldos does so in its
+ * boundary iterations when its energies are symmetric about zero (the
+ * reversed direction at e mirrors energy -e); the LDOS output pass, the
+ * converging LDOS and the Green's function average march every angle.  Set
+ * it before qc_batch_create for grains of a batch.
  * Errors: QC_ERR_INVALID when enabling on a grain where it is unavailable. */
 qc_status qc_grain_set_pairing(qc_grain* grain, int enable);
 /* available / enabled flags and the trajectory steps one Matsubara sweep
@@ -398,7 +401,9 @@ qc_status qc_grain_get_accel_stats(const qc_grain* grain, int64_t* bisected, int
  * real energies e + i*broadening, Delta and A frozen: bc_iters sweeps update
  * only the boundary values (burn-in, App. B), then one sweep produces the
  * output.  The boundary store used starts from bulk roots and is separate
- * from the one of qc_sweep.
+ * from the one of qc_sweep.  With angle pairs on and a set of energies
+ * symmetric about zero (to 1e-12 of the largest |e|), the boundary sweeps
+ * march half the angles (see qc_grain_set_pairing).
  *   energies host double [n_e]
  *   ldos_out device double [n_e][ny][nx] (0 off-grain) */
 qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,

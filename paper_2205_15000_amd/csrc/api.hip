@@ -653,9 +653,9 @@ void launch_sweep_timed(qc_grain* g, int mode, const qc::SweepArgs& a, const qc:
 void mirror_fill(qc_grain* g, void* bc_g, void* bc_gt, hipStream_t st) {
   if (!g->pairing) return;
   if (g->precision == QC_MIXED)
-    qc::launch_mirror_fill<float>(g->mirror_pairs, g->npairs, g->n_poles, bc_g, bc_gt, st);
+    qc::launch_mirror_fill<float>(g->mirror_pairs, g->npairs, g->n_poles, nullptr, bc_g, bc_gt, st);
   else
-    qc::launch_mirror_fill<double>(g->mirror_pairs, g->npairs, g->n_poles, bc_g, bc_gt, st);
+    qc::launch_mirror_fill<double>(g->mirror_pairs, g->npairs, g->n_poles, nullptr, bc_g, bc_gt, st);
 }
 
 double omega_from_parts(const qc_grain* g) {
@@ -1622,6 +1622,24 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
   });
 }
 
+// Partner of each real energy under e -> -e (to 1e-12 of the largest |e|)
+// when the set is symmetric about zero (as a multiset); false otherwise
+bool energy_partners(const double* en, int n, std::vector<int32_t>& partner) {
+  double emax = 0.0;
+  for (int i = 0; i < n; ++i) emax = std::max(emax, std::fabs(en[i]));
+  const double tol = 1e-12 * std::max(emax, 1e-300);
+  std::vector<int32_t> idx(static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return en[x] < en[y]; });
+  partner.assign(static_cast<size_t>(n), -1);
+  for (int k = 0; k < n; ++k) {
+    const int32_t i = idx[k], j = idx[n - 1 - k];
+    if (std::fabs(en[i] + en[j]) > tol) return false;
+    partner[i] = j;
+  }
+  return true;
+}
+
 qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const double* energies, int n_e,
                   double broadening, int bc_iters, double* ldos_out, void* stream) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
@@ -1632,6 +1650,7 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     if (!std::isfinite(energies[i])) return fail(QC_ERR_INVALID, "energies must be finite");
   void* bcl[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   double* deps = nullptr;
+  int32_t* dpart = nullptr;
   void* lg = nullptr;
   void* le = nullptr;
   qc_status rs = guarded([&]() -> qc_status {
@@ -1647,6 +1666,15 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) bcl[a][b] = dalloc(2 * rb * g->nseg * n_e);
     do_interp(g, delta, A_ind, st);
+    // Angle pairs in the boundary iterations: with an energy set symmetric
+    // about zero, the reversed direction at e + i delta follows from its
+    // mirror at -e + i delta (Sec. II.A symmetry with z -> -z*), so the
+    // boundary sweeps march the lower angle of each pair and the store of
+    // the upper one is filled from its mirror after every iteration.  The
+    // output pass marches every angle from the complete store.
+    std::vector<int32_t> partner;
+    const bool pair = g->pairing && energy_partners(energies, n_e, partner);
+    if (pair) dpart = static_cast<int32_t*>(upload(partner));
     const int blk_all = 256;  // energies of one boundary-only launch (64 lanes x 4)
     int cur = 0;
     qc::SweepBufs b;
@@ -1656,13 +1684,19 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     for (int it = 0; it < bc_iters; ++it) {
       for (int e0 = 0; e0 < n_e; e0 += blk_all) {
         const int ne = std::min(blk_all, n_e - e0);
-        qc::SweepArgs a = sweep_args(g, ne, n_e, e0, deps, nullptr);
+        qc::SweepArgs a = sweep_args(g, ne, n_e, e0, deps, nullptr, pair);
         a.bc_valid = it > 0;
         b.bc_g_prev = bcl[cur][0];
         b.bc_gt_prev = bcl[cur][1];
         b.bc_g_next = bcl[1 - cur][0];
         b.bc_gt_next = bcl[1 - cur][1];
         launch_sweep_timed(g, 2, a, b, st);
+      }
+      if (pair) {
+        if (g->precision == QC_MIXED)
+          qc::launch_mirror_fill<float>(g->mirror_pairs, g->npairs, n_e, dpart, bcl[1 - cur][0], bcl[1 - cur][1], st);
+        else
+          qc::launch_mirror_fill<double>(g->mirror_pairs, g->npairs, n_e, dpart, bcl[1 - cur][0], bcl[1 - cur][1], st);
       }
       cur = 1 - cur;
     }
@@ -1714,6 +1748,7 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     for (int b = 0; b < 2; ++b)
       if (bcl[a][b]) (void)hipFree(bcl[a][b]);
   if (deps) (void)hipFree(deps);
+  if (dpart) (void)hipFree(dpart);
   if (lg) (void)hipFree(lg);
   if (le) (void)hipFree(le);
   return rs;

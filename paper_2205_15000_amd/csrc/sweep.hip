@@ -765,13 +765,16 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
 // from its mirror segment's
 template <typename T>
 __global__ void __launch_bounds__(256) mirror_fill_kernel(const int2* __restrict__ pairs, int64_t npairs, int n_e,
+                                                          const int32_t* __restrict__ partner,
                                                           cpx<T>* __restrict__ bc_g, cpx<T>* __restrict__ bc_gt) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= npairs * n_e) return;
   const int64_t q = t / n_e;
   const int e = static_cast<int>(t - q * n_e);
   const int2 pr = pairs[q];
-  const int64_t dst = static_cast<int64_t>(pr.x) * n_e + e, src = static_cast<int64_t>(pr.y) * n_e + e;
+  // real energies: the reversed direction at e mirrors energy -e (partner)
+  const int es = partner ? partner[e] : e;
+  const int64_t dst = static_cast<int64_t>(pr.x) * n_e + e, src = static_cast<int64_t>(pr.y) * n_e + es;
   const cpx<T> g = bc_g[src], gt = bc_gt[src];
   bc_g[dst] = mk(gt.x, -gt.y);
   bc_gt[dst] = mk(g.x, -g.y);
@@ -1368,13 +1371,14 @@ void launch_valu_rate(int op, float* out, int nblocks, int iters, hipStream_t st
 }
 
 template <typename T>
-void launch_mirror_fill(const int2* pairs, int64_t npairs, int n_e, void* bc_g, void* bc_gt, hipStream_t st) {
+void launch_mirror_fill(const int2* pairs, int64_t npairs, int n_e, const int32_t* partner, void* bc_g, void* bc_gt,
+                        hipStream_t st) {
   if (npairs * n_e > 0)
-    hipLaunchKernelGGL(mirror_fill_kernel<T>, dim3(nblk(npairs * n_e)), dim3(256), 0, st, pairs, npairs, n_e,
+    hipLaunchKernelGGL(mirror_fill_kernel<T>, dim3(nblk(npairs * n_e)), dim3(256), 0, st, pairs, npairs, n_e, partner,
                        static_cast<cpx<T>*>(bc_g), static_cast<cpx<T>*>(bc_gt));
 }
-template void launch_mirror_fill<float>(const int2*, int64_t, int, void*, void*, hipStream_t);
-template void launch_mirror_fill<double>(const int2*, int64_t, int, void*, void*, hipStream_t);
+template void launch_mirror_fill<float>(const int2*, int64_t, int, const int32_t*, void*, void*, hipStream_t);
+template void launch_mirror_fill<double>(const int2*, int64_t, int, const int32_t*, void*, void*, hipStream_t);
 
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;

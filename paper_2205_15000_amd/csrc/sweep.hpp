@@ -248,7 +248,11 @@ void launch_rotate_back(const BackArgs& a, hipStream_t st);
 // gamma_end(s') = conj(gamma~_end(s)), gamma~_end(s') = conj(gamma_end(s))
 // for each (s', s) in pairs, n_e energies per segment (T = float or double)
 template <typename T>
-void launch_mirror_fill(const int2* pairs, int64_t npairs, int n_e, void* bc_g, void* bc_gt, hipStream_t st);
+// partner: for real energies, the index of -e for each energy e of the
+// store (the reversed direction at e mirrors energy -e); nullptr for the
+// Matsubara poles (each its own partner)
+void launch_mirror_fill(const int2* pairs, int64_t npairs, int n_e, const int32_t* partner, void* bc_g, void* bc_gt,
+                        hipStream_t st);
 // blocks of 256 lanes, each lane writes out[lane]: out holds nblocks * 256 floats
 void launch_valu_rate(int op, float* out, int nblocks, int iters, hipStream_t st);
 template <typename T>

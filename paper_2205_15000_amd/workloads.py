@@ -211,8 +211,10 @@ def vortex_ldos_energies(n=128):
 
 
 def ldos_energies(n=512):
-    """Real energies -2 DELTA0 + 4 DELTA0 k / n, k = 0..n-1 (includes 0)."""
-    return -2.0 * DELTA0 + 4.0 * DELTA0 * np.arange(n) / n
+    """Real energies at the midpoints of n equal intervals of [-2, 2] DELTA0,
+    -2 DELTA0 + 4 DELTA0 (k + 1/2) / n, k = 0..n-1: symmetric about zero (the
+    two nearest zero are +-2 DELTA0 / n)."""
+    return -2.0 * DELTA0 + 4.0 * DELTA0 * (np.arange(n) + 0.5) / n
 
 
 def batch_specs(n=64, seed0=3):

@@ -306,6 +306,30 @@ def test_ldos_matches_oracle(precision, tol):
     g.close()
 
 
+@pytest.mark.parametrize("name,precision", [("small_d110_field", "fp64"), ("s_disc_32", "fp64"),
+                                            ("small_d110_field", "mixed")])
+def test_ldos_angle_pairs_equal_every_angle(name, precision):
+    """LDOS with an energy set symmetric about zero (e and -e, zero included)
+    and 5 boundary iterations: with angle pairs the boundary sweeps march
+    the lower angle of each pair and fill the upper one's store from its
+    mirror at -e.  The LDOS equals that of the run without pairs (1e-12
+    FP64, 1e-6 mixed); an asymmetric set runs unpaired and equals it too."""
+    qs = _qs()
+    sp = wl.spec(name)
+    _note("case %s %s: LDOS with and without angle pairs" % (name, precision))
+    d0 = _dev(wl.initial_delta(name, sp), torch.complex128)
+    a0 = _dev(wl.initial_A(name, sp), torch.float64)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for en in (np.linspace(-0.45, 0.45, 9), np.array([-0.3, 0.05, 0.2, 0.31])):
+        out = []
+        for pair in (True, False):
+            g = qs.Grain(sp, precision)
+            g.set_pairing(pair)
+            out.append(g.ldos(d0, a0, en, 0.02, 5).cpu().numpy())
+            g.close()
+        assert _close(out[0], out[1], tol), rel_err(out[0], out[1])
+
+
 def test_uniform_s_wave_is_an_exact_fixed_point_on_gpu():
     qs = _qs()
     from oracle import bulk
