@@ -299,15 +299,17 @@ def mode_ldos(qs, torch, wl, n_prior, bc_iters):
     ms, nl = gl.profile_read()
     steps = gl.info["steps_per_sweep"] // sp["n_poles"] * len(en) * (bc_iters + 1)
     # with angle pairs and the symmetric energy set the boundary iterations
-    # march the lower angle of each pair; the output pass marches every angle
+    # march the lower angle of each pair, and so does the output pass when
+    # the pairs share their rotate-back corners
     paired = bool(gl.pairing()[1]) and bool(np.allclose(np.sort(en), -np.sort(en)[::-1], rtol=0, atol=1e-12))
+    out_paired = paired and gl.rotate_fold()
     per_iter = gl.info["steps_per_sweep"] // sp["n_poles"] * len(en)
-    marched = (per_iter // 2 if paired else per_iter) * bc_iters + per_iter
+    marched = (per_iter // 2 if paired else per_iter) * bc_iters + (per_iter // 2 if out_paired else per_iter)
     o = o.cpu().numpy()
     gl.close()
     return {"metric": "LDOS trajectory-steps/s", "workload": name, "energies": len(en), "bc_iters": bc_iters,
             "value": steps / dt, "unit": "trajectory-steps/s", "seconds": dt, "steps": steps,
-            "boundary_iterations_paired": paired, "marched_steps": marched, "marched_steps_per_s": marched / dt,
+            "boundary_iterations_paired": paired, "output_pass_paired": out_paired, "marched_steps": marched, "marched_steps_per_s": marched / dt,
             "sweep_kernel_ms": ms, "sweep_launches": nl, "sweep_only_steps_per_s": steps / (ms * 1e-3),
             "prior_solve_s": prior_s, "prior_iters": prior_it, "prior_converged": bool(prior_conv),
             "prior_res_last": prior_res[prior_it - 1, :4].tolist(), "finite": bool(np.isfinite(o).all())}

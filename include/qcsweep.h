@@ -380,16 +380,19 @@ qc_status qc_grain_set_accelerator(qc_grain* grain, int kind, double beta);
  * agree, and the planner's tables of the two angles mirror each other
  * exactly (same segments, node counts, slot positions within 1e-9 h and
  * fallback cells); enabled by default when available.  The reverse mode
- * marches the lower angles as the sweep does; qc_ldos does so in its
- * boundary iterations when its energies are symmetric about zero (the
- * reversed direction at e mirrors energy -e); the LDOS output pass, the
+ * marches the lower angles as the sweep does; qc_ldos does so when its
+ * energies are symmetric about zero (the reversed direction at e mirrors
+ * energy -e): in its boundary iterations, and in its output pass where the
+ * pairs share their rotate-back corners (available = 3 below); the
  * converging LDOS and the Green's function average march every angle.  Set
  * it before qc_batch_create for grains of a batch.
  * Errors: QC_ERR_INVALID when enabling on a grain where it is unavailable. */
 qc_status qc_grain_set_pairing(qc_grain* grain, int enable);
 /* available / enabled flags and the trajectory steps one Matsubara sweep
  * marches (steps_per_sweep of qc_plan_info counts every angle); any output
- * pointer may be NULL. */
+ * pointer may be NULL.  *available is 3 when, beyond the pairs, every grain
+ * cell has the same rotate-back corners on both angles of a pair (see
+ * qc_plan_get_pairing), 1 with pairs alone, 0 without. */
 qc_status qc_grain_get_pairing(const qc_grain* grain, int* available, int* enabled, int64_t* swept_steps_per_sweep);
 
 /* Counts, over the grain's lifetime, of the CongAcc weights that were set by
@@ -402,8 +405,9 @@ qc_status qc_grain_get_accel_stats(const qc_grain* grain, int64_t* bisected, int
  * only the boundary values (burn-in, App. B), then one sweep produces the
  * output.  The boundary store used starts from bulk roots and is separate
  * from the one of qc_sweep.  With angle pairs on and a set of energies
- * symmetric about zero (to 1e-12 of the largest |e|), the boundary sweeps
- * march half the angles (see qc_grain_set_pairing).
+ * symmetric about zero (to 1e-12 of the largest |e|), the sweeps march half
+ * the angles (see qc_grain_set_pairing); the energies may come in any
+ * order, and ldos_out keeps the caller's order.
  *   energies host double [n_e]
  *   ldos_out device double [n_e][ny][nx] (0 off-grain) */
 qc_status qc_ldos(qc_grain* grain, const double* delta, const double* A_ind,

@@ -561,6 +561,13 @@ class Grain:
         _check(lib.qc_grain_get_pairing(self._g, ctypes.byref(a), ctypes.byref(e), ctypes.byref(n)))
         return bool(a.value), bool(e.value), n.value
 
+    def rotate_fold(self):
+        """Whether each pair of angles shares its rotate-back corners (the
+        paired rotate-back and the paired LDOS output gather once per pair)."""
+        a = ctypes.c_int(0)
+        _check(lib.qc_grain_get_pairing(self._g, ctypes.byref(a), None, None))
+        return bool(a.value & 2)
+
     def accel_stats(self):
         """(bisected, anti_parallel): CongAcc weights set by bisection and by
         the anti-parallel rule over the grain's lifetime."""

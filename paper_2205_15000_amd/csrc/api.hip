@@ -1651,30 +1651,55 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
   void* bcl[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   double* deps = nullptr;
   int32_t* dpart = nullptr;
+  int32_t* dmap = nullptr;
   void* lg = nullptr;
   void* le = nullptr;
   qc_status rs = guarded([&]() -> qc_status {
     hipStream_t st = S(stream);
     hcheck(hipSetDevice(g->device), "hipSetDevice");
     const size_t rb = g->real_bytes();
+    // Angle pairs: with an energy set symmetric about zero, the reversed
+    // direction at e + i delta follows from its mirror at -e + i delta
+    // (Sec. II.A symmetry with z -> -z*).  The boundary sweeps then march
+    // the lower angle of each pair, and the store of the upper one is filled
+    // from its mirror after every iteration.  The energies run in an order
+    // of their own, each e beside its -e (self-partners last), so that every
+    // even-sized block of the output pass holds whole pairs: the output
+    // sweep marches the lower angles too, and the rotate-back reads each
+    // lower angle's corners for both angles of the pair (where the planner
+    // found them equal).
+    std::vector<int32_t> partner;
+    const bool pair = g->pairing && energy_partners(energies, n_e, partner);
+    std::vector<int32_t> perm(static_cast<size_t>(n_e));  // run order -> caller's index
+    for (int i = 0; i < n_e; ++i) perm[i] = i;
+    std::vector<int32_t> part_run;  // partner in the run order
+    if (pair) {
+      std::vector<char> placed(static_cast<size_t>(n_e), 0);
+      int k = 0;
+      for (int i = 0; i < n_e; ++i)
+        if (!placed[i] && partner[i] != i) {
+          perm[k++] = i;
+          perm[k++] = partner[i];
+          placed[i] = placed[partner[i]] = 1;
+        }
+      for (int i = 0; i < n_e; ++i)
+        if (!placed[i]) perm[k++] = i;
+      std::vector<int32_t> inv(static_cast<size_t>(n_e));
+      for (int j = 0; j < n_e; ++j) inv[perm[j]] = j;
+      part_run.resize(static_cast<size_t>(n_e));
+      for (int j = 0; j < n_e; ++j) part_run[j] = inv[partner[perm[j]]];
+      dpart = static_cast<int32_t*>(upload(part_run));
+      dmap = static_cast<int32_t*>(upload(perm));
+    }
     std::vector<double> eps(2 * n_e);
     for (int i = 0; i < n_e; ++i) {
-      eps[2 * i] = energies[i];
+      eps[2 * i] = energies[perm[i]];
       eps[2 * i + 1] = broadening;
     }
     deps = static_cast<double*>(upload(eps));
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) bcl[a][b] = dalloc(2 * rb * g->nseg * n_e);
     do_interp(g, delta, A_ind, st);
-    // Angle pairs in the boundary iterations: with an energy set symmetric
-    // about zero, the reversed direction at e + i delta follows from its
-    // mirror at -e + i delta (Sec. II.A symmetry with z -> -z*), so the
-    // boundary sweeps march the lower angle of each pair and the store of
-    // the upper one is filled from its mirror after every iteration.  The
-    // output pass marches every angle from the complete store.
-    std::vector<int32_t> partner;
-    const bool pair = g->pairing && energy_partners(energies, n_e, partner);
-    if (pair) dpart = static_cast<int32_t*>(upload(partner));
     const int blk_all = 256;  // energies of one boundary-only launch (64 lanes x 4)
     int cur = 0;
     qc::SweepBufs b;
@@ -1710,12 +1735,15 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
     int blk = 64;
     while (blk > 1 && blk * per_e > budget) blk >>= 1;
     blk = std::min(blk, n_e);
+    // paired output: blocks of even size hold whole pairs (self-partners,
+    // last in the run order, pair with themselves)
+    const bool out_pair = pair && g->rb_fold && (blk % 2 == 0 || blk == n_e);
     lg = dalloc(2 * rb * g->nslot * blk);
     le = dalloc(rb * g->nslot * blk);
     qc::launch_fill(ldos_out, static_cast<int64_t>(n_e) * g->ncell, 0.0, st);
     for (int e0 = 0; e0 < n_e; e0 += blk) {
       const int ne = std::min(blk, n_e - e0);
-      qc::SweepArgs a = sweep_args(g, ne, n_e, e0, deps, nullptr);
+      qc::SweepArgs a = sweep_args(g, ne, n_e, e0, deps, nullptr, out_pair);
       a.bc_valid = bc_iters > 0;
       b.bc_g_prev = bcl[cur][0];
       b.bc_gt_prev = bcl[cur][1];
@@ -1724,7 +1752,7 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
       b.gbuf = lg;
       b.ebuf = le;
       launch_sweep_timed(g, 1, a, b, st);
-      qc::LdosBackArgs la;
+      qc::LdosBackArgs la{};
       la.ncg = g->ncg;
       la.ncell = g->ncell;
       la.n_theta = g->n_theta;
@@ -1735,6 +1763,9 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
       la.rb_w = g->rb_w;
       la.wk = g->wk;
       la.out = ldos_out;
+      la.e_map = dmap;
+      la.e_partner = out_pair ? dpart : nullptr;
+      la.fold_k0 = out_pair ? g->n_theta / 2 : 0;
       if (g->precision == QC_MIXED)
         qc::launch_ldos_back<float>(la, le, st);
       else
@@ -1749,6 +1780,7 @@ qc_status qc_ldos(qc_grain* g, const double* delta, const double* A_ind, const d
       if (bcl[a][b]) (void)hipFree(bcl[a][b]);
   if (deps) (void)hipFree(deps);
   if (dpart) (void)hipFree(dpart);
+  if (dmap) (void)hipFree(dmap);
   if (lg) (void)hipFree(lg);
   if (le) (void)hipFree(le);
   return rs;
@@ -1820,7 +1852,7 @@ qc_status qc_ldos_converge(qc_grain* g, const double* delta, const double* A_ind
         cur = 1 - cur;
         if (it > 0)
           hcheck(hipMemcpyAsync(prev, out, sizeof(double) * ne * g->ncell, hipMemcpyDeviceToDevice, st), "copy");
-        qc::LdosBackArgs la;
+        qc::LdosBackArgs la{};
         la.ncg = g->ncg;
         la.ncell = g->ncell;
         la.n_theta = g->n_theta;
@@ -1907,7 +1939,7 @@ qc_status qc_green_average(qc_grain* g, const double* delta, const double* A_ind
       qc::SweepArgs a = sweep_args(g, ne, g->n_poles, e0, g->eps, nullptr);
       a.bc_valid = g->bc_valid;  // the start values the next sweep would use
       launch_sweep_timed(g, 3, a, b, st);
-      qc::LdosBackArgs la;
+      qc::LdosBackArgs la{};
       la.ncg = g->ncg;
       la.ncell = g->ncell;
       la.n_theta = g->n_theta;
@@ -2278,7 +2310,7 @@ qc_status qc_grain_set_pairing(qc_grain* g, int enable) {
 
 qc_status qc_grain_get_pairing(const qc_grain* g, int* available, int* enabled, int64_t* swept_steps_per_sweep) {
   if (!g) return fail(QC_ERR_INVALID, "grain is NULL");
-  if (available) *available = g->pair_ok ? 1 : 0;
+  if (available) *available = g->pair_ok ? (g->rb_fold ? 3 : 1) : 0;
   if (enabled) *enabled = g->pairing ? 1 : 0;
   if (swept_steps_per_sweep) {
     if (!g->pairing) {

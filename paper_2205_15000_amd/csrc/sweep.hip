@@ -787,16 +787,26 @@ __global__ void __launch_bounds__(256) ldos_back_kernel(LdosBackArgs a, const T*
   const int64_t c = tid / a.n_e;
   const int e = static_cast<int>(tid - c * a.n_e);
   if (c >= a.ncg) return;
+  // with fold_k0 each lower angle's corners serve its upper angle too, at
+  // the partner energy (N of the reversed direction at e is N at -e)
+  const bool fold = a.fold_k0 > 0;
+  const int kend = fold ? a.fold_k0 : a.n_theta;
+  const int ep = fold ? a.e_partner[a.e_off + e] - a.e_off : e;
   double acc = 0.0;
-  for (int k = 0; k < a.n_theta; ++k) {
-    double v = 0.0;
+  for (int k = 0; k < kend; ++k) {
+    double v = 0.0, vp = 0.0;
     for (int qd = 0; qd < 4; ++qd) {
       const int64_t o = (static_cast<int64_t>(k) * 4 + qd) * a.ncg + c;
-      v += static_cast<double>(ebuf[static_cast<int64_t>(a.rb_idx[o]) * a.n_e + e]) * a.rb_w[o];
+      const int64_t row = static_cast<int64_t>(a.rb_idx[o]) * a.n_e;
+      const double w = a.rb_w[o];
+      v += static_cast<double>(ebuf[row + e]) * w;
+      if (fold) vp += static_cast<double>(ebuf[row + ep]) * w;
     }
     acc += a.wk[k] * v;
+    if (fold) acc += a.wk[k + a.fold_k0] * vp;
   }
-  a.out[static_cast<int64_t>(a.e_off + e) * a.ncell + a.grain_cells[c]] = acc;
+  const int64_t eo = a.e_map ? a.e_map[a.e_off + e] : a.e_off + e;
+  a.out[eo * a.ncell + a.grain_cells[c]] = acc;
 }
 
 // Fermi-surface average of g = -i pi (1-X)/(1+X) per cell and energy of the

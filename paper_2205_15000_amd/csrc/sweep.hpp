@@ -126,6 +126,14 @@ struct LdosBackArgs {
   const double* rb_w;
   const double* wk;
   double* out;  // [n_e_total][ny][nx]
+  // e_map: output energy index of each energy of the launch order (nullptr:
+  // e_off + e).  fold_k0 > 0 (LDOS only): the per-node values exist for the
+  // angles k < fold_k0 alone; angle k + fold_k0 has the corners of angle k
+  // and takes the values of energy e_partner[e] (both indices of the launch
+  // order, partners within the block)
+  const int32_t* e_map;
+  const int32_t* e_partner;
+  int fold_k0;
 };
 
 struct DiffNormArgs {

@@ -310,17 +310,22 @@ def test_ldos_matches_oracle(precision, tol):
                                             ("small_d110_field", "mixed")])
 def test_ldos_angle_pairs_equal_every_angle(name, precision):
     """LDOS with an energy set symmetric about zero (e and -e, zero included)
-    and 5 boundary iterations: with angle pairs the boundary sweeps march
-    the lower angle of each pair and fill the upper one's store from its
-    mirror at -e.  The LDOS equals that of the run without pairs (1e-12
-    FP64, 1e-6 mixed); an asymmetric set runs unpaired and equals it too."""
+    and 5 boundary iterations: with angle pairs the boundary and output
+    sweeps march the lower angle of each pair (the upper one's store filled
+    from its mirror at -e; its LDOS share read at -e through the lower
+    angle's corners).  The LDOS equals that of the run without pairs (1e-12
+    FP64, 1e-6 mixed), for one output block (9 energies), for several
+    (131 energies in the caller's shuffled order: blocks of 64 holding
+    whole pairs, zero last), and for an asymmetric set, which runs
+    unpaired."""
     qs = _qs()
     sp = wl.spec(name)
     _note("case %s %s: LDOS with and without angle pairs" % (name, precision))
     d0 = _dev(wl.initial_delta(name, sp), torch.complex128)
     a0 = _dev(wl.initial_A(name, sp), torch.float64)
     tol = 1e-12 if precision == "fp64" else 1e-6
-    for en in (np.linspace(-0.45, 0.45, 9), np.array([-0.3, 0.05, 0.2, 0.31])):
+    shuffled = np.random.default_rng(4).permutation(np.linspace(-0.5, 0.5, 131))
+    for en in (np.linspace(-0.45, 0.45, 9), shuffled, np.array([-0.3, 0.05, 0.2, 0.31])):
         out = []
         for pair in (True, False):
             g = qs.Grain(sp, precision)
