@@ -150,19 +150,6 @@ __device__ __forceinline__ cpx<T> riccati_step(cpx<T> g, const StepNode<T>& s, T
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Principal square root as csqrt, with u = v/2, v = |w| + |x|: sqrt u = v k and
-// y / (2 sqrt u) = y k for k = 1/sqrt(2 v).
-template <typename T>
-__device__ __forceinline__ cpx<T> csqrt_v(T wx, T wy) {
-  const T r = dsqrt(fmaT(wx, wx, wy * wy));
-  const T v = r + dabs(wx);
-  const T k = drsq(dmax(v + v, tiny<T>()));
-  const T t = v * k;
-  const T yq = wy * k;
-  const bool pos = wx >= T(0);
-  return mk(pos ? t : dabs(yq), pos ? yq : dsign(t, wy));
-}
-
 // The same implicit-midpoint step as riccati_step, rearranged for fewer
 // operations.  Per step (shared by all energies): C2 = 2 c2 and C8 = 8 c2
 // with c2 = (i h/4) conj(dm).  Per energy: kx = -h Im z - 1 and ky = h Re z
@@ -171,6 +158,11 @@ __device__ __forceinline__ cpx<T> csqrt_v(T wx, T wy) {
 //   disc = c1^2 - 4 c2 c0 = c1^2 - C2 C0,
 //   g' = 2 c0 / (-c1 + sqrt(disc)) = C0 / (s sqrt(disc) - c1)
 // with the sign s = -1 where the principal root points away from -c1.
+// The roots of disc = (dx, dy) are +-(a, b) k with v = |disc| + |dx|,
+// k = 1/sqrt(2 v) and (a, b) = (v, dy) for dx >= 0, (dy, v) otherwise
+// ((a + i b)^2 k^2 = disc in both cases); since k > 0, the sign of
+// a c1x + b c1y picks the root that points away from c1, i.e. the sign
+// s above applied to the principal root, without forming that root.
 template <typename T>
 struct StepC {
   T C2x, C2y, C8x, C8y;
@@ -185,9 +177,12 @@ __device__ __forceinline__ cpx<T> riccati_step_c(cpx<T> g, const StepC<T>& s, T 
   const T dx = fmaT(c1x, c1x, fmaT(-c1y, c1y, fmaT(-s.C2x, C0x, s.C2y * C0y)));
   const T tq = fmaT(s.C2x, C0y, s.C2y * C0x);
   const T dy = fmaT(c1x + c1x, c1y, -tq);
-  const cpx<T> rt = csqrt_v(dx, dy);
-  const T sg = rt.x * c1x + rt.y * c1y > T(0) ? T(-1) : T(1);
-  const T ex = fmaT(sg, rt.x, -c1x), ey = fmaT(sg, rt.y, -c1y);
+  const T v = dsqrt(fmaT(dx, dx, dy * dy)) + dabs(dx);
+  const T k = drsq(fmaT(v, T(2), tiny<T>()));
+  const bool pos = dx >= T(0);
+  const T ra = pos ? v : dy, rb = pos ? dy : v;
+  const T ks = fmaT(ra, c1x, rb * c1y) > T(0) ? -k : k;
+  const T ex = fmaT(ks, ra, -c1x), ey = fmaT(ks, rb, -c1y);
   const T rn = drcp(fmaT(ex, ex, ey * ey));
   return mk(fmaT(C0x, ex, C0y * ey) * rn, fmaT(C0y, ex, -(C0x * ey)) * rn);
 }

@@ -265,7 +265,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 
   // ---- gamma: R_min -> R_max
   cpx<T> g[EPL];
-  node4<T> prev = nodes[slot0];
+  // the segment's slot values; indexed with unsigned 32-bit offsets, which
+  // widen to the 64-bit address without a sign extension
+  const node4<T>* const nseg = nodes + slot0;
+  node4<T> prev = nseg[0];
   {
     const int64_t tb = seg * 4;
     const double wsum = a.tap_start_w[tb] + a.tap_start_w[tb + 1] + a.tap_start_w[tb + 2] + a.tap_start_w[tb + 3];
@@ -304,7 +307,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   // below step 0's store, a node's gamma is stored in the next step, right
   // after that step's prefetch.
   constexpr bool late_store = sizeof(T) == 4;
-  node4<T> nxt = nodes[slot0 + min(1, last)];
+  node4<T> nxt = nseg[static_cast<uint32_t>(min(1, last))];
   // step 0 from R_min (the boundary point takes slot 0's values); a segment
   // with no node still owns one slot, so its store is in range
   end_step(g, prev, prev, hfirst, T(1));
@@ -315,7 +318,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
 #pragma unroll kUnrollG
   for (int t = 1; t < n; ++t) {
     const node4<T> cur = nxt;
-    nxt = nodes[slot0 + min(t + 1, last)];
+    nxt = nseg[static_cast<uint32_t>(min(t + 1, last))];
     if (!late_store && MODE != 2) store_g(t - 1);
     mid_step(g, prev, cur, T(1));
     prev = cur;
@@ -340,7 +343,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   for (int i = 0; i < EPL; ++i)
     rw[i] = (MODE == 0 && own[i]) ? a.rp[a.e_off + es + i] : 0.0;
   cpx<T> gt[EPL];
-  prev = nodes[slot0 + last];
+  prev = nseg[static_cast<uint32_t>(last)];
   {
     const int64_t tb = seg * 4;
     const double wsum = a.tap_end_w[tb] + a.tap_end_w[tb + 1] + a.tap_end_w[tb + 2] + a.tap_end_w[tb + 3];
@@ -383,8 +386,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
     const int lp = lg - 3;  // log2 P
     const int o = lane >> lp, r = lane & ((1 << lp) - 1);
     const double2* src = reinterpret_cast<const double2*>(lsum + o * 64 + (l64 - lane));
-    double v = 0.0;
-    for (int j = 0; j < 4; ++j) {  // partials of lanes 8 r .. 8 r + 7 of the group
+    // partials of lanes 8 r .. 8 r + 7 of the group
+    const double2 x0 = src[r << 2];
+    double v = x0.x + x0.y;
+    for (int j = 1; j < 4; ++j) {
       const double2 x = src[(r << 2) + j];
       v += x.x + x.y;
     }
@@ -410,11 +415,12 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
           const T dxr = T(1) + xx;
           // I = 1/(1+X) = (dxr - i xy) u with u = 1 / |1+X|^2
           const T u = drcp(fmaT(dxr, dxr, xy * xy));
+          const T ix = dxr * u, iy = xy * u;  // I = ix - i iy
           const T sxs = gg.x + gt[i].x, sys = gg.y + gt[i].y;
           const T dxs = gg.x - gt[i].x, dys = gg.y - gt[i].y;
-          const double tfx = static_cast<double>(u * fmaT(sxs, dxr, sys * xy));     // Re((gamma + gamma~) I)
-          const double tfy = static_cast<double>(u * fmaT(dys, dxr, -(dxs * xy)));  // Im((gamma - gamma~) I)
-          const double tg = static_cast<double>(u * xy);                            // -Im I
+          const double tfx = static_cast<double>(fmaT(sxs, ix, sys * iy));     // Re((gamma + gamma~) I)
+          const double tfy = static_cast<double>(fmaT(dys, ix, -(dxs * iy)));  // Im((gamma - gamma~) I)
+          const double tg = static_cast<double>(iy);                           // -Im I
           const double ti = static_cast<double>(fmaT(nv.dx, dys, -(nv.dy * sxs)));  // Im(D* gamma - D gamma~)
           if (i == 0) {
             sfx = rw[0] * tfx;
@@ -516,7 +522,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   constexpr bool gpre = MODE != 2 && sizeof(T) == 4;
   // (the prefetched row, max(t - 2, 0) at step t, is walked down with a
   // pointer rather than formed from t, which costs 64-bit multiplies)
-  nxt = nodes[slot0 + max(n - 2, 0)];
+  nxt = nseg[static_cast<uint32_t>(max(n - 2, 0))];
   cpx<T> gnx[EPL];
   const cpx<T>* grow = glane + static_cast<int64_t>(max(n - 2, 0)) * a.n_e;
   auto load_row = [&](cpx<T>* gv, const cpx<T>* row) {
@@ -525,7 +531,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   if (gpre) load_row(gnx, grow);
   for (int t = n - 1; t >= 1; --t) {
     const node4<T> cur = nxt;
-    nxt = nodes[slot0 + max(t - 2, 0)];
+    nxt = nseg[static_cast<uint32_t>(max(t - 2, 0))];
     if (gpre) {
       for (int i = 0; i < EPL; ++i) gn[i] = gnx[i];
       if (t >= 2) grow -= a.n_e;
