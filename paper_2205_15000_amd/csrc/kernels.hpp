@@ -150,58 +150,59 @@ __device__ __forceinline__ cpx<T> riccati_step(cpx<T> g, const StepNode<T>& s, T
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// The same implicit-midpoint step as riccati_step, rearranged for fewer
-// operations.  Per step (shared by all energies): C2 = 2 c2 and C8 = 8 c2
-// with c2 = (i h/4) conj(dm).  Per energy: kx = -h Im z - 1 and ky = h Re z
-// (k = i h z - 1) and kx4 = kx + 4.  Then
-//   c1 = C2 g + k,   C0 = 2 c0 = (c1 + k + 4) g - 8 conj(c2),
-//   disc = c1^2 - 4 c2 c0 = c1^2 - C2 C0,
-//   g' = 2 c0 / (-c1 + sqrt(disc)) = C0 / (s sqrt(disc) - c1)
-// with the sign s = -1 where the principal root points away from -c1.
-// The roots of disc = (dx, dy) are +-(a, b) k with v = |disc| + |dx|,
-// k = 1/sqrt(2 v) and (a, b) = (v, dy) for dx >= 0, (dy, v) otherwise
-// ((a + i b)^2 k^2 = disc in both cases); since k > 0, the sign of
-// a c1x + b c1y picks the root that points away from c1, i.e. the sign
-// s above applied to the principal root, without forming that root.
+// The same implicit-midpoint step as riccati_step, solved for the midpoint
+// value w = (g + g')/2 instead of g'.  With D the half-step order parameter,
+// k = i h z - 1 and the step equation g' - g = i h [D* w^2 + 2 z w + D]:
+//   (i h D*) w^2 + 2 k w + U = 0,   U = 2 g + i h D.
+// With K = k/2 and c2 = (i h/4) conj(D) (so i h D* = 4 c2 and i h D =
+// -4 conj(c2)) the stable root is w = -U / (2 e), e = K + s sqrt(disc),
+//   disc = K^2 - c2 U,
+// the sign s taken so that s sqrt(disc) points along K (|e| is then the
+// larger of the two choices and w -> g as h -> 0).  So g' = 2 w - g =
+// -U conj(e) / |e|^2 - g.  (disc is a quarter of c1^2 - 4 c2 c0 of
+// riccati_step with the terms in g^2 cancelled.)
+// The roots of disc = (dx, dy) are +-(a, b) r with v = |disc| + |dx|,
+// r = 1/sqrt(2 v) and (a, b) = (v, dy) for dx >= 0, (dy, v) otherwise
+// ((a + i b)^2 r^2 = disc in both cases); since r > 0 the sign of
+// a Kx + b Ky picks s without forming the principal root.
+// Per step (shared by all energies): c2 and U0 = i h D = -4 conj(c2).  Per
+// energy: Kx = (-h Im z - 1)/2, its square Kx2, and Ky = h Re z / 2.
 template <typename T>
 struct StepC {
-  T C2x, C2y, C8x, C8y;
+  T c2x, c2y, U0x, U0y;
 };
 template <typename T>
-__device__ __forceinline__ cpx<T> riccati_step_c(cpx<T> g, const StepC<T>& s, T kx, T kx4, T ky) {
-  const T c1x = fmaT(s.C2x, g.x, fmaT(-s.C2y, g.y, kx));
-  const T c1y = fmaT(s.C2x, g.y, fmaT(s.C2y, g.x, ky));
-  const T p2x = c1x + kx4, p2y = c1y + ky;
-  const T C0x = fmaT(p2x, g.x, fmaT(-p2y, g.y, -s.C8x));
-  const T C0y = fmaT(p2x, g.y, fmaT(p2y, g.x, s.C8y));
-  const T dx = fmaT(c1x, c1x, fmaT(-c1y, c1y, fmaT(-s.C2x, C0x, s.C2y * C0y)));
-  const T tq = fmaT(s.C2x, C0y, s.C2y * C0x);
-  const T dy = fmaT(c1x + c1x, c1y, -tq);
+__device__ __forceinline__ cpx<T> riccati_step_c(cpx<T> g, const StepC<T>& s, T Kx, T Kx2, T Ky) {
+  const T Ux = fmaT(T(2), g.x, s.U0x), Uy = fmaT(T(2), g.y, s.U0y);
+  const T dx = fmaT(-s.c2x, Ux, fmaT(s.c2y, Uy, fmaT(-Ky, Ky, Kx2)));
+  const T dy = fmaT(-s.c2x, Uy, fmaT(-s.c2y, Ux, (Kx + Kx) * Ky));
   const T v = dsqrt(fmaT(dx, dx, dy * dy)) + dabs(dx);
-  const T k = drsq(fmaT(v, T(2), tiny<T>()));
+  const T r = drsq(fmaT(v, T(2), tiny<T>()));
   const bool pos = dx >= T(0);
   const T ra = pos ? v : dy, rb = pos ? dy : v;
-  const T ks = fmaT(ra, c1x, rb * c1y) > T(0) ? -k : k;
-  const T ex = fmaT(ks, ra, -c1x), ey = fmaT(ks, rb, -c1y);
+  const T rs = fmaT(ra, Kx, rb * Ky) < T(0) ? -r : r;
+  const T ex = fmaT(rs, ra, Kx), ey = fmaT(rs, rb, Ky);
   const T rn = drcp(fmaT(ex, ex, ey * ey));
-  return mk(fmaT(C0x, ex, C0y * ey) * rn, fmaT(C0y, ex, -(C0x * ey)) * rn);
+  const T nx = fmaT(Ux, ex, Uy * ey), ny = fmaT(Uy, ex, -(Ux * ey));
+  return mk(fmaT(-nx, rn, -g.x), fmaT(-ny, rn, -g.y));
 }
 
 // Step constants of riccati_step_c for half-step value dm and length hs
 template <typename T>
 __device__ __forceinline__ StepC<T> step_consts(T dmx, T dmy, T hs) {
   StepC<T> c;
-  const T h2 = T(0.5) * hs;
-  c.C2x = h2 * dmy;
-  c.C2y = h2 * dmx;
-  c.C8x = T(4) * c.C2x;
-  c.C8y = T(4) * c.C2y;
+  const T h4 = T(0.25) * hs;
+  c.c2x = h4 * dmy;
+  c.c2y = h4 * dmx;
+  c.U0x = T(-4) * c.c2x;
+  c.U0y = T(4) * c.c2y;
   return c;
 }
 // riccati_step_c with the per-energy constants formed from z = (zx, zy)
 template <typename T>
 __device__ __forceinline__ cpx<T> riccati_step_z(cpx<T> g, const StepC<T>& c, T hs, T zx, T zy) {
-  return riccati_step_c(g, c, fmaT(-hs, zy, T(-1)), fmaT(-hs, zy, T(3)), hs * zx);
+  const T Kx = fmaT(T(-0.5) * hs, zy, T(-0.5));
+  return riccati_step_c(g, c, Kx, Kx * Kx, T(0.5) * hs * zx);
 }
 
 // Stable homogeneous root of D* g^2 + 2 z g + D = 0: -D / (z + s) with

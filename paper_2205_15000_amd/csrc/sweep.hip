@@ -229,38 +229,40 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int64_t wseg, 
   for (int i = 0; i < EPL; ++i) own[i] = es + i >= e0;
 
   T ex[EPL], ey[EPL];
-  // interior steps (length h): kx = -h Im z - 1 and kx + 4 per energy
-  T kxi[EPL], kx4i[EPL];
+  // interior steps (length h): Kx = (-h Im z - 1)/2 and its square per energy
+  T kxi[EPL], kx2i[EPL];
   for (int i = 0; i < EPL; ++i) {
     const int e = es + i;
     ex[i] = static_cast<T>(a.eps[2 * (a.e_off + e)]);
     ey[i] = static_cast<T>(a.eps[2 * (a.e_off + e) + 1]);
-    kxi[i] = fmaT(-hfull, ey[i], T(-1));
-    kx4i[i] = fmaT(-hfull, ey[i], T(3));
+    kxi[i] = fmaT(T(-0.5) * hfull, ey[i], T(-0.5));
+    kx2i[i] = kxi[i] * kxi[i];
   }
-  const T hq4 = T(0.25) * hfull, hqa = T(0.5) * q * hfull;
+  const T hh = T(0.5) * hfull, hq8 = T(0.125) * hfull, hqa = T(0.25) * q * hfull;
 
   // Step with the half-step values (mean of two slots; sd = -1 applies
   // D -> -D* for gamma~).  End steps take every constant from their length.
   auto end_step = [&](cpx<T>* gv, const node4<T>& pv, const node4<T>& cv, T hs, T sd) {
-    const T h4 = T(0.25) * hs;
+    const T h8 = T(0.125) * hs;
     StepC<T> c;
-    c.C2x = h4 * (pv.dy + cv.dy);
-    c.C2y = h4 * (sd * (pv.dx + cv.dx));
-    c.C8x = T(4) * c.C2x;
-    c.C8y = T(4) * c.C2y;
+    c.c2x = h8 * (pv.dy + cv.dy);
+    c.c2y = h8 * (sd * (pv.dx + cv.dx));
+    c.U0x = T(-4) * c.c2x;
+    c.U0y = T(4) * c.c2y;
     const T qa = T(0.5) * q * (pv.a + cv.a);
-    for (int i = 0; i < EPL; ++i)
-      gv[i] = riccati_step_c(gv[i], c, fmaT(-hs, ey[i], T(-1)), fmaT(-hs, ey[i], T(3)), hs * (qa + ex[i]));
+    for (int i = 0; i < EPL; ++i) {
+      const T kx = fmaT(T(-0.5) * hs, ey[i], T(-0.5));
+      gv[i] = riccati_step_c(gv[i], c, kx, kx * kx, T(0.5) * hs * (qa + ex[i]));
+    }
   };
   auto mid_step = [&](cpx<T>* gv, const node4<T>& pv, const node4<T>& cv, T sd) {
     StepC<T> c;
-    c.C2x = hq4 * (pv.dy + cv.dy);
-    c.C2y = hq4 * (sd * (pv.dx + cv.dx));
-    c.C8x = T(4) * c.C2x;
-    c.C8y = T(4) * c.C2y;
+    c.c2x = hq8 * (pv.dy + cv.dy);
+    c.c2y = hq8 * (sd * (pv.dx + cv.dx));
+    c.U0x = T(-4) * c.c2x;
+    c.U0y = T(4) * c.c2y;
     const T hq = hqa * (pv.a + cv.a);
-    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_c(gv[i], c, kxi[i], kx4i[i], fmaT(hfull, ex[i], hq));
+    for (int i = 0; i < EPL; ++i) gv[i] = riccati_step_c(gv[i], c, kxi[i], kx2i[i], fmaT(hh, ex[i], hq));
   };
 
   // ---- gamma: R_min -> R_max
