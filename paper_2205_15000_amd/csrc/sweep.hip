@@ -653,6 +653,9 @@ __global__ void reset_counter_kernel(int* counter) {
 constexpr int kBackWaves = 4;
 constexpr int kBackFields = 12;  // 2 x (up to 4 components) + jx, jy, I, <|Delta|^2>
 
+// NC = 1: one order-parameter component (its arrays in fixed registers);
+// NC = 4: a.ncomp <= 4 components
+template <int NC>
 __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a) {
   __shared__ double part[kBackWaves - 1][kBackFields][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -661,9 +664,10 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   const int64_t c = xcd_block(blockIdx.x, gridDim.x) * 64 + lane;
   const bool live = c < a.ncg;
   const int cell = live ? a.grain_cells[c] : 0;
-  constexpr int MAXC = 4;
+  constexpr int MAXC = NC;
+  const int ncomp = NC == 1 ? 1 : a.ncomp;
   double nx_[MAXC], ny_[MAXC], dx_[MAXC], dy_[MAXC];
-  for (int g = 0; g < a.ncomp; ++g) {
+  for (int g = 0; g < ncomp; ++g) {
     nx_[g] = 0.0;
     ny_[g] = 0.0;
     dx_[g] = a.delta[2 * (static_cast<int64_t>(g) * a.ncell + cell)];
@@ -679,7 +683,7 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   auto add_angle = [&](int kk, double cfx, double cfy, double cg, double ci) {
     const double wk = a.wk[kk];
     double dkx = 0.0, dky = 0.0;
-    for (int g = 0; g < a.ncomp; ++g) {
+    for (int g = 0; g < ncomp; ++g) {
       const double ex = a.eta[2 * (g * a.n_theta + kk)], ey = a.eta[2 * (g * a.n_theta + kk) + 1];
       const double px = wk * ex, py = -wk * ey;  // wk conj(eta)
       nx_[g] += px * cfx - py * cfy;
@@ -694,8 +698,14 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   };
   // with pair_fold each gather of a lower angle serves its upper angle too
   const int kend = a.pair_fold ? a.pair_k0 : a.n_theta;
-  for (int k = live ? wv : kend; k < kend; k += kBackWaves) {
-    const int4 ix = a.rb4[static_cast<int64_t>(k) * a.ncg + c];
+  // the corner record of the wave's next angle is loaded one iteration
+  // ahead, so only the node-sum gathers wait in each iteration
+  int k = live ? wv : kend;
+  int4 ixn = make_int4(0, 0, 0, 0);
+  if (k < kend) ixn = a.rb4[static_cast<int64_t>(k) * a.ncg + c];
+  for (; k < kend; k += kBackWaves) {
+    const int4 ix = ixn;
+    if (k + kBackWaves < kend) ixn = a.rb4[static_cast<int64_t>(k + kBackWaves) * a.ncg + c];
     const double epx = a.cosk[k], epy = a.sink[k];
     // lattice coordinates (line u, node v) of the cell centre
     const double u = rn_lattice(rx, epy, ry, -epx, a.h, a.half);
@@ -733,7 +743,7 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   }
   if (wv > 0) {
     double* p = &part[wv - 1][0][lane];
-    for (int g = 0; g < a.ncomp; ++g) {
+    for (int g = 0; g < ncomp; ++g) {
       p[64 * (2 * g)] = nx_[g];
       p[64 * (2 * g + 1)] = ny_[g];
     }
@@ -746,7 +756,7 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
   if (wv > 0 || !live) return;
   for (int w = 0; w < kBackWaves - 1; ++w) {
     const double* p = &part[w][0][lane];
-    for (int g = 0; g < a.ncomp; ++g) {
+    for (int g = 0; g < ncomp; ++g) {
       nx_[g] += p[64 * (2 * g)];
       ny_[g] += p[64 * (2 * g + 1)];
     }
@@ -756,7 +766,7 @@ __global__ void __launch_bounds__(64 * kBackWaves) rotate_back_kernel(BackArgs a
     d2avg += p[64 * 11];
   }
   double om = 0.0;
-  for (int g = 0; g < a.ncomp; ++g) {
+  for (int g = 0; g < ncomp; ++g) {
     a.delta_new[2 * (static_cast<int64_t>(g) * a.ncell + cell)] = nx_[g] / a.den[g];
     a.delta_new[2 * (static_cast<int64_t>(g) * a.ncell + cell) + 1] = ny_[g] / a.den[g];
     om += (dx_[g] * dx_[g] + dy_[g] * dy_[g]) * a.logt[g];
@@ -1400,7 +1410,10 @@ template void launch_mirror_fill<double>(const int2*, int64_t, int, const int32_
 
 void launch_rotate_back(const BackArgs& a, hipStream_t st) {
   if (a.ncg == 0) return;
-  hipLaunchKernelGGL(rotate_back_kernel, dim3((a.ncg + 63) / 64), dim3(64 * kBackWaves), 0, st, a);
+  if (a.ncomp == 1)
+    hipLaunchKernelGGL(rotate_back_kernel<1>, dim3((a.ncg + 63) / 64), dim3(64 * kBackWaves), 0, st, a);
+  else
+    hipLaunchKernelGGL(rotate_back_kernel<4>, dim3((a.ncg + 63) / 64), dim3(64 * kBackWaves), 0, st, a);
 }
 
 template <typename T>
