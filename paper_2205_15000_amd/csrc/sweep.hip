@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(256) interp1_kernel(InterpArgs a, const cell4<
     node4<T> o;
     o.dx = static_cast<T>(dx);
     o.dy = static_cast<T>(dy);
-    // external field (analytic, Sec. III.C gauges)
+    // external field: symmetric, Landau or solenoid gauge (App. B; Eq. solenoid_gauge)
     double ex_x = 0.0, ex_y = 0.0;
     const double rx = px - a.cx, ry = py - a.cy;
     if (a.gauge == 0) {
