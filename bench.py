@@ -421,7 +421,7 @@ def mode_lanes(qs, torch, wl, name, iters):
                          "sweep_ms": ms / max(n, 1)})
         # the split launch shape at the automatic lane shape (0: off)
         g.set_lanes(0)
-        for frac in (0.0, 0.6, 0.7, 0.75, 0.8, 0.85, 0.9):
+        for frac in (0.0, 0.5, 0.6, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95):
             g.set_split(frac)
             g.reset_bc()
             g.sweep(d0, a0)

@@ -540,7 +540,7 @@ qc_status qc_grain_get_lanes(const qc_grain* grain, int* energies_per_lane, int*
  * energies per lane and twice the lanes still within 64, the segments longer
  * than frac x the longest then march with twice the lanes and half the
  * energies per lane (rounded up to whole waves).  frac in [0, 1]; 0 turns
- * the split off; the default is 0.9.  Results are identical up to the order
+ * the split off; the default is 0.8.  Results are identical up to the order
  * of the FP64 pole sums.  Errors: QC_ERR_INVALID for frac outside [0, 1]. */
 qc_status qc_grain_set_split(qc_grain* grain, double frac);
 /* The fraction set and the number of segments the next SCF sweep launches

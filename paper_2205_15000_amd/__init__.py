@@ -595,7 +595,7 @@ class Grain:
     def set_split(self, frac):
         """Split launch shape of the SCF sweep: segments longer than frac x
         the longest march with twice the lanes when the launch is short
-        (0 turns it off; default 0.9)."""
+        (0 turns it off; default 0.8)."""
         _check(lib.qc_grain_set_split(self._g, float(frac)))
 
     def split(self):

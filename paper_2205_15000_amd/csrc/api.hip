@@ -294,7 +294,7 @@ struct qc_grain {
   // pairs), the split fraction of the Matsubara sweep's launch shape and the
   // device's wave slots per (precision, energies per lane), found on first use
   std::vector<int32_t> len_order, len_order_pair;
-  double split_frac = 0.9;
+  double split_frac = 0.8;
   int64_t wave_slots[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
   void* gbuf = nullptr;
   double* node_out = nullptr;
