@@ -59,8 +59,9 @@ WORKLOAD = "d110_square_400"
 # (about 75 flops per node and pole, i.e. about 37 per step): 96 flops.
 FLOPS_PER_STEP = 96
 # A recount of the final formulas (complex ops expanded, sqrt and reciprocal
-# one flop each): 71 per step plus 82 per (node, pole); reported beside.
-RECOUNT_PER_STEP = 71
+# one flop each; the step solved for its midpoint value): 47 per step plus
+# 82 per (node, pole); reported beside.
+RECOUNT_PER_STEP = 47
 RECOUNT_PER_NODE_POLE = 82
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6      # MI355X published FP64 vector peak
@@ -70,7 +71,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep launch (mixed) from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs scaled by a plain-copy calibration (profiles/sweep_kernel_d110_square_400.md);
 # None whenever the kernel changed after the counters were taken.
-SWEEP_TRAFFIC_BYTES = 5.740e9
+SWEEP_TRAFFIC_BYTES = 5.737e9
 
 
 def parse():
