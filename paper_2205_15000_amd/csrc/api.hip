@@ -716,10 +716,12 @@ void do_sweep(qc_grain* g, const double* delta, const double* A, double* delta_n
   qc::launch_rotate_back(back_args(g, delta, delta_new, j, omega), st);
   hcheck(hipGetLastError(), "rotate-back launch");
   // block partials of the free energy (condensation and magnetic parts)
-  qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, region(g, kROmega), kParts, st);
   if (g->kappa > 0.0) {
     qc::launch_curl(A, g->bbuf, g->nx, g->ny, g->h, st);
-    qc::launch_block_sum(g->bbuf, nullptr, g->ncell, 1, region(g, kRB2), kParts, st);
+    qc::launch_block_sum2({g->omega_cell, nullptr, g->ncg, 0, region(g, kROmega)},
+                          {g->bbuf, nullptr, g->ncell, 1, region(g, kRB2)}, kParts, st);
+  } else {
+    qc::launch_block_sum(g->omega_cell, nullptr, g->ncg, 0, region(g, kROmega), kParts, st);
   }
   if (omega_total) {
     fetch_parts(g, st);
@@ -1200,8 +1202,8 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
     return;
   }
   // mean current over the grain cells, subtracted before the solve (App. D)
-  qc::launch_block_sum(j, g->grain_cells, g->ncg, 0, region(g, kRJx), kParts, st);
-  qc::launch_block_sum(j + g->ncell, g->grain_cells, g->ncg, 0, region(g, kRJy), kParts, st);
+  qc::launch_block_sum2({j, g->grain_cells, g->ncg, 0, region(g, kRJx)},
+                        {j + g->ncell, g->grain_cells, g->ncg, 0, region(g, kRJy)}, kParts, st);
   qc::launch_means(region(g, kRJx), kParts, 1.0 / static_cast<double>(g->ncg), g->dmean, st);
   if (g->a_nmodes > 0) {
     // the separable kernel kept to its largest modes: two MFMA contractions
@@ -1224,13 +1226,13 @@ void do_solve_A(qc_grain* g, const double* j, double* A_out, double* B_out, hipS
   hcheck(hipGetLastError(), "A-solve launch");
 }
 
-// block partials of the p-norms of (new - old) and old over n elements of
-// `stride` doubles, gathered through idx when given, for nrep fields
-// block partials of ||xnew - xold||_p and ||xold||_p; with update, also the
-// Picard step xold += alpha (xnew - xold) in the same pass
-void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* idx, int64_t n, int nrep,
-                  int64_t field_stride, int stride, int p, int reg, hipStream_t st, bool update = false,
-                  double alpha = 1.0, double* vel = nullptr) {
+// Arguments of the pass that forms the block partials of ||xnew - xold||_p
+// and ||xold||_p over n elements of `stride` doubles (gathered through idx
+// when given) for nrep fields into region reg; with update, the pass also
+// takes the Picard step xold += alpha (xnew - xold)
+qc::DiffNormArgs diff_args(qc_grain* g, const double* xnew, double* xold, const int32_t* idx, int64_t n, int nrep,
+                           int64_t field_stride, int stride, int p, int reg, bool update = false, double alpha = 1.0,
+                           double* vel = nullptr) {
   qc::DiffNormArgs a;
   a.xnew = xnew;
   a.xold = xold;
@@ -1245,7 +1247,7 @@ void enqueue_diff(qc_grain* g, const double* xnew, double* xold, const int32_t* 
   a.alpha = alpha;
   a.vel = vel;
   a.beta = g->beta;
-  qc::launch_diff_norm(a, kParts, st);
+  return a;
 }
 
 // ||new - old||_p / ||old||_p from fetched partials (0/0 = 0, x/0 = inf)
@@ -1517,11 +1519,17 @@ qc_status qc_scf_run(qc_grain* g, double* delta_io, double* A_io, int max_iter, 
       do_solve_A(g, g->jcur, g->anew, nullptr, st);
       // residuals of Delta and A with their Picard steps fused in
       // (BB: norms and dot products first; the step follows once its size is known)
-      enqueue_diff(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD, st,
-                   !bb && !cong, alpha, polyak ? g->vel_d : nullptr);
-      if (have_old) enqueue_diff(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ, st);
-      enqueue_diff(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, st, !bb && !cong, alpha,
-                   polyak ? g->vel_a : nullptr);
+      // (the three fields in one launch)
+      {
+        qc::DiffNormArgs da[3];
+        int nd = 0;
+        da[nd++] = diff_args(g, g->dnew, delta_io, g->grain_cells, g->ncg, g->ncomp, g->ncell, 2, norm_p, kRDiffD,
+                             !bb && !cong, alpha, polyak ? g->vel_d : nullptr);
+        if (have_old) da[nd++] = diff_args(g, g->jcur, g->jold, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffJ);
+        da[nd++] = diff_args(g, g->anew, A_io, nullptr, 2 * g->ncell, 1, 0, 1, norm_p, kRDiffA, !bb && !cong, alpha,
+                             polyak ? g->vel_a : nullptr);
+        qc::launch_diff_norm_n(da, nd, kParts, st);
+      }
       if (cong && !cg_first) {
         for (int c = 0; c < ncx; ++c) {
           double* pc = g->cpart + static_cast<int64_t>(c) * 3 * kParts;

@@ -887,9 +887,15 @@ __global__ void __launch_bounds__(256) curl_kernel(const double* __restrict__ A,
 // Block partial sums of f(x) (x gathered through idx when given): mode 0
 // sum x, mode 1 sum x^2.  One partial per block written to part[blockIdx.x];
 // the host adds them in order.
-__global__ void __launch_bounds__(256) block_sum_kernel(const double* __restrict__ x,
-                                                        const int32_t* __restrict__ idx, int64_t n, int mode,
-                                                        double* __restrict__ part) {
+// Up to two sums per launch: blockIdx.y picks the row (BlockSumRow r0, r1);
+// each row's partials are those a launch of its own would give.
+__global__ void __launch_bounds__(256) block_sum_kernel(BlockSumRow r0, BlockSumRow r1) {
+  const BlockSumRow& r = blockIdx.y == 0 ? r0 : r1;
+  const double* __restrict__ x = r.x;
+  const int32_t* __restrict__ idx = r.idx;
+  const int64_t n = r.n;
+  const int mode = r.mode;
+  double* __restrict__ part = r.part;
   __shared__ double sh[256];
   double acc = 0.0;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -970,7 +976,9 @@ __global__ void __launch_bounds__(256) scale_kernel(const double* __restrict__ x
 // doubles each (stride 2: complex modulus).  p = 1, 2, or 0 (max).
 // Elements may be gathered through idx (grain cells) when idx != nullptr,
 // for `nrep` consecutive fields of `field_stride` elements.
-__global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a) {
+// up to three independent fields per launch, picked by blockIdx.y
+__global__ void __launch_bounds__(256) diff_norm_kernel(DiffNormArgs a0, DiffNormArgs a1, DiffNormArgs a2) {
+  const DiffNormArgs& a = blockIdx.y == 0 ? a0 : (blockIdx.y == 1 ? a1 : a2);
   __shared__ double s0[256], s1[256];
   double acc0 = 0.0, acc1 = 0.0;
   const int64_t total = a.n * a.nrep;
@@ -1440,10 +1448,19 @@ void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream
 }
 void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,
                       hipStream_t st) {
-  hipLaunchKernelGGL(block_sum_kernel, dim3(nparts), dim3(256), 0, st, x, idx, n, mode, part);
+  const BlockSumRow r{x, idx, n, mode, part};
+  hipLaunchKernelGGL(block_sum_kernel, dim3(nparts), dim3(256), 0, st, r, r);
+}
+void launch_block_sum2(const BlockSumRow& r0, const BlockSumRow& r1, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(block_sum_kernel, dim3(nparts, 2), dim3(256), 0, st, r0, r1);
 }
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st) {
-  hipLaunchKernelGGL(diff_norm_kernel, dim3(nparts), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(diff_norm_kernel, dim3(nparts), dim3(256), 0, st, a, a, a);
+}
+void launch_diff_norm_n(const DiffNormArgs* a, int count, int nparts, hipStream_t st) {
+  if (count < 1 || count > 3) return;
+  hipLaunchKernelGGL(diff_norm_kernel, dim3(nparts, count), dim3(256), 0, st, a[0], a[count > 1 ? 1 : 0],
+                     a[count > 2 ? 2 : 0]);
 }
 void launch_congacc_dots(const double* xnew, const double* xold, const int32_t* idx, int64_t n, int64_t base,
                          int stride, int c, const double* m, double* part, int nparts, hipStream_t st) {

@@ -274,9 +274,22 @@ template <typename T>
 void launch_green_back(const LdosBackArgs& a, const void* ebuf, hipStream_t st);
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_curl(const double* A, double* B, int nx, int ny, double h, hipStream_t st);
+// one block-partial sum: nparts partials of x[i] (mode 0) or x[i]^2 (mode 1)
+// over i < n, gathered through idx when given
+struct BlockSumRow {
+  const double* x;
+  const int32_t* idx;
+  int64_t n;
+  int mode;
+  double* part;
+};
+// two independent sums in one launch
+void launch_block_sum2(const BlockSumRow& r0, const BlockSumRow& r1, int nparts, hipStream_t st);
 void launch_block_sum(const double* x, const int32_t* idx, int64_t n, int mode, double* part, int nparts,
                       hipStream_t st);
 void launch_diff_norm(const DiffNormArgs& a, int nparts, hipStream_t st);
+// 1 to 3 independent fields in one launch (blockIdx.y picks the field)
+void launch_diff_norm_n(const DiffNormArgs* a, int count, int nparts, hipStream_t st);
 // CongAcc (App. E): per-component step sizes and weights of one field
 constexpr int kCongMaxComp = 8;
 struct CongCoef {
