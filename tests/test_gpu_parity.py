@@ -306,6 +306,29 @@ def test_ldos_matches_oracle(precision, tol):
     g.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", 2e-4)])
+def test_ldos_far_from_the_gap_matches_oracle(precision, tol):
+    """LDOS at energies far outside the gap (up to about 20 times the gap)
+    with a small broadening: there h Re(z)/2 exceeds (1 + h Im z)/2, so the
+    discriminant of the implicit-midpoint step (App. C) has a negative real
+    part and its root is taken on the other branch; the step's stable root
+    must still be the oracle's."""
+    qs = _qs()
+    name = "small_d110_field"
+    sp = wl.spec(name)
+    _note("case %s: LDOS far from the gap %s" % (name, precision))
+    g = qs.Grain(sp, precision)
+    og = oracle_grain(sp)
+    d0 = wl.initial_delta(name, sp)
+    a0 = wl.initial_A(name, sp)
+    en = np.array([-6.0, -3.0, -1.2, 0.1, 1.2, 3.0, 6.0])
+    out = g.ldos(_dev(d0, torch.complex128), _dev(a0, torch.float64), en, 0.005, 2)
+    ref = og.ldos(d0, a0, en, 0.005, 2)
+    assert np.all(np.isfinite(out.cpu().numpy()))
+    assert _close(out.cpu().numpy(), ref, tol), rel_err(out.cpu().numpy(), ref)
+    g.close()
+
+
 @pytest.mark.parametrize("name,precision", [("small_d110_field", "fp64"), ("s_disc_32", "fp64"),
                                             ("small_d110_field", "mixed")])
 def test_ldos_angle_pairs_equal_every_angle(name, precision):
